@@ -1,0 +1,268 @@
+#!/usr/bin/env python3
+"""Benchmark of the spin summation on one MI355X.
+
+Headline workload: 3D spin summation, FP64, in place, of the amplitude
+tensor T[a,b,c,i,j,k] with v = 64 virtual and o = 32 occupied extents,
+processed as 8 slabs of 64 x 64 x 8 x 32^3 (1.07G elements, 8.6 GB each);
+coefficients identity 4, each transposition -2, each 3-cycle +1.  One step
+is one in-place pass over all 8 slabs (8 launches, one per slab).  The
+metric is the paper's bandwidth measure (Eq. 12, one read and one write of
+every element) in GB/s, and its fraction of the 8 TB/s HBM peak.
+
+Also reported, each against the plain FP64 kernel (``forms``): the 4D
+in-place summation, the chained (2 - P_ij)(2 - P_jk) form, the batched
+persistent launch replayed from a hipGraph against per-block launches, the
+adjoint, and FP32 storage.  ``cpu_baseline`` is the CPU oracle timed on a
+bounded sample of the headline workload.
+
+    python bench.py [--steps K] [--warmup W] [--forms all|none] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_GBPS = 8000.0
+METRIC = "effective GB/s & % HBM peak, FP64 in-place 3D/4D spinsum; batched/adjoint/FP32 vs plain"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("spinsum_kernels.hip", "spinsum_internal.h"):
+        with open(os.path.join(ROOT, "paper_1705_06661_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(name: str, algo_bytes: float):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{name}.traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def timed(fn, reps, stream):
+    import torch
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record(stream)
+    for _ in range(reps):
+        fn()
+    e.record(stream)
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps
+
+
+def form_entry(nbytes, ms, ref_gbps=None):
+    gbps = nbytes / (ms * 1e-3) / 1e9
+    d = {"GBps": round(gbps, 1), "frac_peak": round(gbps / PEAK_GBPS, 4), "ms": round(ms, 4)}
+    if ref_gbps:
+        d["vs_plain_fp64"] = round(gbps / ref_gbps, 3)
+    return d
+
+
+def cpu_baseline(seconds: float):
+    """The oracle on a bounded sample of the headline workload: whole
+    32^3 spectator cubes of slab 0, regenerated on the host."""
+    import numpy as np
+    import oracle
+    import workloads
+    cube = 32 ** 3
+    threads = max(1, min(16, os.cpu_count() or 1))
+
+    def run(ncubes):
+        x = workloads.uniform_numpy(ncubes * cube, 1000).reshape(ncubes, 32, 32, 32)
+        t0 = time.perf_counter()
+        oracle.spinsum(x, workloads.CONFIG_3D_ALPHA, 1, 3, nthreads=threads)
+        return time.perf_counter() - t0
+
+    n0 = 2 * threads
+    t0 = run(n0)
+    n = int(max(n0, min(4096, n0 * seconds / max(t0, 1e-3))))
+    t = run(n)
+    elems = n * cube
+    return {"value": round(2 * elems * 8 / t / 1e9, 4), "unit": "GB/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{n} spectator cubes (32^3, {elems} elements, fp64) of the v=64 o=32 slab 0, "
+                      f"long-double nested loops, {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--forms", default="all", choices=["all", "none"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--slabs", type=int, default=8)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the spin summation shards over spectator "
+              "slabs with no communication, so multi-GPU runs are not part of this build.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+    import paper_1705_06661_amd as ss
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    alpha = [workloads.CONFIG_3D_ALPHA]
+    slab_shape = workloads.WORKLOADS["3d_v64_o32_slab"]["shape"]
+    nslabs = args.slabs
+
+    log(f"allocating {nslabs} slabs of {slab_shape} fp64")
+    big = torch.empty((nslabs,) + tuple(slab_shape), dtype=torch.float64, device=dev)
+    for s in range(nslabs):
+        workloads.fill_uniform(big[s], 1000 + s)
+    torch.cuda.synchronize()
+    plan = ss.spinsum_plan(slab_shape, 3, 3, alpha, inplace=True)
+    info = ss.spinsum_plan_get_info(plan)
+    log("plan", info)
+
+    def step():
+        for s in range(nslabs):
+            ss.spinsum_exec(plan, big[s], big[s], stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("timing")
+    ms_step = timed(step, args.steps, stream)
+    elems_step = nslabs * info["elems"]
+    value = 2 * elems_step * 8 / (ms_step * 1e-3) / 1e9
+    launch_ms = ms_step / nslabs
+    algo_per_launch = 2.0 * info["elems"] * 8
+    achieved = algo_per_launch / (launch_ms * 1e-3) / 1e9
+    assert bool(torch.isfinite(big[0, 0, 0]).all()), "non-finite output"
+    log(f"headline: {ms_step:.3f} ms/step, {value:.1f} GB/s")
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3d_v64_o32_inplace", "tensor": [64, 64, 64, 32, 32, 32],
+                   "slabs": nslabs, "slab_shape": list(slab_shape), "group": "ijk",
+                   "alpha": "id 4, transpositions -2, 3-cycles +1", "inplace": True,
+                   "values": "U(-1,1) from seed", "tile_edge": info["bl"],
+                   "tile_orbits_per_cube": info["norbits"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_GBPS, 4),
+                     "traffic": traffic_from_profile("spinsum_3d_v64_o32_inplace",
+                                                     algo_per_launch),
+                     "kernel": "k_exec<double,3,2,false,true>",
+                     "algorithmic_bytes_per_launch": algo_per_launch,
+                     "avg_launch_ms": round(launch_ms, 4)},
+    }
+
+    forms = {}
+    if args.forms == "all":
+        # achievable ceiling: plain copy of one slab with the same instructions
+        dst = torch.empty_like(big[0])
+        cms = timed(lambda: ss.spinsum_stream_copy(big[0], dst, stream), 5, stream)
+        forms["stream_copy_ceiling"] = form_entry(2 * big[0].numel() * 8, cms)
+        out["roofline"]["frac_of_copy_ceiling"] = round(
+            achieved / forms["stream_copy_ceiling"]["GBps"], 4)
+        del dst
+        # chained (2 - P_ij)(2 - P_jk) vs its pre-multiplied operator, slab 0
+        for name, flags in [("3d_factored_premultiplied", 0),
+                            ("3d_factored_chained", ss.SPINSUM_FLAG_CHAIN_STAGES)]:
+            pf = ss.spinsum_plan(slab_shape, 3, 3, workloads.FACTORED_PIJ_PJK, inplace=True,
+                                 flags=flags)
+            fms = timed(lambda: ss.spinsum_exec(pf, big[0], big[0], stream), 5, stream)
+            forms[name] = form_entry(2 * big[0].numel() * 8, fms, value)
+        for name, flags in [("3d_no_nt_stores", ss.SPINSUM_FLAG_NO_NT_STORES),
+                            ("3d_no_xcd_grouping", ss.SPINSUM_FLAG_NO_XCD_REMAP)]:
+            pf = ss.spinsum_plan(slab_shape, 3, 3, alpha, inplace=True, flags=flags)
+            fms = timed(lambda: ss.spinsum_exec(pf, big[0], big[0], stream), 5, stream)
+            forms[name] = form_entry(2 * big[0].numel() * 8, fms, value)
+        del big
+        torch.cuda.empty_cache()
+
+        # 4D in place, one a-slab 1 x 24^3 x 12^4, 24 random integer coefficients
+        w4 = workloads.WORKLOADS["4d_v24_o12_slab"]
+        x4 = workloads.uniform(w4["shape"], 2000, device=dev)
+        a4 = workloads.random_4d_alpha(7)
+        p4 = ss.spinsum_plan(w4["shape"], 4, 4, [a4], inplace=True)
+        ss.spinsum_exec(p4, x4, x4, stream)
+        ms4 = timed(lambda: ss.spinsum_exec(p4, x4, x4, stream), 10, stream)
+        forms["4d_v24_o12_inplace"] = form_entry(2 * x4.numel() * 8, ms4, value)
+        forms["4d_v24_o12_inplace"]["tile_edge"] = ss.spinsum_plan_get_info(p4)["bl"]
+        forms["4d_v24_o12_inplace"]["alpha_seed"] = 7
+        del x4
+        torch.cuda.empty_cache()
+
+        # batched: 200 power-law blocks, one persistent launch from a hipGraph
+        seed, blocks = workloads.batched_blocks()
+        shapes = [(v, v, v, o, o, o) for v, o in blocks]
+        xs = [workloads.uniform(s, 3000 + k, device=dev) for k, s in enumerate(shapes)]
+        nbytes = 2 * 8 * sum(x.numel() for x in xs)
+        bp = ss.spinsum_plan_batched(shapes, 3, alpha, inplace=True)
+        graph = ss.spinsum_graph_create(bp, xs, xs)
+        ss.spinsum_graph_launch(graph, stream)
+        bms = timed(lambda: ss.spinsum_graph_launch(graph, stream), 10, stream)
+        singles = [ss.spinsum_plan(s, 3, 3, alpha, inplace=True) for s in shapes]
+
+        def per_block():
+            for p, x in zip(singles, xs):
+                ss.spinsum_exec(p, x, x, stream)
+
+        per_block()
+        pms = timed(per_block, 5, stream)
+        forms["batched_graph"] = form_entry(nbytes, bms, value)
+        forms["batched_graph"].update({"blocks": len(blocks), "block_seed": seed,
+                                       "vs_per_block_launches": round(pms / bms, 3)})
+        forms["batched_per_block_launches"] = form_entry(nbytes, pms, value)
+        del xs, graph, singles
+        torch.cuda.empty_cache()
+
+        # adjoint and FP32: v=48, o=24, forward and backward (autograd form)
+        w5 = workloads.WORKLOADS["3d_v48_o24"]
+        st5 = workloads.FACTORED_PIJ_PJK
+        for dt, tag in [(torch.float64, "fp64"), (torch.float32, "fp32")]:
+            x5 = workloads.uniform(w5["shape"], 4000, device=dev, dtype=dt)
+            y5 = torch.empty_like(x5)
+            p5 = ss.spinsum_plan(w5["shape"], 3, 3, st5, dtype=dt, inplace=False)
+            ss.spinsum_exec(p5, x5, y5, stream)
+            fwd = timed(lambda: ss.spinsum_exec(p5, x5, y5, stream), 5, stream)
+            bwd = timed(lambda: ss.spinsum_adjoint(p5, y5, x5, stream), 5, stream)
+            nb = 2 * x5.numel() * x5.element_size()
+            forms[f"3d_v48_o24_forward_{tag}"] = form_entry(nb, fwd, value)
+            forms[f"3d_v48_o24_adjoint_{tag}"] = form_entry(nb, bwd, value)
+            del x5, y5
+            torch.cuda.empty_cache()
+        out["forms"] = forms
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

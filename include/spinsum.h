@@ -1,0 +1,201 @@
+/*
+ * spinsum.h -- C-ABI of libspinsum, spin summations on AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The operation (Springer, Matthews, Bientinesi, "Spin Summations: A
+ * High-Performance Perspective"):
+ *
+ *   Def. 1 (Eq. 1-2)  a permutation pi_{phi(1)...phi(d)} maps the index tuple
+ *                     (i_1..i_d) to (i_phi(1)..i_phi(d)).  In this API a
+ *                     permutation is an array p[0..d-1] of 0-based positions,
+ *                     p[m] = phi(m+1) - 1.
+ *   Def. 2 (Eq. 3)    B_i <- A_{pi(i)}: a term (p, alpha) adds
+ *                     alpha * In[.., i_{p[0]}, .., i_{p[d-1]}, ..] to
+ *                     Out[.., i_0, .., i_{d-1}, ..].
+ *   Def. 3 (Eq. 4)    a spin summation is Out <- sum_t alpha_t pi_t(In).
+ *   Def. 4 (Eq. 5-6)  a factorised summation is a chain of stages
+ *                     S_K(...S_1(In)); stage 0 of the arrays below is S_1,
+ *                     the innermost factor, applied first.
+ *   Sec. 4.6.5        the in-place form In <- sum_t alpha_t pi_t(In) on
+ *                     hyper-square groups.
+ *
+ * Tensor layout: C-contiguous (row-major, last index fastest), extents
+ * [outer spectators..., N x d]: the permuted group is the trailing d
+ * dimensions, all of extent N (Sec. 3.1 "hyper-square"); every spectator
+ * index selects one "cube" of N^d contiguous elements.  A group followed by
+ * further (inner) dimensions is rejected with SPINSUM_ERR_UNSUPPORTED.
+ *
+ * Conventions shared by every entry point:
+ *   - every function returns a spinsum_status; no exception crosses the ABI;
+ *   - the caller owns all tensor buffers and streams; a plan owns its host
+ *     and device tables and frees them in spinsum_plan_destroy;
+ *   - `stream` is a hipStream_t (NULL = the default stream);
+ *   - tensor pointers are device pointers, 16-byte aligned;
+ *   - exec/adjoint calls are asynchronous and stream-ordered, allocate
+ *     nothing and never synchronise, so they may be captured in a hipGraph;
+ *   - a plan is bound to the device that was current when it was made;
+ *   - HIP failures return SPINSUM_ERR_HIP and the hipError_t is kept on the
+ *     plan (spinsum_plan_last_hip_error).
+ */
+#ifndef SPINSUM_H
+#define SPINSUM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SPINSUM_OK = 0,
+  SPINSUM_ERR_INVALID_ARG = -1,      /* null pointer, bad count, bad dim, wrong device */
+  SPINSUM_ERR_NOT_PERMUTATION = -2,  /* a term is not a bijection of 0..d-1 */
+  SPINSUM_ERR_EXTENT_MISMATCH = -3,  /* group extents differ (not hyper-square) */
+  SPINSUM_ERR_UNSUPPORTED = -4,      /* d not in {2,3,4}, inner spectators, tile too big */
+  SPINSUM_ERR_ALIASING = -5,         /* out-of-place buffers overlap */
+  SPINSUM_ERR_MISALIGNED = -6,       /* tensor pointer not 16-byte aligned */
+  SPINSUM_ERR_OUT_OF_MEMORY = -7,    /* host or device allocation failed */
+  SPINSUM_ERR_HIP = -8,              /* a HIP runtime call failed */
+  SPINSUM_ERR_NO_DEVICE = -9         /* plan made with SPINSUM_FLAG_HOST_ONLY */
+} spinsum_status;
+
+typedef enum { SPINSUM_F64 = 0, SPINSUM_F32 = 1 } spinsum_dtype;
+
+/* Plan flags (bitwise or). */
+#define SPINSUM_FLAG_HOST_ONLY 0x1u      /* build host tables only, for inspection: exec is
+                                            refused and tiles larger than a CU's LDS are kept */
+#define SPINSUM_FLAG_NO_NT_STORES 0x2u   /* cached stores instead of non-temporal ones (Sec. 4.6.3 ablation) */
+#define SPINSUM_FLAG_CHAIN_STAGES 0x4u   /* apply the stages one after another in registers
+                                            instead of their pre-multiplied product (Def. 4)  */
+#define SPINSUM_FLAG_NO_XCD_REMAP 0x8u   /* plain workgroup order (ablation of XCD grouping) */
+#define SPINSUM_FLAG_REVERSE_ORDER 0x10u /* process work items in reverse order (ownership test) */
+#define SPINSUM_FLAG_NO_LDS_PAD 0x20u    /* unpadded LDS tiles (bank-conflict ablation) */
+
+typedef struct spinsum_plan_s* spinsum_plan_t;
+typedef struct spinsum_graph_s* spinsum_graph_t;
+
+/* Tile configuration (the blocking of Alg. 5a/5b, Sec. 4.5).
+ * bl: tile edge along every group axis, 1 <= bl <= N; bl == N processes whole
+ *     cubes.  cubes_per_wg: whole-cube mode only, spectator cubes per
+ *     workgroup (>= 1).  threads: workgroup size (256).  0 in any field means
+ *     "choose". */
+typedef struct {
+  int bl;
+  int cubes_per_wg;
+  int threads;
+  int lds_pad;
+} spinsum_tile_t;
+
+typedef struct {
+  int d;                 /* group size                                   */
+  int n;                 /* group extent N                               */
+  int64_t ncubes;        /* spectator cubes (sum over blocks if batched) */
+  int64_t elems;         /* total elements                               */
+  int nstages;           /* stages after canonicalisation                */
+  int nterms_expanded;   /* distinct permutations of the expanded sum    */
+  int bl, nb, norbits, cubes_per_wg, threads, max_tiles;
+  int64_t lds_bytes;     /* LDS per workgroup                            */
+  int64_t nitems;        /* workgroup work items per exec                */
+  int nblocks;           /* 1, or the batch size                         */
+  int dtype, inplace, vector_width, ragged;
+  int fits_lds;          /* 1 if the largest work item fits the LDS of a CU */
+} spinsum_plan_info_t;
+
+/* Create a plan for Out = S_K(...S_1(In)) (Def. 3-4; in-place: Sec. 4.6.5).
+ *   ndim, extents : tensor shape, C-contiguous, all extents >= 0.
+ *   group_first, d: the permuted group is dims [group_first, group_first+d);
+ *                   d in {2,3,4}; group_first + d must equal ndim.
+ *   nstages >= 1, nterms[k] >= 0 terms in stage k; perms holds sum(nterms)
+ *                   rows of d 0-based entries; alpha holds sum(nterms)
+ *                   coefficients.  Duplicate permutations within a stage are
+ *                   merged (coefficients summed) and zero coefficients are
+ *                   dropped.
+ *   dtype         : storage and accumulation type (coefficients are rounded
+ *                   to it).  inplace: 1 = exec requires in == out.
+ *   flags         : SPINSUM_FLAG_*.
+ * Host arrays are copied; the caller keeps ownership.  On error *plan is set
+ * to NULL. */
+spinsum_status spinsum_plan(spinsum_plan_t* plan, int ndim, const int64_t* extents,
+                            int group_first, int d, int nstages, const int* nterms,
+                            const int* perms, const double* alpha, spinsum_dtype dtype,
+                            int inplace, unsigned flags);
+
+/* Plan for many tensors ("blocks") that share d, the terms, dtype and the
+ * in-place choice but have their own shapes: block b has ndims[b] dims with
+ * extents extents[b][0..ndims[b]-1], group = its trailing d dims.  Executed
+ * by one persistent kernel (spinsum_exec_batched). */
+spinsum_status spinsum_plan_batched(spinsum_plan_t* plan, int nblocks, const int* ndims,
+                                    const int64_t* const* extents, int d, int nstages,
+                                    const int* nterms, const int* perms,
+                                    const double* alpha, spinsum_dtype dtype, int inplace,
+                                    unsigned flags);
+
+/* Replace the tile configuration of a single-tensor plan and rebuild its
+ * tables (used by the autotuner).  Fields equal to 0 are chosen by the
+ * planner.  Returns SPINSUM_ERR_UNSUPPORTED if the tile orbit does not fit
+ * the 160 KiB LDS of a CU. */
+spinsum_status spinsum_plan_set_tile(spinsum_plan_t plan, const spinsum_tile_t* tile);
+
+spinsum_status spinsum_plan_get_info(spinsum_plan_t plan, spinsum_plan_info_t* info);
+
+/* The expanded operator: the distinct permutations of the product of all
+ * stages with non-zero coefficient (host arrays of capacity `cap` terms;
+ * *nterms receives the count even when it exceeds cap). */
+spinsum_status spinsum_plan_expanded(spinsum_plan_t plan, int cap, int* nterms, int* perms,
+                                     double* alpha);
+
+/* Host check of the work decomposition of block `block` of the plan: every
+ * tile orbit is closed under all permutations of the group, and every
+ * element of a cube is owned by exactly one (orbit, representative,
+ * permutation) triple up to the repeats of degenerate element orbits.
+ * Returns SPINSUM_OK or SPINSUM_ERR_INVALID_ARG with a message in *why. */
+spinsum_status spinsum_plan_check_ownership(spinsum_plan_t plan, int block, const char** why);
+
+/* Out = S(In) on `stream` (Def. 3-4).  In-place plans need in == out;
+ * out-of-place plans reject overlapping buffers (SPINSUM_ERR_ALIASING). */
+spinsum_status spinsum_exec(spinsum_plan_t plan, const void* in, void* out, void* stream);
+
+/* Batched form: in/out are DEVICE arrays of nblocks device pointers. */
+spinsum_status spinsum_exec_batched(spinsum_plan_t plan, const void* const* in,
+                                    void* const* out, void* stream);
+
+/* grad_in = S^T grad_out, the adjoint of the linear map (the transpose of
+ * the permutation matrices of Def. 2: every permutation replaced by its
+ * inverse, stages in reverse order).  In-place plans need grad_out ==
+ * grad_in. */
+spinsum_status spinsum_adjoint(spinsum_plan_t plan, const void* grad_out, void* grad_in,
+                               void* stream);
+
+/* Capture one spinsum_exec_batched launch into a hipGraph (captured on a
+ * private stream) and instantiate it.  The pointer arrays must stay valid
+ * for the life of the graph. */
+spinsum_status spinsum_graph_create(spinsum_plan_t plan, const void* const* in,
+                                    void* const* out, spinsum_graph_t* graph);
+spinsum_status spinsum_graph_launch(spinsum_graph_t graph, void* stream);
+void spinsum_graph_destroy(spinsum_graph_t graph);
+
+/* Time candidate tile configurations of a single-tensor plan on the given
+ * buffers (their contents are overwritten with unspecified values), keep
+ * the fastest in the plan and, if cache_path is not NULL, record it in that
+ * cache file (one "key value" line per configuration).  *best_ms receives
+ * the best time of one exec.  Synchronises the stream. */
+spinsum_status spinsum_autotune(spinsum_plan_t plan, void* in, void* out, void* stream,
+                                const char* cache_path, spinsum_tile_t* best,
+                                float* best_ms);
+
+/* Copy nbytes (multiple of 16) from in to out with the same load/store
+ * instructions as the spin-summation kernels: the achievable HBM ceiling. */
+spinsum_status spinsum_stream_copy(const void* in, void* out, int64_t nbytes, void* stream);
+
+/* The hipError_t of the last failed HIP call made for this plan (0 if none). */
+int spinsum_plan_last_hip_error(spinsum_plan_t plan);
+
+void spinsum_plan_destroy(spinsum_plan_t plan);
+const char* spinsum_status_string(spinsum_status s);
+const char* spinsum_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPINSUM_H */

@@ -1,0 +1,416 @@
+"""paper_1705_06661_amd -- spin summations on AMD Instinct MI355X (gfx950).
+
+Thin ctypes binding of ``libspinsum.so`` (C-ABI declared in
+``include/spinsum.h``).  Every function here only marshals arguments; all
+arithmetic runs in the library's HIP kernels.  torch is used for device
+memory and streams only.  There is no CPU fallback: importing this package
+without the built library raises ImportError.
+
+Operation (Springer, Matthews, Bientinesi, "Spin Summations: A
+High-Performance Perspective", Def. 1-4 and Sec. 4.6.5):
+``Out = S_K(...S_1(In))`` with ``S_k = sum_t alpha_t pi_t`` acting on the
+trailing ``d`` dimensions of a row-major tensor; a term ``(p, alpha)`` adds
+``alpha * In[..., i_{p[0]}, ..., i_{p[d-1]}]`` to ``Out[..., i_0, ..., i_{d-1}]``.
+A coefficient set is given as a list of stages, each a list of
+``(perm, alpha)`` with 0-based ``perm``; stage 0 is applied first.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspinsum.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python paper_1705_06661_amd/build.py` "
+        "(there is no CPU fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ------------------------------------------------------------ C declarations
+SPINSUM_OK = 0
+SPINSUM_ERR_INVALID_ARG = -1
+SPINSUM_ERR_NOT_PERMUTATION = -2
+SPINSUM_ERR_EXTENT_MISMATCH = -3
+SPINSUM_ERR_UNSUPPORTED = -4
+SPINSUM_ERR_ALIASING = -5
+SPINSUM_ERR_MISALIGNED = -6
+SPINSUM_ERR_OUT_OF_MEMORY = -7
+SPINSUM_ERR_HIP = -8
+SPINSUM_ERR_NO_DEVICE = -9
+
+SPINSUM_F64 = 0
+SPINSUM_F32 = 1
+
+SPINSUM_FLAG_HOST_ONLY = 0x1
+SPINSUM_FLAG_NO_NT_STORES = 0x2
+SPINSUM_FLAG_CHAIN_STAGES = 0x4
+SPINSUM_FLAG_NO_XCD_REMAP = 0x8
+SPINSUM_FLAG_REVERSE_ORDER = 0x10
+SPINSUM_FLAG_NO_LDS_PAD = 0x20
+
+
+class _Tile(ctypes.Structure):
+    _fields_ = [("bl", ctypes.c_int), ("cubes_per_wg", ctypes.c_int),
+                ("threads", ctypes.c_int), ("lds_pad", ctypes.c_int)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int), ("n", ctypes.c_int), ("ncubes", ctypes.c_int64),
+                ("elems", ctypes.c_int64), ("nstages", ctypes.c_int),
+                ("nterms_expanded", ctypes.c_int), ("bl", ctypes.c_int), ("nb", ctypes.c_int),
+                ("norbits", ctypes.c_int), ("cubes_per_wg", ctypes.c_int),
+                ("threads", ctypes.c_int), ("max_tiles", ctypes.c_int),
+                ("lds_bytes", ctypes.c_int64), ("nitems", ctypes.c_int64),
+                ("nblocks", ctypes.c_int), ("dtype", ctypes.c_int), ("inplace", ctypes.c_int),
+                ("vector_width", ctypes.c_int), ("ragged", ctypes.c_int),
+                ("fits_lds", ctypes.c_int)]
+
+
+_vp = ctypes.c_void_p
+_ip = ctypes.POINTER(ctypes.c_int)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_dp = ctypes.POINTER(ctypes.c_double)
+_st = ctypes.c_int
+
+
+def _decl(name, argtypes, restype=_st):
+    f = getattr(_lib, name)
+    f.argtypes = argtypes
+    f.restype = restype
+    return f
+
+
+_c_plan = _decl("spinsum_plan", [ctypes.POINTER(_vp), ctypes.c_int, _i64p, ctypes.c_int,
+                                 ctypes.c_int, ctypes.c_int, _ip, _ip, _dp, ctypes.c_int,
+                                 ctypes.c_int, ctypes.c_uint])
+_c_plan_batched = _decl("spinsum_plan_batched",
+                        [ctypes.POINTER(_vp), ctypes.c_int, _ip, ctypes.POINTER(_i64p),
+                         ctypes.c_int, ctypes.c_int, _ip, _ip, _dp, ctypes.c_int, ctypes.c_int,
+                         ctypes.c_uint])
+_c_set_tile = _decl("spinsum_plan_set_tile", [_vp, ctypes.POINTER(_Tile)])
+_c_get_info = _decl("spinsum_plan_get_info", [_vp, ctypes.POINTER(_Info)])
+_c_expanded = _decl("spinsum_plan_expanded", [_vp, ctypes.c_int, _ip, _ip, _dp])
+_c_check = _decl("spinsum_plan_check_ownership", [_vp, ctypes.c_int,
+                                                  ctypes.POINTER(ctypes.c_char_p)])
+_c_exec = _decl("spinsum_exec", [_vp, _vp, _vp, _vp])
+_c_exec_batched = _decl("spinsum_exec_batched", [_vp, _vp, _vp, _vp])
+_c_adjoint = _decl("spinsum_adjoint", [_vp, _vp, _vp, _vp])
+_c_graph_create = _decl("spinsum_graph_create", [_vp, _vp, _vp, ctypes.POINTER(_vp)])
+_c_graph_launch = _decl("spinsum_graph_launch", [_vp, _vp])
+_c_graph_destroy = _decl("spinsum_graph_destroy", [_vp], None)
+_c_autotune = _decl("spinsum_autotune", [_vp, _vp, _vp, _vp, ctypes.c_char_p,
+                                         ctypes.POINTER(_Tile), ctypes.POINTER(ctypes.c_float)])
+_c_copy = _decl("spinsum_stream_copy", [_vp, _vp, ctypes.c_int64, _vp])
+_c_last_err = _decl("spinsum_plan_last_hip_error", [_vp], ctypes.c_int)
+_c_destroy = _decl("spinsum_plan_destroy", [_vp], None)
+_c_status_string = _decl("spinsum_status_string", [ctypes.c_int], ctypes.c_char_p)
+_c_version = _decl("spinsum_version", [], ctypes.c_char_p)
+
+EXPORTED = ["spinsum_plan", "spinsum_plan_batched", "spinsum_plan_set_tile",
+            "spinsum_plan_get_info", "spinsum_plan_expanded", "spinsum_plan_check_ownership",
+            "spinsum_exec", "spinsum_exec_batched", "spinsum_adjoint", "spinsum_graph_create",
+            "spinsum_graph_launch", "spinsum_graph_destroy", "spinsum_autotune",
+            "spinsum_stream_copy", "spinsum_plan_last_hip_error", "spinsum_plan_destroy",
+            "spinsum_status_string", "spinsum_version"]
+
+
+class SpinSumError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = int(status)
+        msg = _c_status_string(int(status)).decode()
+        super().__init__(f"{what}: {msg} (status {status})" if what else msg)
+
+
+def _check(st: int, what: str, plan=None):
+    if st != SPINSUM_OK:
+        err = SpinSumError(st, what)
+        if plan is not None and st == SPINSUM_ERR_HIP:
+            err.hip_error = int(_c_last_err(plan._h))
+        raise err
+
+
+def spinsum_status_string(status: int) -> str:
+    return _c_status_string(int(status)).decode()
+
+
+def spinsum_version() -> str:
+    return _c_version().decode()
+
+
+# ------------------------------------------------------------------- plans
+_DTYPES = {"f64": SPINSUM_F64, torch.float64: SPINSUM_F64, "f32": SPINSUM_F32,
+           torch.float32: SPINSUM_F32}
+
+
+def _flatten(stages, d):
+    nterms = [len(s) for s in stages]
+    perms, alpha = [], []
+    for s in stages:
+        for p, a in s:
+            if len(p) != d:
+                raise SpinSumError(SPINSUM_ERR_INVALID_ARG, "permutation of wrong degree")
+            perms.extend(int(v) for v in p)
+            alpha.append(float(a))
+    return ((ctypes.c_int * max(1, len(nterms)))(*nterms),
+            (ctypes.c_int * max(1, len(perms)))(*perms),
+            (ctypes.c_double * max(1, len(alpha)))(*alpha))
+
+
+class Plan:
+    """Owns a spinsum_plan_t (destroyed with the object)."""
+
+    def __init__(self, handle, d, shapes, dtype, inplace, batched, stages):
+        self._h = handle
+        self.d = d
+        self.shapes = shapes
+        self.dtype = torch.float64 if dtype == SPINSUM_F64 else torch.float32
+        self.inplace = bool(inplace)
+        self.batched = batched
+        self.stages = stages
+
+    @property
+    def shape(self):
+        return self.shapes[0]
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h:
+            _c_destroy(h)
+
+    def info(self) -> dict:
+        return spinsum_plan_get_info(self)
+
+
+def spinsum_plan(extents: Sequence[int], group_first: int, d: int, stages, dtype="f64",
+                 inplace: bool = False, flags: int = 0) -> Plan:
+    """Plan Out = S_K(...S_1(In)) over dims [group_first, group_first + d)."""
+    ext = (ctypes.c_int64 * len(extents))(*[int(e) for e in extents])
+    nt, pp, aa = _flatten(stages, d)
+    h = _vp()
+    dt = _DTYPES[dtype]
+    _check(_c_plan(ctypes.byref(h), len(extents), ext, int(group_first), int(d), len(stages),
+                   nt, pp, aa, dt, int(bool(inplace)), int(flags)), "spinsum_plan")
+    return Plan(h, d, [tuple(int(e) for e in extents)], dt, inplace, False, stages)
+
+
+def spinsum_plan_batched(shapes: Sequence[Sequence[int]], d: int, stages, dtype="f64",
+                         inplace: bool = False, flags: int = 0) -> Plan:
+    """Plan one persistent launch over many tensors (group = trailing d dims)."""
+    nb = len(shapes)
+    ndims = (ctypes.c_int * nb)(*[len(s) for s in shapes])
+    rows = [(ctypes.c_int64 * len(s))(*[int(e) for e in s]) for s in shapes]
+    ptrs = (_i64p * nb)(*[ctypes.cast(r, _i64p) for r in rows])
+    nt, pp, aa = _flatten(stages, d)
+    h = _vp()
+    dt = _DTYPES[dtype]
+    _check(_c_plan_batched(ctypes.byref(h), nb, ndims, ptrs, int(d), len(stages), nt, pp, aa, dt,
+                           int(bool(inplace)), int(flags)), "spinsum_plan_batched")
+    return Plan(h, d, [tuple(int(e) for e in s) for s in shapes], dt, inplace, True, stages)
+
+
+def spinsum_plan_set_tile(plan: Plan, bl: int, cubes_per_wg: int = 1, lds_pad: int = 1,
+                          threads: int = 256):
+    t = _Tile(int(bl), int(cubes_per_wg), int(threads), int(lds_pad))
+    _check(_c_set_tile(plan._h, ctypes.byref(t)), "spinsum_plan_set_tile", plan)
+
+
+def spinsum_plan_get_info(plan: Plan) -> dict:
+    info = _Info()
+    _check(_c_get_info(plan._h, ctypes.byref(info)), "spinsum_plan_get_info")
+    return {k: getattr(info, k) for k, _ in _Info._fields_}
+
+
+def spinsum_plan_expanded(plan: Plan) -> List[Tuple[Tuple[int, ...], float]]:
+    n = ctypes.c_int(0)
+    _check(_c_expanded(plan._h, 0, ctypes.byref(n), None, None), "spinsum_plan_expanded")
+    cap = n.value
+    perms = (ctypes.c_int * max(1, cap * plan.d))()
+    alpha = (ctypes.c_double * max(1, cap))()
+    _check(_c_expanded(plan._h, cap, ctypes.byref(n), perms, alpha), "spinsum_plan_expanded")
+    return [(tuple(perms[k * plan.d:(k + 1) * plan.d]), alpha[k]) for k in range(n.value)]
+
+
+def spinsum_plan_check_ownership(plan: Plan, block: int = 0) -> Tuple[bool, str]:
+    why = ctypes.c_char_p()
+    st = _c_check(plan._h, int(block), ctypes.byref(why))
+    return st == SPINSUM_OK, (why.value or b"").decode()
+
+
+def spinsum_plan_last_hip_error(plan: Plan) -> int:
+    return int(_c_last_err(plan._h))
+
+
+def spinsum_plan_destroy(plan: Plan):
+    plan.__del__()
+
+
+# ------------------------------------------------------------------- exec
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _tensor_ptr(t: torch.Tensor, plan: Plan, shape, what: str) -> int:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{what} must be a torch tensor")
+    if not t.is_cuda:
+        raise SpinSumError(SPINSUM_ERR_INVALID_ARG, f"{what} must be a GPU tensor")
+    if t.dtype != plan.dtype:
+        raise SpinSumError(SPINSUM_ERR_INVALID_ARG, f"{what} has dtype {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise SpinSumError(SPINSUM_ERR_INVALID_ARG, f"{what} has shape {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise SpinSumError(SPINSUM_ERR_INVALID_ARG, f"{what} is not contiguous")
+    return t.data_ptr()
+
+
+def spinsum_exec(plan: Plan, inp: torch.Tensor, out: torch.Tensor, stream=None):
+    """out = S(inp) (in-place plans: pass the same tensor twice)."""
+    a = _tensor_ptr(inp, plan, plan.shape, "input")
+    b = _tensor_ptr(out, plan, plan.shape, "output")
+    _check(_c_exec(plan._h, a, b, _stream(stream)), "spinsum_exec", plan)
+    return out
+
+
+def spinsum_adjoint(plan: Plan, grad_out: torch.Tensor, grad_in: torch.Tensor, stream=None):
+    """grad_in = S^T grad_out."""
+    a = _tensor_ptr(grad_out, plan, plan.shape, "grad_out")
+    b = _tensor_ptr(grad_in, plan, plan.shape, "grad_in")
+    _check(_c_adjoint(plan._h, a, b, _stream(stream)), "spinsum_adjoint", plan)
+    return grad_in
+
+
+class PointerArrays:
+    """Device-resident arrays of block pointers for the batched entry points."""
+
+    def __init__(self, plan: Plan, ins: Sequence[torch.Tensor], outs: Sequence[torch.Tensor]):
+        if len(ins) != len(plan.shapes) or len(outs) != len(plan.shapes):
+            raise SpinSumError(SPINSUM_ERR_INVALID_ARG, "one tensor per block expected")
+        pin = [_tensor_ptr(t, plan, s, "input") for t, s in zip(ins, plan.shapes)]
+        pout = [_tensor_ptr(t, plan, s, "output") for t, s in zip(outs, plan.shapes)]
+        for k, (a, b) in enumerate(zip(pin, pout)):
+            nbytes = ins[k].numel() * ins[k].element_size()
+            if plan.inplace and a != b:
+                raise SpinSumError(SPINSUM_ERR_INVALID_ARG, "in-place plan needs in == out")
+            if not plan.inplace and nbytes and a < b + nbytes and b < a + nbytes:
+                raise SpinSumError(SPINSUM_ERR_ALIASING, f"block {k} overlaps")
+        dev = ins[0].device if ins else torch.device("cuda")
+        self.d_in = torch.tensor(pin, dtype=torch.int64, device=dev)
+        self.d_out = torch.tensor(pout, dtype=torch.int64, device=dev)
+        self.keep = (list(ins), list(outs))
+
+
+def spinsum_exec_batched(plan: Plan, ins, outs, stream=None, arrays: Optional[PointerArrays] = None):
+    """One persistent launch over all blocks of a batched plan."""
+    arrays = arrays or PointerArrays(plan, ins, outs)
+    _check(_c_exec_batched(plan._h, arrays.d_in.data_ptr(), arrays.d_out.data_ptr(),
+                           _stream(stream)), "spinsum_exec_batched", plan)
+    return arrays
+
+
+class Graph:
+    def __init__(self, handle, keep):
+        self._h = handle
+        self._keep = keep
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h:
+            _c_graph_destroy(h)
+
+
+def spinsum_graph_create(plan: Plan, ins, outs) -> Graph:
+    """Capture one exec (batched: one persistent launch) into a hipGraph."""
+    h = _vp()
+    if plan.batched:
+        arrays = PointerArrays(plan, ins, outs)
+        _check(_c_graph_create(plan._h, arrays.d_in.data_ptr(), arrays.d_out.data_ptr(),
+                               ctypes.byref(h)), "spinsum_graph_create", plan)
+        torch.cuda.synchronize()
+        return Graph(h, (plan, arrays))
+    a = _tensor_ptr(ins, plan, plan.shape, "input")
+    b = _tensor_ptr(outs, plan, plan.shape, "output")
+    _check(_c_graph_create(plan._h, a, b, ctypes.byref(h)), "spinsum_graph_create", plan)
+    return Graph(h, (plan, ins, outs))
+
+
+def spinsum_graph_launch(graph: Graph, stream=None):
+    _check(_c_graph_launch(graph._h, _stream(stream)), "spinsum_graph_launch")
+
+
+def spinsum_graph_destroy(graph: Graph):
+    graph.__del__()
+
+
+def spinsum_autotune(plan: Plan, inp: torch.Tensor, out: torch.Tensor, stream=None,
+                     cache_path: Optional[str] = None):
+    """Time tile candidates on these buffers (overwritten) and keep the best."""
+    a = _tensor_ptr(inp, plan, plan.shape, "input")
+    b = _tensor_ptr(out, plan, plan.shape, "output")
+    best = _Tile()
+    ms = ctypes.c_float(0)
+    cp = cache_path.encode() if cache_path else None
+    _check(_c_autotune(plan._h, a, b, _stream(stream), cp, ctypes.byref(best), ctypes.byref(ms)),
+           "spinsum_autotune", plan)
+    return {"bl": best.bl, "cubes_per_wg": best.cubes_per_wg, "threads": best.threads,
+            "lds_pad": best.lds_pad}, float(ms.value)
+
+
+def spinsum_stream_copy(inp: torch.Tensor, out: torch.Tensor, stream=None):
+    """out <- inp with the kernels' own load/store instructions (HBM ceiling)."""
+    nbytes = inp.numel() * inp.element_size()
+    if out.numel() * out.element_size() < nbytes or not (inp.is_cuda and out.is_cuda):
+        raise SpinSumError(SPINSUM_ERR_INVALID_ARG, "stream copy")
+    _check(_c_copy(inp.data_ptr(), out.data_ptr(), nbytes, _stream(stream)), "spinsum_stream_copy")
+    return out
+
+
+# ----------------------------------------------------------- conveniences
+def apply(x: torch.Tensor, plan: Plan, out: Optional[torch.Tensor] = None, stream=None):
+    """S(x); in-place plans overwrite x and return it."""
+    if plan.inplace:
+        return spinsum_exec(plan, x, x, stream)
+    if out is None:
+        out = torch.empty_like(x)
+    return spinsum_exec(plan, x, out, stream)
+
+
+class SpinSumFunction(torch.autograd.Function):
+    """Autograd wrapper: forward = spinsum_exec, backward = spinsum_adjoint.
+    The map is linear, so nothing is saved for backward."""
+
+    @staticmethod
+    def forward(ctx, x, plan: Plan):
+        ctx.plan = plan
+        if plan.inplace:
+            spinsum_exec(plan, x, x)
+            ctx.mark_dirty(x)
+            return x
+        out = torch.empty_like(x)
+        spinsum_exec(plan, x, out)
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        plan = ctx.plan
+        g = g.contiguous()
+        if plan.inplace:
+            gi = g.clone()
+            spinsum_adjoint(plan, gi, gi)
+        else:
+            gi = torch.empty_like(g)
+            spinsum_adjoint(plan, g, gi)
+        return gi, None
+
+
+__all__ = EXPORTED + ["Plan", "Graph", "PointerArrays", "SpinSumError", "SpinSumFunction",
+                      "apply"]

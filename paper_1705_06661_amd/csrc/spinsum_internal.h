@@ -1,0 +1,189 @@
+// spinsum_internal.h -- data layout shared by the host planner and the gfx950
+// kernels of libspinsum.  Not part of the public C-ABI (include/spinsum.h).
+//
+// Work decomposition (the GPU form of the blocked schedule of Alg. 5a/5b):
+//   * the permuted group of every spectator "cube" (N^d contiguous elements,
+//     the group being the trailing d dimensions) is cut into tiles by the
+//     same partition of [0,N) on every axis (block edge bl, Sec. 4.5);
+//   * a tile orbit is the set of tiles {sigma . B : sigma in S_d} of one
+//     sorted block tuple B (the b1 <= b2 <= ... loop bounds of Alg. 5a);
+//     one workgroup owns one (cube, tile orbit) pair, so every element is
+//     read and written by exactly one workgroup -- this ownership is what
+//     makes the in-place form (Sec. 4.6.5) safe;
+//   * inside the workgroup every element orbit {sigma . x} is combined in
+//     registers: with v_sigma = A[sigma . x] the outputs are
+//     w_tau = B[tau . x] = sum_sigma M[tau][sigma] v_sigma, where
+//     M[tau][sigma] = a(tau^-1 o sigma) and a() is the coefficient of each
+//     permutation in the (expanded) operator -- Alg. 2's d! update
+//     statements of one element orbit, written as one d! x d! product.
+#pragma once
+#include <stdint.h>
+
+#ifndef __HIPCC__
+#define __host__
+#define __device__
+#endif
+
+namespace spinsum {
+
+constexpr int kMaxD = 4;
+constexpr int kMaxDF = 24;          // 4!
+constexpr int kMaxLdsBytes = 163840; // 160 KiB per CU on gfx950
+
+// Exact division of 0 <= n < 2^31 by a runtime constant (multiply-high
+// method, Granlund & Montgomery 1994).
+struct FastDiv {
+  uint32_t div;
+  uint32_t mul;
+  uint32_t shift;
+  uint32_t pad;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f{};
+  f.div = d;
+  uint32_t s = 0;
+  while ((1ull << s) < d) ++s;
+  f.shift = s;
+  f.mul = (uint32_t)((((1ull << 32) * ((1ull << s) - d)) / d) + 1);
+  return f;
+}
+
+// One tile orbit of the block grid of a cube.
+struct alignas(16) OrbitDev {
+  int32_t ntiles;    // distinct tiles sigma . B
+  int32_t rep_off;   // first representative in the representative pool
+  int32_t rep_cnt;   // number of element-orbit representatives
+  int32_t ragged;    // 1 if some tile is cut by the cube edge
+  FastDiv fd_rep;    // / rep_cnt
+  int32_t tile_off[kMaxDF];  // element offset of each tile origin inside the cube
+  int32_t tile_ext[kMaxDF];  // extents of each tile, 8 bits per axis (axis 0 lowest)
+  int32_t slot_base[kMaxDF]; // LDS element offset of tile sigma . B, sigma in lex order
+};
+
+// Geometry of one tensor (or one block of a batch).
+struct alignas(16) Geom {
+  int64_t cube_elems;  // N^d
+  int64_t ncubes;      // spectator cubes
+  int32_t n;           // group extent N
+  int32_t bl;          // tile edge
+  int32_t norbits;     // tile orbits per cube
+  int32_t cpw;         // cubes per workgroup (whole-cube mode), else 1
+  int32_t gst[kMaxD];  // element strides of the group axes inside a cube
+  int32_t lst[kMaxD];  // LDS strides of a tile (padded)
+  int32_t ts;          // LDS elements per tile slot
+  int32_t cube_lds;    // LDS elements per cube in whole-cube mode
+  int32_t rows;        // bl^(d-1) rows per tile
+  int32_t vpr;         // vectors per row, bl / VW
+  FastDiv fd_vpr;      // / vpr
+  FastDiv fd_rows;     // / rows
+  FastDiv fd_bl;       // / bl
+  FastDiv fd_norbits;  // / norbits
+};
+
+// One item of a batched launch: a run of whole cubes, or one tile orbit of
+// one cube, of one block.
+struct alignas(16) BatchItem {
+  int64_t cube0;
+  int32_t block;
+  int32_t orbit;   // global index into the orbit pool
+  int32_t ncubes;
+  int32_t pad;
+};
+
+struct alignas(16) BatchBlock {
+  Geom g;
+  int32_t orbit_base;
+  int32_t pad[3];
+};
+
+// ------------------------------------------------------------------------
+// Index arithmetic shared by the kernels and by the host-side checker of the
+// work decomposition (spinsum_plan_check_ownership), so that the checker
+// exercises exactly the addresses the kernels compute.
+
+__host__ __device__ inline uint32_t fdiv(uint32_t n, const FastDiv& f) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return (__umulhi(n, f.mul) + n) >> f.shift;
+#else
+  return ((uint32_t)(((uint64_t)n * f.mul) >> 32) + n) >> f.shift;
+#endif
+}
+
+// Element m of the r-th permutation of (0..d-1) in lexicographic order.
+__host__ __device__ constexpr int lex_perm(int d, int r, int m) {
+  int avail[4] = {0, 1, 2, 3};
+  int navail = d;
+  int f = 1;
+  for (int k = 2; k < d; ++k) f *= k;
+  int res = 0;
+  for (int pos = 0; pos < d; ++pos) {
+    int idx = r / f;
+    r = r % f;
+    int val = avail[idx];
+    for (int j = idx; j < navail - 1; ++j) avail[j] = avail[j + 1];
+    --navail;
+    if (pos == m) res = val;
+    if (d - 1 - pos > 0) f = f / (d - 1 - pos);
+  }
+  return res;
+}
+
+// Chunk c of a work item (one VW-vector of one tile row) -> global element
+// offset from the item's first cube and LDS element offset; false if the
+// chunk lies outside a ragged tile.  toff/text: tile origins and packed
+// extents of the item's orbit.
+template <int D, int VW>
+__host__ __device__ inline bool chunk_addr(const Geom& g, uint32_t c, int ntiles,
+                                           const int32_t* toff, const int32_t* text,
+                                           bool ragged, int64_t* goff, int* loff) {
+  uint32_t q = fdiv(c, g.fd_vpr);
+  int v = (int)(c - q * (uint32_t)g.vpr);
+  uint32_t q2 = fdiv(q, g.fd_rows);
+  int row = (int)(q - q2 * (uint32_t)g.rows);
+  int s = (ntiles == 1) ? 0 : (int)q2;
+  int cube_i = (ntiles == 1) ? (int)q2 : 0;
+  int l[D];
+  l[D - 1] = v * VW;
+  if constexpr (D == 2) {
+    l[0] = row;
+  } else {
+    uint32_t r = (uint32_t)row;
+#pragma unroll
+    for (int m = D - 2; m >= 1; --m) {
+      uint32_t qq = fdiv(r, g.fd_bl);
+      l[m] = (int)(r - qq * (uint32_t)g.bl);
+      r = qq;
+    }
+    l[0] = (int)r;
+  }
+  bool ok = true;
+  if (ragged) {
+    int ext = text[s];
+#pragma unroll
+    for (int m = 0; m < D; ++m) ok = ok && (l[m] < ((ext >> (8 * m)) & 255));
+  }
+  int go = toff[s];
+  int lo = s * g.ts;
+#pragma unroll
+  for (int m = 0; m < D; ++m) {
+    go += l[m] * g.gst[m];
+    lo += l[m] * g.lst[m];
+  }
+  *goff = (int64_t)cube_i * g.cube_elems + go;
+  *loff = cube_i * g.cube_lds + lo;
+  return ok;
+}
+
+// LDS element offset of sigma_r . x for representative x = l[] of a cube
+// whose LDS image starts at `base` (combine phase).
+template <int D>
+__host__ __device__ inline int orbit_lds_addr(const Geom& g, int base, const int32_t* slot_base,
+                                              int r, const int* l) {
+  int a = base + slot_base[r];
+#pragma unroll
+  for (int m = 0; m < D; ++m) a += l[lex_perm(D, r, m)] * g.lst[m];
+  return a;
+}
+
+}  // namespace spinsum

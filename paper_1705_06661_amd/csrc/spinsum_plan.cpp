@@ -1,0 +1,914 @@
+// spinsum_plan.cpp -- host planner of libspinsum: argument validation,
+// canonicalisation of the coefficient sets, the group-algebra product of a
+// factorised chain (Def. 4), the orbit matrices, the tile-orbit tables of the
+// blocked schedule (Alg. 5a/5b) and their upload to the GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <utility>
+
+#include "spinsum_plan_host.h"
+
+using spinsum::BatchBlock;
+using spinsum::BatchItem;
+using spinsum::Geom;
+using spinsum::OrbitDev;
+using spinsum::Tiling;
+
+namespace spinsum {
+
+template <int D>
+constexpr int Fact() {
+  return D <= 1 ? 1 : D * Fact<(D > 1 ? D - 1 : 1)>();
+}
+
+// ------------------------------------------------------------- S_d algebra
+void SymGroup::init(int d_) {
+  d = d_;
+  p.clear();
+  std::vector<int> q(d);
+  std::iota(q.begin(), q.end(), 0);
+  do {
+    p.push_back(q);
+  } while (std::next_permutation(q.begin(), q.end()));
+  df = (int)p.size();
+  inv.assign(df, 0);
+  mul.assign((size_t)df * df, 0);
+  std::vector<int> t(d);
+  for (int a = 0; a < df; ++a) {
+    for (int m = 0; m < d; ++m) t[p[a][m]] = m;
+    inv[a] = rank(t.data());
+  }
+  for (int a = 0; a < df; ++a)
+    for (int b = 0; b < df; ++b) {
+      // operator a applied after operator b reads position m -> a[b[m]]
+      for (int m = 0; m < d; ++m) t[m] = p[a][p[b][m]];
+      mul[(size_t)a * df + b] = rank(t.data());
+    }
+}
+
+int SymGroup::rank(const int* q) const {
+  // Lehmer code in the factorial number system = lexicographic rank
+  int r = 0;
+  for (int m = 0; m < d; ++m) {
+    int smaller = 0;
+    for (int j = m + 1; j < d; ++j) smaller += (q[j] < q[m]);
+    int f = 1;
+    for (int k = 2; k <= d - 1 - m; ++k) f *= k;
+    r += smaller * f;
+  }
+  return r;
+}
+
+int elem_size(const spinsum_plan_s& P) { return P.dtype == SPINSUM_F32 ? 4 : 8; }
+
+static int64_t ipow(int64_t b, int e) {
+  int64_t r = 1;
+  for (int k = 0; k < e; ++k) r *= b;
+  return r;
+}
+
+int max_vector_width(const spinsum_plan_s& P, int n) {
+  int v = 16 / elem_size(P);
+  while (v > 1 && (n % v) != 0) v /= 2;
+  return v;
+}
+
+static int vw_for(int n, int bl, int vmax) {
+  int v = vmax;
+  while (v > 1 && ((n % v) != 0 || (bl % v) != 0)) v /= 2;
+  return v;
+}
+
+static void lds_strides(int d, int bl, int pad, int32_t* lst, int32_t* ts) {
+  lst[d - 1] = 1;
+  for (int m = d - 2; m >= 0; --m) {
+    int64_t s = (int64_t)lst[m + 1] * bl;
+    if (pad && (s % 2) == 0) s += 1;
+    lst[m] = (int32_t)s;
+  }
+  for (int m = d; m < kMaxD; ++m) lst[m] = 0;
+  int64_t t = (int64_t)lst[0] * bl;
+  if (pad && (t % 2) == 0) t += 1;
+  *ts = (int32_t)t;
+}
+
+// Largest number of distinct tiles in one orbit for nb blocks per axis.
+static int max_orbit_tiles(const SymGroup& G, int nb) {
+  const int d = G.d;
+  std::vector<int> B(d, 0);
+  int best = 0;
+  while (true) {
+    std::vector<std::vector<int>> tl;
+    for (int r = 0; r < G.df; ++r) {
+      std::vector<int> t(d);
+      for (int m = 0; m < d; ++m) t[m] = B[G.p[r][m]];
+      if (std::find(tl.begin(), tl.end(), t) == tl.end()) tl.push_back(t);
+    }
+    best = std::max(best, (int)tl.size());
+    if (best == G.df) break;
+    int m = d - 1;
+    while (m >= 0 && B[m] == nb - 1) --m;
+    if (m < 0) break;
+    B[m]++;
+    for (int j = m + 1; j < d; ++j) B[j] = B[m];
+  }
+  return best;
+}
+
+static int64_t tile_lds_bytes(const spinsum_plan_s& P, int n, int bl, int cpw, int pad) {
+  int32_t lst[kMaxD], ts;
+  lds_strides(P.d, bl, pad, lst, &ts);
+  int nb = (n + bl - 1) / bl;
+  int tiles = (bl == n) ? cpw : max_orbit_tiles(P.G, nb);
+  return (int64_t)tiles * ts * elem_size(P);
+}
+
+spinsum_status choose_tile(const spinsum_plan_s& P, int n, int64_t ncubes, int vw,
+                           spinsum_tile_t* tile) {
+  const int esz = elem_size(P);
+  const int d = P.d;
+  const int pad = (P.flags & SPINSUM_FLAG_NO_LDS_PAD) ? 0 : 1;
+  const int64_t budget = P.lds_limit - 512;
+  spinsum_tile_t t{};
+  t.threads = 256;
+  t.lds_pad = pad;
+  const int64_t cube_bytes = ipow(n, d) * esz;
+  if (cube_bytes <= 40 * 1024) {
+    t.bl = n;
+    int cpw = (int)std::max<int64_t>(1, (32 * 1024) / std::max<int64_t>(1, cube_bytes));
+    // keep at least ~8 workgroups per CU of work when the tensor allows it
+    int64_t cap = std::max<int64_t>(1, ncubes / (8 * (int64_t)P.num_cus));
+    cpw = (int)std::min<int64_t>(cpw, cap);
+    t.cubes_per_wg = std::max(1, cpw);
+    *tile = t;
+    return SPINSUM_OK;
+  }
+  t.cubes_per_wg = 1;
+  struct Pass {
+    int min_row_bytes;
+    int64_t max_lds;
+  };
+  const Pass passes[] = {{64, 48 * 1024}, {32, 80 * 1024}, {0, budget}};
+  for (const Pass& ps : passes) {
+    for (int bl = n - 1; bl >= 1; --bl) {
+      if (n % bl != 0 && ps.min_row_bytes > 0) continue;
+      if (vw > 1 && bl % vw != 0 && ps.min_row_bytes > 0) continue;
+      if (bl * esz < ps.min_row_bytes) continue;
+      if (bl > 255) continue;
+      int64_t lb = tile_lds_bytes(P, n, bl, 1, pad);
+      if (lb > std::min<int64_t>(ps.max_lds, budget)) continue;
+      t.bl = bl;
+      *tile = t;
+      return SPINSUM_OK;
+    }
+  }
+  return SPINSUM_ERR_UNSUPPORTED;
+}
+
+spinsum_status build_tiling(const spinsum_plan_s& P, int n, int64_t ncubes,
+                            const spinsum_tile_t& tile, int vmax, Tiling* out) {
+  const SymGroup& G = P.G;
+  const int d = P.d;
+  Tiling T;
+  if (n <= 0 || ncubes <= 0) {
+    T.g.ncubes = std::max<int64_t>(0, ncubes);
+    T.g.n = n;
+    *out = T;
+    return SPINSUM_OK;
+  }
+  int bl = tile.bl <= 0 ? n : std::min(tile.bl, n);
+  if (bl > 255) return SPINSUM_ERR_UNSUPPORTED;
+  const int pad = tile.lds_pad ? 1 : 0;
+  const int cpw = (bl == n) ? std::max(1, tile.cubes_per_wg) : 1;
+  const int64_t cube_elems = ipow(n, d);
+  if (cube_elems >= (1ll << 31)) return SPINSUM_ERR_UNSUPPORTED;
+  const int nb = (n + bl - 1) / bl;
+  const int vw = vw_for(n, bl, vmax);
+
+  Geom& g = T.g;
+  g.cube_elems = cube_elems;
+  g.ncubes = ncubes;
+  g.n = n;
+  g.bl = bl;
+  g.cpw = cpw;
+  for (int m = 0; m < kMaxD; ++m) g.gst[m] = 0;
+  for (int m = 0; m < d; ++m) g.gst[m] = (int32_t)ipow(n, d - 1 - m);
+  lds_strides(d, bl, pad, g.lst, &g.ts);
+  g.cube_lds = g.ts;
+  g.rows = (int32_t)ipow(bl, d - 1);
+  g.vpr = bl / vw;
+  g.fd_vpr = make_fastdiv((uint32_t)g.vpr);
+  g.fd_rows = make_fastdiv((uint32_t)g.rows);
+  g.fd_bl = make_fastdiv((uint32_t)bl);
+
+  // representative lists, shared by orbits with the same tie pattern and extents
+  std::map<std::vector<int>, std::pair<int, int>> rep_index;
+  std::vector<int> B(d, 0);
+  while (true) {
+    OrbitDev od;
+    std::memset(&od, 0, sizeof(od));
+    std::vector<std::vector<int>> tl;
+    int slot[kMaxDF];
+    for (int r = 0; r < G.df; ++r) {
+      std::vector<int> t(d);
+      for (int m = 0; m < d; ++m) t[m] = B[G.p[r][m]];
+      auto it = std::find(tl.begin(), tl.end(), t);
+      if (it == tl.end()) {
+        slot[r] = (int)tl.size();
+        tl.push_back(t);
+      } else {
+        slot[r] = (int)(it - tl.begin());
+      }
+    }
+    od.ntiles = (int32_t)tl.size();
+    for (int s = 0; s < od.ntiles; ++s) {
+      int64_t off = 0;
+      int32_t ext = 0;
+      for (int m = 0; m < d; ++m) {
+        off += (int64_t)tl[s][m] * bl * g.gst[m];
+        int e = std::min(bl, n - tl[s][m] * bl);
+        if (e < bl) od.ragged = 1;
+        ext |= (e & 255) << (8 * m);
+      }
+      od.tile_off[s] = (int32_t)off;
+      od.tile_ext[s] = ext;
+    }
+    for (int r = 0; r < G.df; ++r) od.slot_base[r] = slot[r] * g.ts;
+    // canonical representatives: inside tile B, sorted within runs of equal blocks
+    std::vector<int> key;
+    int extB[kMaxD];
+    for (int m = 0; m < d; ++m) {
+      extB[m] = std::min(bl, n - B[m] * bl);
+      key.push_back(extB[m]);
+    }
+    for (int m = 0; m + 1 < d; ++m) key.push_back(B[m] == B[m + 1]);
+    auto ri = rep_index.find(key);
+    if (ri == rep_index.end()) {
+      int off = (int)T.reps.size();
+      std::vector<int> l(d, 0);
+      int64_t box = 1;
+      for (int m = 0; m < d; ++m) box *= extB[m];
+      for (int64_t e = 0; e < box; ++e) {
+        int64_t rem = e;
+        for (int m = d - 1; m >= 0; --m) {
+          l[m] = (int)(rem % extB[m]);
+          rem /= extB[m];
+        }
+        bool ok = true;
+        for (int m = 0; m + 1 < d; ++m)
+          if (B[m] == B[m + 1] && l[m] > l[m + 1]) ok = false;
+        if (!ok) continue;
+        uint32_t pk = 0;
+        for (int m = 0; m < d; ++m) pk |= (uint32_t)l[m] << (8 * m);
+        T.reps.push_back(pk);
+      }
+      ri = rep_index.emplace(key, std::make_pair(off, (int)T.reps.size() - off)).first;
+    }
+    od.rep_off = ri->second.first;
+    od.rep_cnt = ri->second.second;
+    od.fd_rep = make_fastdiv((uint32_t)std::max(1, od.rep_cnt));
+    T.max_tiles = std::max(T.max_tiles, (int)od.ntiles);
+    T.ragged |= od.ragged;
+    T.orbits.push_back(od);
+    // next non-decreasing block tuple (the loop nest of Alg. 5a)
+    int m = d - 1;
+    while (m >= 0 && B[m] == nb - 1) --m;
+    if (m < 0) break;
+    B[m]++;
+    for (int j = m + 1; j < d; ++j) B[j] = B[m];
+  }
+  g.norbits = (int32_t)T.orbits.size();
+  g.fd_norbits = make_fastdiv((uint32_t)g.norbits);
+  T.nb = nb;
+  T.vw = vw;
+  T.lds_elems = (bl == n) ? (int64_t)cpw * g.ts : (int64_t)T.max_tiles * g.ts;
+  T.nitems = (bl == n) ? (ncubes + cpw - 1) / cpw : ncubes * g.norbits;
+  T.fits = (T.lds_elems * elem_size(P) + 512 <= P.lds_limit) ? 1 : 0;
+  if (!T.fits && !(P.flags & SPINSUM_FLAG_HOST_ONLY)) return SPINSUM_ERR_UNSUPPORTED;
+  if (T.nitems >= (1ll << 31) - 8) return SPINSUM_ERR_UNSUPPORTED;
+  *out = std::move(T);
+  return SPINSUM_OK;
+}
+
+// ------------------------------------------------------------ device tables
+static spinsum_status hip_fail(spinsum_plan_s* P, hipError_t e) {
+  P->last_hip_error = (int)e;
+  return SPINSUM_ERR_HIP;
+}
+
+void free_device(spinsum_plan_s* P) {
+  void** ptrs[] = {&P->d_orbits, &P->d_reps, &P->d_mats, &P->d_blocks, &P->d_items};
+  for (void** p : ptrs) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+  }
+  P->has_dev = false;
+}
+
+template <typename V>
+static spinsum_status upload(spinsum_plan_s* P, void** dst, const V* src, size_t count) {
+  size_t bytes = std::max<size_t>(sizeof(V), count * sizeof(V));
+  hipError_t e = hipMalloc(dst, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *dst = nullptr;
+    P->last_hip_error = (int)e;
+    return e == hipErrorOutOfMemory ? SPINSUM_ERR_OUT_OF_MEMORY : SPINSUM_ERR_HIP;
+  }
+  if (count) {
+    e = hipMemcpy(*dst, src, count * sizeof(V), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(P, e);
+  }
+  return SPINSUM_OK;
+}
+
+spinsum_status upload_tables(spinsum_plan_s* P) {
+  free_device(P);
+  if (P->flags & SPINSUM_FLAG_HOST_ONLY) return SPINSUM_OK;
+  spinsum_status st;
+  // orbit matrices in the storage type: M | MT | SM | SMT
+  std::vector<double> all;
+  all.insert(all.end(), P->M.begin(), P->M.end());
+  all.insert(all.end(), P->MT.begin(), P->MT.end());
+  all.insert(all.end(), P->SM.begin(), P->SM.end());
+  all.insert(all.end(), P->SMT.begin(), P->SMT.end());
+  if (P->dtype == SPINSUM_F32) {
+    std::vector<float> f(all.begin(), all.end());
+    st = upload(P, &P->d_mats, f.data(), f.size());
+  } else {
+    st = upload(P, &P->d_mats, all.data(), all.size());
+  }
+  if (st != SPINSUM_OK) return st;
+  if (!P->batched) {
+    st = upload(P, &P->d_orbits, P->T.orbits.data(), P->T.orbits.size());
+    if (st != SPINSUM_OK) return st;
+    st = upload(P, &P->d_reps, P->T.reps.data(), P->T.reps.size());
+    if (st != SPINSUM_OK) return st;
+  } else {
+    std::vector<OrbitDev> orbits;
+    std::vector<uint32_t> reps;
+    for (const Tiling& t : P->btil) {
+      int roff = (int)reps.size();
+      for (OrbitDev od : t.orbits) {
+        od.rep_off += roff;
+        orbits.push_back(od);
+      }
+      reps.insert(reps.end(), t.reps.begin(), t.reps.end());
+    }
+    st = upload(P, &P->d_orbits, orbits.data(), orbits.size());
+    if (st != SPINSUM_OK) return st;
+    st = upload(P, &P->d_reps, reps.data(), reps.size());
+    if (st != SPINSUM_OK) return st;
+    st = upload(P, &P->d_blocks, P->blocks.data(), P->blocks.size());
+    if (st != SPINSUM_OK) return st;
+    st = upload(P, &P->d_items, P->items.data(), P->items.size());
+    if (st != SPINSUM_OK) return st;
+  }
+  P->has_dev = true;
+  return SPINSUM_OK;
+}
+
+}  // namespace spinsum
+
+using namespace spinsum;
+
+// ------------------------------------------------------------ plan building
+static spinsum_status set_terms(spinsum_plan_s* P, int nstages, const int* nterms,
+                                const int* perms, const double* alpha) {
+  const int d = P->d;
+  if (nstages < 1 || nstages > 64 || nterms == nullptr) return SPINSUM_ERR_INVALID_ARG;
+  int total = 0;
+  for (int k = 0; k < nstages; ++k) {
+    if (nterms[k] < 0 || nterms[k] > 1 << 20) return SPINSUM_ERR_INVALID_ARG;
+    total += nterms[k];
+  }
+  if (total > 0 && (perms == nullptr || alpha == nullptr)) return SPINSUM_ERR_INVALID_ARG;
+  for (int t = 0; t < total; ++t) {
+    bool seen[kMaxD] = {false, false, false, false};
+    for (int m = 0; m < d; ++m) {
+      int v = perms[t * d + m];
+      if (v < 0 || v >= d || seen[v]) return SPINSUM_ERR_NOT_PERMUTATION;
+      seen[v] = true;
+    }
+    if (!std::isfinite(alpha[t])) return SPINSUM_ERR_INVALID_ARG;
+  }
+  const SymGroup& G = P->G;
+  const int df = G.df;
+  P->stage_a.assign(nstages, std::vector<double>(df, 0.0));
+  int t = 0;
+  for (int k = 0; k < nstages; ++k)
+    for (int j = 0; j < nterms[k]; ++j, ++t) P->stage_a[k][G.rank(perms + (size_t)t * d)] += alpha[t];
+  // expanded operator: E = a_{K-1} * ... * a_0 (later stages act after earlier ones)
+  P->expanded = P->stage_a[0];
+  for (int k = 1; k < nstages; ++k) {
+    std::vector<double> e(df, 0.0);
+    for (int a = 0; a < df; ++a) {
+      if (P->stage_a[k][a] == 0.0) continue;
+      for (int b = 0; b < df; ++b)
+        if (P->expanded[b] != 0.0) e[G.mul[(size_t)a * df + b]] += P->stage_a[k][a] * P->expanded[b];
+    }
+    P->expanded = e;
+  }
+  // orbit matrices: w_tau = sum_sigma a(tau^-1 o sigma) v_sigma
+  auto orbit_matrix = [&](const std::vector<double>& a, std::vector<double>& M) {
+    M.assign((size_t)df * df, 0.0);
+    for (int tau = 0; tau < df; ++tau)
+      for (int sg = 0; sg < df; ++sg) M[(size_t)tau * df + sg] = a[G.mul[(size_t)G.inv[tau] * df + sg]];
+  };
+  auto transpose = [&](const std::vector<double>& M) {
+    std::vector<double> R((size_t)df * df);
+    for (int i = 0; i < df; ++i)
+      for (int j = 0; j < df; ++j) R[(size_t)j * df + i] = M[(size_t)i * df + j];
+    return R;
+  };
+  orbit_matrix(P->expanded, P->M);
+  P->MT = transpose(P->M);
+  P->SM.clear();
+  P->SMT.clear();
+  std::vector<std::vector<double>> sm(nstages);
+  for (int k = 0; k < nstages; ++k) {
+    orbit_matrix(P->stage_a[k], sm[k]);
+    P->SM.insert(P->SM.end(), sm[k].begin(), sm[k].end());
+  }
+  for (int k = nstages - 1; k >= 0; --k) {
+    std::vector<double> tr = transpose(sm[k]);
+    P->SMT.insert(P->SMT.end(), tr.begin(), tr.end());
+  }
+  return SPINSUM_OK;
+}
+
+static void query_device(spinsum_plan_s* P) {
+  P->num_cus = 256;
+  P->lds_limit = kMaxLdsBytes;
+  if (P->flags & SPINSUM_FLAG_HOST_ONLY) return;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  P->device = dev;
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+    P->num_cus = v;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+    P->lds_limit = std::min(v, kMaxLdsBytes);
+  (void)hipGetLastError();
+}
+
+static spinsum_status apply_tile(spinsum_plan_s* P, const spinsum_tile_t* req) {
+  spinsum_tile_t t{};
+  const int vmax = max_vector_width(*P, std::max(1, P->n));
+  if (req && req->bl > 0) {
+    t = *req;
+    if (t.threads <= 0) t.threads = 256;
+    if (t.cubes_per_wg <= 0) t.cubes_per_wg = 1;
+  } else if (P->n > 0 && P->ncubes > 0) {
+    if (!cache_lookup(*P, &t)) {
+      spinsum_status st = choose_tile(*P, P->n, P->ncubes, vmax, &t);
+      if (st != SPINSUM_OK) return st;
+    }
+  }
+  if (req && req->lds_pad >= 0 && req->bl > 0) t.lds_pad = req->lds_pad;
+  if (t.threads != 256 && t.threads != 0) return SPINSUM_ERR_UNSUPPORTED;
+  t.threads = 256;
+  Tiling T;
+  spinsum_status st = build_tiling(*P, P->n, P->ncubes, t, vmax, &T);
+  if (st != SPINSUM_OK) return st;
+  P->tile = t;
+  P->T = std::move(T);
+  return SPINSUM_OK;
+}
+
+static spinsum_status common_checks(int d, spinsum_dtype dtype, int inplace) {
+  if (d < 2 || d > 4) return SPINSUM_ERR_UNSUPPORTED;
+  if (dtype != SPINSUM_F64 && dtype != SPINSUM_F32) return SPINSUM_ERR_INVALID_ARG;
+  if (inplace != 0 && inplace != 1) return SPINSUM_ERR_INVALID_ARG;
+  return SPINSUM_OK;
+}
+
+static spinsum_status shape_info(int ndim, const int64_t* extents, int group_first, int d,
+                                 int* n, int64_t* ncubes) {
+  if (ndim < 1 || ndim > 64 || extents == nullptr) return SPINSUM_ERR_INVALID_ARG;
+  if (group_first < 0 || group_first + d > ndim) return SPINSUM_ERR_INVALID_ARG;
+  for (int k = 0; k < ndim; ++k)
+    if (extents[k] < 0) return SPINSUM_ERR_INVALID_ARG;
+  for (int m = 1; m < d; ++m)
+    if (extents[group_first + m] != extents[group_first]) return SPINSUM_ERR_EXTENT_MISMATCH;
+  if (group_first + d != ndim) return SPINSUM_ERR_UNSUPPORTED;  // inner spectators
+  if (extents[group_first] > 255 * 255) return SPINSUM_ERR_UNSUPPORTED;
+  *n = (int)extents[group_first];
+  int64_t c = 1;
+  for (int k = 0; k < group_first; ++k) {
+    if (extents[k] > 0 && c > (1ll << 62) / extents[k]) return SPINSUM_ERR_UNSUPPORTED;
+    c *= extents[k];
+  }
+  *ncubes = c;
+  return SPINSUM_OK;
+}
+
+extern "C" spinsum_status spinsum_plan(spinsum_plan_t* plan, int ndim, const int64_t* extents,
+                                       int group_first, int d, int nstages, const int* nterms,
+                                       const int* perms, const double* alpha,
+                                       spinsum_dtype dtype, int inplace, unsigned flags) {
+  if (plan == nullptr) return SPINSUM_ERR_INVALID_ARG;
+  *plan = nullptr;
+  spinsum_status st = common_checks(d, dtype, inplace);
+  if (st != SPINSUM_OK) return st;
+  int n = 0;
+  int64_t ncubes = 0;
+  st = shape_info(ndim, extents, group_first, d, &n, &ncubes);
+  if (st != SPINSUM_OK) return st;
+  spinsum_plan_s* P = new (std::nothrow) spinsum_plan_s();
+  if (!P) return SPINSUM_ERR_OUT_OF_MEMORY;
+  P->d = d;
+  P->n = n;
+  P->ndim = ndim;
+  P->extents.assign(extents, extents + ndim);
+  P->ncubes = ncubes;
+  P->dtype = dtype;
+  P->inplace = inplace;
+  P->flags = flags;
+  P->G.init(d);
+  if (n > 0 && ipow(n, d) >= (1ll << 31)) {
+    delete P;
+    return SPINSUM_ERR_UNSUPPORTED;
+  }
+  P->elems = ncubes * ipow(n, d);
+  st = set_terms(P, nstages, nterms, perms, alpha);
+  if (st == SPINSUM_OK) {
+    query_device(P);
+    st = apply_tile(P, nullptr);
+  }
+  if (st == SPINSUM_OK) st = upload_tables(P);
+  if (st != SPINSUM_OK) {
+    free_device(P);
+    delete P;
+    return st;
+  }
+  *plan = P;
+  return SPINSUM_OK;
+}
+
+extern "C" spinsum_status spinsum_plan_batched(spinsum_plan_t* plan, int nblocks, const int* ndims,
+                                               const int64_t* const* extents, int d, int nstages,
+                                               const int* nterms, const int* perms,
+                                               const double* alpha, spinsum_dtype dtype,
+                                               int inplace, unsigned flags) {
+  if (plan == nullptr) return SPINSUM_ERR_INVALID_ARG;
+  *plan = nullptr;
+  spinsum_status st = common_checks(d, dtype, inplace);
+  if (st != SPINSUM_OK) return st;
+  if (nblocks < 1 || nblocks > (1 << 20) || ndims == nullptr || extents == nullptr)
+    return SPINSUM_ERR_INVALID_ARG;
+  std::vector<int> ns(nblocks);
+  std::vector<int64_t> cs(nblocks);
+  for (int b = 0; b < nblocks; ++b) {
+    if (ndims[b] < d) return SPINSUM_ERR_INVALID_ARG;
+    st = shape_info(ndims[b], extents[b], ndims[b] - d, d, &ns[b], &cs[b]);
+    if (st != SPINSUM_OK) return st;
+    if (ns[b] > 0 && ipow(ns[b], d) >= (1ll << 31)) return SPINSUM_ERR_UNSUPPORTED;
+  }
+  spinsum_plan_s* P = new (std::nothrow) spinsum_plan_s();
+  if (!P) return SPINSUM_ERR_OUT_OF_MEMORY;
+  P->batched = true;
+  P->nblocks = nblocks;
+  P->d = d;
+  P->dtype = dtype;
+  P->inplace = inplace;
+  P->flags = flags;
+  P->G.init(d);
+  st = set_terms(P, nstages, nterms, perms, alpha);
+  if (st != SPINSUM_OK) {
+    delete P;
+    return st;
+  }
+  query_device(P);
+  int vmax = 16 / elem_size(*P);
+  for (int b = 0; b < nblocks; ++b)
+    if (ns[b] > 0 && cs[b] > 0) vmax = std::min(vmax, max_vector_width(*P, ns[b]));
+  P->batch_vw = vmax;
+  P->btil.resize(nblocks);
+  P->blocks.resize(nblocks);
+  P->block_elems.resize(nblocks);
+  int orbit_base = 0;
+  for (int b = 0; b < nblocks; ++b) {
+    spinsum_tile_t t{};
+    if (ns[b] > 0 && cs[b] > 0) {
+      st = choose_tile(*P, ns[b], cs[b], vmax, &t);
+      if (st == SPINSUM_OK && t.bl % vmax != 0) st = SPINSUM_ERR_UNSUPPORTED;
+    }
+    if (st == SPINSUM_OK) st = build_tiling(*P, ns[b], cs[b], t, vmax, &P->btil[b]);
+    if (st != SPINSUM_OK) {
+      delete P;
+      return st;
+    }
+    Tiling& T = P->btil[b];
+    std::memset(&P->blocks[b], 0, sizeof(BatchBlock));
+    P->blocks[b].g = T.g;
+    P->blocks[b].orbit_base = orbit_base;
+    P->block_elems[b] = (ns[b] > 0 ? cs[b] * ipow(ns[b], d) : 0);
+    P->elems += P->block_elems[b];
+    P->ncubes += cs[b];
+    P->batch_lds_elems = std::max(P->batch_lds_elems, T.lds_elems);
+    // items of this block
+    const Geom& g = T.g;
+    if (T.nitems > 0) {
+      if (g.bl == g.n) {
+        for (int64_t c0 = 0; c0 < g.ncubes; c0 += g.cpw) {
+          BatchItem it{};
+          it.cube0 = c0;
+          it.block = b;
+          it.orbit = orbit_base;
+          it.ncubes = (int32_t)std::min<int64_t>(g.cpw, g.ncubes - c0);
+          P->items.push_back(it);
+        }
+      } else {
+        for (int64_t c = 0; c < g.ncubes; ++c)
+          for (int o = 0; o < g.norbits; ++o) {
+            BatchItem it{};
+            it.cube0 = c;
+            it.block = b;
+            it.orbit = orbit_base + o;
+            it.ncubes = 1;
+            P->items.push_back(it);
+          }
+      }
+    }
+    orbit_base += (int)T.orbits.size();
+  }
+  // larger items first so the static round-robin of the persistent kernel balances
+  auto cost = [&](const BatchItem& it) {
+    const Tiling& T = P->btil[it.block];
+    const OrbitDev& od = T.orbits[it.orbit - P->blocks[it.block].orbit_base];
+    int64_t tile = ipow(T.g.bl, d);
+    return (int64_t)it.ncubes * od.ntiles * tile;
+  };
+  std::stable_sort(P->items.begin(), P->items.end(),
+                   [&](const BatchItem& a, const BatchItem& b) { return cost(a) > cost(b); });
+  if ((int64_t)P->items.size() >= (1ll << 31)) {
+    delete P;
+    return SPINSUM_ERR_UNSUPPORTED;
+  }
+  if (P->batch_lds_elems * elem_size(*P) + 512 > P->lds_limit) {
+    delete P;
+    return SPINSUM_ERR_UNSUPPORTED;
+  }
+  int64_t lds_b = std::max<int64_t>(1, P->batch_lds_elems * elem_size(*P) + 512);
+  int per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(8, P->lds_limit / lds_b));
+  P->batch_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)P->items.size(),
+                                                               (int64_t)P->num_cus * per_cu));
+  st = upload_tables(P);
+  if (st != SPINSUM_OK) {
+    free_device(P);
+    delete P;
+    return st;
+  }
+  *plan = P;
+  return SPINSUM_OK;
+}
+
+extern "C" spinsum_status spinsum_plan_set_tile(spinsum_plan_t P, const spinsum_tile_t* tile) {
+  if (P == nullptr || tile == nullptr || P->batched) return SPINSUM_ERR_INVALID_ARG;
+  if (tile->bl < 0 || tile->cubes_per_wg < 0) return SPINSUM_ERR_INVALID_ARG;
+  spinsum_tile_t keep = P->tile;
+  Tiling keepT = P->T;
+  spinsum_status st = apply_tile(P, tile);
+  if (st == SPINSUM_OK) st = upload_tables(P);
+  if (st != SPINSUM_OK) {
+    P->tile = keep;
+    P->T = keepT;
+    spinsum_status st2 = upload_tables(P);
+    (void)st2;
+  }
+  return st;
+}
+
+extern "C" spinsum_status spinsum_plan_get_info(spinsum_plan_t P, spinsum_plan_info_t* info) {
+  if (P == nullptr || info == nullptr) return SPINSUM_ERR_INVALID_ARG;
+  std::memset(info, 0, sizeof(*info));
+  info->d = P->d;
+  info->n = P->n;
+  info->ncubes = P->ncubes;
+  info->elems = P->elems;
+  info->nstages = (int)P->stage_a.size();
+  int nz = 0;
+  for (double v : P->expanded) nz += (v != 0.0);
+  info->nterms_expanded = nz;
+  info->nblocks = P->nblocks;
+  info->dtype = P->dtype;
+  info->inplace = P->inplace;
+  info->threads = 256;
+  if (!P->batched) {
+    info->bl = P->T.g.bl;
+    info->nb = P->T.nb;
+    info->norbits = P->T.g.norbits;
+    info->cubes_per_wg = P->T.g.cpw;
+    info->max_tiles = P->T.max_tiles;
+    info->lds_bytes = P->T.lds_elems * elem_size(*P);
+    info->nitems = P->T.nitems;
+    info->vector_width = P->T.vw;
+    info->ragged = P->T.ragged;
+    info->fits_lds = P->T.fits;
+  } else {
+    info->lds_bytes = P->batch_lds_elems * elem_size(*P);
+    info->nitems = (int64_t)P->items.size();
+    info->vector_width = P->batch_vw;
+    int norb = 0, mt = 0;
+    for (const Tiling& t : P->btil) {
+      norb += (int)t.orbits.size();
+      mt = std::max(mt, t.max_tiles);
+      info->ragged |= t.ragged;
+    }
+    info->norbits = norb;
+    info->max_tiles = mt;
+    info->fits_lds = P->batch_lds_elems * elem_size(*P) + 512 <= P->lds_limit;
+  }
+  return SPINSUM_OK;
+}
+
+extern "C" spinsum_status spinsum_plan_expanded(spinsum_plan_t P, int cap, int* nterms, int* perms,
+                                                double* alpha) {
+  if (P == nullptr || nterms == nullptr || cap < 0) return SPINSUM_ERR_INVALID_ARG;
+  int k = 0;
+  for (int r = 0; r < P->G.df; ++r) {
+    if (P->expanded[r] == 0.0) continue;
+    if (k < cap) {
+      if (perms == nullptr || alpha == nullptr) return SPINSUM_ERR_INVALID_ARG;
+      for (int m = 0; m < P->d; ++m) perms[k * P->d + m] = P->G.p[r][m];
+      alpha[k] = P->expanded[r];
+    }
+    ++k;
+  }
+  *nterms = k;
+  return SPINSUM_OK;
+}
+
+// Replays, on the host, the addresses one work item computes on the device
+// (load, combine, store) with the kernels' own index functions, and checks
+// that they stay in bounds and agree with each other.
+template <int D, int VW>
+static bool emulate_item(const Tiling& T, const OrbitDev& od, int ncub, std::string* why) {
+  const Geom& g = T.g;
+  const int d = D;
+  const int64_t span = (int64_t)ncub * g.cube_elems;
+  const uint32_t nchunks = (uint32_t)ncub * (uint32_t)od.ntiles * (uint32_t)g.rows * (uint32_t)g.vpr;
+  std::vector<int64_t> lds_of(T.lds_elems, -1);  // LDS slot -> element loaded there
+  std::vector<int> loaded((size_t)span, 0);
+  for (uint32_t c = 0; c < nchunks; ++c) {
+    int64_t go = 0;
+    int lo = 0;
+    if (!chunk_addr<D, VW>(g, c, od.ntiles, od.tile_off, od.tile_ext, od.ragged != 0, &go, &lo))
+      continue;
+    if (go < 0 || go + VW > span || (go % VW) != 0) { *why = "global chunk out of bounds"; return false; }
+    if (lo < 0 || lo + VW > T.lds_elems) { *why = "LDS chunk out of bounds"; return false; }
+    for (int k = 0; k < VW; ++k) {
+      if (lds_of[lo + k] != -1) { *why = "LDS slot written twice"; return false; }
+      lds_of[lo + k] = go + k;
+      loaded[go + k] += 1;
+    }
+  }
+  // every element of the item's tiles is loaded exactly once
+  for (int ci = 0; ci < ncub; ++ci)
+    for (int s = 0; s < od.ntiles; ++s) {
+      int ext[kMaxD];
+      for (int m = 0; m < d; ++m) ext[m] = (od.tile_ext[s] >> (8 * m)) & 255;
+      int64_t cnt = 1;
+      for (int m = 0; m < d; ++m) cnt *= ext[m];
+      for (int64_t e = 0; e < cnt; ++e) {
+        int64_t rem = e, off = (int64_t)ci * g.cube_elems + od.tile_off[s];
+        for (int m = d - 1; m >= 0; --m) {
+          off += (rem % ext[m]) * g.gst[m];
+          rem /= ext[m];
+        }
+        if (loaded[off] != 1) { *why = "tile element not loaded exactly once"; return false; }
+      }
+    }
+  // combine: the LDS address of sigma . x holds global element sigma . x
+  const uint32_t nrep = (uint32_t)ncub * (uint32_t)od.rep_cnt;
+  for (uint32_t i = 0; i < nrep; ++i) {
+    uint32_t ci = (ncub == 1) ? 0u : fdiv(i, od.fd_rep);
+    uint32_t ri = i - ci * (uint32_t)od.rep_cnt;
+    if (ci >= (uint32_t)ncub || ri >= (uint32_t)od.rep_cnt) { *why = "bad representative index"; return false; }
+    uint32_t pk = T.reps[od.rep_off + ri];
+    int l[D];
+    for (int m = 0; m < d; ++m) l[m] = (int)((pk >> (8 * m)) & 255u);
+    // global coordinates of x: tile of the identity permutation + l
+    int x[D];
+    int64_t o0 = od.tile_off[od.slot_base[0] / g.ts];
+    for (int m = 0; m < d; ++m) x[m] = (int)((o0 / g.gst[m]) % g.n) + l[m];
+    for (int r = 0; r < Fact<D>(); ++r) {
+      int a = orbit_lds_addr<D>(g, (int)ci * g.cube_lds, od.slot_base, r, l);
+      if (a < 0 || a >= T.lds_elems) { *why = "combine address out of bounds"; return false; }
+      int64_t want = (int64_t)ci * g.cube_elems;
+      for (int m = 0; m < d; ++m) want += (int64_t)x[lex_perm(D, r, m)] * g.gst[m];
+      if (lds_of[a] != want) { *why = "combine address does not hold sigma . x"; return false; }
+    }
+  }
+  return true;
+}
+
+template <int D>
+static bool emulate_all(const Tiling& T, std::string* why) {
+  const Geom& g = T.g;
+  std::vector<int> ncubs;
+  if (g.bl == g.n) {
+    ncubs.push_back((int)std::min<int64_t>(g.cpw, g.ncubes));
+    if (g.ncubes % g.cpw) ncubs.push_back((int)(g.ncubes % g.cpw));
+  } else {
+    ncubs.push_back(1);
+  }
+  for (const OrbitDev& od : T.orbits)
+    for (int nc : ncubs) {
+      bool ok = false;
+      if (T.vw == 4) ok = emulate_item<D, 4>(T, od, nc, why);
+      else if (T.vw == 2) ok = emulate_item<D, 2>(T, od, nc, why);
+      else ok = emulate_item<D, 1>(T, od, nc, why);
+      if (!ok) return false;
+    }
+  return true;
+}
+
+extern "C" spinsum_status spinsum_plan_check_ownership(spinsum_plan_t P, int block, const char** why) {
+  static thread_local std::string msg;
+  auto fail = [&](const std::string& m) {
+    msg = m;
+    if (why) *why = msg.c_str();
+    return SPINSUM_ERR_INVALID_ARG;
+  };
+  if (why) *why = "";
+  if (P == nullptr) return SPINSUM_ERR_INVALID_ARG;
+  if (block < 0 || block >= P->nblocks) return SPINSUM_ERR_INVALID_ARG;
+  const Tiling& T = P->batched ? P->btil[block] : P->T;
+  const Geom& g = T.g;
+  if (g.n <= 0 || g.ncubes <= 0) return SPINSUM_OK;
+  const int d = P->d, df = P->G.df, n = g.n, bl = g.bl;
+  std::vector<int64_t> owner((size_t)g.cube_elems, -1);
+  for (size_t o = 0; o < T.orbits.size(); ++o) {
+    const OrbitDev& od = T.orbits[o];
+    // block tuple of the representative tile = the tile of the identity
+    int B[kMaxD];
+    for (int m = 0; m < d; ++m) B[m] = (od.tile_off[od.slot_base[0] / g.ts] / g.gst[m]) % n / bl;
+    for (int r = 0; r < df; ++r) {
+      // the tile recorded for sigma must be sigma . B
+      int s = od.slot_base[r] / g.ts;
+      if (s < 0 || s >= od.ntiles || od.slot_base[r] != s * g.ts) return fail("bad slot");
+      int64_t off = 0;
+      for (int m = 0; m < d; ++m) off += (int64_t)B[P->G.p[r][m]] * bl * g.gst[m];
+      if (off != od.tile_off[s]) return fail("slot table does not match sigma . B");
+    }
+    for (int k = 0; k < od.rep_cnt; ++k) {
+      uint32_t pk = T.reps[od.rep_off + k];
+      int x[kMaxD];
+      for (int m = 0; m < d; ++m) {
+        int l = (pk >> (8 * m)) & 255;
+        if (l >= std::min(bl, n - B[m] * bl)) return fail("representative outside its tile");
+        x[m] = B[m] * bl + l;
+      }
+      int64_t id = (int64_t)o * (1ll << 32) + k;
+      for (int r = 0; r < df; ++r) {
+        int64_t e = 0;
+        for (int m = 0; m < d; ++m) e += (int64_t)x[P->G.p[r][m]] * g.gst[m];
+        if (owner[e] != -1 && owner[e] != id) return fail("element owned twice");
+        owner[e] = id;
+      }
+    }
+  }
+  for (int64_t e = 0; e < g.cube_elems; ++e)
+    if (owner[e] == -1) return fail("element not owned");
+  std::string w;
+  bool ok = (d == 2) ? emulate_all<2>(T, &w) : (d == 3) ? emulate_all<3>(T, &w) : emulate_all<4>(T, &w);
+  if (!ok) return fail(w);
+  return SPINSUM_OK;
+}
+
+extern "C" void spinsum_plan_destroy(spinsum_plan_t P) {
+  if (!P) return;
+  free_device(P);
+  delete P;
+}
+
+extern "C" int spinsum_plan_last_hip_error(spinsum_plan_t P) { return P ? P->last_hip_error : 0; }
+
+extern "C" const char* spinsum_status_string(spinsum_status s) {
+  switch (s) {
+    case SPINSUM_OK: return "ok";
+    case SPINSUM_ERR_INVALID_ARG: return "invalid argument";
+    case SPINSUM_ERR_NOT_PERMUTATION: return "a term is not a permutation";
+    case SPINSUM_ERR_EXTENT_MISMATCH: return "group extents differ";
+    case SPINSUM_ERR_UNSUPPORTED: return "unsupported configuration";
+    case SPINSUM_ERR_ALIASING: return "out-of-place buffers overlap";
+    case SPINSUM_ERR_MISALIGNED: return "tensor pointer not 16-byte aligned";
+    case SPINSUM_ERR_OUT_OF_MEMORY: return "out of memory";
+    case SPINSUM_ERR_HIP: return "HIP runtime error";
+    case SPINSUM_ERR_NO_DEVICE: return "plan has no device tables";
+  }
+  return "unknown status";
+}
+
+extern "C" const char* spinsum_version(void) { return "spinsum 0.1 (gfx950)"; }

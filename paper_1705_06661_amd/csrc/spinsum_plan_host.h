@@ -1,0 +1,95 @@
+// spinsum_plan_host.h -- host-side plan object of libspinsum (internal).
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/spinsum.h"
+#include "spinsum_internal.h"
+
+namespace spinsum {
+
+// The symmetric group S_d with its elements in lexicographic order.
+struct SymGroup {
+  int d = 0;
+  int df = 0;
+  std::vector<std::vector<int>> p;  // p[r] = the r-th permutation
+  std::vector<int> inv;             // rank of the inverse
+  std::vector<int> mul;             // mul[a*df+b] = rank of "a after b": m -> a[b[m]]
+  void init(int d);
+  int rank(const int* q) const;
+};
+
+// Tables of one tensor (or one block of a batch) for one tile choice.
+struct Tiling {
+  Geom g{};
+  int nb = 0;
+  int vw = 1;
+  int max_tiles = 0;
+  int ragged = 0;
+  int fits = 1;
+  int64_t lds_elems = 0;
+  int64_t nitems = 0;
+  std::vector<OrbitDev> orbits;
+  std::vector<uint32_t> reps;
+};
+
+}  // namespace spinsum
+
+struct spinsum_plan_s {
+  // problem
+  int d = 0, n = 0;
+  int ndim = 0;
+  std::vector<int64_t> extents;
+  int64_t ncubes = 0, elems = 0;
+  int dtype = 0, inplace = 0;
+  unsigned flags = 0;
+  spinsum::SymGroup G;
+  std::vector<std::vector<double>> stage_a;  // per stage: coefficient of each permutation rank
+  std::vector<double> expanded;              // coefficient of each permutation rank
+  std::vector<double> M, MT;                 // df x df orbit matrices (forward, adjoint)
+  std::vector<double> SM, SMT;               // per-stage orbit matrices, application order
+
+  // tiling (single tensor)
+  spinsum_tile_t tile{};
+  spinsum::Tiling T;
+
+  // batch
+  bool batched = false;
+  int nblocks = 1;
+  std::vector<spinsum::Tiling> btil;
+  std::vector<spinsum::BatchBlock> blocks;
+  std::vector<spinsum::BatchItem> items;
+  std::vector<int64_t> block_elems;
+  int batch_vw = 1;
+  int64_t batch_lds_elems = 0;
+  int batch_grid = 0;
+
+  // device
+  bool has_dev = false;
+  int device = -1;
+  int num_cus = 256;
+  int lds_limit = spinsum::kMaxLdsBytes;
+  void* d_orbits = nullptr;
+  void* d_reps = nullptr;
+  void* d_mats = nullptr;   // M | MT | SM | SMT in the storage type
+  void* d_blocks = nullptr;
+  void* d_items = nullptr;
+  int last_hip_error = 0;
+  std::string why;
+};
+
+namespace spinsum {
+// Implemented in spinsum_plan.cpp
+spinsum_status build_tiling(const spinsum_plan_s& P, int n, int64_t ncubes,
+                            const spinsum_tile_t& tile, int vw, Tiling* out);
+spinsum_status choose_tile(const spinsum_plan_s& P, int n, int64_t ncubes, int vw,
+                           spinsum_tile_t* tile);
+int max_vector_width(const spinsum_plan_s& P, int n);
+spinsum_status upload_tables(spinsum_plan_s* P);
+void free_device(spinsum_plan_s* P);
+int elem_size(const spinsum_plan_s& P);
+// Implemented in spinsum_tune.cpp
+bool cache_lookup(const spinsum_plan_s& P, spinsum_tile_t* tile);
+}  // namespace spinsum

@@ -1,0 +1,165 @@
+// spinsum_tune.cpp -- tile autotuner of libspinsum and its cache file.
+//
+// The tile edge bl of the blocked schedule trades contiguous bytes per row
+// (bl * sizeof(T) along the stride-one axis) against LDS per workgroup
+// (the largest tile orbit), i.e. against how many workgroups a CU can keep
+// in flight.  The paper picks bl from the cache size (Sec. 4.5, Eq. 11);
+// here the candidates are timed on the device and the winner is kept.
+//
+// Cache file: plain text, one line per configuration:
+//   <key> <bl> <cubes_per_wg> <threads> <lds_pad> <ms>
+// key = d<d>_n<N>_<f64|f32>_ip<0|1>_c<floor(log2(ncubes))>_<arch>.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "spinsum_plan_host.h"
+
+namespace spinsum {
+
+static std::string arch_name(int device) {
+  hipDeviceProp_t prop;
+  if (device < 0 || hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    (void)hipGetLastError();
+    return "gfx950";
+  }
+  std::string a = prop.gcnArchName;
+  size_t c = a.find(':');
+  if (c != std::string::npos) a = a.substr(0, c);
+  return a.empty() ? std::string("gfx950") : a;
+}
+
+static std::string cache_key(const spinsum_plan_s& P) {
+  int lg = 0;
+  while ((1ll << (lg + 1)) <= P.ncubes) ++lg;
+  std::ostringstream os;
+  os << "d" << P.d << "_n" << P.n << "_" << (P.dtype == SPINSUM_F32 ? "f32" : "f64") << "_ip"
+     << P.inplace << "_c" << lg << "_" << arch_name(P.device);
+  return os.str();
+}
+
+bool cache_lookup(const spinsum_plan_s& P, spinsum_tile_t* tile) {
+  const char* path = std::getenv("SPINSUM_AUTOTUNE_CACHE");
+  if (path == nullptr || *path == 0) return false;
+  std::ifstream f(path);
+  if (!f) return false;
+  const std::string key = cache_key(P);
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    std::istringstream is(line);
+    std::string k;
+    spinsum_tile_t t{};
+    double ms = 0;
+    if (!(is >> k >> t.bl >> t.cubes_per_wg >> t.threads >> t.lds_pad >> ms)) continue;
+    if (k != key) continue;
+    if (t.bl < 1 || t.bl > P.n || t.cubes_per_wg < 1) continue;
+    *tile = t;  // the last matching line wins
+    found = true;
+  }
+  return found;
+}
+
+static void cache_store(const spinsum_plan_s& P, const char* path, const spinsum_tile_t& t,
+                        float ms) {
+  const std::string key = cache_key(P);
+  std::vector<std::string> keep;
+  {
+    std::ifstream f(path);
+    std::string line;
+    while (f && std::getline(f, line)) {
+      std::istringstream is(line);
+      std::string k;
+      if (is >> k && k == key) continue;
+      if (!line.empty()) keep.push_back(line);
+    }
+  }
+  std::ostringstream os;
+  os << key << " " << t.bl << " " << t.cubes_per_wg << " " << t.threads << " " << t.lds_pad << " "
+     << ms;
+  keep.push_back(os.str());
+  std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream o(tmp, std::ios::trunc);
+    for (const std::string& l : keep) o << l << "\n";
+  }
+  std::rename(tmp.c_str(), path);
+}
+
+}  // namespace spinsum
+
+using namespace spinsum;
+
+extern "C" spinsum_status spinsum_autotune(spinsum_plan_t P, void* in, void* out, void* stream,
+                                           const char* cache_path, spinsum_tile_t* best,
+                                           float* best_ms) {
+  if (P == nullptr || P->batched) return SPINSUM_ERR_INVALID_ARG;
+  if (!P->has_dev) return SPINSUM_ERR_NO_DEVICE;
+  if (P->elems == 0) return SPINSUM_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const int esz = elem_size(*P);
+  const int n = P->n, d = P->d;
+  int64_t cube_bytes = esz;
+  for (int m = 0; m < d; ++m) cube_bytes *= n;
+  std::vector<spinsum_tile_t> cands;
+  for (int pad = 1; pad >= 0; --pad) {
+    if (cube_bytes * 2 <= P->lds_limit) {
+      for (int cpw = 1; cpw <= 64; cpw *= 2) {
+        if (cpw * cube_bytes > 96 * 1024 || cpw > P->ncubes) break;
+        cands.push_back({n, cpw, 256, pad});
+      }
+    }
+    for (int bl = n - 1; bl >= 2; --bl) {
+      if (n % bl != 0) continue;
+      if (bl * esz < 32) continue;
+      cands.push_back({bl, 1, 256, pad});
+    }
+  }
+  spinsum_tile_t keep = P->tile;
+  spinsum_tile_t win{};
+  float win_ms = 0;
+  bool have = false;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipGetLastError();
+    return SPINSUM_ERR_HIP;
+  }
+  for (const spinsum_tile_t& t : cands) {
+    if (spinsum_plan_set_tile(P, &t) != SPINSUM_OK) continue;
+    if (spinsum_exec(P, in, out, stream) != SPINSUM_OK) continue;  // warm-up
+    const int reps = 3;
+    float ms_min = 1e30f;
+    bool ok = true;
+    for (int r = 0; r < reps && ok; ++r) {
+      (void)hipEventRecord(e0, s);
+      ok = spinsum_exec(P, in, out, stream) == SPINSUM_OK;
+      (void)hipEventRecord(e1, s);
+      (void)hipEventSynchronize(e1);
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      ms_min = std::min(ms_min, ms);
+    }
+    if (!ok) continue;
+    if (!have || ms_min < win_ms) {
+      have = true;
+      win = P->tile;
+      win_ms = ms_min;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  spinsum_status st = spinsum_plan_set_tile(P, have ? &win : &keep);
+  if (st != SPINSUM_OK) return st;
+  if (best) *best = P->tile;
+  if (best_ms) *best_ms = have ? win_ms : 0.0f;
+  if (have && cache_path != nullptr && *cache_path) cache_store(*P, cache_path, P->tile, win_ms);
+  return have ? SPINSUM_OK : SPINSUM_ERR_UNSUPPORTED;
+}

@@ -1,0 +1,353 @@
+"""GPU parity of libspinsum against the CPU oracle (run on an MI355X).
+
+Tolerances (from the normwise error bar of the method, FP64 <= 1e-14 and
+FP32 <= 2e-6): err = max|gpu - ref| / max|ref| with ref the long-double
+oracle (FP32: the oracle on the FP32-rounded input).  Integer-valued inputs
+(|x| <= 1024) make every summation order exact, so there the comparison is
+bit-exact, in FP64 and FP32.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+ss = pytest.importorskip("paper_1705_06661_amd")
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+DEV = torch.device("cuda:0")
+TOL = {torch.float64: 1e-14, torch.float32: 2e-6}
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def nerr(got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = np.max(np.abs(ref)) if ref.size else 0.0
+    if scale == 0.0:
+        return float(np.max(np.abs(got))) if got.size else 0.0
+    return float(np.max(np.abs(got - ref)) / scale)
+
+
+def gpu_uniform(shape, seed, dtype=torch.float64):
+    return workloads.uniform(shape, seed, device=DEV, dtype=dtype)
+
+
+def gpu_ints(shape, seed, dtype=torch.float64):
+    return workloads.integers(shape, seed, device=DEV, dtype=dtype)
+
+
+def mk(shape, stages, d, dtype=torch.float64, inplace=False, flags=0, tile=None):
+    p = ss.spinsum_plan(shape, len(shape) - d, d, stages, dtype=dtype, inplace=inplace,
+                        flags=flags)
+    if tile is not None:
+        ss.spinsum_plan_set_tile(p, *tile)
+    return p
+
+
+def run(plan, x):
+    if plan.inplace:
+        y = x.clone()
+        ss.spinsum_exec(plan, y, y)
+    else:
+        y = torch.empty_like(x)
+        ss.spinsum_exec(plan, x, y)
+    torch.cuda.synchronize()
+    return y
+
+
+def ref_of(x, stages, d):
+    xh = x.detach().to("cpu", torch.float64).numpy()
+    return oracle.spinsum_chain(xh, stages, xh.ndim - d, d, nthreads=8)
+
+
+# --------------------------------------------------------------- config 1
+@pytest.mark.parametrize("inplace", [False, True])
+def test_config_3d_v16_o8(inplace):
+    w = workloads.WORKLOADS["3d_v16_o8"]
+    _say("case 3d_v16_o8 inplace", inplace)
+    x = gpu_uniform(w["shape"], 1)
+    p = mk(w["shape"], [workloads.CONFIG_3D_ALPHA], 3, inplace=inplace)
+    y = run(p, x)
+    ref = ref_of(x, [workloads.CONFIG_3D_ALPHA], 3)
+    assert nerr(y.cpu().numpy(), ref) <= 1e-14
+    xi = gpu_ints(w["shape"], 2)
+    yi = run(p, xi)
+    np.testing.assert_array_equal(yi.cpu().numpy(), ref_of(xi, [workloads.CONFIG_3D_ALPHA], 3))
+
+
+def test_inplace_equals_out_of_place_bitwise():
+    shape = (5, 7, 16, 16, 16)
+    x = gpu_uniform(shape, 3)
+    for tile in [(16, 2), (8, 1), (4, 1), (6, 1)]:
+        a = run(mk(shape, [workloads.CONFIG_3D_ALPHA], 3, tile=tile), x)
+        b = run(mk(shape, [workloads.CONFIG_3D_ALPHA], 3, inplace=True, tile=tile), x)
+        assert torch.equal(a, b), tile
+
+
+def test_worked_example_pi312():
+    """Single term pi_312 on In[i,j,k] = 100i + 10j + k gives 100k + 10i + j."""
+    n = 8
+    i, j, k = torch.meshgrid(*(torch.arange(n, dtype=torch.float64),) * 3, indexing="ij")
+    x = (100 * i + 10 * j + k).unsqueeze(0).to(DEV).contiguous()
+    for tile in [(8, 1), (4, 1), (3, 1)]:
+        y = run(mk(x.shape, [[(workloads.P("312"), 1.0)]], 3, tile=tile), x)
+        want = (100 * k + 10 * i + j).unsqueeze(0)
+        assert torch.equal(y.cpu(), want), tile
+
+
+# ------------------------------------------------------- tiles and shapes
+CASES = [
+    # (shape, d, tile(bl, cpw))
+    ((3, 8, 8, 8), 3, (8, 2)),        # whole cubes, ragged last item
+    ((5, 8, 8, 8), 3, (8, 4)),
+    ((2, 16, 16, 16), 3, (8, 1)),     # 4 tile orbits
+    ((2, 16, 16, 16), 3, (4, 1)),     # 20 tile orbits, generic ones with 6 tiles
+    ((3, 13, 13, 13), 3, (4, 1)),     # ragged tiles, odd extent (scalar loads)
+    ((2, 12, 12, 12), 3, (5, 1)),     # ragged, even extent
+    ((2, 1, 1, 1), 3, (1, 1)),
+    ((4, 2, 2, 2), 3, (1, 1)),
+    ((2, 12, 12, 12, 12), 4, (6, 1)),
+    ((1, 12, 12, 12, 12), 4, (4, 1)),
+    ((2, 7, 7, 7, 7), 4, (3, 1)),
+    ((3, 5, 5, 5, 5), 4, (5, 2)),
+    ((4, 33, 33), 2, (8, 1)),
+    ((6, 16, 16), 2, (16, 3)),
+]
+
+
+@pytest.mark.parametrize("shape,d,tile", CASES)
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_tiles_against_oracle(shape, d, tile, dtype):
+    _say("case", shape, d, tile, dtype)
+    rng = np.random.default_rng(sum(shape) + d)
+    perms = list(itertools.permutations(range(d)))
+    terms = [(p, float(rng.integers(-3, 4))) for p in perms]
+    for inplace in (False, True):
+        p = mk(shape, [terms], d, dtype=dtype, inplace=inplace, tile=tile)
+        x = gpu_uniform(shape, 5, dtype)
+        y = run(p, x)
+        assert nerr(y.cpu().numpy(), ref_of(x, [terms], d)) <= TOL[dtype]
+        xi = gpu_ints(shape, 6, dtype)
+        yi = run(p, xi)
+        np.testing.assert_array_equal(yi.cpu().numpy().astype(np.float64), ref_of(xi, [terms], d))
+
+
+@pytest.mark.parametrize("case", [1, 2, 4, 5, 6, 8, 9, 11, 13, 17, 21])
+@pytest.mark.parametrize("chain", [False, True])
+def test_table2_cases(case, chain):
+    d, stages = workloads.table2_case(case)
+    n = 9 if d == 3 else 6
+    shape = (3,) + (n,) * d
+    flags = ss.SPINSUM_FLAG_CHAIN_STAGES if chain else 0
+    for tile in [(n, 1), (3, 1)]:
+        p = mk(shape, stages, d, flags=flags, tile=tile, inplace=True)
+        x = gpu_uniform(shape, case)
+        y = run(p, x)
+        assert nerr(y.cpu().numpy(), ref_of(x, stages, d)) <= 1e-14, tile
+        xi = gpu_ints(shape, case + 100)
+        np.testing.assert_array_equal(run(p, xi).cpu().numpy(), ref_of(xi, stages, d))
+
+
+def test_factored_form_chained_and_expanded():
+    shape = (4, 16, 16, 16)
+    x = gpu_uniform(shape, 9)
+    st = workloads.FACTORED_PIJ_PJK
+    ref = ref_of(x, st, 3)
+    for flags in (0, ss.SPINSUM_FLAG_CHAIN_STAGES):
+        y = run(mk(shape, st, 3, flags=flags, inplace=True), x)
+        assert nerr(y.cpu().numpy(), ref) <= 1e-14
+
+
+@pytest.mark.parametrize("flags", [ss.SPINSUM_FLAG_REVERSE_ORDER, ss.SPINSUM_FLAG_NO_XCD_REMAP,
+                                   ss.SPINSUM_FLAG_NO_LDS_PAD, ss.SPINSUM_FLAG_NO_NT_STORES])
+def test_schedule_variants_are_bitwise_equal(flags):
+    shape = (3, 24, 24, 24)
+    x = gpu_uniform(shape, 11)
+    for tile in [(8, 1), (12, 1), (24, 1)]:
+        base = run(mk(shape, [workloads.CONFIG_3D_ALPHA], 3, inplace=True, tile=tile), x)
+        other = run(mk(shape, [workloads.CONFIG_3D_ALPHA], 3, inplace=True, flags=flags, tile=tile), x)
+        assert torch.equal(base, other), (flags, tile)
+
+
+def test_empty_tensors_are_no_ops():
+    for shape in [(0, 4, 4, 4), (3, 0, 0, 0)]:
+        p = mk(shape, [workloads.CONFIG_3D_ALPHA], 3)
+        x = torch.empty(shape, dtype=torch.float64, device=DEV)
+        ss.spinsum_exec(p, x, torch.empty_like(x))
+
+
+def test_error_paths_on_device():
+    shape = (4, 8, 8, 8)
+    x = gpu_uniform(shape, 1)
+    p = mk(shape, [workloads.CONFIG_3D_ALPHA], 3)
+    with pytest.raises(ss.SpinSumError) as e:
+        ss.spinsum_exec(p, x, x)
+    assert e.value.status == ss.SPINSUM_ERR_ALIASING
+    big = torch.empty(2 * x.numel() + 1, dtype=torch.float64, device=DEV)
+    st = ss._c_exec(p._h, big.data_ptr() + 8, big.data_ptr() + 8 * (x.numel() + 1), None)
+    assert st == ss.SPINSUM_ERR_MISALIGNED
+    st = ss._c_exec(p._h, big.data_ptr(), big.data_ptr() + 8 * (x.numel() // 2), None)
+    assert st == ss.SPINSUM_ERR_ALIASING
+    q = mk(shape, [workloads.CONFIG_3D_ALPHA], 3, inplace=True)
+    with pytest.raises(ss.SpinSumError) as e:
+        ss.spinsum_exec(q, x, torch.empty_like(x))
+    assert e.value.status == ss.SPINSUM_ERR_INVALID_ARG
+    torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------- adjoint
+@pytest.mark.parametrize("stages_name", ["config", "factored", "table2_6"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_adjoint_against_oracle(stages_name, dtype):
+    if stages_name == "config":
+        d, stages = 3, [workloads.CONFIG_3D_ALPHA]
+    elif stages_name == "factored":
+        d, stages = 3, workloads.FACTORED_PIJ_PJK
+    else:
+        d, stages = workloads.table2_case(6)
+    n = 12 if d == 3 else 6
+    shape = (3,) + (n,) * d
+    g = gpu_uniform(shape, 21, dtype)
+    gh = g.cpu().to(torch.float64).numpy()
+    ref = oracle.spinsum_chain_adjoint(gh, stages, 1, d, nthreads=8)
+    for flags in (0, ss.SPINSUM_FLAG_CHAIN_STAGES):
+        for inplace in (False, True):
+            p = mk(shape, stages, d, dtype=dtype, inplace=inplace, flags=flags)
+            if inplace:
+                gi = g.clone()
+                ss.spinsum_adjoint(p, gi, gi)
+            else:
+                gi = torch.empty_like(g)
+                ss.spinsum_adjoint(p, g, gi)
+            torch.cuda.synchronize()
+            assert nerr(gi.cpu().numpy(), ref) <= TOL[dtype]
+
+
+def test_adjoint_identity_on_gpu():
+    d, stages = workloads.table2_case(9)
+    shape = (4, 8, 8, 8, 8)
+    x = gpu_uniform(shape, 31)
+    y = gpu_uniform(shape, 32)
+    p = mk(shape, stages, d)
+    sx = run(p, x)
+    sty = torch.empty_like(y)
+    ss.spinsum_adjoint(p, y, sty)
+    torch.cuda.synchronize()
+    lhs = float((sx * y).sum())
+    rhs = float((x * sty).sum())
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+@pytest.mark.parametrize("shape,gf,d", [((2, 3, 3, 3), 1, 3), ((1, 2, 2, 2, 2), 1, 4),
+                                        ((3, 3, 3, 3), 0, 4), ((1, 1, 1, 1), 1, 3),
+                                        ((5, 5, 5), 0, 3)])
+def test_autograd_gradcheck_and_dense_matrix(shape, gf, d):
+    stages = workloads.FACTORED_PIJ_PJK if d == 3 else workloads.table2_case(6)[1]
+    for inplace in (False, True):
+        p = ss.spinsum_plan(shape, gf, d, stages, inplace=inplace)
+
+        def f(x):
+            return ss.SpinSumFunction.apply(x.clone() if inplace else x, p)
+
+        x = gpu_uniform(shape, 41).requires_grad_(True)
+        assert torch.autograd.gradcheck(f, (x,), eps=1e-6, atol=1e-10, rtol=1e-9)
+        M = oracle.dense_chain_matrix(shape, stages, gf, d)
+        g = gpu_uniform(shape, 42)
+        y = f(x)
+        (gx,) = torch.autograd.grad(y, x, g)
+        np.testing.assert_allclose(gx.detach().cpu().numpy().ravel(), M.T @ g.cpu().numpy().ravel(),
+                                   rtol=0, atol=1e-12)
+        np.testing.assert_allclose(y.detach().cpu().numpy().ravel(),
+                                   M @ x.detach().cpu().numpy().ravel(), rtol=0, atol=1e-12)
+
+
+# ----------------------------------------------------------------- batched
+def _small_blocks():
+    rng = np.random.default_rng(5)
+    return [(int(rng.integers(1, 7)), int(o)) for o in [2, 3, 5, 8, 12, 16, 7, 4, 16, 1, 9, 13]]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batched_equals_per_block_and_oracle(dtype):
+    blocks = _small_blocks()
+    shapes = [(v, v, v, o, o, o) for v, o in blocks]
+    xs = [gpu_uniform(s, 50 + k, dtype) for k, s in enumerate(shapes)]
+    for inplace in (False, True):
+        bp = ss.spinsum_plan_batched(shapes, 3, [workloads.CONFIG_3D_ALPHA], dtype=dtype,
+                                     inplace=inplace)
+        if inplace:
+            outs = [x.clone() for x in xs]
+            ins = outs
+        else:
+            ins = xs
+            outs = [torch.empty_like(x) for x in xs]
+        ss.spinsum_exec_batched(bp, ins, outs)
+        torch.cuda.synchronize()
+        for k, (s, x) in enumerate(zip(shapes, xs)):
+            single = run(mk(s, [workloads.CONFIG_3D_ALPHA], 3, dtype=dtype), x)
+            ref = ref_of(x, [workloads.CONFIG_3D_ALPHA], 3)
+            assert nerr(outs[k].cpu().numpy(), ref) <= TOL[dtype], k
+            # tiling and vector width change no arithmetic: bit-identical
+            assert torch.equal(outs[k], single), k
+
+
+def test_batched_graph_replays():
+    blocks = _small_blocks()
+    shapes = [(v, v, v, o, o, o) for v, o in blocks]
+    xs = [gpu_uniform(s, 60 + k) for k, s in enumerate(shapes)]
+    bp = ss.spinsum_plan_batched(shapes, 3, [workloads.CONFIG_3D_ALPHA], inplace=False)
+    outs = [torch.empty_like(x) for x in xs]
+    ss.spinsum_exec_batched(bp, xs, outs)
+    torch.cuda.synchronize()
+    eager = [o.clone() for o in outs]
+    gouts = [torch.full_like(x, float("nan")) for x in xs]
+    graph = ss.spinsum_graph_create(bp, xs, gouts)
+    for rep in range(3):
+        for o in gouts:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        ss.spinsum_graph_launch(graph)
+        torch.cuda.synchronize()
+        for e, o in zip(eager, gouts):
+            assert torch.equal(e, o), rep
+        _ = sum(float(o.sum()) for o in gouts)  # eager work between replays
+
+
+# --------------------------------------------------------------- utilities
+def test_stream_copy():
+    x = gpu_uniform((1 << 20) + 2, 70)
+    y = torch.empty_like(x)
+    ss.spinsum_stream_copy(x, y)
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
+
+
+def test_autotune_and_cache(tmp_path):
+    shape = (64, 24, 24, 24)
+    x = gpu_uniform(shape, 80)
+    p = mk(shape, [workloads.CONFIG_3D_ALPHA], 3)
+    out = torch.empty_like(x)
+    cache = str(tmp_path / "tune.txt")
+    best, ms = ss.spinsum_autotune(p, x, out, cache_path=cache)
+    assert ms > 0 and best["bl"] in (24, 12, 8, 6, 4)
+    assert os.path.exists(cache) and "d3_n24_f64_ip0" in open(cache).read()
+    y = run(p, x)
+    assert nerr(y.cpu().numpy(), ref_of(x, [workloads.CONFIG_3D_ALPHA], 3)) <= 1e-14
+    os.environ["SPINSUM_AUTOTUNE_CACHE"] = cache
+    try:
+        q = mk(shape, [workloads.CONFIG_3D_ALPHA], 3)
+        assert ss.spinsum_plan_get_info(q)["bl"] == best["bl"]
+    finally:
+        del os.environ["SPINSUM_AUTOTUNE_CACHE"]

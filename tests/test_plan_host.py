@@ -1,0 +1,271 @@
+"""Host-side tests of libspinsum (no GPU): exported symbols, argument
+validation, canonicalisation, the expanded operator, the tile-orbit tables
+and the work ownership that makes the in-place form safe.
+
+Plans are made with SPINSUM_FLAG_HOST_ONLY, so no HIP call is made.
+"""
+import itertools
+import math
+import os
+import re
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+import paper_1705_06661_amd as ss
+from workloads import P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HOST = ss.SPINSUM_FLAG_HOST_ONLY
+
+
+def plan(shape, stages, d=None, dtype="f64", inplace=False, flags=0):
+    d = d or len(stages[0][0][0])
+    return ss.spinsum_plan(shape, len(shape) - d, d, stages, dtype=dtype, inplace=inplace,
+                           flags=flags | HOST)
+
+
+def _rand(shape, seed):
+    return workloads.uniform(shape, seed).numpy()
+
+
+# ------------------------------------------------------------------ ABI
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "spinsum.h")).read()
+    declared = set(re.findall(r"^[A-Za-z_][\w \*]*?\b(spinsum_\w+)\s*\(", hdr, re.M))
+    assert len(declared) >= 18
+    lib = ctypes.CDLL(ss.LIB_PATH)
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+    assert set(ss.EXPORTED) == declared
+
+
+def test_version_and_status_strings():
+    assert "spinsum" in ss.spinsum_version()
+    for st in range(-9, 1):
+        assert ss.spinsum_status_string(st) != "unknown status"
+
+
+# ------------------------------------------------------------ validation
+@pytest.mark.parametrize("shape,stages,d,code", [
+    ((4, 3, 3, 3), [[((0, 0, 1), 1.0)]], 3, ss.SPINSUM_ERR_NOT_PERMUTATION),
+    ((4, 3, 3, 3), [[((0, 1, 3), 1.0)]], 3, ss.SPINSUM_ERR_NOT_PERMUTATION),
+    ((4, 3, 3, 4), [[((0, 1, 2), 1.0)]], 3, ss.SPINSUM_ERR_EXTENT_MISMATCH),
+    ((2, 2, 2, 2, 2, 2), [[((0, 1, 2, 3, 4), 1.0)]], 5, ss.SPINSUM_ERR_UNSUPPORTED),
+    ((3, 3), [[((0,), 1.0)]], 1, ss.SPINSUM_ERR_UNSUPPORTED),
+    ((4, 3, 3, 3), [[((0, 1, 2), float("nan"))]], 3, ss.SPINSUM_ERR_INVALID_ARG),
+    ((4, 3, 3, 3), [], 3, ss.SPINSUM_ERR_INVALID_ARG),
+    ((-1, 3, 3, 3), [[((0, 1, 2), 1.0)]], 3, ss.SPINSUM_ERR_INVALID_ARG),
+])
+def test_plan_rejects_bad_arguments(shape, stages, d, code):
+    with pytest.raises(ss.SpinSumError) as e:
+        ss.spinsum_plan(shape, len(shape) - d, d, stages, flags=HOST)
+    assert e.value.status == code
+
+
+def test_inner_spectators_are_unsupported():
+    with pytest.raises(ss.SpinSumError) as e:
+        ss.spinsum_plan((4, 3, 3, 3, 2), 1, 3, [workloads.CONFIG_3D_ALPHA], flags=HOST)
+    assert e.value.status == ss.SPINSUM_ERR_UNSUPPORTED
+
+
+def test_host_only_plan_refuses_exec():
+    p = plan((4, 3, 3, 3), [workloads.CONFIG_3D_ALPHA])
+    st = ss._c_exec(p._h, 256, 4096, None)
+    assert st == ss.SPINSUM_ERR_NO_DEVICE
+    st = ss._c_adjoint(p._h, 256, 4096, None)
+    assert st == ss.SPINSUM_ERR_NO_DEVICE
+
+
+def test_exec_rejects_null_plan_and_batched_misuse():
+    assert ss._c_exec(None, 256, 4096, None) == ss.SPINSUM_ERR_INVALID_ARG
+    assert ss._c_exec_batched(None, 256, 4096, None) == ss.SPINSUM_ERR_INVALID_ARG
+    bp = ss.spinsum_plan_batched([(2, 3, 3, 3)], 3, [workloads.CONFIG_3D_ALPHA], flags=HOST)
+    assert ss._c_exec(bp._h, 256, 4096, None) == ss.SPINSUM_ERR_INVALID_ARG
+
+
+def test_stream_copy_argument_checks():
+    assert ss._c_copy(256, 4096, 15, None) == ss.SPINSUM_ERR_INVALID_ARG
+    assert ss._c_copy(256, 4096, 0, None) == ss.SPINSUM_OK
+    assert ss._c_copy(8, 4096, 16, None) == ss.SPINSUM_ERR_MISALIGNED
+
+
+# ------------------------------------------------------- expanded operator
+def _as_dict(terms):
+    return {tuple(p): a for p, a in terms}
+
+
+def test_expanded_3d_factorisations():
+    d, st1 = workloads.table2_case(1)
+    assert _as_dict(ss.spinsum_plan_expanded(plan((2, 4, 4, 4), st1))) == \
+        _as_dict(workloads.CONFIG_3D_ALPHA)
+    want = {P("123"): 4.0, P("213"): -2.0, P("132"): -2.0, P("231"): 1.0}
+    assert _as_dict(ss.spinsum_plan_expanded(plan((2, 4, 4, 4), workloads.FACTORED_PIJ_PJK))) == want
+    eq8 = [workloads.stage((1, "123"), (1, "321"), (1, "132")),
+           workloads.stage((1, "123"), (1, "213"))]
+    assert _as_dict(ss.spinsum_plan_expanded(plan((1, 3, 3, 3), eq8))) == \
+        {p: 1.0 for p in itertools.permutations(range(3))}
+
+
+@pytest.mark.parametrize("case,count", [(1, 6), (2, 3), (5, 24), (6, 12), (8, 9), (9, 10),
+                                        (11, 9), (17, 8), (18, 4), (21, 4)])
+def test_expanded_term_counts_table2(case, count):
+    d, stages = workloads.table2_case(case)
+    p = plan((1,) + (3,) * d, stages, d=d)
+    assert ss.spinsum_plan_get_info(p)["nterms_expanded"] == count
+
+
+@pytest.mark.parametrize("case", [1, 5, 6, 9, 13, 17])
+def test_expanded_operator_matches_oracle_chain(case):
+    d, stages = workloads.table2_case(case)
+    p = plan((2,) + (4,) * d, stages, d=d)
+    x = _rand((2,) + (4,) * d, case)
+    exp = ss.spinsum_plan_expanded(p)
+    np.testing.assert_allclose(oracle.spinsum(x, exp, 1, d), oracle.spinsum_chain(x, stages, 1, d),
+                               rtol=0, atol=1e-11)
+
+
+def test_duplicates_merge_and_zeros_drop():
+    ident = (0, 1, 2)
+    p = plan((2, 3, 3, 3), [[(ident, 1.0), (P("213"), 2.0), (ident, -1.0), (P("213"), 0.5)]])
+    assert _as_dict(ss.spinsum_plan_expanded(p)) == {P("213"): 2.5}
+    z = plan((2, 3, 3, 3), [[(ident, 0.0)]])
+    assert ss.spinsum_plan_expanded(z) == []
+
+
+# --------------------------------------------------------- tile orbits
+def _counts():
+    rows = {}
+    for ln in open(os.path.join(ROOT, "tests", "golden", "counts.txt")):
+        if ln.strip() and not ln.startswith("#"):
+            tok = ln.split()
+            rows.setdefault(tok[0], []).append(dict(kv.split("=") for kv in tok[1:]))
+    return rows
+
+
+def test_task_count_of_sec45():
+    """A 40^4 tensor blocked with bl = 8 gives 70 tile orbits (Sec. 4.5)."""
+    for r in _counts()["tasks"]:
+        d, n, bl = int(r["d"]), int(r["N"]), int(r["bl"])
+        p = plan((1,) + (n,) * d, [[(tuple(range(d)), 1.0)]], d=d)
+        ss.spinsum_plan_set_tile(p, bl, lds_pad=1)
+        assert ss.spinsum_plan_get_info(p)["norbits"] == int(r["count"])
+
+
+@pytest.mark.parametrize("d,n,bl", [(3, 32, 16), (3, 32, 8), (4, 12, 6), (4, 12, 4), (4, 12, 3),
+                                    (3, 24, 12), (3, 24, 8), (2, 10, 5), (3, 13, 4), (4, 7, 3)])
+def test_orbit_count_is_multiset_count(d, n, bl):
+    """C(nb + d - 1, d) tile orbits for nb blocks per axis (Alg. 5a loop nest)."""
+    p = plan((2,) + (n,) * d, [[(tuple(range(d)), 1.0)]], d=d)
+    ss.spinsum_plan_set_tile(p, bl)
+    nb = -(-n // bl)
+    info = ss.spinsum_plan_get_info(p)
+    assert info["norbits"] == math.comb(nb + d - 1, d)
+    assert info["nb"] == nb
+    assert info["max_tiles"] == max(
+        len({tuple(B[i] for i in s) for s in itertools.permutations(range(d))})
+        for B in itertools.combinations_with_replacement(range(nb), d))
+
+
+@pytest.mark.parametrize("d,n,bl", [(3, 8, 8), (3, 8, 4), (3, 32, 8), (3, 12, 5), (3, 13, 4),
+                                    (4, 12, 6), (4, 12, 4), (4, 7, 3), (4, 5, 5), (2, 9, 4),
+                                    (2, 16, 16), (3, 1, 1), (4, 2, 1), (3, 24, 12)])
+def test_ownership_every_element_exactly_once(d, n, bl):
+    p = plan((1,) + (n,) * d, [[(tuple(range(d)), 1.0)]], d=d)
+    ss.spinsum_plan_set_tile(p, bl)
+    ok, why = ss.spinsum_plan_check_ownership(p)
+    assert ok, why
+
+
+def test_lds_footprint_matches_eq11():
+    """Eq. 11: C_min = bl^d * m * x * 8 B with x = 2 d! blocks per thread.
+    The GPU form keeps one copy of the d! tiles of an orbit in LDS and
+    overwrites it in place, so an unpadded orbit occupies C_min / 2."""
+    for r in _counts()["cmin"]:
+        d, bl, kib = int(r["d"]), int(r["bl"]), int(r["kib"])
+        assert bl ** d * 1 * (2 * math.factorial(d)) * 8 == kib * 1024
+    # checkable sizes that fit the 160 KiB LDS
+    for d, bl in [(3, 8), (3, 6), (4, 3), (4, 2)]:
+        n = d * bl
+        p = plan((1,) + (n,) * d, [[(tuple(range(d)), 1.0)]], d=d,
+                 flags=ss.SPINSUM_FLAG_NO_LDS_PAD)
+        ss.spinsum_plan_set_tile(p, bl, lds_pad=0)
+        cmin = bl ** d * 1 * (2 * math.factorial(d)) * 8
+        assert ss.spinsum_plan_get_info(p)["lds_bytes"] == cmin // 2
+    # the paper's own choices (3D bl=16, 4D bl=8) do not fit one CU's LDS
+    for d, bl in [(3, 16), (4, 8)]:
+        n = d * bl
+        p = plan((1,) + (n,) * d, [[(tuple(range(d)), 1.0)]], d=d)
+        ss.spinsum_plan_set_tile(p, bl, lds_pad=0)
+        info = ss.spinsum_plan_get_info(p)
+        assert info["lds_bytes"] == bl ** d * math.factorial(d) * 8 and not info["fits_lds"]
+
+
+@pytest.mark.parametrize("name,bl,whole", [("3d_v16_o8", 8, True), ("3d_v64_o32_slab", 8, False),
+                                           ("4d_v24_o12_slab", 6, False), ("3d_v48_o24", 12, False)])
+def test_default_tiles_of_the_workloads(name, bl, whole):
+    w = workloads.WORKLOADS[name]
+    p = ss.spinsum_plan(w["shape"], w["group_first"], w["d"], [workloads.CONFIG_3D_ALPHA] if w["d"] == 3
+                        else [workloads.random_4d_alpha(1)], inplace=True, flags=HOST)
+    info = ss.spinsum_plan_get_info(p)
+    assert info["bl"] == bl
+    assert (info["norbits"] == 1) == whole
+    assert info["lds_bytes"] <= 160 * 1024
+    assert info["vector_width"] == 2
+    assert info["elems"] == int(np.prod(w["shape"]))
+
+
+def test_batched_plan_tables():
+    seed, blocks = workloads.batched_blocks()
+    shapes = [(v, v, v, o, o, o) for v, o in blocks]
+    p = ss.spinsum_plan_batched(shapes, 3, [workloads.CONFIG_3D_ALPHA], inplace=True, flags=HOST)
+    info = ss.spinsum_plan_get_info(p)
+    assert info["nblocks"] == 200
+    assert info["elems"] == sum(v ** 3 * o ** 3 for v, o in blocks)
+    assert info["lds_bytes"] <= 160 * 1024
+    for b in (0, 17, 199):
+        ok, why = ss.spinsum_plan_check_ownership(p, b)
+        assert ok, why
+
+
+def test_set_tile_rebuilds_and_rejects():
+    p = plan((3, 16, 16, 16), [workloads.CONFIG_3D_ALPHA])
+    for bl, norb in [(16, 1), (8, 4), (4, 20), (5, 20)]:
+        ss.spinsum_plan_set_tile(p, bl)
+        assert ss.spinsum_plan_get_info(p)["norbits"] == norb
+        ok, why = ss.spinsum_plan_check_ownership(p)
+        assert ok, why
+    with pytest.raises(ss.SpinSumError):
+        ss.spinsum_plan_set_tile(p, -3)
+
+
+def test_fp32_plan_vector_width():
+    p = plan((3, 16, 16, 16), [workloads.CONFIG_3D_ALPHA], dtype="f32")
+    assert ss.spinsum_plan_get_info(p)["vector_width"] == 4
+    q = plan((3, 6, 6, 6), [workloads.CONFIG_3D_ALPHA], dtype="f32")
+    assert ss.spinsum_plan_get_info(q)["vector_width"] == 2
+    r = plan((3, 5, 5, 5), [workloads.CONFIG_3D_ALPHA])
+    assert ss.spinsum_plan_get_info(r)["vector_width"] == 1
+
+
+@pytest.mark.parametrize("shape,d,tile,dtype", [
+    ((5, 8, 8, 8), 3, (8, 2), "f64"), ((7, 8, 8, 8), 3, (8, 4), "f32"),
+    ((9, 6, 6, 6), 3, (6, 4), "f32"), ((3, 5, 5, 5, 5), 4, (5, 2), "f64"),
+    ((6, 16, 16), 2, (16, 4), "f32"), ((4, 33, 33), 2, (8, 1), "f64"),
+    ((2, 32, 32, 32), 3, (8, 1), "f64"), ((2, 32, 32, 32), 3, (16, 1), "f32"),
+    ((2, 12, 12, 12, 12), 4, (6, 1), "f64"), ((2, 12, 12, 12, 12), 4, (4, 1), "f32"),
+    ((2, 24, 24, 24), 3, (12, 1), "f64"), ((2, 24, 24, 24), 3, (24, 1), "f32"),
+    ((3, 13, 13, 13), 3, (4, 1), "f64"), ((2, 12, 12, 12), 3, (5, 1), "f32"),
+])
+def test_kernel_addresses_replayed_on_host(shape, d, tile, dtype):
+    """The checker replays every load/combine/store address of every work
+    item (including a partial last item of whole cubes) with the kernels'
+    own index functions and checks bounds and consistency."""
+    for pad in (1, 0):
+        p = plan(shape, [[(tuple(range(d)), 1.0)]], d=d, dtype=dtype)
+        ss.spinsum_plan_set_tile(p, tile[0], cubes_per_wg=tile[1], lds_pad=pad)
+        ok, why = ss.spinsum_plan_check_ownership(p)
+        assert ok, why

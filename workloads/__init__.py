@@ -76,6 +76,11 @@ def _fill(out: torch.Tensor, seed: int, offset: int, kind: str) -> torch.Tensor:
     return out
 
 
+def fill_uniform(t: torch.Tensor, seed: int, offset: int = 0) -> torch.Tensor:
+    """Fill a contiguous tensor in place with the U(-1,1) stream."""
+    return _fill(t, seed, offset, "uniform")
+
+
 def uniform(shape: Sequence[int], seed: int, device="cpu", dtype=torch.float64,
             offset: int = 0) -> torch.Tensor:
     """U(-1,1) values for linear indices offset .. offset+numel-1.
