@@ -91,21 +91,20 @@ def cpu_baseline(seconds: float):
     cube = 32 ** 3
     threads = max(1, min(16, os.cpu_count() or 1))
 
-    def run(ncubes):
-        x = workloads.uniform_numpy(ncubes * cube, 1000).reshape(ncubes, 32, 32, 32)
+    # consecutive chunks of cubes of slab 0 until about `seconds` of CPU work
+    chunk = 1024
+    done, total = 0, 0.0
+    while total < seconds and done < 32768:
+        x = workloads.uniform_numpy(chunk * cube, 1000, offset=done * cube).reshape(chunk, 32, 32, 32)
         t0 = time.perf_counter()
         oracle.spinsum(x, workloads.CONFIG_3D_ALPHA, 1, 3, nthreads=threads)
-        return time.perf_counter() - t0
-
-    n0 = 2 * threads
-    t0 = run(n0)
-    n = int(max(n0, min(4096, n0 * seconds / max(t0, 1e-3))))
-    t = run(n)
-    elems = n * cube
-    return {"value": round(2 * elems * 8 / t / 1e9, 4), "unit": "GB/s", "cores": threads,
+        total += time.perf_counter() - t0
+        done += chunk
+    elems = done * cube
+    return {"value": round(2 * elems * 8 / total / 1e9, 4), "unit": "GB/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{n} spectator cubes (32^3, {elems} elements, fp64) of the v=64 o=32 slab 0, "
-                      f"long-double nested loops, {t:.1f} s"}
+            "sample": f"first {done} of the 32768 spectator cubes (32^3 each, {elems} elements, fp64) "
+                      f"of slab 0 of the v=64 o=32 in-place workload, {total:.1f} s of oracle time"}
 
 
 def main():
@@ -113,7 +112,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--forms", default="all", choices=["all", "none"])
+    ap.add_argument("--forms", default="all", choices=["all", "copy", "none"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--slabs", type=int, default=8)
@@ -181,6 +180,11 @@ def main():
     }
 
     forms = {}
+    if args.forms == "copy":
+        dst = torch.empty_like(big[0])
+        cms = timed(lambda: ss.spinsum_stream_copy(big[0], dst, stream), 2, stream)
+        forms["stream_copy_ceiling"] = form_entry(2 * big[0].numel() * 8, cms)
+        out["forms"] = forms
     if args.forms == "all":
         # achievable ceiling: plain copy of one slab with the same instructions
         dst = torch.empty_like(big[0])

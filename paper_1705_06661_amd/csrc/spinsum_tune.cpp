@@ -111,11 +111,10 @@ extern "C" spinsum_status spinsum_autotune(spinsum_plan_t P, void* in, void* out
   for (int m = 0; m < d; ++m) cube_bytes *= n;
   std::vector<spinsum_tile_t> cands;
   for (int pad = 1; pad >= 0; --pad) {
-    if (cube_bytes * 2 <= P->lds_limit) {
-      for (int cpw = 1; cpw <= 64; cpw *= 2) {
-        if (cpw * cube_bytes > 96 * 1024 || cpw > P->ncubes) break;
-        cands.push_back({n, cpw, 256, pad});
-      }
+    for (int cpw = 1; cpw <= 64; cpw *= 2) {
+      if (cpw * cube_bytes + 1024 > P->lds_limit || cpw > P->ncubes) break;
+      if (cpw > 1 && cpw * cube_bytes > 96 * 1024) break;
+      cands.push_back({n, cpw, 256, pad});
     }
     for (int bl = n - 1; bl >= 2; --bl) {
       if (n % bl != 0) continue;

@@ -1,0 +1,184 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times (run on an MI355X).
+
+At these sizes the oracle cannot take the whole tensor, so each test
+ * compares sampled spectator cubes with the oracle run on that cube alone
+   (a cube's output depends only on that cube); the input of a sampled cube
+   is regenerated on the host from the counter-based generator, so the
+   multi-GB input is never copied back;
+ * checks on every cube the sum invariant sum(Out) = (sum of coefficients)
+   * sum(In) (exact in exact arithmetic), which fails for any cube that is
+   skipped, written twice or mixed with another one.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+ss = pytest.importorskip("paper_1705_06661_amd")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+DEV = torch.device("cuda:0")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def sample_cubes(ncubes, k, seed):
+    rng = np.random.default_rng(seed)
+    picks = set(int(c) for c in rng.choice(ncubes, size=min(k, ncubes), replace=False))
+    picks.update({0, ncubes - 1})
+    return sorted(picks)
+
+
+def check_sampled(out, seed, stages, d, cubes, tol, in_dtype=torch.float64, adjoint=False):
+    """out: GPU tensor viewed as (ncubes, n^d); input of cube c = the
+    generator stream at offset c * n^d, rounded to in_dtype."""
+    n = round(out.shape[-1] ** (1.0 / d))
+    cube = n ** d
+    worst = 0.0
+    for c in cubes:
+        x = workloads.uniform_numpy(cube, seed, offset=c * cube)
+        if in_dtype == torch.float32:
+            x = x.astype(np.float32).astype(np.float64)
+        x = x.reshape((1,) + (n,) * d)
+        if adjoint:
+            ref = oracle.spinsum_chain_adjoint(x, stages, 1, d)
+        else:
+            ref = oracle.spinsum_chain(x, stages, 1, d)
+        got = out[c].to("cpu", torch.float64).numpy().reshape(ref.shape)
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        worst = max(worst, float(err))
+    _say(f"  sampled {len(cubes)} cubes, worst normwise error {worst:.3e}")
+    assert worst <= tol
+
+
+def check_cube_sums(out2d, in_sums, coef_sum, rel):
+    """|sum(Out_c) - coef_sum * sum(In_c)| <= rel * sum|Out_c| for every cube c."""
+    out_sums = out2d.sum(dim=1, dtype=torch.float64)
+    abs_sums = out2d.abs().sum(dim=1, dtype=torch.float64)
+    bad = (out_sums - coef_sum * in_sums).abs() > rel * abs_sums + 1e-300
+    nbad = int(bad.sum())
+    _say(f"  cube sums checked on {out2d.shape[0]} cubes, violations {nbad}")
+    assert nbad == 0
+
+
+def expanded_sum(stages):
+    return float(np.prod([sum(a for _, a in s) for s in stages]))
+
+
+@pytest.mark.parametrize("form", ["expanded", "factored_chained", "table2_1_chained"])
+def test_3d_v64_o32_slab_inplace(form):
+    w = workloads.WORKLOADS["3d_v64_o32_slab"]
+    shape = w["shape"]
+    _say("case 3d_v64_o32_slab", form, shape)
+    if form == "expanded":
+        stages, flags = [workloads.CONFIG_3D_ALPHA], 0
+    elif form == "factored_chained":
+        stages, flags = workloads.FACTORED_PIJ_PJK, ss.SPINSUM_FLAG_CHAIN_STAGES
+    else:
+        stages, flags = workloads.table2_case(1)[1], ss.SPINSUM_FLAG_CHAIN_STAGES
+    seed = 1000
+    x = workloads.uniform(shape, seed, device=DEV)
+    cube = 32 ** 3
+    x2 = x.view(-1, cube)
+    in_sums = x2.sum(dim=1, dtype=torch.float64)
+    p = ss.spinsum_plan(shape, 3, 3, stages, inplace=True, flags=flags)
+    ss.spinsum_exec(p, x, x)
+    torch.cuda.synchronize()
+    check_sampled(x2, seed, stages, 3, sample_cubes(x2.shape[0], 48, 1), 1e-14)
+    check_cube_sums(x2, in_sums, expanded_sum(stages), 1e-12)
+
+
+def test_4d_v24_o12_slab_inplace():
+    w = workloads.WORKLOADS["4d_v24_o12_slab"]
+    shape = w["shape"]
+    _say("case 4d_v24_o12_slab", shape)
+    a = workloads.random_4d_alpha(7)
+    seed = 2000
+    x = workloads.uniform(shape, seed, device=DEV)
+    x2 = x.view(-1, 12 ** 4)
+    in_sums = x2.sum(dim=1, dtype=torch.float64)
+    p = ss.spinsum_plan(shape, 4, 4, [a], inplace=True)
+    ss.spinsum_exec(p, x, x)
+    torch.cuda.synchronize()
+    check_sampled(x2, seed, [a], 4, sample_cubes(x2.shape[0], 32, 2), 1e-14)
+    check_cube_sums(x2, in_sums, expanded_sum([a]), 1e-12)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_3d_v48_o24_forward_and_adjoint(dtype):
+    w = workloads.WORKLOADS["3d_v48_o24"]
+    shape = w["shape"]
+    _say("case 3d_v48_o24", dtype)
+    stages = workloads.FACTORED_PIJ_PJK
+    tol = 1e-14 if dtype == torch.float64 else 2e-6
+    seed = 4000
+    x = workloads.uniform(shape, seed, device=DEV, dtype=dtype)
+    y = torch.empty_like(x)
+    p = ss.spinsum_plan(shape, 3, 3, stages, dtype=dtype)
+    ss.spinsum_exec(p, x, y)
+    torch.cuda.synchronize()
+    cube = 24 ** 3
+    cubes = sample_cubes(x.numel() // cube, 32, 3)
+    check_sampled(y.view(-1, cube), seed, stages, 3, cubes, tol, in_dtype=dtype)
+    in_sums = x.view(-1, cube).sum(dim=1, dtype=torch.float64)
+    check_cube_sums(y.view(-1, cube).to(torch.float64) if dtype == torch.float32 else y.view(-1, cube),
+                    in_sums, expanded_sum(stages), 1e-12 if dtype == torch.float64 else 1e-5)
+    del y
+    # backward: grad_in = S^T g with g the same stream (seed), adjoint form
+    g = x
+    gi = torch.empty_like(g)
+    ss.spinsum_adjoint(p, g, gi)
+    torch.cuda.synchronize()
+    check_sampled(gi.view(-1, cube), seed, stages, 3, cubes, tol, in_dtype=dtype, adjoint=True)
+
+
+def test_batched_power_law_blocks():
+    seed, blocks = workloads.batched_blocks()
+    shapes = [(v, v, v, o, o, o) for v, o in blocks]
+    _say("case batched 200 blocks, block seed", seed)
+    alpha = [workloads.CONFIG_3D_ALPHA]
+    xs = [workloads.uniform(s, 3000 + k, device=DEV) for k, s in enumerate(shapes)]
+    ref_out = []
+    for s, x in zip(shapes, xs):
+        y = torch.empty_like(x)
+        ss.spinsum_exec(ss.spinsum_plan(s, 3, 3, alpha), x, y)
+        ref_out.append(y)
+    bp = ss.spinsum_plan_batched(shapes, 3, alpha, inplace=True)
+    graph = ss.spinsum_graph_create(bp, xs, xs)
+    ss.spinsum_graph_launch(graph)
+    torch.cuda.synchronize()
+    for k, (x, y) in enumerate(zip(xs, ref_out)):
+        assert torch.equal(x, y), k
+    for k in (0, 1, 57, 123, 199):
+        v, o = blocks[k]
+        check_sampled(xs[k].view(-1, o ** 3), 3000 + k, alpha, 3,
+                      sample_cubes(v ** 3, 8, k), 1e-14)
+
+
+@pytest.mark.slow
+def test_3d_v64_o32_whole_tensor_one_launch():
+    """All 8.6G elements (68.7 GB) in one launch: element offsets beyond 2^32."""
+    shape = (64, 64, 64, 32, 32, 32)
+    _say("case whole v64 o32 tensor", shape)
+    seed = 1100
+    x = workloads.uniform(shape, seed, device=DEV)
+    cube = 32 ** 3
+    x2 = x.view(-1, cube)
+    in_sums = x2.sum(dim=1, dtype=torch.float64)
+    p = ss.spinsum_plan(shape, 3, 3, [workloads.CONFIG_3D_ALPHA], inplace=True)
+    ss.spinsum_exec(p, x, x)
+    torch.cuda.synchronize()
+    ncubes = x2.shape[0]
+    cubes = sample_cubes(ncubes, 24, 4) + [ncubes // 2, (1 << 31) // cube, (1 << 32) // cube + 1]
+    check_sampled(x2, seed, [workloads.CONFIG_3D_ALPHA], 3, sorted(set(cubes)), 1e-14)
+    check_cube_sums(x2, in_sums, 0.0, 1e-12)
+    del x, x2
+    torch.cuda.empty_cache()
