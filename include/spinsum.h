@@ -64,26 +64,38 @@ typedef enum { SPINSUM_F64 = 0, SPINSUM_F32 = 1 } spinsum_dtype;
 /* Plan flags (bitwise or). */
 #define SPINSUM_FLAG_HOST_ONLY 0x1u      /* build host tables only, for inspection: exec is
                                             refused and tiles larger than a CU's LDS are kept */
-#define SPINSUM_FLAG_NO_NT_STORES 0x2u   /* cached stores instead of non-temporal ones (Sec. 4.6.3 ablation) */
+#define SPINSUM_FLAG_NO_NT_STORES 0x2u   /* cached stores instead of non-temporal ones (Sec. 4.6.3
+                                            ablation; implies the one-shot kernel) */
 #define SPINSUM_FLAG_CHAIN_STAGES 0x4u   /* apply the stages one after another in registers
                                             instead of their pre-multiplied product (Def. 4)  */
 #define SPINSUM_FLAG_NO_XCD_REMAP 0x8u   /* plain workgroup order (ablation of XCD grouping) */
 #define SPINSUM_FLAG_REVERSE_ORDER 0x10u /* process work items in reverse order (ownership test) */
 #define SPINSUM_FLAG_NO_LDS_PAD 0x20u    /* unpadded LDS tiles (bank-conflict ablation) */
+#define SPINSUM_FLAG_NO_DIRECT_LDS 0x40u /* never use the direct-LDS variant (ablation)  */
 
 typedef struct spinsum_plan_s* spinsum_plan_t;
 typedef struct spinsum_graph_s* spinsum_graph_t;
 
+/* Kernel variants (spinsum_tile_t.variant). */
+#define SPINSUM_VARIANT_AUTO 0
+#define SPINSUM_VARIANT_DIRECT_LDS 1   /* one item per workgroup, loads straight into LDS
+                                          (16-byte rows only; unpadded LDS)               */
+#define SPINSUM_VARIANT_REG_PIPELINE 2 /* persistent workgroups, next item prefetched into
+                                          registers while the current one is processed   */
+#define SPINSUM_VARIANT_REG_ONESHOT 3  /* one item per workgroup, loads through registers */
+
 /* Tile configuration (the blocking of Alg. 5a/5b, Sec. 4.5).
  * bl: tile edge along every group axis, 1 <= bl <= N; bl == N processes whole
  *     cubes.  cubes_per_wg: whole-cube mode only, spectator cubes per
- *     workgroup (>= 1).  threads: workgroup size (256).  0 in any field means
- *     "choose". */
+ *     workgroup (>= 1).  threads: workgroup size (256).  lds_pad: 1 = odd
+ *     LDS strides (register variants only).  variant: SPINSUM_VARIANT_*.
+ *     0 in bl / cubes_per_wg / threads / variant means "choose". */
 typedef struct {
   int bl;
   int cubes_per_wg;
   int threads;
   int lds_pad;
+  int variant;
 } spinsum_tile_t;
 
 typedef struct {
@@ -93,12 +105,14 @@ typedef struct {
   int64_t elems;         /* total elements                               */
   int nstages;           /* stages after canonicalisation                */
   int nterms_expanded;   /* distinct permutations of the expanded sum    */
-  int bl, nb, norbits, cubes_per_wg, threads, max_tiles;
+  int bl, nb, norbits, cubes_per_wg, threads, max_tiles, variant, lds_pad;
   int64_t lds_bytes;     /* LDS per workgroup                            */
   int64_t nitems;        /* workgroup work items per exec                */
   int nblocks;           /* 1, or the batch size                         */
   int dtype, inplace, vector_width, ragged;
   int fits_lds;          /* 1 if the largest work item fits the LDS of a CU */
+  int chunks_per_thread; /* 16-byte loads per thread for the largest item */
+  int64_t rep_lds_bytes; /* LDS for the element-orbit representatives      */
 } spinsum_plan_info_t;
 
 /* Create a plan for Out = S_K(...S_1(In)) (Def. 3-4; in-place: Sec. 4.6.5).

@@ -53,11 +53,17 @@ SPINSUM_FLAG_CHAIN_STAGES = 0x4
 SPINSUM_FLAG_NO_XCD_REMAP = 0x8
 SPINSUM_FLAG_REVERSE_ORDER = 0x10
 SPINSUM_FLAG_NO_LDS_PAD = 0x20
+SPINSUM_FLAG_NO_DIRECT_LDS = 0x40
+
+SPINSUM_VARIANT_AUTO = 0
+SPINSUM_VARIANT_DIRECT_LDS = 1
+SPINSUM_VARIANT_REG_PIPELINE = 2
+SPINSUM_VARIANT_REG_ONESHOT = 3
 
 
 class _Tile(ctypes.Structure):
     _fields_ = [("bl", ctypes.c_int), ("cubes_per_wg", ctypes.c_int),
-                ("threads", ctypes.c_int), ("lds_pad", ctypes.c_int)]
+                ("threads", ctypes.c_int), ("lds_pad", ctypes.c_int), ("variant", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -65,11 +71,13 @@ class _Info(ctypes.Structure):
                 ("elems", ctypes.c_int64), ("nstages", ctypes.c_int),
                 ("nterms_expanded", ctypes.c_int), ("bl", ctypes.c_int), ("nb", ctypes.c_int),
                 ("norbits", ctypes.c_int), ("cubes_per_wg", ctypes.c_int),
-                ("threads", ctypes.c_int), ("max_tiles", ctypes.c_int),
+                ("threads", ctypes.c_int), ("max_tiles", ctypes.c_int), ("variant", ctypes.c_int),
+                ("lds_pad", ctypes.c_int),
                 ("lds_bytes", ctypes.c_int64), ("nitems", ctypes.c_int64),
                 ("nblocks", ctypes.c_int), ("dtype", ctypes.c_int), ("inplace", ctypes.c_int),
                 ("vector_width", ctypes.c_int), ("ragged", ctypes.c_int),
-                ("fits_lds", ctypes.c_int)]
+                ("fits_lds", ctypes.c_int), ("chunks_per_thread", ctypes.c_int),
+                ("rep_lds_bytes", ctypes.c_int64)]
 
 
 _vp = ctypes.c_void_p
@@ -215,8 +223,8 @@ def spinsum_plan_batched(shapes: Sequence[Sequence[int]], d: int, stages, dtype=
 
 
 def spinsum_plan_set_tile(plan: Plan, bl: int, cubes_per_wg: int = 1, lds_pad: int = 1,
-                          threads: int = 256):
-    t = _Tile(int(bl), int(cubes_per_wg), int(threads), int(lds_pad))
+                          threads: int = 256, variant: int = SPINSUM_VARIANT_AUTO):
+    t = _Tile(int(bl), int(cubes_per_wg), int(threads), int(lds_pad), int(variant))
     _check(_c_set_tile(plan._h, ctypes.byref(t)), "spinsum_plan_set_tile", plan)
 
 
@@ -362,7 +370,7 @@ def spinsum_autotune(plan: Plan, inp: torch.Tensor, out: torch.Tensor, stream=No
     _check(_c_autotune(plan._h, a, b, _stream(stream), cp, ctypes.byref(best), ctypes.byref(ms)),
            "spinsum_autotune", plan)
     return {"bl": best.bl, "cubes_per_wg": best.cubes_per_wg, "threads": best.threads,
-            "lds_pad": best.lds_pad}, float(ms.value)
+            "lds_pad": best.lds_pad, "variant": best.variant}, float(ms.value)
 
 
 def spinsum_stream_copy(inp: torch.Tensor, out: torch.Tensor, stream=None):

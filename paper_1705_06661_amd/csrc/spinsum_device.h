@@ -1,0 +1,669 @@
+// spinsum_kernels.hip -- gfx950 kernels of libspinsum and the exec entry
+// points of the C-ABI.
+//
+// A work item is a run of whole spectator cubes, or one tile orbit
+// {sigma . B} of one cube (the macro-kernel of Alg. 5b/6).  A workgroup
+//   1. loads every tile of the item from HBM once, with 16-byte vector loads
+//      along the fastest (stride-one) axis, into LDS (padded strides);
+//   2. combines every element orbit in registers: each thread takes
+//      representatives x, reads v_sigma = tile[sigma . x] for all sigma in
+//      S_d, forms w_tau = sum_sigma a(tau^-1 o sigma) v_sigma (a = the
+//      coefficient of each permutation in the operator, held in scalar
+//      registers; with stage chaining the stages are applied one after the
+//      other) and writes w_tau to tile[tau . x];
+//   3. stores the tiles back once with 16-byte stores, non-temporal by
+//      default (Sec. 4.6.3), in place (Sec. 4.6.5) or to the output.
+// Every element belongs to exactly one item, and inside an item to the
+// element orbit of exactly one representative, so in-place needs only the
+// workgroup barriers.
+//
+// The main kernel (k_pipe) is persistent and software-pipelined: while an
+// item is combined and stored, the loads of the workgroup's next item are
+// already in flight in registers.  Items are grouped per XCD: the workgroups
+// of XCD x (blockIdx % 8 == x) sweep a contiguous range of items, so the
+// tile orbits of one cube -- which share 128-byte lines along the fastest
+// axis -- meet in the same L2.  k_exec is the one-shot form (one item per
+// workgroup), used for items too large for the register prefetch buffer and
+// as an ablation.  The work is HBM-bound (0.75 flop/byte in 3D, 3 in 4D):
+// no matrix cores are used.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "spinsum_plan_host.h"
+
+namespace spinsum {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kUnroll = 4;
+
+template <int D>
+struct Fact {
+  static constexpr int v = D * Fact<D - 1>::v;
+};
+template <>
+struct Fact<0> {
+  static constexpr int v = 1;
+};
+
+template <typename T, int VW>
+struct VecT;
+template <>
+struct VecT<double, 1> {
+  typedef double type;
+};
+template <>
+struct VecT<double, 2> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct VecT<float, 1> {
+  typedef float type;
+};
+template <>
+struct VecT<float, 2> {
+  typedef float type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct VecT<float, 4> {
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+
+template <typename V, typename T, int VW>
+__device__ __forceinline__ T vget(const V& v, int k) {
+  if constexpr (VW == 1)
+    return v;
+  else
+    return v[k];
+}
+template <typename V, typename T, int VW>
+__device__ __forceinline__ void vset(V& v, int k, T x) {
+  if constexpr (VW == 1)
+    v = x;
+  else
+    v[k] = x;
+}
+
+// Uniform tables (orbit descriptors, coefficients, batch items) are read
+// through the constant address space: the compiler then uses scalar loads,
+// which neither take vector registers nor wait behind the in-flight tile
+// prefetch (vector-memory loads complete in order).
+template <typename X>
+using cptr = const __attribute__((address_space(4))) X*;
+
+template <typename X>
+__device__ __forceinline__ cptr<X> as_const(const X* p) {
+  return (cptr<X>)(p);
+}
+
+__device__ __forceinline__ FastDiv load_fd(const __attribute__((address_space(4))) FastDiv& f) {
+  FastDiv r;
+  r.div = f.div;
+  r.mul = f.mul;
+  r.shift = f.shift;
+  r.pad = 0;
+  return r;
+}
+
+__device__ __forceinline__ Geom load_geom(const __attribute__((address_space(4))) Geom& s) {
+  Geom g;
+  g.cube_elems = s.cube_elems;
+  g.ncubes = s.ncubes;
+  g.n = s.n;
+  g.bl = s.bl;
+  g.norbits = s.norbits;
+  g.cpw = s.cpw;
+#pragma unroll
+  for (int m = 0; m < kMaxD; ++m) {
+    g.gst[m] = s.gst[m];
+    g.lst[m] = s.lst[m];
+  }
+  g.ts = s.ts;
+  g.cube_lds = s.cube_lds;
+  g.rows = s.rows;
+  g.vpr = s.vpr;
+  g.fd_vpr = load_fd(s.fd_vpr);
+  g.fd_rows = load_fd(s.fd_rows);
+  g.fd_bl = load_fd(s.fd_bl);
+  g.fd_norbits = load_fd(s.fd_norbits);
+  return g;
+}
+
+template <typename T>
+struct ExecArgs {
+  const T* in;
+  T* out;
+  const OrbitDev* orbits;
+  const uint32_t* reps;
+  const T* coef;    // coefficient vector(s), d! per stage
+  Geom g;
+  int64_t nitems;
+  int64_t xcd_per;  // > 0: items grouped per XCD (items per XCD range)
+  int32_t nstages;  // stages applied one after the other (chain mode)
+  int32_t reverse;
+  int32_t lds_tile_bytes;  // start of the representative copy in LDS (k_pipe)
+  int32_t pad;
+};
+
+template <typename T>
+struct BatchArgs {
+  const T* const* in;
+  T* const* out;
+  const OrbitDev* orbits;
+  const uint32_t* reps;
+  const T* coef;
+  const BatchBlock* blocks;
+  const BatchItem* items;
+  int64_t nitems;
+};
+
+// w_tau = sum_sigma a(tau^-1 o sigma) v_sigma, sigma in lexicographic
+// order, every index a compile-time constant
+template <typename T, int D, int TAU, int... S>
+__device__ __forceinline__ T orbit_row(const T* a, const T* v, std::integer_sequence<int, S...>) {
+  T acc = T(0);
+  ((acc = __builtin_fma(a[GinvMul<D, TAU, S>::value], v[S], acc)), ...);
+  return acc;
+}
+
+template <typename T, int D, int... TAU>
+__device__ __forceinline__ void orbit_rows(const T* a, const T* v, T* w,
+                                           std::integer_sequence<int, TAU...>) {
+  ((w[TAU] = orbit_row<T, D, TAU>(a, v, std::make_integer_sequence<int, Fact<D>::v>{})), ...);
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void orbit_product(const T (&a)[Fact<D>::v], const T (&v)[Fact<D>::v],
+                                              T (&w)[Fact<D>::v]) {
+  orbit_rows<T, D>(a, v, w, std::make_integer_sequence<int, Fact<D>::v>{});
+}
+
+// 2. combine every element orbit of the item in LDS
+// rp: the item's representatives (global memory, or an LDS copy)
+template <typename T, int D, bool CHAIN>
+__device__ __forceinline__ void combine_item(const Geom& g, cptr<OrbitDev> od,
+                                             const uint32_t* rp, cptr<T> coef, int nstages,
+                                             int ncub, T* lds) {
+  constexpr int DF = Fact<D>::v;
+  int32_t sb[DF];
+#pragma unroll
+  for (int r = 0; r < DF; ++r) sb[r] = od->slot_base[r];
+  T a[DF];
+  if constexpr (!CHAIN) {
+#pragma unroll
+    for (int r = 0; r < DF; ++r) a[r] = coef[r];
+  }
+  const uint32_t rep_cnt = (uint32_t)od->rep_cnt;
+  const uint32_t nrep = (uint32_t)ncub * rep_cnt;
+  const FastDiv fdr = load_fd(od->fd_rep);
+  for (uint32_t i = threadIdx.x; i < nrep; i += kThreads) {
+    uint32_t ci = (ncub == 1) ? 0u : fdiv(i, fdr);
+    uint32_t ri = i - ci * rep_cnt;
+    uint32_t pk = rp[ri];
+    int l[D];
+#pragma unroll
+    for (int m = 0; m < D; ++m) l[m] = (int)((pk >> (8 * m)) & 255u);
+    const int base = (int)ci * g.cube_lds;
+    int addr[DF];
+    T v[DF];
+    T w[DF];
+    orbit_addrs<D>(g, base, sb, l, addr, std::make_integer_sequence<int, DF>{});
+#pragma unroll
+    for (int r = 0; r < DF; ++r) v[r] = lds[addr[r]];
+    if constexpr (!CHAIN) {
+      orbit_product<T, D>(a, v, w);
+    } else {
+      for (int k = 0; k < nstages; ++k) {
+#pragma unroll
+        for (int r = 0; r < DF; ++r) a[r] = coef[k * DF + r];
+        orbit_product<T, D>(a, v, w);
+#pragma unroll
+        for (int r = 0; r < DF; ++r) v[r] = w[r];
+      }
+#pragma unroll
+      for (int r = 0; r < DF; ++r) w[r] = v[r];
+    }
+#pragma unroll
+    for (int r = 0; r < DF; ++r) lds[addr[r]] = w[r];
+  }
+}
+
+__device__ __forceinline__ void stage_tinfo(int32_t* tinfo, const OrbitDev* __restrict__ od) {
+  const int nt = od->ntiles;
+  if ((int)threadIdx.x < nt) {
+    tinfo[threadIdx.x] = od->tile_off[threadIdx.x];
+    tinfo[kMaxDF + threadIdx.x] = od->tile_ext[threadIdx.x];
+  }
+}
+
+// 1a. issue the loads of an item into registers (no wait)
+template <typename T, int D, int VW, int MAXC>
+__device__ __forceinline__ void issue_loads(const Geom& g, const int32_t* tinfo, int ntiles,
+                                            bool ragged, uint32_t nchunks, const T* sbase,
+                                            typename VecT<T, VW>::type (&buf)[MAXC],
+                                            int (&lo)[MAXC]) {
+  typedef typename VecT<T, VW>::type V;
+#pragma unroll
+  for (int u = 0; u < MAXC; ++u) {
+    uint32_t c = threadIdx.x + u * kThreads;
+    int go = 0;
+    int l = 0;
+    bool ok = (c < nchunks) && chunk_addr<D, VW>(g, c, ntiles, tinfo, tinfo + kMaxDF, ragged, &go, &l);
+    lo[u] = ok ? l : -1;
+    if (ok) buf[u] = *reinterpret_cast<const V*>(sbase + go);
+  }
+}
+
+// 1b. write the loaded registers to LDS (waits for the loads)
+template <typename T, int VW, int MAXC>
+__device__ __forceinline__ void fill_lds(const typename VecT<T, VW>::type (&buf)[MAXC],
+                                         const int (&lo)[MAXC], T* lds) {
+  typedef typename VecT<T, VW>::type V;
+#pragma unroll
+  for (int u = 0; u < MAXC; ++u)
+    if (lo[u] >= 0) {
+#pragma unroll
+      for (int k = 0; k < VW; ++k) lds[lo[u] + k] = vget<V, T, VW>(buf[u], k);
+    }
+}
+
+// 3. store every tile of the item
+template <typename T, int D, int VW, bool NTS>
+__device__ __forceinline__ void store_item(const Geom& g, const int32_t* tinfo, int ntiles,
+                                           bool ragged, uint32_t nchunks, T* dbase,
+                                           const T* lds) {
+  typedef typename VecT<T, VW>::type V;
+  for (uint32_t c0 = threadIdx.x; c0 < nchunks; c0 += kUnroll * kThreads) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      uint32_t c = c0 + u * kThreads;
+      int go = 0;
+      int lo = 0;
+      bool ok = (c < nchunks) && chunk_addr<D, VW>(g, c, ntiles, tinfo, tinfo + kMaxDF, ragged, &go, &lo);
+      if (ok) {
+        V val;
+#pragma unroll
+        for (int k = 0; k < VW; ++k) vset<V, T, VW>(val, k, lds[lo + k]);
+        V* p = reinterpret_cast<V*>(dbase + go);
+        if constexpr (NTS)
+          __builtin_nontemporal_store(val, p);
+        else
+          *p = val;
+      }
+    }
+  }
+}
+
+// item index -> (first cube, orbit, cube count)
+__device__ __forceinline__ void decode_item(const Geom& g, int64_t item, int64_t* cube0,
+                                            int* orbit, int* ncub) {
+  if (g.bl == g.n) {
+    *cube0 = item * g.cpw;
+    *orbit = 0;
+    int64_t left = g.ncubes - *cube0;
+    *ncub = (int)(left < g.cpw ? left : g.cpw);
+  } else {
+    uint32_t q = fdiv((uint32_t)item, g.fd_norbits);
+    *cube0 = q;
+    *orbit = (int)((uint32_t)item - q * (uint32_t)g.norbits);
+    *ncub = 1;
+  }
+}
+
+// One-shot: one item per workgroup.
+template <typename T, int D, int VW, bool CHAIN, bool NTS>
+__global__ void __launch_bounds__(kThreads) k_exec(const ExecArgs<T> a) {
+  typedef typename VecT<T, VW>::type V;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __shared__ int32_t tinfo[2 * kMaxDF];
+  T* lds = reinterpret_cast<T*>(smem);
+  int64_t item;
+  if (a.xcd_per > 0)
+    item = (int64_t)(blockIdx.x & 7u) * a.xcd_per + (int64_t)(blockIdx.x >> 3);
+  else
+    item = blockIdx.x;
+  if (item >= a.nitems) return;
+  if (a.reverse) item = a.nitems - 1 - item;
+  const Geom& g = a.g;
+  int64_t cube0;
+  int orbit, ncub;
+  decode_item(g, item, &cube0, &orbit, &ncub);
+  const OrbitDev* od = a.orbits + orbit;
+  cptr<OrbitDev> cod = as_const(od);
+  stage_tinfo(tinfo, od);
+  __syncthreads();
+  const int ntiles = cod->ntiles;
+  const bool ragged = cod->ragged != 0;
+  const uint32_t nchunks = (uint32_t)ncub * (uint32_t)ntiles * (uint32_t)g.rows * (uint32_t)g.vpr;
+  const T* sbase = a.in + cube0 * g.cube_elems;
+  for (uint32_t c0 = 0; c0 < nchunks; c0 += kUnroll * kThreads) {
+    V buf[kUnroll];
+    int lo[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      uint32_t c = c0 + threadIdx.x + u * kThreads;
+      int go = 0;
+      int l = 0;
+      bool ok = (c < nchunks) && chunk_addr<D, VW>(g, c, ntiles, tinfo, tinfo + kMaxDF, ragged, &go, &l);
+      lo[u] = ok ? l : -1;
+      if (ok) buf[u] = *reinterpret_cast<const V*>(sbase + go);
+    }
+    fill_lds<T, VW, kUnroll>(buf, lo, lds);
+  }
+  __syncthreads();
+  combine_item<T, D, CHAIN>(g, cod, a.reps + cod->rep_off, as_const(a.coef), a.nstages, ncub, lds);
+  __syncthreads();
+  store_item<T, D, VW, NTS>(g, tinfo, ntiles, ragged, nchunks, a.out + cube0 * g.cube_elems, lds);
+}
+
+// One-shot with direct global->LDS loads (global_load_lds_dwordx4, 16 bytes
+// per lane, no register staging): every load of the item is in flight at
+// once.  LDS holds the tiles densely in chunk order -- tile t at t * ts,
+// chunk c of a tile at c * VW -- which is the unpadded tile layout, so the
+// planner builds this variant's tables with lds_pad = 0.  Tiles of a tile
+// orbit, or the cubes of a whole-cube item, are visited with a uniform loop
+// so that their base offsets come from scalar loads.
+template <typename T, int D, bool CHAIN>
+__global__ void __launch_bounds__(kThreads) k_lds(const ExecArgs<T> a) {
+  constexpr int VW = 16 / sizeof(T);
+  typedef typename VecT<T, VW>::type V;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  T* lds = reinterpret_cast<T*>(smem);
+  int64_t item;
+  if (a.xcd_per > 0)
+    item = (int64_t)(blockIdx.x & 7u) * a.xcd_per + (int64_t)(blockIdx.x >> 3);
+  else
+    item = blockIdx.x;
+  if (item >= a.nitems) return;
+  if (a.reverse) item = a.nitems - 1 - item;
+  const Geom& g = a.g;
+  int64_t cube0;
+  int orbit, ncub;
+  decode_item(g, item, &cube0, &orbit, &ncub);
+  const cptr<OrbitDev> od = as_const(a.orbits + orbit);
+  const bool whole = (g.bl == g.n);
+  const int ntl = whole ? ncub : od->ntiles;
+  const bool ragged = od->ragged != 0;
+  const uint32_t cpt = (uint32_t)g.rows * (uint32_t)g.vpr;  // chunks per full tile
+  const T* src = a.in + cube0 * g.cube_elems;
+  T* dst = a.out + cube0 * g.cube_elems;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t wave_bytes = (tid >> 6) * 1024u;
+  // per-lane position of chunk c inside a tile: offset and local coordinates
+  auto chunk_in_tile = [&](uint32_t c, int ext, bool* ok) -> int {
+    uint32_t q = fdiv(c, g.fd_vpr);
+    int l[D];
+    l[D - 1] = (int)(c - q * (uint32_t)g.vpr) * VW;
+    if constexpr (D == 2) {
+      l[0] = (int)q;
+    } else {
+      uint32_t r = q;
+#pragma unroll
+      for (int m = D - 2; m >= 1; --m) {
+        uint32_t qq = fdiv(r, g.fd_bl);
+        l[m] = (int)(r - qq * (uint32_t)g.bl);
+        r = qq;
+      }
+      l[0] = (int)r;
+    }
+    bool in = c < cpt;
+    if (ragged) {
+#pragma unroll
+      for (int m = 0; m < D; ++m) in = in && (l[m] < ((ext >> (8 * m)) & 255));
+    }
+    *ok = in;
+    int off = 0;
+#pragma unroll
+    for (int m = 0; m < D; ++m) off += l[m] * g.gst[m];
+    return off;
+  };
+  // 1. loads straight into LDS
+  for (int t = 0; t < ntl; ++t) {
+    const int toff = whole ? t * (int)g.cube_elems : od->tile_off[t];
+    const int text = whole ? 0 : od->tile_ext[t];
+    for (uint32_t c0 = 0; c0 < cpt; c0 += kThreads) {
+      bool ok;
+      const int off = chunk_in_tile(c0 + tid, text, &ok);
+      const uint32_t lbyte = (uint32_t)(t * g.ts + (int)c0 * VW) * (uint32_t)sizeof(T) + wave_bytes;
+      if (ok)
+        __builtin_amdgcn_global_load_lds(
+            (const void*)(src + toff + off),
+            (__attribute__((address_space(3))) void*)(smem + lbyte), 16, 0, 0);
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the tiles are in LDS
+  __syncthreads();
+  // 2. combine
+  combine_item<T, D, CHAIN>(g, od, a.reps + od->rep_off, as_const(a.coef), a.nstages, ncub, lds);
+  __syncthreads();
+  // 3. store
+  for (int t = 0; t < ntl; ++t) {
+    const int toff = whole ? t * (int)g.cube_elems : od->tile_off[t];
+    const int text = whole ? 0 : od->tile_ext[t];
+    for (uint32_t c0 = 0; c0 < cpt; c0 += kThreads) {
+      bool ok;
+      const uint32_t c = c0 + tid;
+      const int off = chunk_in_tile(c, text, &ok);
+      if (ok) {
+        const V val = *reinterpret_cast<const V*>(lds + t * g.ts + (int)c * VW);
+        __builtin_nontemporal_store(val, reinterpret_cast<V*>(dst + toff + off));
+      }
+    }
+  }
+}
+
+// Persistent, software-pipelined: the loads of the next item are in flight
+// while the current item is combined and stored.  gridDim.x is a multiple of
+// 8.  Per item:
+//   A. stage the next item's tile table and this item's representatives in
+//      LDS, wait for this item's tiles and write them to LDS;   barrier
+//   B. issue the loads of the next item (registers, no wait)
+//   C. combine this item in LDS (LDS and scalar loads only); barrier
+//   D. store this item;                                       barrier
+// LDS: [tiles | representatives (g.rep_lds entries)].
+template <typename T, int D, int VW, bool CHAIN, int MAXC>
+__global__ void __launch_bounds__(kThreads) k_pipe(const ExecArgs<T> a) {
+  typedef typename VecT<T, VW>::type V;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __shared__ int32_t tinfo[2][2 * kMaxDF];
+  T* lds = reinterpret_cast<T*>(smem);
+  uint32_t* rep_lds = reinterpret_cast<uint32_t*>(smem + (size_t)a.lds_tile_bytes);
+  const Geom& g = a.g;
+  const int64_t x = blockIdx.x & 7u;
+  const int64_t nj = gridDim.x >> 3;
+  auto item_at = [&](int64_t k) -> int64_t {
+    int64_t it;
+    if (a.xcd_per > 0) {
+      int64_t L = (int64_t)(blockIdx.x >> 3) + k * nj;
+      if (L >= a.xcd_per) return -1;
+      it = x * a.xcd_per + L;
+    } else {
+      it = (int64_t)blockIdx.x + k * (int64_t)gridDim.x;
+    }
+    if (it >= a.nitems) return -1;
+    return a.reverse ? a.nitems - 1 - it : it;
+  };
+  const cptr<T> coef = as_const(a.coef);
+  int64_t k = 0;
+  int64_t it = item_at(0);
+  if (it < 0) return;
+  int64_t cube0;
+  int orbit, ncub;
+  decode_item(g, it, &cube0, &orbit, &ncub);
+  const OrbitDev* od = a.orbits + orbit;
+  stage_tinfo(tinfo[0], od);
+  __syncthreads();
+  V buf[MAXC];
+  int lo[MAXC];
+  int ntiles = as_const(od)->ntiles;
+  bool ragged = as_const(od)->ragged != 0;
+  uint32_t nchunks = (uint32_t)ncub * (uint32_t)ntiles * (uint32_t)g.rows * (uint32_t)g.vpr;
+  issue_loads<T, D, VW, MAXC>(g, tinfo[0], ntiles, ragged, nchunks, a.in + cube0 * g.cube_elems,
+                              buf, lo);
+  int par = 0;
+  while (true) {
+    const int64_t nx = item_at(k + 1);
+    int64_t cube0n = 0;
+    int orbitn = 0, ncubn = 0;
+    const OrbitDev* odn = od;
+    // A.
+    if (nx >= 0) {
+      decode_item(g, nx, &cube0n, &orbitn, &ncubn);
+      odn = a.orbits + orbitn;
+      stage_tinfo(tinfo[par ^ 1], odn);
+    }
+    {
+      cptr<OrbitDev> cod = as_const(od);
+      const int rc = cod->rep_cnt;
+      const uint32_t* rsrc = a.reps + cod->rep_off;
+      for (int i = threadIdx.x; i < rc; i += kThreads) rep_lds[i] = rsrc[i];
+    }
+    fill_lds<T, VW, MAXC>(buf, lo, lds);
+    // Every load of the previous phase has landed.  Saying so explicitly
+    // (s_waitcnt vmcnt(0), gfx9 encoding) keeps the compiler from waiting
+    // between the prefetch loads below, which reuse the same registers.
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    // B.
+    int ntilesn = 0;
+    bool raggedn = false;
+    uint32_t nchunksn = 0;
+    if (nx >= 0) {
+      ntilesn = as_const(odn)->ntiles;
+      raggedn = as_const(odn)->ragged != 0;
+      nchunksn = (uint32_t)ncubn * (uint32_t)ntilesn * (uint32_t)g.rows * (uint32_t)g.vpr;
+      issue_loads<T, D, VW, MAXC>(g, tinfo[par ^ 1], ntilesn, raggedn, nchunksn,
+                                  a.in + cube0n * g.cube_elems, buf, lo);
+    }
+    // C.
+    combine_item<T, D, CHAIN>(g, as_const(od), rep_lds, coef, a.nstages, ncub, lds);
+    __syncthreads();
+    // D.
+    store_item<T, D, VW, true>(g, tinfo[par], ntiles, ragged, nchunks,
+                               a.out + cube0 * g.cube_elems, lds);
+    __syncthreads();
+    if (nx < 0) break;
+    ++k;
+    cube0 = cube0n;
+    ncub = ncubn;
+    od = odn;
+    ntiles = ntilesn;
+    ragged = raggedn;
+    nchunks = nchunksn;
+    par ^= 1;
+  }
+}
+
+template <typename T, int D, int VW>
+__global__ void __launch_bounds__(kThreads) k_batched(const BatchArgs<T> a) {
+  typedef typename VecT<T, VW>::type V;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __shared__ int32_t tinfo[2 * kMaxDF];
+  T* lds = reinterpret_cast<T*>(smem);
+  for (int64_t it = blockIdx.x; it < a.nitems; it += gridDim.x) {
+    const cptr<BatchItem> item = as_const(a.items) + it;
+    const int blk = item->block;
+    const int64_t icube0 = item->cube0;
+    const int incubes = item->ncubes;
+    const Geom g = load_geom(as_const(a.blocks)[blk].g);
+    const T* src = as_const(a.in)[blk] + icube0 * g.cube_elems;
+    T* dst = as_const(a.out)[blk] + icube0 * g.cube_elems;
+    const OrbitDev* od = a.orbits + item->orbit;
+    cptr<OrbitDev> cod = as_const(od);
+    stage_tinfo(tinfo, od);
+    __syncthreads();
+    const int ntiles = cod->ntiles;
+    const bool ragged = cod->ragged != 0;
+    const uint32_t nchunks =
+        (uint32_t)incubes * (uint32_t)ntiles * (uint32_t)g.rows * (uint32_t)g.vpr;
+    for (uint32_t c0 = 0; c0 < nchunks; c0 += kUnroll * kThreads) {
+      V buf[kUnroll];
+      int lo[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        uint32_t c = c0 + threadIdx.x + u * kThreads;
+        int go = 0;
+        int l = 0;
+        bool ok = (c < nchunks) && chunk_addr<D, VW>(g, c, ntiles, tinfo, tinfo + kMaxDF, ragged, &go, &l);
+        lo[u] = ok ? l : -1;
+        if (ok) buf[u] = *reinterpret_cast<const V*>(src + go);
+      }
+      fill_lds<T, VW, kUnroll>(buf, lo, lds);
+    }
+    __syncthreads();
+    combine_item<T, D, false>(g, cod, a.reps + cod->rep_off, as_const(a.coef), 1, incubes, lds);
+    __syncthreads();
+    store_item<T, D, VW, true>(g, tinfo, ntiles, ragged, nchunks, dst, lds);
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ dispatch
+template <typename T, int D, bool CHAIN, bool NTS>
+const void* exec_kernel(int vw) {
+  if constexpr (sizeof(T) == 8) {
+    if (vw == 2) return (const void*)k_exec<T, D, 2, CHAIN, NTS>;
+    return (const void*)k_exec<T, D, 1, CHAIN, NTS>;
+  } else {
+    if (vw == 4) return (const void*)k_exec<T, D, 4, CHAIN, NTS>;
+    if (vw == 2) return (const void*)k_exec<T, D, 2, CHAIN, NTS>;
+    return (const void*)k_exec<T, D, 1, CHAIN, NTS>;
+  }
+}
+
+template <typename T, int D, bool CHAIN, int MAXC>
+const void* pipe_kernel(int vw) {
+  if constexpr (sizeof(T) == 8) {
+    if (vw == 2) return (const void*)k_pipe<T, D, 2, CHAIN, MAXC>;
+    return (const void*)k_pipe<T, D, 1, CHAIN, MAXC>;
+  } else {
+    if (vw == 4) return (const void*)k_pipe<T, D, 4, CHAIN, MAXC>;
+    if (vw == 2) return (const void*)k_pipe<T, D, 2, CHAIN, MAXC>;
+    return (const void*)k_pipe<T, D, 1, CHAIN, MAXC>;
+  }
+}
+
+// kind: 1 direct-LDS one-shot, 2 register-prefetch persistent (maxc = 8 or
+// 16), 3 register one-shot
+template <typename T, int D>
+const void* pick_d(int kind, int vw, bool chain, bool nts, int maxc) {
+  if (kind == 1) return chain ? (const void*)k_lds<T, D, true> : (const void*)k_lds<T, D, false>;
+  if (kind == 2) {
+    if (maxc == 8) return chain ? pipe_kernel<T, D, true, 8>(vw) : pipe_kernel<T, D, false, 8>(vw);
+    return chain ? pipe_kernel<T, D, true, 16>(vw) : pipe_kernel<T, D, false, 16>(vw);
+  }
+  if (chain) return nts ? exec_kernel<T, D, true, true>(vw) : exec_kernel<T, D, true, false>(vw);
+  return nts ? exec_kernel<T, D, false, true>(vw) : exec_kernel<T, D, false, false>(vw);
+}
+
+template <typename T, int D>
+const void* batched_kernel(int vw) {
+  if constexpr (sizeof(T) == 8) {
+    if (vw == 2) return (const void*)k_batched<T, D, 2>;
+    return (const void*)k_batched<T, D, 1>;
+  } else {
+    if (vw == 4) return (const void*)k_batched<T, D, 4>;
+    if (vw == 2) return (const void*)k_batched<T, D, 2>;
+    return (const void*)k_batched<T, D, 1>;
+  }
+}
+
+}  // namespace
+
+// Kernel selection, one definition per (storage type, group size) in
+// spinsum_kern_<type>_d<d>.hip.
+#define SPINSUM_DECLARE_PICK(tag, d)                                                    \
+  const void* pick_##tag##_d##d(int kind, int vw, bool chain, bool nts, int maxc);     \
+  const void* pick_batched_##tag##_d##d(int vw);
+SPINSUM_DECLARE_PICK(f64, 2)
+SPINSUM_DECLARE_PICK(f64, 3)
+SPINSUM_DECLARE_PICK(f64, 4)
+SPINSUM_DECLARE_PICK(f32, 2)
+SPINSUM_DECLARE_PICK(f32, 3)
+SPINSUM_DECLARE_PICK(f32, 4)
+#undef SPINSUM_DECLARE_PICK
+
+}  // namespace spinsum

@@ -1,0 +1,295 @@
+// spinsum_exec.hip -- exec / adjoint / batched / graph / copy entry points of
+// the C-ABI of libspinsum (argument checks and dispatch to the per-dtype
+// launchers).
+#include "spinsum_device.h"
+
+namespace spinsum {
+namespace {
+
+// Plain copy with the same 16-byte loads and non-temporal stores, one
+// vector per thread: the achievable HBM ceiling for a read-once /
+// write-once kernel.
+__global__ void __launch_bounds__(kThreads) k_copy(const double* __restrict__ in,
+                                                   double* __restrict__ out, int64_t nvec) {
+  typedef double V __attribute__((ext_vector_type(2)));
+  const V* src = reinterpret_cast<const V*>(in);
+  V* dst = reinterpret_cast<V*>(out);
+  int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (i < nvec) __builtin_nontemporal_store(src[i], dst + i);
+}
+
+template <typename T>
+const void* pick_kernel(int d, int kind, int vw, bool chain, bool nts, int maxc) {
+  if constexpr (sizeof(T) == 8) {
+    if (d == 2) return pick_f64_d2(kind, vw, chain, nts, maxc);
+    if (d == 3) return pick_f64_d3(kind, vw, chain, nts, maxc);
+    return pick_f64_d4(kind, vw, chain, nts, maxc);
+  } else {
+    if (d == 2) return pick_f32_d2(kind, vw, chain, nts, maxc);
+    if (d == 3) return pick_f32_d3(kind, vw, chain, nts, maxc);
+    return pick_f32_d4(kind, vw, chain, nts, maxc);
+  }
+}
+
+template <typename T>
+const void* pick_batched(int d, int vw) {
+  if constexpr (sizeof(T) == 8) {
+    if (d == 2) return pick_batched_f64_d2(vw);
+    if (d == 3) return pick_batched_f64_d3(vw);
+    return pick_batched_f64_d4(vw);
+  } else {
+    if (d == 2) return pick_batched_f32_d2(vw);
+    if (d == 3) return pick_batched_f32_d3(vw);
+    return pick_batched_f32_d4(vw);
+  }
+}
+
+spinsum_status hip_error(spinsum_plan_s* P, hipError_t e) {
+  P->last_hip_error = (int)e;
+  (void)hipGetLastError();
+  return SPINSUM_ERR_HIP;
+}
+
+spinsum_status prepare_kernel(spinsum_plan_s* P, const void* k, size_t shmem) {
+  if (shmem > 65536) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    if (e != hipSuccess) return hip_error(P, e);
+  }
+  return SPINSUM_OK;
+}
+
+// Workgroups of a persistent launch: the occupancy of the kernel times the
+// CUs, rounded down to a multiple of 8 (one share per XCD).
+spinsum_status persistent_grid(spinsum_plan_s* P, const void* k, size_t shmem, int64_t nitems,
+                               int64_t* grid) {
+  if (P->occ_kernel != k || P->occ_shmem != (int64_t)shmem) {
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kThreads, shmem);
+    if (e != hipSuccess) return hip_error(P, e);
+    P->occ_kernel = k;
+    P->occ_shmem = (int64_t)shmem;
+    P->occ_blocks = std::max(1, per_cu);
+  }
+  int64_t g = (int64_t)P->occ_blocks * P->num_cus;
+  g = std::min<int64_t>(g, ((nitems + 7) / 8) * 8);
+  g = std::max<int64_t>(8, (g / 8) * 8);
+  *grid = g;
+  return SPINSUM_OK;
+}
+
+template <typename T>
+spinsum_status launch_exec(spinsum_plan_s* P, const void* in, void* out, hipStream_t stream,
+                           bool adjoint) {
+  const Tiling& Tl = P->T;
+  if (Tl.nitems <= 0) return SPINSUM_OK;
+  const int df = P->G.df;
+  const int K = (int)P->stage_a.size();
+  const bool chain = (P->flags & SPINSUM_FLAG_CHAIN_STAGES) != 0;
+  const bool nts = (P->flags & SPINSUM_FLAG_NO_NT_STORES) == 0;
+  const T* coef = reinterpret_cast<const T*>(P->d_mats);
+  ExecArgs<T> a;
+  std::memset(&a, 0, sizeof(a));
+  a.in = reinterpret_cast<const T*>(in);
+  a.out = reinterpret_cast<T*>(out);
+  a.orbits = reinterpret_cast<const OrbitDev*>(P->d_orbits);
+  a.reps = reinterpret_cast<const uint32_t*>(P->d_reps);
+  if (!chain) {
+    a.coef = coef + (adjoint ? df : 0);
+    a.nstages = 1;
+  } else {
+    a.coef = coef + 2 * df + (adjoint ? (size_t)K * df : 0);
+    a.nstages = K;
+  }
+  a.g = Tl.g;
+  a.nitems = Tl.nitems;
+  a.reverse = (P->flags & SPINSUM_FLAG_REVERSE_ORDER) ? 1 : 0;
+  // kernel variant chosen by the planner (see spinsum_tile_t.variant)
+  int kind = P->tile.variant;
+  if (!nts && kind != SPINSUM_VARIANT_REG_ONESHOT) kind = SPINSUM_VARIANT_REG_ONESHOT;
+  const int maxc = (kind == SPINSUM_VARIANT_REG_PIPELINE) ? (Tl.chunks_per_thread <= 8 ? 8 : 16) : 0;
+  const void* k = pick_kernel<T>(P->d, kind, Tl.vw, chain, nts, maxc);
+  a.lds_tile_bytes = (int32_t)(((size_t)Tl.lds_elems * sizeof(T) + 15) / 16 * 16);
+  const size_t shmem = (kind == SPINSUM_VARIANT_REG_PIPELINE)
+                           ? (size_t)a.lds_tile_bytes + (size_t)Tl.max_rep_cnt * 4
+                           : (size_t)Tl.lds_elems * sizeof(T);
+  spinsum_status st = prepare_kernel(P, k, shmem);
+  if (st != SPINSUM_OK) return st;
+  int64_t grid;
+  if (kind == SPINSUM_VARIANT_REG_PIPELINE) {
+    st = persistent_grid(P, k, shmem, Tl.nitems, &grid);
+    if (st != SPINSUM_OK) return st;
+    a.xcd_per = (P->flags & SPINSUM_FLAG_NO_XCD_REMAP) ? 0 : (Tl.nitems + 7) / 8;
+  } else if (P->flags & SPINSUM_FLAG_NO_XCD_REMAP) {
+    a.xcd_per = 0;
+    grid = Tl.nitems;
+  } else {
+    a.xcd_per = (Tl.nitems + 7) / 8;
+    grid = a.xcd_per * 8;
+  }
+  void* kargs[] = {&a};
+  hipError_t e = hipLaunchKernel(k, dim3((unsigned)grid), dim3(kThreads), kargs, shmem, stream);
+  if (e != hipSuccess) return hip_error(P, e);
+  return SPINSUM_OK;
+}
+
+template <typename T>
+spinsum_status launch_batched(spinsum_plan_s* P, const void* const* in, void* const* out,
+                              hipStream_t stream) {
+  if (P->items.empty()) return SPINSUM_OK;
+  BatchArgs<T> a;
+  std::memset(&a, 0, sizeof(a));
+  a.in = reinterpret_cast<const T* const*>(in);
+  a.out = reinterpret_cast<T* const*>(out);
+  a.orbits = reinterpret_cast<const OrbitDev*>(P->d_orbits);
+  a.reps = reinterpret_cast<const uint32_t*>(P->d_reps);
+  a.coef = reinterpret_cast<const T*>(P->d_mats);
+  a.blocks = reinterpret_cast<const BatchBlock*>(P->d_blocks);
+  a.items = reinterpret_cast<const BatchItem*>(P->d_items);
+  a.nitems = (int64_t)P->items.size();
+  const void* k = pick_batched<T>(P->d, P->batch_vw);
+  const size_t shmem = (size_t)P->batch_lds_elems * sizeof(T);
+  spinsum_status st = prepare_kernel(P, k, shmem);
+  if (st != SPINSUM_OK) return st;
+  void* kargs[] = {&a};
+  hipError_t e =
+      hipLaunchKernel(k, dim3((unsigned)P->batch_grid), dim3(kThreads), kargs, shmem, stream);
+  if (e != hipSuccess) return hip_error(P, e);
+  return SPINSUM_OK;
+}
+
+spinsum_status check_device(spinsum_plan_s* P) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_error(P, e);
+  if (dev != P->device) return SPINSUM_ERR_INVALID_ARG;
+  return SPINSUM_OK;
+}
+
+spinsum_status check_tensor_args(spinsum_plan_s* P, const void* in, const void* out) {
+  if (P == nullptr) return SPINSUM_ERR_INVALID_ARG;
+  if (P->batched) return SPINSUM_ERR_INVALID_ARG;
+  if (!P->has_dev) return SPINSUM_ERR_NO_DEVICE;
+  if (P->elems == 0) return SPINSUM_OK;
+  if (in == nullptr || out == nullptr) return SPINSUM_ERR_INVALID_ARG;
+  if ((((uintptr_t)in) | ((uintptr_t)out)) & 15u) return SPINSUM_ERR_MISALIGNED;
+  if (P->inplace) {
+    if (in != out) return SPINSUM_ERR_INVALID_ARG;
+  } else {
+    const uintptr_t bytes = (uintptr_t)P->elems * (uintptr_t)elem_size(*P);
+    const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out;
+    if (a < b + bytes && b < a + bytes) return SPINSUM_ERR_ALIASING;
+  }
+  return check_device(P);
+}
+
+}  // namespace
+
+}  // namespace spinsum
+
+using namespace spinsum;
+
+extern "C" spinsum_status spinsum_exec(spinsum_plan_t P, const void* in, void* out, void* stream) {
+  spinsum_status st = check_tensor_args(P, in, out);
+  if (st != SPINSUM_OK || P->elems == 0) return st;
+  if (P->dtype == SPINSUM_F32)
+    return launch_exec<float>(P, in, out, (hipStream_t)stream, false);
+  return launch_exec<double>(P, in, out, (hipStream_t)stream, false);
+}
+
+extern "C" spinsum_status spinsum_adjoint(spinsum_plan_t P, const void* grad_out, void* grad_in,
+                                          void* stream) {
+  spinsum_status st = check_tensor_args(P, grad_out, grad_in);
+  if (st != SPINSUM_OK || P->elems == 0) return st;
+  if (P->dtype == SPINSUM_F32)
+    return launch_exec<float>(P, grad_out, grad_in, (hipStream_t)stream, true);
+  return launch_exec<double>(P, grad_out, grad_in, (hipStream_t)stream, true);
+}
+
+extern "C" spinsum_status spinsum_exec_batched(spinsum_plan_t P, const void* const* in,
+                                               void* const* out, void* stream) {
+  if (P == nullptr || !P->batched) return SPINSUM_ERR_INVALID_ARG;
+  if (!P->has_dev) return SPINSUM_ERR_NO_DEVICE;
+  if (P->items.empty()) return SPINSUM_OK;
+  if (in == nullptr || out == nullptr) return SPINSUM_ERR_INVALID_ARG;
+  if ((((uintptr_t)in) | ((uintptr_t)out)) & 7u) return SPINSUM_ERR_MISALIGNED;
+  spinsum_status st = check_device(P);
+  if (st != SPINSUM_OK) return st;
+  if (P->dtype == SPINSUM_F32) return launch_batched<float>(P, in, out, (hipStream_t)stream);
+  return launch_batched<double>(P, in, out, (hipStream_t)stream);
+}
+
+struct spinsum_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" spinsum_status spinsum_graph_create(spinsum_plan_t P, const void* const* in,
+                                               void* const* out, spinsum_graph_t* graph) {
+  if (P == nullptr || graph == nullptr) return SPINSUM_ERR_INVALID_ARG;
+  *graph = nullptr;
+  if (!P->has_dev) return SPINSUM_ERR_NO_DEVICE;
+  hipStream_t s = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_error(P, e);
+  spinsum_graph_s* G = new (std::nothrow) spinsum_graph_s();
+  if (!G) {
+    (void)hipStreamDestroy(s);
+    return SPINSUM_ERR_OUT_OF_MEMORY;
+  }
+  spinsum_status st = SPINSUM_OK;
+  e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    if (P->batched)
+      st = spinsum_exec_batched(P, in, out, s);
+    else
+      st = spinsum_exec(P, (const void*)in, (void*)out, s);
+    hipError_t e2 = hipStreamEndCapture(s, &G->graph);
+    if (e == hipSuccess) e = e2;
+  }
+  if (e == hipSuccess && st == SPINSUM_OK) e = hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(s);
+  if (e != hipSuccess || st != SPINSUM_OK) {
+    if (e != hipSuccess) {
+      P->last_hip_error = (int)e;
+      (void)hipGetLastError();
+    }
+    if (G->exec) (void)hipGraphExecDestroy(G->exec);
+    if (G->graph) (void)hipGraphDestroy(G->graph);
+    delete G;
+    return st != SPINSUM_OK ? st : SPINSUM_ERR_HIP;
+  }
+  *graph = G;
+  return SPINSUM_OK;
+}
+
+extern "C" spinsum_status spinsum_graph_launch(spinsum_graph_t G, void* stream) {
+  if (G == nullptr || G->exec == nullptr) return SPINSUM_ERR_INVALID_ARG;
+  hipError_t e = hipGraphLaunch(G->exec, (hipStream_t)stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return SPINSUM_ERR_HIP;
+  }
+  return SPINSUM_OK;
+}
+
+extern "C" void spinsum_graph_destroy(spinsum_graph_t G) {
+  if (!G) return;
+  if (G->exec) (void)hipGraphExecDestroy(G->exec);
+  if (G->graph) (void)hipGraphDestroy(G->graph);
+  delete G;
+}
+
+extern "C" spinsum_status spinsum_stream_copy(const void* in, void* out, int64_t nbytes,
+                                              void* stream) {
+  if (nbytes < 0 || (nbytes % 16) != 0) return SPINSUM_ERR_INVALID_ARG;
+  if (nbytes == 0) return SPINSUM_OK;
+  if (in == nullptr || out == nullptr) return SPINSUM_ERR_INVALID_ARG;
+  if ((((uintptr_t)in) | ((uintptr_t)out)) & 15u) return SPINSUM_ERR_MISALIGNED;
+  const int64_t nvec = nbytes / 16;
+  const int64_t grid = (nvec + kThreads - 1) / kThreads;
+  if (grid >= (1ll << 31)) return SPINSUM_ERR_UNSUPPORTED;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)grid), dim3(kThreads), 0, (hipStream_t)stream,
+                     (const double*)in, (double*)out, nvec);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? SPINSUM_OK : SPINSUM_ERR_HIP;
+}

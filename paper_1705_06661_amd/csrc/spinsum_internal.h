@@ -19,6 +19,8 @@
 #pragma once
 #include <stdint.h>
 
+#include <utility>
+
 #ifndef __HIPCC__
 #define __host__
 #define __device__
@@ -129,14 +131,39 @@ __host__ __device__ constexpr int lex_perm(int d, int r, int m) {
   return res;
 }
 
+// Lexicographic rank of a permutation q of (0..d-1) (Lehmer code).
+__host__ __device__ constexpr int lex_rank(int d, const int* q) {
+  int r = 0;
+  for (int m = 0; m < d; ++m) {
+    int smaller = 0;
+    for (int j = m + 1; j < d; ++j) smaller += (q[j] < q[m]) ? 1 : 0;
+    int f = 1;
+    for (int k = 2; k <= d - 1 - m; ++k) f *= k;
+    r += smaller * f;
+  }
+  return r;
+}
+
+// Rank of tau^-1 o sigma, where (a o b)[m] = a[b[m]] is "operator a applied
+// after operator b".  With v_sigma = In[sigma . x] the outputs of an element
+// orbit are w_tau = sum_sigma a(tau^-1 o sigma) v_sigma, a() being the
+// coefficient of each permutation in the operator.
+__host__ __device__ constexpr int ginv_mul(int d, int t, int s) {
+  int pt[4] = {0, 0, 0, 0}, inv[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};
+  for (int m = 0; m < d; ++m) pt[m] = lex_perm(d, t, m);
+  for (int m = 0; m < d; ++m) inv[pt[m]] = m;
+  for (int m = 0; m < d; ++m) c[m] = inv[lex_perm(d, s, m)];
+  return lex_rank(d, c);
+}
+
 // Chunk c of a work item (one VW-vector of one tile row) -> global element
-// offset from the item's first cube and LDS element offset; false if the
-// chunk lies outside a ragged tile.  toff/text: tile origins and packed
-// extents of the item's orbit.
+// offset from the item's first cube (32 bits: an item spans less than 2^31
+// bytes) and LDS element offset; false if the chunk lies outside a ragged
+// tile.  toff/text: tile origins and packed extents of the item's orbit.
 template <int D, int VW>
 __host__ __device__ inline bool chunk_addr(const Geom& g, uint32_t c, int ntiles,
                                            const int32_t* toff, const int32_t* text,
-                                           bool ragged, int64_t* goff, int* loff) {
+                                           bool ragged, int* goff, int* loff) {
   uint32_t q = fdiv(c, g.fd_vpr);
   int v = (int)(c - q * (uint32_t)g.vpr);
   uint32_t q2 = fdiv(q, g.fd_rows);
@@ -170,20 +197,38 @@ __host__ __device__ inline bool chunk_addr(const Geom& g, uint32_t c, int ntiles
     go += l[m] * g.gst[m];
     lo += l[m] * g.lst[m];
   }
-  *goff = (int64_t)cube_i * g.cube_elems + go;
+  *goff = cube_i * (int)g.cube_elems + go;
   *loff = cube_i * g.cube_lds + lo;
   return ok;
 }
 
-// LDS element offset of sigma_r . x for representative x = l[] of a cube
+// Compile-time tables of S_d: element m of permutation r, and the rank of
+// r^-1 o s (template constants, so that unrolled kernel code indexes
+// registers with literals).
+template <int D, int R, int M>
+struct LexPerm {
+  static constexpr int value = lex_perm(D, R, M);
+};
+template <int D, int T, int S>
+struct GinvMul {
+  static constexpr int value = ginv_mul(D, T, S);
+};
+
+// LDS element offset of sigma_R . x for representative x = l[] of a cube
 // whose LDS image starts at `base` (combine phase).
-template <int D>
-__host__ __device__ inline int orbit_lds_addr(const Geom& g, int base, const int32_t* slot_base,
-                                              int r, const int* l) {
-  int a = base + slot_base[r];
-#pragma unroll
-  for (int m = 0; m < D; ++m) a += l[lex_perm(D, r, m)] * g.lst[m];
-  return a;
+template <int D, int R, int... M>
+__host__ __device__ inline int orbit_addr_one(const Geom& g, int base, int32_t slot_base_r,
+                                              const int* l, std::integer_sequence<int, M...>) {
+  return base + slot_base_r + ((l[LexPerm<D, R, M>::value] * g.lst[M]) + ... + 0);
+}
+
+// Offsets of sigma . x for every sigma in S_d (lexicographic order).
+template <int D, int... R>
+__host__ __device__ inline void orbit_addrs(const Geom& g, int base, const int32_t* slot_base,
+                                            const int* l, int* addr,
+                                            std::integer_sequence<int, R...>) {
+  ((addr[R] = orbit_addr_one<D, R>(g, base, slot_base[R], l, std::make_integer_sequence<int, D>{})),
+   ...);
 }
 
 }  // namespace spinsum

@@ -1,0 +1,13 @@
+// spinsum_kern_f64_d2.hip -- instantiates the double kernels of libspinsum for
+// a group of 2 indices (kernel templates in spinsum_device.h).
+#include "spinsum_device.h"
+
+namespace spinsum {
+
+const void* pick_f64_d2(int kind, int vw, bool chain, bool nts, int maxc) {
+  return pick_d<double, 2>(kind, vw, chain, nts, maxc);
+}
+
+const void* pick_batched_f64_d2(int vw) { return batched_kernel<double, 2>(vw); }
+
+}  // namespace spinsum

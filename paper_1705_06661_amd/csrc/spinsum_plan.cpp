@@ -126,7 +126,8 @@ static int64_t tile_lds_bytes(const spinsum_plan_s& P, int n, int bl, int cpw, i
   lds_strides(P.d, bl, pad, lst, &ts);
   int nb = (n + bl - 1) / bl;
   int tiles = (bl == n) ? cpw : max_orbit_tiles(P.G, nb);
-  return (int64_t)tiles * ts * elem_size(P);
+  // plus the representative copy of the pipelined kernel (at most bl^d)
+  return (int64_t)tiles * ts * elem_size(P) + ipow(bl, P.d) * 4;
 }
 
 spinsum_status choose_tile(const spinsum_plan_s& P, int n, int64_t ncubes, int vw,
@@ -187,7 +188,7 @@ spinsum_status build_tiling(const spinsum_plan_s& P, int n, int64_t ncubes,
   const int pad = tile.lds_pad ? 1 : 0;
   const int cpw = (bl == n) ? std::max(1, tile.cubes_per_wg) : 1;
   const int64_t cube_elems = ipow(n, d);
-  if (cube_elems >= (1ll << 31)) return SPINSUM_ERR_UNSUPPORTED;
+  if (cube_elems * elem_size(P) >= (1ll << 31)) return SPINSUM_ERR_UNSUPPORTED;
   const int nb = (n + bl - 1) / bl;
   const int vw = vw_for(n, bl, vmax);
 
@@ -274,6 +275,7 @@ spinsum_status build_tiling(const spinsum_plan_s& P, int n, int64_t ncubes,
     od.rep_cnt = ri->second.second;
     od.fd_rep = make_fastdiv((uint32_t)std::max(1, od.rep_cnt));
     T.max_tiles = std::max(T.max_tiles, (int)od.ntiles);
+    T.max_rep_cnt = std::max(T.max_rep_cnt, (int)od.rep_cnt);
     T.ragged |= od.ragged;
     T.orbits.push_back(od);
     // next non-decreasing block tuple (the loop nest of Alg. 5a)
@@ -289,7 +291,14 @@ spinsum_status build_tiling(const spinsum_plan_s& P, int n, int64_t ncubes,
   T.vw = vw;
   T.lds_elems = (bl == n) ? (int64_t)cpw * g.ts : (int64_t)T.max_tiles * g.ts;
   T.nitems = (bl == n) ? (ncubes + cpw - 1) / cpw : ncubes * g.norbits;
-  T.fits = (T.lds_elems * elem_size(P) + 512 <= P.lds_limit) ? 1 : 0;
+  {
+    int64_t chunks = (int64_t)((bl == n) ? cpw : T.max_tiles) * g.rows * g.vpr;
+    T.chunks_per_thread = (int)((chunks + 255) / 256);
+  }
+  if ((bl == n) && (int64_t)cpw * cube_elems * elem_size(P) >= (1ll << 31)) return SPINSUM_ERR_UNSUPPORTED;
+  // tiles, the representative copy of the pipelined kernel, static tables
+  T.fits = ((T.lds_elems * elem_size(P) + 15) / 16 * 16 + (int64_t)T.max_rep_cnt * 4 + 512 <=
+            P.lds_limit) ? 1 : 0;
   if (!T.fits && !(P.flags & SPINSUM_FLAG_HOST_ONLY)) return SPINSUM_ERR_UNSUPPORTED;
   if (T.nitems >= (1ll << 31) - 8) return SPINSUM_ERR_UNSUPPORTED;
   *out = std::move(T);
@@ -415,30 +424,27 @@ static spinsum_status set_terms(spinsum_plan_s* P, int nstages, const int* nterm
     }
     P->expanded = e;
   }
-  // orbit matrices: w_tau = sum_sigma a(tau^-1 o sigma) v_sigma
-  auto orbit_matrix = [&](const std::vector<double>& a, std::vector<double>& M) {
-    M.assign((size_t)df * df, 0.0);
-    for (int tau = 0; tau < df; ++tau)
-      for (int sg = 0; sg < df; ++sg) M[(size_t)tau * df + sg] = a[G.mul[(size_t)G.inv[tau] * df + sg]];
+  // The kernels index the coefficient vector with ginv_mul(); it must agree
+  // with the group tables used here.
+  for (int t = 0; t < df; ++t)
+    for (int sg = 0; sg < df; ++sg)
+      if (ginv_mul(P->d, t, sg) != G.mul[(size_t)G.inv[t] * df + sg]) return SPINSUM_ERR_UNSUPPORTED;
+  // coefficient vectors: forward (expanded), adjoint a'(g) = a(g^-1), and
+  // per stage in application order (forward: stage 0 first; adjoint: last
+  // stage first, each inverted)
+  auto adjoint_of = [&](const std::vector<double>& a) {
+    std::vector<double> r(df);
+    for (int g = 0; g < df; ++g) r[g] = a[G.inv[g]];
+    return r;
   };
-  auto transpose = [&](const std::vector<double>& M) {
-    std::vector<double> R((size_t)df * df);
-    for (int i = 0; i < df; ++i)
-      for (int j = 0; j < df; ++j) R[(size_t)j * df + i] = M[(size_t)i * df + j];
-    return R;
-  };
-  orbit_matrix(P->expanded, P->M);
-  P->MT = transpose(P->M);
+  P->M = P->expanded;
+  P->MT = adjoint_of(P->expanded);
   P->SM.clear();
   P->SMT.clear();
-  std::vector<std::vector<double>> sm(nstages);
-  for (int k = 0; k < nstages; ++k) {
-    orbit_matrix(P->stage_a[k], sm[k]);
-    P->SM.insert(P->SM.end(), sm[k].begin(), sm[k].end());
-  }
+  for (int k = 0; k < nstages; ++k) P->SM.insert(P->SM.end(), P->stage_a[k].begin(), P->stage_a[k].end());
   for (int k = nstages - 1; k >= 0; --k) {
-    std::vector<double> tr = transpose(sm[k]);
-    P->SMT.insert(P->SMT.end(), tr.begin(), tr.end());
+    std::vector<double> r = adjoint_of(P->stage_a[k]);
+    P->SMT.insert(P->SMT.end(), r.begin(), r.end());
   }
   return SPINSUM_OK;
 }
@@ -474,12 +480,22 @@ static spinsum_status apply_tile(spinsum_plan_s* P, const spinsum_tile_t* req) {
       if (st != SPINSUM_OK) return st;
     }
   }
-  if (req && req->lds_pad >= 0 && req->bl > 0) t.lds_pad = req->lds_pad;
   if (t.threads != 256 && t.threads != 0) return SPINSUM_ERR_UNSUPPORTED;
   t.threads = 256;
+  if (t.variant < 0 || t.variant > SPINSUM_VARIANT_REG_ONESHOT) return SPINSUM_ERR_INVALID_ARG;
+  // kernel variant: loads straight into LDS need whole 16-byte rows
+  const int bl = t.bl <= 0 ? std::max(1, P->n) : std::min(t.bl, std::max(1, P->n));
+  const bool direct_ok = vw_for(std::max(1, P->n), bl, vmax) * elem_size(*P) == 16 &&
+                         !(P->flags & SPINSUM_FLAG_NO_DIRECT_LDS);
+  if (t.variant == SPINSUM_VARIANT_AUTO)
+    t.variant = direct_ok ? SPINSUM_VARIANT_DIRECT_LDS : SPINSUM_VARIANT_REG_ONESHOT;
+  if (t.variant == SPINSUM_VARIANT_DIRECT_LDS && !direct_ok) t.variant = SPINSUM_VARIANT_REG_ONESHOT;
+  if (t.variant == SPINSUM_VARIANT_DIRECT_LDS) t.lds_pad = 0;  // dense chunk-order layout
   Tiling T;
   spinsum_status st = build_tiling(*P, P->n, P->ncubes, t, vmax, &T);
   if (st != SPINSUM_OK) return st;
+  if (t.variant == SPINSUM_VARIANT_REG_PIPELINE && T.chunks_per_thread > 16)
+    t.variant = SPINSUM_VARIANT_REG_ONESHOT;
   P->tile = t;
   P->T = std::move(T);
   return SPINSUM_OK;
@@ -706,6 +722,8 @@ extern "C" spinsum_status spinsum_plan_get_info(spinsum_plan_t P, spinsum_plan_i
   info->threads = 256;
   if (!P->batched) {
     info->bl = P->T.g.bl;
+    info->variant = P->tile.variant;
+    info->lds_pad = P->tile.lds_pad;
     info->nb = P->T.nb;
     info->norbits = P->T.g.norbits;
     info->cubes_per_wg = P->T.g.cpw;
@@ -715,6 +733,8 @@ extern "C" spinsum_status spinsum_plan_get_info(spinsum_plan_t P, spinsum_plan_i
     info->vector_width = P->T.vw;
     info->ragged = P->T.ragged;
     info->fits_lds = P->T.fits;
+    info->rep_lds_bytes = (int64_t)P->T.max_rep_cnt * 4;
+    info->chunks_per_thread = P->T.chunks_per_thread;
   } else {
     info->lds_bytes = P->batch_lds_elems * elem_size(*P);
     info->nitems = (int64_t)P->items.size();
@@ -758,10 +778,14 @@ static bool emulate_item(const Tiling& T, const OrbitDev& od, int ncub, std::str
   const int d = D;
   const int64_t span = (int64_t)ncub * g.cube_elems;
   const uint32_t nchunks = (uint32_t)ncub * (uint32_t)od.ntiles * (uint32_t)g.rows * (uint32_t)g.vpr;
+  if ((int64_t)nchunks > (int64_t)T.chunks_per_thread * 256) {
+    *why = "item has more chunks than the prefetch buffer holds";
+    return false;
+  }
   std::vector<int64_t> lds_of(T.lds_elems, -1);  // LDS slot -> element loaded there
   std::vector<int> loaded((size_t)span, 0);
   for (uint32_t c = 0; c < nchunks; ++c) {
-    int64_t go = 0;
+    int go = 0;
     int lo = 0;
     if (!chunk_addr<D, VW>(g, c, od.ntiles, od.tile_off, od.tile_ext, od.ragged != 0, &go, &lo))
       continue;
@@ -802,8 +826,11 @@ static bool emulate_item(const Tiling& T, const OrbitDev& od, int ncub, std::str
     int x[D];
     int64_t o0 = od.tile_off[od.slot_base[0] / g.ts];
     for (int m = 0; m < d; ++m) x[m] = (int)((o0 / g.gst[m]) % g.n) + l[m];
+    int addrs[kMaxDF];
+    orbit_addrs<D>(g, (int)ci * g.cube_lds, od.slot_base, l, addrs,
+                   std::make_integer_sequence<int, Fact<D>()>{});
     for (int r = 0; r < Fact<D>(); ++r) {
-      int a = orbit_lds_addr<D>(g, (int)ci * g.cube_lds, od.slot_base, r, l);
+      int a = addrs[r];
       if (a < 0 || a >= T.lds_elems) { *why = "combine address out of bounds"; return false; }
       int64_t want = (int64_t)ci * g.cube_elems;
       for (int m = 0; m < d; ++m) want += (int64_t)x[lex_perm(D, r, m)] * g.gst[m];

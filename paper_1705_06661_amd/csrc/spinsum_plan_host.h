@@ -31,6 +31,8 @@ struct Tiling {
   int fits = 1;
   int64_t lds_elems = 0;
   int64_t nitems = 0;
+  int chunks_per_thread = 0;  // 16-byte loads per thread for the largest item
+  int max_rep_cnt = 0;        // representatives of the largest orbit
   std::vector<OrbitDev> orbits;
   std::vector<uint32_t> reps;
 };
@@ -48,8 +50,8 @@ struct spinsum_plan_s {
   spinsum::SymGroup G;
   std::vector<std::vector<double>> stage_a;  // per stage: coefficient of each permutation rank
   std::vector<double> expanded;              // coefficient of each permutation rank
-  std::vector<double> M, MT;                 // df x df orbit matrices (forward, adjoint)
-  std::vector<double> SM, SMT;               // per-stage orbit matrices, application order
+  std::vector<double> M, MT;                 // coefficient vectors (forward, adjoint), df each
+  std::vector<double> SM, SMT;               // per-stage coefficient vectors, application order
 
   // tiling (single tensor)
   spinsum_tile_t tile{};
@@ -77,6 +79,9 @@ struct spinsum_plan_s {
   void* d_blocks = nullptr;
   void* d_items = nullptr;
   int last_hip_error = 0;
+  const void* occ_kernel = nullptr;  // occupancy cache of the persistent kernel
+  int64_t occ_shmem = -1;
+  int occ_blocks = 1;
   std::string why;
 };
 

@@ -48,11 +48,15 @@ def gpu_ints(shape, seed, dtype=torch.float64):
     return workloads.integers(shape, seed, device=DEV, dtype=dtype)
 
 
-def mk(shape, stages, d, dtype=torch.float64, inplace=False, flags=0, tile=None):
+VARIANTS = [ss.SPINSUM_VARIANT_DIRECT_LDS, ss.SPINSUM_VARIANT_REG_PIPELINE,
+            ss.SPINSUM_VARIANT_REG_ONESHOT]
+
+
+def mk(shape, stages, d, dtype=torch.float64, inplace=False, flags=0, tile=None, variant=0):
     p = ss.spinsum_plan(shape, len(shape) - d, d, stages, dtype=dtype, inplace=inplace,
                         flags=flags)
     if tile is not None:
-        ss.spinsum_plan_set_tile(p, *tile)
+        ss.spinsum_plan_set_tile(p, *tile, variant=variant)
     return p
 
 
@@ -134,14 +138,17 @@ def test_tiles_against_oracle(shape, d, tile, dtype):
     rng = np.random.default_rng(sum(shape) + d)
     perms = list(itertools.permutations(range(d)))
     terms = [(p, float(rng.integers(-3, 4))) for p in perms]
-    for inplace in (False, True):
-        p = mk(shape, [terms], d, dtype=dtype, inplace=inplace, tile=tile)
-        x = gpu_uniform(shape, 5, dtype)
-        y = run(p, x)
-        assert nerr(y.cpu().numpy(), ref_of(x, [terms], d)) <= TOL[dtype]
-        xi = gpu_ints(shape, 6, dtype)
-        yi = run(p, xi)
-        np.testing.assert_array_equal(yi.cpu().numpy().astype(np.float64), ref_of(xi, [terms], d))
+    x = gpu_uniform(shape, 5, dtype)
+    ref = ref_of(x, [terms], d)
+    xi = gpu_ints(shape, 6, dtype)
+    refi = ref_of(xi, [terms], d)
+    for variant in VARIANTS:
+        for inplace in (False, True):
+            p = mk(shape, [terms], d, dtype=dtype, inplace=inplace, tile=tile, variant=variant)
+            y = run(p, x)
+            assert nerr(y.cpu().numpy(), ref) <= TOL[dtype], variant
+            yi = run(p, xi)
+            np.testing.assert_array_equal(yi.cpu().numpy().astype(np.float64), refi)
 
 
 @pytest.mark.parametrize("case", [1, 2, 4, 5, 6, 8, 9, 11, 13, 17, 21])
@@ -151,8 +158,9 @@ def test_table2_cases(case, chain):
     n = 9 if d == 3 else 6
     shape = (3,) + (n,) * d
     flags = ss.SPINSUM_FLAG_CHAIN_STAGES if chain else 0
-    for tile in [(n, 1), (3, 1)]:
-        p = mk(shape, stages, d, flags=flags, tile=tile, inplace=True)
+    for tile, variant in [((n, 1), 0), ((3, 1), 0), ((n, 1), ss.SPINSUM_VARIANT_REG_PIPELINE),
+                          ((3, 1), ss.SPINSUM_VARIANT_REG_ONESHOT)]:
+        p = mk(shape, stages, d, flags=flags, tile=tile, inplace=True, variant=variant)
         x = gpu_uniform(shape, case)
         y = run(p, x)
         assert nerr(y.cpu().numpy(), ref_of(x, stages, d)) <= 1e-14, tile
@@ -171,7 +179,9 @@ def test_factored_form_chained_and_expanded():
 
 
 @pytest.mark.parametrize("flags", [ss.SPINSUM_FLAG_REVERSE_ORDER, ss.SPINSUM_FLAG_NO_XCD_REMAP,
-                                   ss.SPINSUM_FLAG_NO_LDS_PAD, ss.SPINSUM_FLAG_NO_NT_STORES])
+                                   ss.SPINSUM_FLAG_NO_LDS_PAD, ss.SPINSUM_FLAG_NO_NT_STORES,
+                                   ss.SPINSUM_FLAG_NO_DIRECT_LDS,
+                                   ss.SPINSUM_FLAG_NO_DIRECT_LDS | ss.SPINSUM_FLAG_REVERSE_ORDER])
 def test_schedule_variants_are_bitwise_equal(flags):
     shape = (3, 24, 24, 24)
     x = gpu_uniform(shape, 11)
@@ -179,6 +189,10 @@ def test_schedule_variants_are_bitwise_equal(flags):
         base = run(mk(shape, [workloads.CONFIG_3D_ALPHA], 3, inplace=True, tile=tile), x)
         other = run(mk(shape, [workloads.CONFIG_3D_ALPHA], 3, inplace=True, flags=flags, tile=tile), x)
         assert torch.equal(base, other), (flags, tile)
+        for variant in VARIANTS:
+            v = run(mk(shape, [workloads.CONFIG_3D_ALPHA], 3, inplace=True, flags=flags, tile=tile,
+                       variant=variant), x)
+            assert torch.equal(base, v), (flags, tile, variant)
 
 
 def test_empty_tensors_are_no_ops():

@@ -205,7 +205,7 @@ def test_lds_footprint_matches_eq11():
 
 
 @pytest.mark.parametrize("name,bl,whole", [("3d_v16_o8", 8, True), ("3d_v64_o32_slab", 8, False),
-                                           ("4d_v24_o12_slab", 6, False), ("3d_v48_o24", 12, False)])
+                                           ("4d_v24_o12_slab", 6, False), ("3d_v48_o24", 8, False)])
 def test_default_tiles_of_the_workloads(name, bl, whole):
     w = workloads.WORKLOADS[name]
     p = ss.spinsum_plan(w["shape"], w["group_first"], w["d"], [workloads.CONFIG_3D_ALPHA] if w["d"] == 3
@@ -269,3 +269,21 @@ def test_kernel_addresses_replayed_on_host(shape, d, tile, dtype):
         ss.spinsum_plan_set_tile(p, tile[0], cubes_per_wg=tile[1], lds_pad=pad)
         ok, why = ss.spinsum_plan_check_ownership(p)
         assert ok, why
+
+
+def test_direct_lds_variant_uses_dense_tiles():
+    """The direct-LDS kernel lands 16-byte rows in chunk order: unpadded."""
+    for shape, d, dtype, bl in [((3, 32, 32, 32), 3, "f64", 8), ((2, 12, 12, 12, 12), 4, "f64", 6),
+                                ((3, 16, 16, 16), 3, "f32", 8), ((5, 8, 8, 8), 3, "f64", 8)]:
+        p = plan(shape, [[(tuple(range(d)), 1.0)]], d=d, dtype=dtype)
+        ss.spinsum_plan_set_tile(p, bl, lds_pad=1, variant=ss.SPINSUM_VARIANT_DIRECT_LDS)
+        info = ss.spinsum_plan_get_info(p)
+        assert info["variant"] == ss.SPINSUM_VARIANT_DIRECT_LDS and info["lds_pad"] == 0
+        ok, why = ss.spinsum_plan_check_ownership(p)
+        assert ok, why
+    # rows that are not 16 bytes fall back to the register one-shot kernel
+    p = plan((3, 6, 6, 6), [[((0, 1, 2), 1.0)]], dtype="f32")
+    ss.spinsum_plan_set_tile(p, 6, variant=ss.SPINSUM_VARIANT_DIRECT_LDS)
+    assert ss.spinsum_plan_get_info(p)["variant"] == ss.SPINSUM_VARIANT_REG_ONESHOT
+    q = plan((3, 5, 5, 5), [[((0, 1, 2), 1.0)]])
+    assert ss.spinsum_plan_get_info(q)["variant"] == ss.SPINSUM_VARIANT_REG_ONESHOT
