@@ -39,9 +39,11 @@ def log(*a):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("spinsum_kernels.hip", "spinsum_internal.h"):
-        with open(os.path.join(ROOT, "paper_1705_06661_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_1705_06661_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -59,6 +61,17 @@ def traffic_from_profile(name: str, algo_bytes: float):
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def kernel_name(info, dtype="double"):
+    """Name of the device kernel a plan launches, as rocprofv3 lists it."""
+    d = info["d"]
+    v = info["variant"]
+    if v == 1:
+        return f"k_lds<{dtype},{d},false>"
+    if v == 2:
+        return f"k_pipe<{dtype},{d},{info['vector_width']},false,*>"
+    return f"k_exec<{dtype},{d},{info['vector_width']},false,true>"
 
 
 def timed(fn, reps, stream):
@@ -119,7 +132,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the spin summation shards over spectator "
-              "slabs with no communication, so multi-GPU runs are not part of this build.",
+              "slabs with no communication, and no multi-GPU path is implemented.",
               file=sys.stderr)
         sys.exit(2)
 
@@ -169,12 +182,13 @@ def main():
                    "slabs": nslabs, "slab_shape": list(slab_shape), "group": "ijk",
                    "alpha": "id 4, transpositions -2, 3-cycles +1", "inplace": True,
                    "values": "U(-1,1) from seed", "tile_edge": info["bl"],
-                   "tile_orbits_per_cube": info["norbits"]},
+                   "tile_orbits_per_cube": info["norbits"],
+                   "work_items_per_cube": info["items_per_cube"], "tiles_per_item": info["item_tiles"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_GBPS, 4),
                      "traffic": traffic_from_profile("spinsum_3d_v64_o32_inplace",
                                                      algo_per_launch),
-                     "kernel": "k_exec<double,3,2,false,true>",
+                     "kernel": kernel_name(info),
                      "algorithmic_bytes_per_launch": algo_per_launch,
                      "avg_launch_ms": round(launch_ms, 4)},
     }

@@ -83,6 +83,9 @@ typedef struct spinsum_graph_s* spinsum_graph_t;
 #define SPINSUM_VARIANT_REG_PIPELINE 2 /* persistent workgroups, next item prefetched into
                                           registers while the current one is processed   */
 #define SPINSUM_VARIANT_REG_ONESHOT 3  /* one item per workgroup, loads through registers */
+#define SPINSUM_VARIANT_LDS_PIPELINE 4 /* persistent workgroups, direct LDS loads of the next
+                                          item into a second LDS buffer (16-byte rows only;
+                                          unpadded LDS)                                  */
 
 /* Tile configuration (the blocking of Alg. 5a/5b, Sec. 4.5).
  * bl: tile edge along every group axis, 1 <= bl <= N; bl == N processes whole
@@ -96,6 +99,9 @@ typedef struct {
   int threads;
   int lds_pad;
   int variant;
+  int item_tiles;  /* tile-orbit mode: 0 = one tile orbit per work item; > 0 =
+                      orbits of a cube packed (first fit, decreasing size) into
+                      items of at most max(item_tiles, largest orbit) tiles */
 } spinsum_tile_t;
 
 typedef struct {
@@ -111,6 +117,8 @@ typedef struct {
   int nblocks;           /* 1, or the batch size                         */
   int dtype, inplace, vector_width, ragged;
   int fits_lds;          /* 1 if the largest work item fits the LDS of a CU */
+  int items_per_cube;    /* work items (groups of tile orbits) per cube    */
+  int item_tiles;        /* tiles of the largest work item                 */
   int chunks_per_thread; /* 16-byte loads per thread for the largest item */
   int64_t rep_lds_bytes; /* LDS for the element-orbit representatives      */
 } spinsum_plan_info_t;

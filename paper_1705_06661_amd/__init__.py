@@ -59,11 +59,13 @@ SPINSUM_VARIANT_AUTO = 0
 SPINSUM_VARIANT_DIRECT_LDS = 1
 SPINSUM_VARIANT_REG_PIPELINE = 2
 SPINSUM_VARIANT_REG_ONESHOT = 3
+SPINSUM_VARIANT_LDS_PIPELINE = 4
 
 
 class _Tile(ctypes.Structure):
     _fields_ = [("bl", ctypes.c_int), ("cubes_per_wg", ctypes.c_int),
-                ("threads", ctypes.c_int), ("lds_pad", ctypes.c_int), ("variant", ctypes.c_int)]
+                ("threads", ctypes.c_int), ("lds_pad", ctypes.c_int), ("variant", ctypes.c_int),
+                ("item_tiles", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -76,7 +78,8 @@ class _Info(ctypes.Structure):
                 ("lds_bytes", ctypes.c_int64), ("nitems", ctypes.c_int64),
                 ("nblocks", ctypes.c_int), ("dtype", ctypes.c_int), ("inplace", ctypes.c_int),
                 ("vector_width", ctypes.c_int), ("ragged", ctypes.c_int),
-                ("fits_lds", ctypes.c_int), ("chunks_per_thread", ctypes.c_int),
+                ("fits_lds", ctypes.c_int), ("items_per_cube", ctypes.c_int),
+                ("item_tiles", ctypes.c_int), ("chunks_per_thread", ctypes.c_int),
                 ("rep_lds_bytes", ctypes.c_int64)]
 
 
@@ -223,8 +226,10 @@ def spinsum_plan_batched(shapes: Sequence[Sequence[int]], d: int, stages, dtype=
 
 
 def spinsum_plan_set_tile(plan: Plan, bl: int, cubes_per_wg: int = 1, lds_pad: int = 1,
-                          threads: int = 256, variant: int = SPINSUM_VARIANT_AUTO):
-    t = _Tile(int(bl), int(cubes_per_wg), int(threads), int(lds_pad), int(variant))
+                          threads: int = 256, variant: int = SPINSUM_VARIANT_AUTO,
+                          item_tiles: int = 0):
+    t = _Tile(int(bl), int(cubes_per_wg), int(threads), int(lds_pad), int(variant),
+              int(item_tiles))
     _check(_c_set_tile(plan._h, ctypes.byref(t)), "spinsum_plan_set_tile", plan)
 
 
@@ -370,7 +375,8 @@ def spinsum_autotune(plan: Plan, inp: torch.Tensor, out: torch.Tensor, stream=No
     _check(_c_autotune(plan._h, a, b, _stream(stream), cp, ctypes.byref(best), ctypes.byref(ms)),
            "spinsum_autotune", plan)
     return {"bl": best.bl, "cubes_per_wg": best.cubes_per_wg, "threads": best.threads,
-            "lds_pad": best.lds_pad, "variant": best.variant}, float(ms.value)
+            "lds_pad": best.lds_pad, "variant": best.variant,
+            "item_tiles": best.item_tiles}, float(ms.value)
 
 
 def spinsum_stream_copy(inp: torch.Tensor, out: torch.Tensor, stream=None):

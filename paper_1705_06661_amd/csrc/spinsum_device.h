@@ -114,7 +114,7 @@ __device__ __forceinline__ Geom load_geom(const __attribute__((address_space(4))
   g.ncubes = s.ncubes;
   g.n = s.n;
   g.bl = s.bl;
-  g.norbits = s.norbits;
+  g.ngroups = s.ngroups;
   g.cpw = s.cpw;
 #pragma unroll
   for (int m = 0; m < kMaxD; ++m) {
@@ -128,7 +128,7 @@ __device__ __forceinline__ Geom load_geom(const __attribute__((address_space(4))
   g.fd_vpr = load_fd(s.fd_vpr);
   g.fd_rows = load_fd(s.fd_rows);
   g.fd_bl = load_fd(s.fd_bl);
-  g.fd_norbits = load_fd(s.fd_norbits);
+  g.fd_ngroups = load_fd(s.fd_ngroups);
   return g;
 }
 
@@ -136,7 +136,7 @@ template <typename T>
 struct ExecArgs {
   const T* in;
   T* out;
-  const OrbitDev* orbits;
+  const GroupDev* orbits;  // work-item templates (groups of tile orbits)
   const uint32_t* reps;
   const T* coef;    // coefficient vector(s), d! per stage
   Geom g;
@@ -144,15 +144,16 @@ struct ExecArgs {
   int64_t xcd_per;  // > 0: items grouped per XCD (items per XCD range)
   int32_t nstages;  // stages applied one after the other (chain mode)
   int32_t reverse;
-  int32_t lds_tile_bytes;  // start of the representative copy in LDS (k_pipe)
-  int32_t pad;
+  int32_t lds_tile_bytes;  // k_pipe: start of the representative copy in LDS;
+                           // k_ldsp: bytes of one tile buffer
+  int32_t nreps;           // k_ldsp: entries of the shared representative table
 };
 
 template <typename T>
 struct BatchArgs {
   const T* const* in;
   T* const* out;
-  const OrbitDev* orbits;
+  const GroupDev* orbits;  // work-item templates (groups of tile orbits)
   const uint32_t* reps;
   const T* coef;
   const BatchBlock* blocks;
@@ -182,60 +183,67 @@ __device__ __forceinline__ void orbit_product(const T (&a)[Fact<D>::v], const T 
 }
 
 // 2. combine every element orbit of the item in LDS
-// rp: the item's representatives (global memory, or an LDS copy)
-template <typename T, int D, bool CHAIN>
-__device__ __forceinline__ void combine_item(const Geom& g, cptr<OrbitDev> od,
-                                             const uint32_t* rp, cptr<T> coef, int nstages,
+// Combine every element orbit of a work item.  The item's tile orbits are
+// visited in turn (uniform loop); their representatives come from global
+// memory (REPS_IN_LDS false: reps + rep_off[k]) or from the item's LDS copy
+// (true: reps + rep_base[k]).
+template <typename T, int D, bool CHAIN, bool REPS_IN_LDS>
+__device__ __forceinline__ void combine_item(const Geom& g, cptr<GroupDev> gd,
+                                             const uint32_t* reps, cptr<T> coef, int nstages,
                                              int ncub, T* lds) {
   constexpr int DF = Fact<D>::v;
-  int32_t sb[DF];
-#pragma unroll
-  for (int r = 0; r < DF; ++r) sb[r] = od->slot_base[r];
   T a[DF];
   if constexpr (!CHAIN) {
 #pragma unroll
     for (int r = 0; r < DF; ++r) a[r] = coef[r];
   }
-  const uint32_t rep_cnt = (uint32_t)od->rep_cnt;
-  const uint32_t nrep = (uint32_t)ncub * rep_cnt;
-  const FastDiv fdr = load_fd(od->fd_rep);
-  for (uint32_t i = threadIdx.x; i < nrep; i += kThreads) {
-    uint32_t ci = (ncub == 1) ? 0u : fdiv(i, fdr);
-    uint32_t ri = i - ci * rep_cnt;
-    uint32_t pk = rp[ri];
-    int l[D];
+  const int norb = gd->norb;
+  for (int k = 0; k < norb; ++k) {
+    int32_t sb[DF];
 #pragma unroll
-    for (int m = 0; m < D; ++m) l[m] = (int)((pk >> (8 * m)) & 255u);
-    const int base = (int)ci * g.cube_lds;
-    int addr[DF];
-    T v[DF];
-    T w[DF];
-    orbit_addrs<D>(g, base, sb, l, addr, std::make_integer_sequence<int, DF>{});
+    for (int r = 0; r < DF; ++r) sb[r] = gd->slot_base[k][r];
+    const uint32_t rep_cnt = (uint32_t)gd->rep_cnt[k];
+    const uint32_t nrep = (uint32_t)ncub * rep_cnt;
+    const FastDiv fdr = load_fd(gd->fd_rep[k]);
+    const uint32_t* rp = reps + (REPS_IN_LDS ? gd->rep_base[k] : gd->rep_off[k]);
+    for (uint32_t i = threadIdx.x; i < nrep; i += kThreads) {
+      uint32_t ci = (ncub == 1) ? 0u : fdiv(i, fdr);
+      uint32_t ri = i - ci * rep_cnt;
+      uint32_t pk = rp[ri];
+      int l[D];
 #pragma unroll
-    for (int r = 0; r < DF; ++r) v[r] = lds[addr[r]];
-    if constexpr (!CHAIN) {
-      orbit_product<T, D>(a, v, w);
-    } else {
-      for (int k = 0; k < nstages; ++k) {
+      for (int m = 0; m < D; ++m) l[m] = (int)((pk >> (8 * m)) & 255u);
+      const int base = (int)ci * g.cube_lds;
+      int addr[DF];
+      T v[DF];
+      T w[DF];
+      orbit_addrs<D>(g, base, sb, l, addr, std::make_integer_sequence<int, DF>{});
 #pragma unroll
-        for (int r = 0; r < DF; ++r) a[r] = coef[k * DF + r];
+      for (int r = 0; r < DF; ++r) v[r] = lds[addr[r]];
+      if constexpr (!CHAIN) {
         orbit_product<T, D>(a, v, w);
+      } else {
+        for (int s = 0; s < nstages; ++s) {
 #pragma unroll
-        for (int r = 0; r < DF; ++r) v[r] = w[r];
+          for (int r = 0; r < DF; ++r) a[r] = coef[s * DF + r];
+          orbit_product<T, D>(a, v, w);
+#pragma unroll
+          for (int r = 0; r < DF; ++r) v[r] = w[r];
+        }
+#pragma unroll
+        for (int r = 0; r < DF; ++r) w[r] = v[r];
       }
 #pragma unroll
-      for (int r = 0; r < DF; ++r) w[r] = v[r];
+      for (int r = 0; r < DF; ++r) lds[addr[r]] = w[r];
     }
-#pragma unroll
-    for (int r = 0; r < DF; ++r) lds[addr[r]] = w[r];
   }
 }
 
-__device__ __forceinline__ void stage_tinfo(int32_t* tinfo, const OrbitDev* __restrict__ od) {
-  const int nt = od->ntiles;
+__device__ __forceinline__ void stage_tinfo(int32_t* tinfo, const GroupDev* __restrict__ gd) {
+  const int nt = gd->ntiles;
   if ((int)threadIdx.x < nt) {
-    tinfo[threadIdx.x] = od->tile_off[threadIdx.x];
-    tinfo[kMaxDF + threadIdx.x] = od->tile_ext[threadIdx.x];
+    tinfo[threadIdx.x] = gd->tile_off[threadIdx.x];
+    tinfo[kMaxDF + threadIdx.x] = gd->tile_ext[threadIdx.x];
   }
 }
 
@@ -306,9 +314,9 @@ __device__ __forceinline__ void decode_item(const Geom& g, int64_t item, int64_t
     int64_t left = g.ncubes - *cube0;
     *ncub = (int)(left < g.cpw ? left : g.cpw);
   } else {
-    uint32_t q = fdiv((uint32_t)item, g.fd_norbits);
+    uint32_t q = fdiv((uint32_t)item, g.fd_ngroups);
     *cube0 = q;
-    *orbit = (int)((uint32_t)item - q * (uint32_t)g.norbits);
+    *orbit = (int)((uint32_t)item - q * (uint32_t)g.ngroups);
     *ncub = 1;
   }
 }
@@ -331,8 +339,8 @@ __global__ void __launch_bounds__(kThreads) k_exec(const ExecArgs<T> a) {
   int64_t cube0;
   int orbit, ncub;
   decode_item(g, item, &cube0, &orbit, &ncub);
-  const OrbitDev* od = a.orbits + orbit;
-  cptr<OrbitDev> cod = as_const(od);
+  const GroupDev* od = a.orbits + orbit;
+  cptr<GroupDev> cod = as_const(od);
   stage_tinfo(tinfo, od);
   __syncthreads();
   const int ntiles = cod->ntiles;
@@ -354,9 +362,162 @@ __global__ void __launch_bounds__(kThreads) k_exec(const ExecArgs<T> a) {
     fill_lds<T, VW, kUnroll>(buf, lo, lds);
   }
   __syncthreads();
-  combine_item<T, D, CHAIN>(g, cod, a.reps + cod->rep_off, as_const(a.coef), a.nstages, ncub, lds);
+  combine_item<T, D, CHAIN, false>(g, cod, a.reps, as_const(a.coef), a.nstages, ncub, lds);
   __syncthreads();
   store_item<T, D, VW, NTS>(g, tinfo, ntiles, ragged, nchunks, a.out + cube0 * g.cube_elems, lds);
+}
+
+// Chunk c (VW elements) of a full tile, chunks in row-major order: its
+// element offset inside the cube.  *ok is false for chunks past the tile and
+// for chunks outside the extent of a ragged tile (ext packs one byte per
+// index).
+template <int D, int VW>
+__device__ __forceinline__ int tile_chunk(const Geom& g, uint32_t c, uint32_t cpt, int ext,
+                                          bool ragged, bool* ok) {
+  uint32_t q = fdiv(c, g.fd_vpr);
+  int l[D];
+  l[D - 1] = (int)(c - q * (uint32_t)g.vpr) * VW;
+  if constexpr (D == 2) {
+    l[0] = (int)q;
+  } else {
+    uint32_t r = q;
+#pragma unroll
+    for (int m = D - 2; m >= 1; --m) {
+      uint32_t qq = fdiv(r, g.fd_bl);
+      l[m] = (int)(r - qq * (uint32_t)g.bl);
+      r = qq;
+    }
+    l[0] = (int)r;
+  }
+  bool in = c < cpt;
+  if (ragged) {
+#pragma unroll
+    for (int m = 0; m < D; ++m) in = in && (l[m] < ((ext >> (8 * m)) & 255));
+  }
+  *ok = in;
+  int off = 0;
+#pragma unroll
+  for (int m = 0; m < D; ++m) off += l[m] * g.gst[m];
+  return off;
+}
+
+// Issue the loads of one item straight into LDS (global_load_lds_dwordx4:
+// lane i of a wave writes 16 bytes at the wave's LDS base + 16 i).  LDS
+// holds the tiles densely in chunk order: tile t at element t * ts, chunk c
+// at c * VW.  Returns, uniformly over the wave, how many load instructions
+// this wave issued with at least one active lane -- a lower bound on the
+// vector-memory operations the item added to the wave's vmcnt.
+template <typename T, int D>
+__device__ __forceinline__ int issue_item_lds(const Geom& g, cptr<GroupDev> od, bool whole,
+                                              int ntl, bool ragged, const T* src,
+                                              unsigned char* lds_bytes) {
+  constexpr int VW = 16 / sizeof(T);
+  const uint32_t cpt = (uint32_t)g.rows * (uint32_t)g.vpr;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t wave_bytes = (tid >> 6) * 1024u;
+  int issued = 0;
+  for (int t = 0; t < ntl; ++t) {
+    const int toff = whole ? t * (int)g.cube_elems : od->tile_off[t];
+    const int text = whole ? 0 : od->tile_ext[t];
+    for (uint32_t c0 = 0; c0 < cpt; c0 += kThreads) {
+      bool ok;
+      const int off = tile_chunk<D, VW>(g, c0 + tid, cpt, text, ragged, &ok);
+      const uint32_t lbyte = (uint32_t)(t * g.ts + (int)c0 * VW) * (uint32_t)sizeof(T) + wave_bytes;
+      if (ok)
+        __builtin_amdgcn_global_load_lds(
+            (const void*)(src + toff + off),
+            (__attribute__((address_space(3))) void*)(lds_bytes + lbyte), 16, 0, 0);
+      issued += (__builtin_amdgcn_ballot_w64(ok) != 0ull) ? 1 : 0;
+    }
+  }
+  return __builtin_amdgcn_readfirstlane(issued);
+}
+
+// Issue the loads of an item's representative lists straight into LDS
+// (global_load_lds_dword: lane i of a wave writes 4 bytes at the wave's LDS
+// base + 4 i): orbit k's list goes to rep_lds + rep_base[k].
+__device__ __forceinline__ void issue_reps_lds(cptr<GroupDev> od, const uint32_t* reps,
+                                               unsigned char* rep_lds) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t wave0 = tid & ~63u;
+  const int norb = od->norb;
+  for (int k = 0; k < norb; ++k) {
+    const uint32_t cnt = (uint32_t)od->rep_cnt[k];
+    const uint32_t* src = reps + od->rep_off[k];
+    unsigned char* dst = rep_lds + (uint32_t)od->rep_base[k] * 4u;
+    for (uint32_t i0 = 0; i0 < cnt; i0 += kThreads) {
+      if (i0 + tid < cnt)
+        __builtin_amdgcn_global_load_lds(
+            (const void*)(src + i0 + tid),
+            (__attribute__((address_space(3))) void*)(dst + (i0 + wave0) * 4u), 4, 0, 0);
+    }
+  }
+}
+
+// Store every tile of an item from its dense LDS copy (non-temporal when
+// NTS).
+template <typename T, int D, bool NTS>
+__device__ __forceinline__ void store_item_lds(const Geom& g, cptr<GroupDev> od, bool whole,
+                                               int ntl, bool ragged, T* dst, const T* lds) {
+  constexpr int VW = 16 / sizeof(T);
+  typedef typename VecT<T, VW>::type V;
+  const uint32_t cpt = (uint32_t)g.rows * (uint32_t)g.vpr;
+  for (int t = 0; t < ntl; ++t) {
+    const int toff = whole ? t * (int)g.cube_elems : od->tile_off[t];
+    const int text = whole ? 0 : od->tile_ext[t];
+    for (uint32_t c0 = 0; c0 < cpt; c0 += kThreads) {
+      bool ok;
+      const uint32_t c = c0 + threadIdx.x;
+      const int off = tile_chunk<D, VW>(g, c, cpt, text, ragged, &ok);
+      if (ok) {
+        const V val = *reinterpret_cast<const V*>(lds + t * g.ts + (int)c * VW);
+        V* p = reinterpret_cast<V*>(dst + toff + off);
+        if constexpr (NTS)
+          __builtin_nontemporal_store(val, p);
+        else
+          *p = val;
+      }
+    }
+  }
+}
+
+// Workgroup barrier for LDS written by ds_write only: wait for this wave's
+// LDS operations (lgkmcnt(0), gfx9 encoding), then s_barrier; the signal
+// fences keep the compiler from moving memory accesses across it.  A
+// workgroup fence (__syncthreads) would also drain the vector memory
+// counter, which holds the direct-to-LDS loads of the next item that are
+// meant to stay in flight across the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// s_waitcnt vmcnt(n) for a wave-uniform n: wait until at most n vector
+// memory operations of this wave are outstanding (they complete in issue
+// order).  Immediates in the gfx9 encoding (vmcnt in bits 3:0 and 15:14,
+// expcnt and lgkmcnt left at their no-wait values); n above 31 waits for
+// 31, which is stricter.
+__device__ __forceinline__ void wait_vmcnt_atmost(int n) {
+#define SPINSUM_VMCNT(N) \
+  case N:                \
+    __builtin_amdgcn_s_waitcnt(((N) & 15) | (0x7 << 4) | (0xF << 8) | (((N) >> 4) << 14)); \
+    break;
+  switch (n) {
+    SPINSUM_VMCNT(0) SPINSUM_VMCNT(1) SPINSUM_VMCNT(2) SPINSUM_VMCNT(3)
+    SPINSUM_VMCNT(4) SPINSUM_VMCNT(5) SPINSUM_VMCNT(6) SPINSUM_VMCNT(7)
+    SPINSUM_VMCNT(8) SPINSUM_VMCNT(9) SPINSUM_VMCNT(10) SPINSUM_VMCNT(11)
+    SPINSUM_VMCNT(12) SPINSUM_VMCNT(13) SPINSUM_VMCNT(14) SPINSUM_VMCNT(15)
+    SPINSUM_VMCNT(16) SPINSUM_VMCNT(17) SPINSUM_VMCNT(18) SPINSUM_VMCNT(19)
+    SPINSUM_VMCNT(20) SPINSUM_VMCNT(21) SPINSUM_VMCNT(22) SPINSUM_VMCNT(23)
+    SPINSUM_VMCNT(24) SPINSUM_VMCNT(25) SPINSUM_VMCNT(26) SPINSUM_VMCNT(27)
+    SPINSUM_VMCNT(28) SPINSUM_VMCNT(29) SPINSUM_VMCNT(30)
+    default:
+      __builtin_amdgcn_s_waitcnt((31 & 15) | (0x7 << 4) | (0xF << 8) | ((31 >> 4) << 14));
+      break;
+  }
+#undef SPINSUM_VMCNT
 }
 
 // One-shot with direct global->LDS loads (global_load_lds_dwordx4, 16 bytes
@@ -365,11 +526,12 @@ __global__ void __launch_bounds__(kThreads) k_exec(const ExecArgs<T> a) {
 // chunk c of a tile at c * VW -- which is the unpadded tile layout, so the
 // planner builds this variant's tables with lds_pad = 0.  Tiles of a tile
 // orbit, or the cubes of a whole-cube item, are visited with a uniform loop
-// so that their base offsets come from scalar loads.
-template <typename T, int D, bool CHAIN>
+// so that their base offsets come from scalar loads.  The item's
+// representative lists are loaded into LDS behind the tiles in the same
+// way, so the combine step issues no global loads.
+// LDS: [tiles (lds_tile_bytes) | representatives (rep_total entries)].
+template <typename T, int D, bool CHAIN, bool NTS>
 __global__ void __launch_bounds__(kThreads) k_lds(const ExecArgs<T> a) {
-  constexpr int VW = 16 / sizeof(T);
-  typedef typename VecT<T, VW>::type V;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
   int64_t item;
@@ -383,75 +545,99 @@ __global__ void __launch_bounds__(kThreads) k_lds(const ExecArgs<T> a) {
   int64_t cube0;
   int orbit, ncub;
   decode_item(g, item, &cube0, &orbit, &ncub);
-  const cptr<OrbitDev> od = as_const(a.orbits + orbit);
+  const cptr<GroupDev> od = as_const(a.orbits + orbit);
   const bool whole = (g.bl == g.n);
   const int ntl = whole ? ncub : od->ntiles;
   const bool ragged = od->ragged != 0;
-  const uint32_t cpt = (uint32_t)g.rows * (uint32_t)g.vpr;  // chunks per full tile
-  const T* src = a.in + cube0 * g.cube_elems;
-  T* dst = a.out + cube0 * g.cube_elems;
-  const uint32_t tid = threadIdx.x;
-  const uint32_t wave_bytes = (tid >> 6) * 1024u;
-  // per-lane position of chunk c inside a tile: offset and local coordinates
-  auto chunk_in_tile = [&](uint32_t c, int ext, bool* ok) -> int {
-    uint32_t q = fdiv(c, g.fd_vpr);
-    int l[D];
-    l[D - 1] = (int)(c - q * (uint32_t)g.vpr) * VW;
-    if constexpr (D == 2) {
-      l[0] = (int)q;
-    } else {
-      uint32_t r = q;
-#pragma unroll
-      for (int m = D - 2; m >= 1; --m) {
-        uint32_t qq = fdiv(r, g.fd_bl);
-        l[m] = (int)(r - qq * (uint32_t)g.bl);
-        r = qq;
-      }
-      l[0] = (int)r;
-    }
-    bool in = c < cpt;
-    if (ragged) {
-#pragma unroll
-      for (int m = 0; m < D; ++m) in = in && (l[m] < ((ext >> (8 * m)) & 255));
-    }
-    *ok = in;
-    int off = 0;
-#pragma unroll
-    for (int m = 0; m < D; ++m) off += l[m] * g.gst[m];
-    return off;
-  };
-  // 1. loads straight into LDS
-  for (int t = 0; t < ntl; ++t) {
-    const int toff = whole ? t * (int)g.cube_elems : od->tile_off[t];
-    const int text = whole ? 0 : od->tile_ext[t];
-    for (uint32_t c0 = 0; c0 < cpt; c0 += kThreads) {
-      bool ok;
-      const int off = chunk_in_tile(c0 + tid, text, &ok);
-      const uint32_t lbyte = (uint32_t)(t * g.ts + (int)c0 * VW) * (uint32_t)sizeof(T) + wave_bytes;
-      if (ok)
-        __builtin_amdgcn_global_load_lds(
-            (const void*)(src + toff + off),
-            (__attribute__((address_space(3))) void*)(smem + lbyte), 16, 0, 0);
-    }
-  }
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the tiles are in LDS
+  // 1. tiles and representative lists straight into LDS, all in flight
+  //    together
+  unsigned char* rep_lds = smem + a.lds_tile_bytes;
+  issue_item_lds<T, D>(g, od, whole, ntl, ragged, a.in + cube0 * g.cube_elems, smem);
+  issue_reps_lds(od, a.reps, rep_lds);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): everything is in LDS
   __syncthreads();
   // 2. combine
-  combine_item<T, D, CHAIN>(g, od, a.reps + od->rep_off, as_const(a.coef), a.nstages, ncub, lds);
+  combine_item<T, D, CHAIN, true>(g, od, reinterpret_cast<const uint32_t*>(rep_lds),
+                                  as_const(a.coef), a.nstages, ncub, lds);
   __syncthreads();
   // 3. store
-  for (int t = 0; t < ntl; ++t) {
-    const int toff = whole ? t * (int)g.cube_elems : od->tile_off[t];
-    const int text = whole ? 0 : od->tile_ext[t];
-    for (uint32_t c0 = 0; c0 < cpt; c0 += kThreads) {
-      bool ok;
-      const uint32_t c = c0 + tid;
-      const int off = chunk_in_tile(c, text, &ok);
-      if (ok) {
-        const V val = *reinterpret_cast<const V*>(lds + t * g.ts + (int)c * VW);
-        __builtin_nontemporal_store(val, reinterpret_cast<V*>(dst + toff + off));
-      }
+  store_item_lds<T, D, NTS>(g, od, whole, ntl, ragged, a.out + cube0 * g.cube_elems, lds);
+}
+
+// Persistent, double-buffered direct-LDS loads: while item k is combined
+// and stored from one LDS buffer, the loads of item k+1 fill the other.
+// The representative table of every orbit pattern is copied to LDS once.
+// gridDim.x is a multiple of 8; workgroup j of XCD x walks the items of
+// that XCD's contiguous range with stride gridDim.x / 8, so that the
+// workgroups of one XCD work on neighbouring items at any time.
+// LDS: [representatives (nreps, padded to 16 bytes) | buffer 0 | buffer 1].
+template <typename T, int D, bool CHAIN, bool NTS>
+__global__ void __launch_bounds__(kThreads) k_ldsp(const ExecArgs<T> a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const Geom& g = a.g;
+  uint32_t* rep_lds = reinterpret_cast<uint32_t*>(smem);
+  const uint32_t rep_bytes = ((uint32_t)a.nreps * 4u + 15u) & ~15u;
+  unsigned char* buf0 = smem + rep_bytes;
+  const uint32_t bb = (uint32_t)a.lds_tile_bytes;
+  const int64_t x = blockIdx.x & 7u;
+  const int64_t nj = gridDim.x >> 3;
+  auto item_at = [&](int64_t k) -> int64_t {
+    int64_t it;
+    if (a.xcd_per > 0) {
+      int64_t L = (int64_t)(blockIdx.x >> 3) + k * nj;
+      if (L >= a.xcd_per) return -1;
+      it = x * a.xcd_per + L;
+    } else {
+      it = (int64_t)blockIdx.x + k * (int64_t)gridDim.x;
     }
+    if (it >= a.nitems) return -1;
+    return a.reverse ? a.nitems - 1 - it : it;
+  };
+  int64_t it = item_at(0);
+  if (it < 0) return;
+  for (int i = threadIdx.x; i < a.nreps; i += kThreads) rep_lds[i] = a.reps[i];
+  const bool whole = (g.bl == g.n);
+  const cptr<T> coef = as_const(a.coef);
+  int64_t cube0;
+  int orbit, ncub;
+  decode_item(g, it, &cube0, &orbit, &ncub);
+  cptr<GroupDev> od = as_const(a.orbits + orbit);
+  int ntl = whole ? ncub : od->ntiles;
+  bool ragged = od->ragged != 0;
+  issue_item_lds<T, D>(g, od, whole, ntl, ragged, a.in + cube0 * g.cube_elems, buf0);
+  uint32_t par = 0;
+  for (int64_t k = 0;; ++k) {
+    const int64_t nx = item_at(k + 1);
+    int64_t cube0n = 0;
+    int orbitn = 0, ncubn = 0, ntln = 0;
+    cptr<GroupDev> odn = od;
+    bool raggedn = false;
+    int pending = 0;
+    if (nx >= 0) {
+      decode_item(g, nx, &cube0n, &orbitn, &ncubn);
+      odn = as_const(a.orbits + orbitn);
+      ntln = whole ? ncubn : odn->ntiles;
+      raggedn = odn->ragged != 0;
+      pending = issue_item_lds<T, D>(g, odn, whole, ntln, raggedn, a.in + cube0n * g.cube_elems,
+                                     buf0 + (par ^ 1u) * bb);
+    }
+    // everything but the next item's loads has completed: this item's tiles
+    // are in LDS (and the previous item's stores have left)
+    wait_vmcnt_atmost(pending);
+    lds_barrier();
+    T* lds = reinterpret_cast<T*>(buf0 + par * bb);
+    combine_item<T, D, CHAIN, false>(g, od, rep_lds, coef, a.nstages, ncub, lds);
+    lds_barrier();
+    store_item_lds<T, D, NTS>(g, od, whole, ntl, ragged, a.out + cube0 * g.cube_elems, lds);
+    // the buffer is refilled two items on: every wave has read it by then
+    lds_barrier();
+    if (nx < 0) break;
+    cube0 = cube0n;
+    ncub = ncubn;
+    od = odn;
+    ntl = ntln;
+    ragged = raggedn;
+    par ^= 1u;
   }
 }
 
@@ -493,7 +679,7 @@ __global__ void __launch_bounds__(kThreads) k_pipe(const ExecArgs<T> a) {
   int64_t cube0;
   int orbit, ncub;
   decode_item(g, it, &cube0, &orbit, &ncub);
-  const OrbitDev* od = a.orbits + orbit;
+  const GroupDev* od = a.orbits + orbit;
   stage_tinfo(tinfo[0], od);
   __syncthreads();
   V buf[MAXC];
@@ -508,7 +694,7 @@ __global__ void __launch_bounds__(kThreads) k_pipe(const ExecArgs<T> a) {
     const int64_t nx = item_at(k + 1);
     int64_t cube0n = 0;
     int orbitn = 0, ncubn = 0;
-    const OrbitDev* odn = od;
+    const GroupDev* odn = od;
     // A.
     if (nx >= 0) {
       decode_item(g, nx, &cube0n, &orbitn, &ncubn);
@@ -516,10 +702,14 @@ __global__ void __launch_bounds__(kThreads) k_pipe(const ExecArgs<T> a) {
       stage_tinfo(tinfo[par ^ 1], odn);
     }
     {
-      cptr<OrbitDev> cod = as_const(od);
-      const int rc = cod->rep_cnt;
-      const uint32_t* rsrc = a.reps + cod->rep_off;
-      for (int i = threadIdx.x; i < rc; i += kThreads) rep_lds[i] = rsrc[i];
+      cptr<GroupDev> cod = as_const(od);
+      const int norb = cod->norb;
+      for (int kk = 0; kk < norb; ++kk) {
+        const int rc = cod->rep_cnt[kk];
+        const uint32_t* rsrc = a.reps + cod->rep_off[kk];
+        uint32_t* rdst = rep_lds + cod->rep_base[kk];
+        for (int i = threadIdx.x; i < rc; i += kThreads) rdst[i] = rsrc[i];
+      }
     }
     fill_lds<T, VW, MAXC>(buf, lo, lds);
     // Every load of the previous phase has landed.  Saying so explicitly
@@ -539,7 +729,7 @@ __global__ void __launch_bounds__(kThreads) k_pipe(const ExecArgs<T> a) {
                                   a.in + cube0n * g.cube_elems, buf, lo);
     }
     // C.
-    combine_item<T, D, CHAIN>(g, as_const(od), rep_lds, coef, a.nstages, ncub, lds);
+    combine_item<T, D, CHAIN, true>(g, as_const(od), rep_lds, coef, a.nstages, ncub, lds);
     __syncthreads();
     // D.
     store_item<T, D, VW, true>(g, tinfo[par], ntiles, ragged, nchunks,
@@ -571,8 +761,8 @@ __global__ void __launch_bounds__(kThreads) k_batched(const BatchArgs<T> a) {
     const Geom g = load_geom(as_const(a.blocks)[blk].g);
     const T* src = as_const(a.in)[blk] + icube0 * g.cube_elems;
     T* dst = as_const(a.out)[blk] + icube0 * g.cube_elems;
-    const OrbitDev* od = a.orbits + item->orbit;
-    cptr<OrbitDev> cod = as_const(od);
+    const GroupDev* od = a.orbits + item->group;
+    cptr<GroupDev> cod = as_const(od);
     stage_tinfo(tinfo, od);
     __syncthreads();
     const int ntiles = cod->ntiles;
@@ -594,7 +784,7 @@ __global__ void __launch_bounds__(kThreads) k_batched(const BatchArgs<T> a) {
       fill_lds<T, VW, kUnroll>(buf, lo, lds);
     }
     __syncthreads();
-    combine_item<T, D, false>(g, cod, a.reps + cod->rep_off, as_const(a.coef), 1, incubes, lds);
+    combine_item<T, D, false, false>(g, cod, a.reps, as_const(a.coef), 1, incubes, lds);
     __syncthreads();
     store_item<T, D, VW, true>(g, tinfo, ntiles, ragged, nchunks, dst, lds);
     __syncthreads();
@@ -627,10 +817,17 @@ const void* pipe_kernel(int vw) {
 }
 
 // kind: 1 direct-LDS one-shot, 2 register-prefetch persistent (maxc = 8 or
-// 16), 3 register one-shot
+// 16), 3 register one-shot, 4 direct-LDS double-buffered persistent
 template <typename T, int D>
 const void* pick_d(int kind, int vw, bool chain, bool nts, int maxc) {
-  if (kind == 1) return chain ? (const void*)k_lds<T, D, true> : (const void*)k_lds<T, D, false>;
+  if (kind == 1) {
+    if (chain) return nts ? (const void*)k_lds<T, D, true, true> : (const void*)k_lds<T, D, true, false>;
+    return nts ? (const void*)k_lds<T, D, false, true> : (const void*)k_lds<T, D, false, false>;
+  }
+  if (kind == 4) {
+    if (chain) return nts ? (const void*)k_ldsp<T, D, true, true> : (const void*)k_ldsp<T, D, true, false>;
+    return nts ? (const void*)k_ldsp<T, D, false, true> : (const void*)k_ldsp<T, D, false, false>;
+  }
   if (kind == 2) {
     if (maxc == 8) return chain ? pipe_kernel<T, D, true, 8>(vw) : pipe_kernel<T, D, false, 8>(vw);
     return chain ? pipe_kernel<T, D, true, 16>(vw) : pipe_kernel<T, D, false, 16>(vw);

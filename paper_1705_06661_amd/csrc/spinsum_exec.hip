@@ -91,7 +91,7 @@ spinsum_status launch_exec(spinsum_plan_s* P, const void* in, void* out, hipStre
   std::memset(&a, 0, sizeof(a));
   a.in = reinterpret_cast<const T*>(in);
   a.out = reinterpret_cast<T*>(out);
-  a.orbits = reinterpret_cast<const OrbitDev*>(P->d_orbits);
+  a.orbits = reinterpret_cast<const GroupDev*>(P->d_orbits);
   a.reps = reinterpret_cast<const uint32_t*>(P->d_reps);
   if (!chain) {
     a.coef = coef + (adjoint ? df : 0);
@@ -105,17 +105,20 @@ spinsum_status launch_exec(spinsum_plan_s* P, const void* in, void* out, hipStre
   a.reverse = (P->flags & SPINSUM_FLAG_REVERSE_ORDER) ? 1 : 0;
   // kernel variant chosen by the planner (see spinsum_tile_t.variant)
   int kind = P->tile.variant;
-  if (!nts && kind != SPINSUM_VARIANT_REG_ONESHOT) kind = SPINSUM_VARIANT_REG_ONESHOT;
+  if (!nts && kind == SPINSUM_VARIANT_REG_PIPELINE) kind = SPINSUM_VARIANT_REG_ONESHOT;
   const int maxc = (kind == SPINSUM_VARIANT_REG_PIPELINE) ? (Tl.chunks_per_thread <= 8 ? 8 : 16) : 0;
   const void* k = pick_kernel<T>(P->d, kind, Tl.vw, chain, nts, maxc);
   a.lds_tile_bytes = (int32_t)(((size_t)Tl.lds_elems * sizeof(T) + 15) / 16 * 16);
-  const size_t shmem = (kind == SPINSUM_VARIANT_REG_PIPELINE)
-                           ? (size_t)a.lds_tile_bytes + (size_t)Tl.max_rep_cnt * 4
-                           : (size_t)Tl.lds_elems * sizeof(T);
+  a.nreps = (int32_t)Tl.reps.size();
+  size_t shmem = (size_t)Tl.lds_elems * sizeof(T);
+  if (kind == SPINSUM_VARIANT_REG_PIPELINE || kind == SPINSUM_VARIANT_DIRECT_LDS)
+    shmem = (size_t)a.lds_tile_bytes + (size_t)Tl.max_rep_cnt * 4;
+  else if (kind == SPINSUM_VARIANT_LDS_PIPELINE)
+    shmem = ((size_t)a.nreps * 4 + 15) / 16 * 16 + 2 * (size_t)a.lds_tile_bytes;
   spinsum_status st = prepare_kernel(P, k, shmem);
   if (st != SPINSUM_OK) return st;
   int64_t grid;
-  if (kind == SPINSUM_VARIANT_REG_PIPELINE) {
+  if (kind == SPINSUM_VARIANT_REG_PIPELINE || kind == SPINSUM_VARIANT_LDS_PIPELINE) {
     st = persistent_grid(P, k, shmem, Tl.nitems, &grid);
     if (st != SPINSUM_OK) return st;
     a.xcd_per = (P->flags & SPINSUM_FLAG_NO_XCD_REMAP) ? 0 : (Tl.nitems + 7) / 8;
@@ -140,7 +143,7 @@ spinsum_status launch_batched(spinsum_plan_s* P, const void* const* in, void* co
   std::memset(&a, 0, sizeof(a));
   a.in = reinterpret_cast<const T* const*>(in);
   a.out = reinterpret_cast<T* const*>(out);
-  a.orbits = reinterpret_cast<const OrbitDev*>(P->d_orbits);
+  a.orbits = reinterpret_cast<const GroupDev*>(P->d_orbits);
   a.reps = reinterpret_cast<const uint32_t*>(P->d_reps);
   a.coef = reinterpret_cast<const T*>(P->d_mats);
   a.blocks = reinterpret_cast<const BatchBlock*>(P->d_blocks);

@@ -51,16 +51,25 @@ inline FastDiv make_fastdiv(uint32_t d) {
   return f;
 }
 
-// One tile orbit of the block grid of a cube.
-struct alignas(16) OrbitDev {
-  int32_t ntiles;    // distinct tiles sigma . B
-  int32_t rep_off;   // first representative in the representative pool
-  int32_t rep_cnt;   // number of element-orbit representatives
-  int32_t ragged;    // 1 if some tile is cut by the cube edge
-  FastDiv fd_rep;    // / rep_cnt
-  int32_t tile_off[kMaxDF];  // element offset of each tile origin inside the cube
-  int32_t tile_ext[kMaxDF];  // extents of each tile, 8 bits per axis (axis 0 lowest)
-  int32_t slot_base[kMaxDF]; // LDS element offset of tile sigma . B, sigma in lex order
+constexpr int kMaxGroupTiles = 24;   // tiles of one work item
+constexpr int kMaxGroupOrbits = 8;   // tile orbits of one work item
+
+// One work item template of a cube: a group of tile orbits {sigma . B_k}
+// whose tiles sit side by side in LDS (orbit k's tiles after those of
+// orbits 0..k-1).  Grouping small orbits (the diagonal ones hold 1 tile, a
+// generic 3D one 6) evens the bytes each workgroup moves.
+struct alignas(16) GroupDev {
+  int32_t ntiles;     // tiles of all orbits of the group
+  int32_t norb;       // orbits in the group
+  int32_t ragged;     // 1 if some tile is cut by the cube edge
+  int32_t rep_total;  // representatives of all orbits of the group
+  int32_t tile_off[kMaxGroupTiles];  // element offset of each tile origin inside the cube
+  int32_t tile_ext[kMaxGroupTiles];  // extents of each tile, 8 bits per axis (axis 0 lowest)
+  int32_t rep_off[kMaxGroupOrbits];  // first representative of orbit k in the pool
+  int32_t rep_cnt[kMaxGroupOrbits];  // representatives of orbit k
+  int32_t rep_base[kMaxGroupOrbits]; // prefix sum of rep_cnt
+  FastDiv fd_rep[kMaxGroupOrbits];   // / rep_cnt[k]
+  int32_t slot_base[kMaxGroupOrbits][kMaxDF];  // LDS element offset of tile sigma . B_k
 };
 
 // Geometry of one tensor (or one block of a batch).
@@ -69,7 +78,7 @@ struct alignas(16) Geom {
   int64_t ncubes;      // spectator cubes
   int32_t n;           // group extent N
   int32_t bl;          // tile edge
-  int32_t norbits;     // tile orbits per cube
+  int32_t ngroups;     // work items (groups of tile orbits) per cube
   int32_t cpw;         // cubes per workgroup (whole-cube mode), else 1
   int32_t gst[kMaxD];  // element strides of the group axes inside a cube
   int32_t lst[kMaxD];  // LDS strides of a tile (padded)
@@ -80,7 +89,7 @@ struct alignas(16) Geom {
   FastDiv fd_vpr;      // / vpr
   FastDiv fd_rows;     // / rows
   FastDiv fd_bl;       // / bl
-  FastDiv fd_norbits;  // / norbits
+  FastDiv fd_ngroups;  // / ngroups
 };
 
 // One item of a batched launch: a run of whole cubes, or one tile orbit of
@@ -88,14 +97,14 @@ struct alignas(16) Geom {
 struct alignas(16) BatchItem {
   int64_t cube0;
   int32_t block;
-  int32_t orbit;   // global index into the orbit pool
+  int32_t group;   // global index into the group pool
   int32_t ncubes;
   int32_t pad;
 };
 
 struct alignas(16) BatchBlock {
   Geom g;
-  int32_t orbit_base;
+  int32_t group_base;
   int32_t pad[3];
 };
 

@@ -17,7 +17,8 @@
 using spinsum::BatchBlock;
 using spinsum::BatchItem;
 using spinsum::Geom;
-using spinsum::OrbitDev;
+using spinsum::GroupDev;
+using spinsum::OrbitHost;
 using spinsum::Tiling;
 
 namespace spinsum {
@@ -208,39 +209,37 @@ spinsum_status build_tiling(const spinsum_plan_s& P, int n, int64_t ncubes,
   g.fd_rows = make_fastdiv((uint32_t)g.rows);
   g.fd_bl = make_fastdiv((uint32_t)bl);
 
-  // representative lists, shared by orbits with the same tie pattern and extents
-  std::map<std::vector<int>, std::pair<int, int>> rep_index;
+  // 1. tile orbits: one per sorted block tuple B (the loop nest of Alg. 5a)
+  std::map<std::vector<int>, std::pair<int, int>> rep_index;  // shared representative lists
   std::vector<int> B(d, 0);
   while (true) {
-    OrbitDev od;
-    std::memset(&od, 0, sizeof(od));
+    OrbitHost oh;
     std::vector<std::vector<int>> tl;
-    int slot[kMaxDF];
     for (int r = 0; r < G.df; ++r) {
       std::vector<int> t(d);
       for (int m = 0; m < d; ++m) t[m] = B[G.p[r][m]];
       auto it = std::find(tl.begin(), tl.end(), t);
       if (it == tl.end()) {
-        slot[r] = (int)tl.size();
+        oh.slot[r] = (int)tl.size();
         tl.push_back(t);
       } else {
-        slot[r] = (int)(it - tl.begin());
+        oh.slot[r] = (int)(it - tl.begin());
       }
     }
-    od.ntiles = (int32_t)tl.size();
-    for (int s = 0; s < od.ntiles; ++s) {
+    oh.ntiles = (int)tl.size();
+    for (int m = 0; m < d; ++m) oh.B[m] = B[m];
+    for (int s = 0; s < oh.ntiles; ++s) {
       int64_t off = 0;
       int32_t ext = 0;
       for (int m = 0; m < d; ++m) {
         off += (int64_t)tl[s][m] * bl * g.gst[m];
         int e = std::min(bl, n - tl[s][m] * bl);
-        if (e < bl) od.ragged = 1;
+        if (e < bl) oh.ragged = 1;
         ext |= (e & 255) << (8 * m);
       }
-      od.tile_off[s] = (int32_t)off;
-      od.tile_ext[s] = ext;
+      oh.tile_off[s] = (int32_t)off;
+      oh.tile_ext[s] = ext;
     }
-    for (int r = 0; r < G.df; ++r) od.slot_base[r] = slot[r] * g.ts;
     // canonical representatives: inside tile B, sorted within runs of equal blocks
     std::vector<int> key;
     int extB[kMaxD];
@@ -271,26 +270,86 @@ spinsum_status build_tiling(const spinsum_plan_s& P, int n, int64_t ncubes,
       }
       ri = rep_index.emplace(key, std::make_pair(off, (int)T.reps.size() - off)).first;
     }
-    od.rep_off = ri->second.first;
-    od.rep_cnt = ri->second.second;
-    od.fd_rep = make_fastdiv((uint32_t)std::max(1, od.rep_cnt));
-    T.max_tiles = std::max(T.max_tiles, (int)od.ntiles);
-    T.max_rep_cnt = std::max(T.max_rep_cnt, (int)od.rep_cnt);
-    T.ragged |= od.ragged;
-    T.orbits.push_back(od);
-    // next non-decreasing block tuple (the loop nest of Alg. 5a)
+    oh.rep_off = ri->second.first;
+    oh.rep_cnt = ri->second.second;
+    T.max_orbit_tiles = std::max(T.max_orbit_tiles, oh.ntiles);
+    T.ragged |= oh.ragged;
+    T.orbits.push_back(oh);
     int m = d - 1;
     while (m >= 0 && B[m] == nb - 1) --m;
     if (m < 0) break;
     B[m]++;
     for (int j = m + 1; j < d; ++j) B[j] = B[m];
   }
-  g.norbits = (int32_t)T.orbits.size();
-  g.fd_norbits = make_fastdiv((uint32_t)g.norbits);
+
+  // 2. work items: one tile orbit each (item_tiles 0), or groups of orbits,
+  //    first fit in decreasing tile count, holding at most `cap` tiles and
+  //    kMaxGroupOrbits orbits
+  if (T.max_orbit_tiles > kMaxGroupTiles) return SPINSUM_ERR_UNSUPPORTED;
+  int cap = std::min(std::max(tile.item_tiles, T.max_orbit_tiles), kMaxGroupTiles);
+  std::vector<int> order(T.orbits.size());
+  std::iota(order.begin(), order.end(), 0);
+  if (tile.item_tiles > 0)
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return T.orbits[a].ntiles > T.orbits[b].ntiles; });
+  std::vector<std::vector<int>> bins;
+  std::vector<int> fill;
+  for (int o : order) {
+    if (tile.item_tiles <= 0) {
+      bins.push_back({o});
+      fill.push_back(T.orbits[o].ntiles);
+      continue;
+    }
+    int placed = -1;
+    for (size_t k = 0; k < bins.size(); ++k)
+      if (fill[k] + T.orbits[o].ntiles <= cap && (int)bins[k].size() < kMaxGroupOrbits) {
+        placed = (int)k;
+        break;
+      }
+    if (placed < 0) {
+      bins.push_back({});
+      fill.push_back(0);
+      placed = (int)bins.size() - 1;
+    }
+    bins[placed].push_back(o);
+    fill[placed] += T.orbits[o].ntiles;
+  }
+  // keep the groups in the order of their first orbit (cube-local locality)
+  std::stable_sort(bins.begin(), bins.end(), [](const std::vector<int>& a, const std::vector<int>& b) {
+    return *std::min_element(a.begin(), a.end()) < *std::min_element(b.begin(), b.end());
+  });
+  for (const std::vector<int>& bin : bins) {
+    GroupDev gd;
+    std::memset(&gd, 0, sizeof(gd));
+    int tbase = 0, rbase = 0;
+    for (int k = 0; k < (int)bin.size(); ++k) {
+      const OrbitHost& oh = T.orbits[bin[k]];
+      for (int s = 0; s < oh.ntiles; ++s) {
+        gd.tile_off[tbase + s] = oh.tile_off[s];
+        gd.tile_ext[tbase + s] = oh.tile_ext[s];
+      }
+      for (int r = 0; r < G.df; ++r) gd.slot_base[k][r] = (tbase + oh.slot[r]) * g.ts;
+      gd.rep_off[k] = oh.rep_off;
+      gd.rep_cnt[k] = oh.rep_cnt;
+      gd.rep_base[k] = rbase;
+      gd.fd_rep[k] = make_fastdiv((uint32_t)std::max(1, oh.rep_cnt));
+      gd.ragged |= oh.ragged;
+      tbase += oh.ntiles;
+      rbase += oh.rep_cnt;
+    }
+    gd.ntiles = tbase;
+    gd.norb = (int)bin.size();
+    gd.rep_total = rbase;
+    T.max_tiles = std::max(T.max_tiles, tbase);
+    T.max_rep_cnt = std::max(T.max_rep_cnt, rbase);
+    T.groups.push_back(gd);
+  }
+  g.ngroups = (int32_t)T.groups.size();
+  g.fd_ngroups = make_fastdiv((uint32_t)g.ngroups);
   T.nb = nb;
   T.vw = vw;
   T.lds_elems = (bl == n) ? (int64_t)cpw * g.ts : (int64_t)T.max_tiles * g.ts;
-  T.nitems = (bl == n) ? (ncubes + cpw - 1) / cpw : ncubes * g.norbits;
+  T.nitems = (bl == n) ? (ncubes + cpw - 1) / cpw : ncubes * g.ngroups;
   {
     int64_t chunks = (int64_t)((bl == n) ? cpw : T.max_tiles) * g.rows * g.vpr;
     T.chunks_per_thread = (int)((chunks + 255) / 256);
@@ -341,7 +400,7 @@ spinsum_status upload_tables(spinsum_plan_s* P) {
   free_device(P);
   if (P->flags & SPINSUM_FLAG_HOST_ONLY) return SPINSUM_OK;
   spinsum_status st;
-  // orbit matrices in the storage type: M | MT | SM | SMT
+  // coefficient vectors in the storage type: forward | adjoint | stages | adjoint stages
   std::vector<double> all;
   all.insert(all.end(), P->M.begin(), P->M.end());
   all.insert(all.end(), P->MT.begin(), P->MT.end());
@@ -355,22 +414,22 @@ spinsum_status upload_tables(spinsum_plan_s* P) {
   }
   if (st != SPINSUM_OK) return st;
   if (!P->batched) {
-    st = upload(P, &P->d_orbits, P->T.orbits.data(), P->T.orbits.size());
+    st = upload(P, &P->d_orbits, P->T.groups.data(), P->T.groups.size());
     if (st != SPINSUM_OK) return st;
     st = upload(P, &P->d_reps, P->T.reps.data(), P->T.reps.size());
     if (st != SPINSUM_OK) return st;
   } else {
-    std::vector<OrbitDev> orbits;
+    std::vector<GroupDev> groups;
     std::vector<uint32_t> reps;
     for (const Tiling& t : P->btil) {
       int roff = (int)reps.size();
-      for (OrbitDev od : t.orbits) {
-        od.rep_off += roff;
-        orbits.push_back(od);
+      for (GroupDev gd : t.groups) {
+        for (int k = 0; k < gd.norb; ++k) gd.rep_off[k] += roff;
+        groups.push_back(gd);
       }
       reps.insert(reps.end(), t.reps.begin(), t.reps.end());
     }
-    st = upload(P, &P->d_orbits, orbits.data(), orbits.size());
+    st = upload(P, &P->d_orbits, groups.data(), groups.size());
     if (st != SPINSUM_OK) return st;
     st = upload(P, &P->d_reps, reps.data(), reps.size());
     if (st != SPINSUM_OK) return st;
@@ -482,20 +541,27 @@ static spinsum_status apply_tile(spinsum_plan_s* P, const spinsum_tile_t* req) {
   }
   if (t.threads != 256 && t.threads != 0) return SPINSUM_ERR_UNSUPPORTED;
   t.threads = 256;
-  if (t.variant < 0 || t.variant > SPINSUM_VARIANT_REG_ONESHOT) return SPINSUM_ERR_INVALID_ARG;
+  if (t.variant < 0 || t.variant > SPINSUM_VARIANT_LDS_PIPELINE) return SPINSUM_ERR_INVALID_ARG;
   // kernel variant: loads straight into LDS need whole 16-byte rows
   const int bl = t.bl <= 0 ? std::max(1, P->n) : std::min(t.bl, std::max(1, P->n));
   const bool direct_ok = vw_for(std::max(1, P->n), bl, vmax) * elem_size(*P) == 16 &&
                          !(P->flags & SPINSUM_FLAG_NO_DIRECT_LDS);
   if (t.variant == SPINSUM_VARIANT_AUTO)
     t.variant = direct_ok ? SPINSUM_VARIANT_DIRECT_LDS : SPINSUM_VARIANT_REG_ONESHOT;
-  if (t.variant == SPINSUM_VARIANT_DIRECT_LDS && !direct_ok) t.variant = SPINSUM_VARIANT_REG_ONESHOT;
-  if (t.variant == SPINSUM_VARIANT_DIRECT_LDS) t.lds_pad = 0;  // dense chunk-order layout
+  const bool direct = t.variant == SPINSUM_VARIANT_DIRECT_LDS || t.variant == SPINSUM_VARIANT_LDS_PIPELINE;
+  if (direct && !direct_ok) t.variant = SPINSUM_VARIANT_REG_ONESHOT;
+  if (t.variant == SPINSUM_VARIANT_DIRECT_LDS || t.variant == SPINSUM_VARIANT_LDS_PIPELINE)
+    t.lds_pad = 0;  // dense chunk-order layout
   Tiling T;
   spinsum_status st = build_tiling(*P, P->n, P->ncubes, t, vmax, &T);
   if (st != SPINSUM_OK) return st;
   if (t.variant == SPINSUM_VARIANT_REG_PIPELINE && T.chunks_per_thread > 16)
     t.variant = SPINSUM_VARIANT_REG_ONESHOT;
+  // two tile buffers and every representative table must fit in LDS
+  if (t.variant == SPINSUM_VARIANT_LDS_PIPELINE &&
+      (((int64_t)T.reps.size() * 4 + 15) / 16 * 16 + 2 * ((T.lds_elems * elem_size(*P) + 15) / 16 * 16) >
+       P->lds_limit))
+    t.variant = SPINSUM_VARIANT_DIRECT_LDS;
   P->tile = t;
   P->T = std::move(T);
   return SPINSUM_OK;
@@ -612,7 +678,7 @@ extern "C" spinsum_status spinsum_plan_batched(spinsum_plan_t* plan, int nblocks
   P->btil.resize(nblocks);
   P->blocks.resize(nblocks);
   P->block_elems.resize(nblocks);
-  int orbit_base = 0;
+  int group_base = 0;
   for (int b = 0; b < nblocks; ++b) {
     spinsum_tile_t t{};
     if (ns[b] > 0 && cs[b] > 0) {
@@ -627,7 +693,7 @@ extern "C" spinsum_status spinsum_plan_batched(spinsum_plan_t* plan, int nblocks
     Tiling& T = P->btil[b];
     std::memset(&P->blocks[b], 0, sizeof(BatchBlock));
     P->blocks[b].g = T.g;
-    P->blocks[b].orbit_base = orbit_base;
+    P->blocks[b].group_base = group_base;
     P->block_elems[b] = (ns[b] > 0 ? cs[b] * ipow(ns[b], d) : 0);
     P->elems += P->block_elems[b];
     P->ncubes += cs[b];
@@ -640,30 +706,30 @@ extern "C" spinsum_status spinsum_plan_batched(spinsum_plan_t* plan, int nblocks
           BatchItem it{};
           it.cube0 = c0;
           it.block = b;
-          it.orbit = orbit_base;
+          it.group = group_base;
           it.ncubes = (int32_t)std::min<int64_t>(g.cpw, g.ncubes - c0);
           P->items.push_back(it);
         }
       } else {
         for (int64_t c = 0; c < g.ncubes; ++c)
-          for (int o = 0; o < g.norbits; ++o) {
+          for (int o = 0; o < g.ngroups; ++o) {
             BatchItem it{};
             it.cube0 = c;
             it.block = b;
-            it.orbit = orbit_base + o;
+            it.group = group_base + o;
             it.ncubes = 1;
             P->items.push_back(it);
           }
       }
     }
-    orbit_base += (int)T.orbits.size();
+    group_base += (int)T.groups.size();
   }
   // larger items first so the static round-robin of the persistent kernel balances
   auto cost = [&](const BatchItem& it) {
     const Tiling& T = P->btil[it.block];
-    const OrbitDev& od = T.orbits[it.orbit - P->blocks[it.block].orbit_base];
+    const GroupDev& gd = T.groups[it.group - P->blocks[it.block].group_base];
     int64_t tile = ipow(T.g.bl, d);
-    return (int64_t)it.ncubes * od.ntiles * tile;
+    return (int64_t)it.ncubes * gd.ntiles * tile;
   };
   std::stable_sort(P->items.begin(), P->items.end(),
                    [&](const BatchItem& a, const BatchItem& b) { return cost(a) > cost(b); });
@@ -725,7 +791,9 @@ extern "C" spinsum_status spinsum_plan_get_info(spinsum_plan_t P, spinsum_plan_i
     info->variant = P->tile.variant;
     info->lds_pad = P->tile.lds_pad;
     info->nb = P->T.nb;
-    info->norbits = P->T.g.norbits;
+    info->norbits = (int)P->T.orbits.size();
+    info->items_per_cube = P->T.g.ngroups;
+    info->item_tiles = P->T.max_tiles;
     info->cubes_per_wg = P->T.g.cpw;
     info->max_tiles = P->T.max_tiles;
     info->lds_bytes = P->T.lds_elems * elem_size(*P);
@@ -773,11 +841,11 @@ extern "C" spinsum_status spinsum_plan_expanded(spinsum_plan_t P, int cap, int* 
 // (load, combine, store) with the kernels' own index functions, and checks
 // that they stay in bounds and agree with each other.
 template <int D, int VW>
-static bool emulate_item(const Tiling& T, const OrbitDev& od, int ncub, std::string* why) {
+static bool emulate_item(const Tiling& T, const GroupDev& gd, int ncub, std::string* why) {
   const Geom& g = T.g;
   const int d = D;
   const int64_t span = (int64_t)ncub * g.cube_elems;
-  const uint32_t nchunks = (uint32_t)ncub * (uint32_t)od.ntiles * (uint32_t)g.rows * (uint32_t)g.vpr;
+  const uint32_t nchunks = (uint32_t)ncub * (uint32_t)gd.ntiles * (uint32_t)g.rows * (uint32_t)g.vpr;
   if ((int64_t)nchunks > (int64_t)T.chunks_per_thread * 256) {
     *why = "item has more chunks than the prefetch buffer holds";
     return false;
@@ -787,7 +855,7 @@ static bool emulate_item(const Tiling& T, const OrbitDev& od, int ncub, std::str
   for (uint32_t c = 0; c < nchunks; ++c) {
     int go = 0;
     int lo = 0;
-    if (!chunk_addr<D, VW>(g, c, od.ntiles, od.tile_off, od.tile_ext, od.ragged != 0, &go, &lo))
+    if (!chunk_addr<D, VW>(g, c, gd.ntiles, gd.tile_off, gd.tile_ext, gd.ragged != 0, &go, &lo))
       continue;
     if (go < 0 || go + VW > span || (go % VW) != 0) { *why = "global chunk out of bounds"; return false; }
     if (lo < 0 || lo + VW > T.lds_elems) { *why = "LDS chunk out of bounds"; return false; }
@@ -799,13 +867,13 @@ static bool emulate_item(const Tiling& T, const OrbitDev& od, int ncub, std::str
   }
   // every element of the item's tiles is loaded exactly once
   for (int ci = 0; ci < ncub; ++ci)
-    for (int s = 0; s < od.ntiles; ++s) {
+    for (int s = 0; s < gd.ntiles; ++s) {
       int ext[kMaxD];
-      for (int m = 0; m < d; ++m) ext[m] = (od.tile_ext[s] >> (8 * m)) & 255;
+      for (int m = 0; m < d; ++m) ext[m] = (gd.tile_ext[s] >> (8 * m)) & 255;
       int64_t cnt = 1;
       for (int m = 0; m < d; ++m) cnt *= ext[m];
       for (int64_t e = 0; e < cnt; ++e) {
-        int64_t rem = e, off = (int64_t)ci * g.cube_elems + od.tile_off[s];
+        int64_t rem = e, off = (int64_t)ci * g.cube_elems + gd.tile_off[s];
         for (int m = d - 1; m >= 0; --m) {
           off += (rem % ext[m]) * g.gst[m];
           rem /= ext[m];
@@ -813,28 +881,34 @@ static bool emulate_item(const Tiling& T, const OrbitDev& od, int ncub, std::str
         if (loaded[off] != 1) { *why = "tile element not loaded exactly once"; return false; }
       }
     }
-  // combine: the LDS address of sigma . x holds global element sigma . x
-  const uint32_t nrep = (uint32_t)ncub * (uint32_t)od.rep_cnt;
-  for (uint32_t i = 0; i < nrep; ++i) {
-    uint32_t ci = (ncub == 1) ? 0u : fdiv(i, od.fd_rep);
-    uint32_t ri = i - ci * (uint32_t)od.rep_cnt;
-    if (ci >= (uint32_t)ncub || ri >= (uint32_t)od.rep_cnt) { *why = "bad representative index"; return false; }
-    uint32_t pk = T.reps[od.rep_off + ri];
-    int l[D];
-    for (int m = 0; m < d; ++m) l[m] = (int)((pk >> (8 * m)) & 255u);
-    // global coordinates of x: tile of the identity permutation + l
-    int x[D];
-    int64_t o0 = od.tile_off[od.slot_base[0] / g.ts];
-    for (int m = 0; m < d; ++m) x[m] = (int)((o0 / g.gst[m]) % g.n) + l[m];
-    int addrs[kMaxDF];
-    orbit_addrs<D>(g, (int)ci * g.cube_lds, od.slot_base, l, addrs,
-                   std::make_integer_sequence<int, Fact<D>()>{});
-    for (int r = 0; r < Fact<D>(); ++r) {
-      int a = addrs[r];
-      if (a < 0 || a >= T.lds_elems) { *why = "combine address out of bounds"; return false; }
-      int64_t want = (int64_t)ci * g.cube_elems;
-      for (int m = 0; m < d; ++m) want += (int64_t)x[lex_perm(D, r, m)] * g.gst[m];
-      if (lds_of[a] != want) { *why = "combine address does not hold sigma . x"; return false; }
+  // combine: for every orbit of the group, the LDS address of sigma . x
+  // holds global element sigma . x
+  for (int k = 0; k < gd.norb; ++k) {
+    const uint32_t nrep = (uint32_t)ncub * (uint32_t)gd.rep_cnt[k];
+    int x0[D];  // origin of the orbit's identity tile
+    {
+      int64_t o0 = gd.tile_off[gd.slot_base[k][0] / g.ts];
+      for (int m = 0; m < d; ++m) x0[m] = (int)((o0 / g.gst[m]) % g.n);
+    }
+    for (uint32_t i = 0; i < nrep; ++i) {
+      uint32_t ci = (ncub == 1) ? 0u : fdiv(i, gd.fd_rep[k]);
+      uint32_t ri = i - ci * (uint32_t)gd.rep_cnt[k];
+      if (ci >= (uint32_t)ncub || ri >= (uint32_t)gd.rep_cnt[k]) { *why = "bad representative index"; return false; }
+      uint32_t pk = T.reps[gd.rep_off[k] + ri];
+      int l[D];
+      for (int m = 0; m < d; ++m) l[m] = (int)((pk >> (8 * m)) & 255u);
+      int x[D];
+      for (int m = 0; m < d; ++m) x[m] = x0[m] + l[m];
+      int addrs[kMaxDF];
+      orbit_addrs<D>(g, (int)ci * g.cube_lds, gd.slot_base[k], l, addrs,
+                     std::make_integer_sequence<int, Fact<D>()>{});
+      for (int r = 0; r < Fact<D>(); ++r) {
+        int a = addrs[r];
+        if (a < 0 || a >= T.lds_elems) { *why = "combine address out of bounds"; return false; }
+        int64_t want = (int64_t)ci * g.cube_elems;
+        for (int m = 0; m < d; ++m) want += (int64_t)x[lex_perm(D, r, m)] * g.gst[m];
+        if (lds_of[a] != want) { *why = "combine address does not hold sigma . x"; return false; }
+      }
     }
   }
   return true;
@@ -850,12 +924,12 @@ static bool emulate_all(const Tiling& T, std::string* why) {
   } else {
     ncubs.push_back(1);
   }
-  for (const OrbitDev& od : T.orbits)
+  for (const GroupDev& gd : T.groups)
     for (int nc : ncubs) {
       bool ok = false;
-      if (T.vw == 4) ok = emulate_item<D, 4>(T, od, nc, why);
-      else if (T.vw == 2) ok = emulate_item<D, 2>(T, od, nc, why);
-      else ok = emulate_item<D, 1>(T, od, nc, why);
+      if (T.vw == 4) ok = emulate_item<D, 4>(T, gd, nc, why);
+      else if (T.vw == 2) ok = emulate_item<D, 2>(T, gd, nc, why);
+      else ok = emulate_item<D, 1>(T, gd, nc, why);
       if (!ok) return false;
     }
   return true;
@@ -875,37 +949,57 @@ extern "C" spinsum_status spinsum_plan_check_ownership(spinsum_plan_t P, int blo
   const Geom& g = T.g;
   if (g.n <= 0 || g.ncubes <= 0) return SPINSUM_OK;
   const int d = P->d, df = P->G.df, n = g.n, bl = g.bl;
+  // every orbit of the cube belongs to exactly one work item
+  std::vector<int> orbit_in(T.orbits.size(), 0);
   std::vector<int64_t> owner((size_t)g.cube_elems, -1);
-  for (size_t o = 0; o < T.orbits.size(); ++o) {
-    const OrbitDev& od = T.orbits[o];
-    // block tuple of the representative tile = the tile of the identity
-    int B[kMaxD];
-    for (int m = 0; m < d; ++m) B[m] = (od.tile_off[od.slot_base[0] / g.ts] / g.gst[m]) % n / bl;
-    for (int r = 0; r < df; ++r) {
-      // the tile recorded for sigma must be sigma . B
-      int s = od.slot_base[r] / g.ts;
-      if (s < 0 || s >= od.ntiles || od.slot_base[r] != s * g.ts) return fail("bad slot");
-      int64_t off = 0;
-      for (int m = 0; m < d; ++m) off += (int64_t)B[P->G.p[r][m]] * bl * g.gst[m];
-      if (off != od.tile_off[s]) return fail("slot table does not match sigma . B");
-    }
-    for (int k = 0; k < od.rep_cnt; ++k) {
-      uint32_t pk = T.reps[od.rep_off + k];
-      int x[kMaxD];
-      for (int m = 0; m < d; ++m) {
-        int l = (pk >> (8 * m)) & 255;
-        if (l >= std::min(bl, n - B[m] * bl)) return fail("representative outside its tile");
-        x[m] = B[m] * bl + l;
+  int64_t orbit_id = 0;
+  for (const GroupDev& gd : T.groups) {
+    int tiles = 0;
+    for (int k = 0; k < gd.norb; ++k) {
+      // identify the orbit by its identity tile
+      int s0 = gd.slot_base[k][0] / g.ts;
+      int B[kMaxD];
+      for (int m = 0; m < d; ++m) B[m] = (gd.tile_off[s0] / g.gst[m]) % n / bl;
+      int match = -1;
+      for (size_t o = 0; o < T.orbits.size(); ++o) {
+        bool same = true;
+        for (int m = 0; m < d; ++m) same = same && T.orbits[o].B[m] == B[m];
+        if (same) match = (int)o;
       }
-      int64_t id = (int64_t)o * (1ll << 32) + k;
+      if (match < 0) return fail("work item holds an unknown orbit");
+      orbit_in[match] += 1;
+      const OrbitHost& oh = T.orbits[match];
+      tiles += oh.ntiles;
       for (int r = 0; r < df; ++r) {
-        int64_t e = 0;
-        for (int m = 0; m < d; ++m) e += (int64_t)x[P->G.p[r][m]] * g.gst[m];
-        if (owner[e] != -1 && owner[e] != id) return fail("element owned twice");
-        owner[e] = id;
+        // the tile recorded for sigma must be sigma . B
+        int s = gd.slot_base[k][r] / g.ts;
+        if (s < 0 || s >= gd.ntiles || gd.slot_base[k][r] != s * g.ts) return fail("bad slot");
+        int64_t off = 0;
+        for (int m = 0; m < d; ++m) off += (int64_t)B[P->G.p[r][m]] * bl * g.gst[m];
+        if (off != gd.tile_off[s]) return fail("slot table does not match sigma . B");
       }
+      for (int i = 0; i < gd.rep_cnt[k]; ++i) {
+        uint32_t pk = T.reps[gd.rep_off[k] + i];
+        int x[kMaxD];
+        for (int m = 0; m < d; ++m) {
+          int l = (pk >> (8 * m)) & 255;
+          if (l >= std::min(bl, n - B[m] * bl)) return fail("representative outside its tile");
+          x[m] = B[m] * bl + l;
+        }
+        int64_t id = orbit_id * (1ll << 32) + i;
+        for (int r = 0; r < df; ++r) {
+          int64_t e = 0;
+          for (int m = 0; m < d; ++m) e += (int64_t)x[P->G.p[r][m]] * g.gst[m];
+          if (owner[e] != -1 && owner[e] != id) return fail("element owned twice");
+          owner[e] = id;
+        }
+      }
+      ++orbit_id;
     }
+    if (tiles != gd.ntiles) return fail("work item tile count");
   }
+  for (int c : orbit_in)
+    if (c != 1) return fail("tile orbit not in exactly one work item");
   for (int64_t e = 0; e < g.cube_elems; ++e)
     if (owner[e] == -1) return fail("element not owned");
   std::string w;

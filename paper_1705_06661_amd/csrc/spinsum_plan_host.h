@@ -21,19 +21,32 @@ struct SymGroup {
   int rank(const int* q) const;
 };
 
+// One tile orbit {sigma . B} of the block grid of a cube (host tables).
+struct OrbitHost {
+  int ntiles = 0;
+  int ragged = 0;
+  int B[kMaxD] = {0, 0, 0, 0};        // sorted block tuple
+  int32_t tile_off[kMaxDF] = {};      // element offset of each tile origin
+  int32_t tile_ext[kMaxDF] = {};      // packed extents of each tile
+  int slot[kMaxDF] = {};              // tile of sigma . B, sigma in lex order
+  int rep_off = 0, rep_cnt = 0;       // representatives in the pool
+};
+
 // Tables of one tensor (or one block of a batch) for one tile choice.
 struct Tiling {
   Geom g{};
   int nb = 0;
   int vw = 1;
-  int max_tiles = 0;
+  int max_tiles = 0;        // tiles of the largest work item (group)
+  int max_orbit_tiles = 0;  // tiles of the largest tile orbit
   int ragged = 0;
   int fits = 1;
   int64_t lds_elems = 0;
   int64_t nitems = 0;
   int chunks_per_thread = 0;  // 16-byte loads per thread for the largest item
-  int max_rep_cnt = 0;        // representatives of the largest orbit
-  std::vector<OrbitDev> orbits;
+  int max_rep_cnt = 0;        // representatives of the largest work item
+  std::vector<OrbitHost> orbits;
+  std::vector<GroupDev> groups;
   std::vector<uint32_t> reps;
 };
 

@@ -7,7 +7,7 @@
 // here the candidates are timed on the device and the winner is kept.
 //
 // Cache file: plain text, one line per configuration:
-//   <key> <bl> <cubes_per_wg> <threads> <lds_pad> <variant> <ms>
+//   <key> <bl> <cubes_per_wg> <threads> <lds_pad> <variant> <item_tiles> <ms>
 // key = d<d>_n<N>_<f64|f32>_ip<0|1>_c<floor(log2(ncubes))>_<arch>.
 #include <hip/hip_runtime.h>
 
@@ -59,10 +59,11 @@ bool cache_lookup(const spinsum_plan_s& P, spinsum_tile_t* tile) {
     std::string k;
     spinsum_tile_t t{};
     double ms = 0;
-    if (!(is >> k >> t.bl >> t.cubes_per_wg >> t.threads >> t.lds_pad >> t.variant >> ms)) continue;
+    if (!(is >> k >> t.bl >> t.cubes_per_wg >> t.threads >> t.lds_pad >> t.variant >> t.item_tiles >> ms))
+      continue;
     if (k != key) continue;
     if (t.bl < 1 || t.bl > P.n || t.cubes_per_wg < 1) continue;
-    if (t.variant < 0 || t.variant > SPINSUM_VARIANT_REG_ONESHOT) continue;
+    if (t.variant < 0 || t.variant > SPINSUM_VARIANT_LDS_PIPELINE) continue;
     *tile = t;  // the last matching line wins
     found = true;
   }
@@ -85,7 +86,7 @@ static void cache_store(const spinsum_plan_s& P, const char* path, const spinsum
   }
   std::ostringstream os;
   os << key << " " << t.bl << " " << t.cubes_per_wg << " " << t.threads << " " << t.lds_pad << " "
-     << t.variant << " " << ms;
+     << t.variant << " " << t.item_tiles << " " << ms;
   keep.push_back(os.str());
   std::string tmp = std::string(path) + ".tmp";
   {
@@ -115,18 +116,26 @@ extern "C" spinsum_status spinsum_autotune(spinsum_plan_t P, void* in, void* out
   for (int cpw = 1; cpw <= 64; cpw *= 2) {
     if (cpw * cube_bytes + 1024 > P->lds_limit || cpw > P->ncubes) break;
     if (cpw > 1 && cpw * cube_bytes > 96 * 1024) break;
-    shapes.push_back({n, cpw, 256, 0, 0});
+    shapes.push_back({n, cpw, 256, 0, 0, 0});
   }
   for (int bl = n - 1; bl >= 2; --bl) {
     if (n % bl != 0) continue;
     if (bl * esz < 32) continue;
-    shapes.push_back({bl, 1, 256, 0, 0});
+    shapes.push_back({bl, 1, 256, 0, 0, 0});
+    // work items packing several orbits: up to one and two largest orbits
+    spinsum_tile_t probe{bl, 1, 256, 0, 0, 0};
+    if (spinsum_plan_set_tile(P, &probe) != SPINSUM_OK) continue;
+    const int mo = P->T.max_orbit_tiles;
+    shapes.push_back({bl, 1, 256, 0, 0, mo});
+    if (2 * mo <= kMaxGroupTiles) shapes.push_back({bl, 1, 256, 0, 0, 2 * mo});
   }
   std::vector<spinsum_tile_t> cands;
   for (const spinsum_tile_t& sh : shapes) {
     spinsum_tile_t t = sh;
-    t.variant = SPINSUM_VARIANT_DIRECT_LDS;
     t.lds_pad = 0;
+    t.variant = SPINSUM_VARIANT_DIRECT_LDS;
+    cands.push_back(t);
+    t.variant = SPINSUM_VARIANT_LDS_PIPELINE;
     cands.push_back(t);
     for (int pad = 1; pad >= 0; --pad) {
       t.lds_pad = pad;

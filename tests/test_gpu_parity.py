@@ -49,14 +49,15 @@ def gpu_ints(shape, seed, dtype=torch.float64):
 
 
 VARIANTS = [ss.SPINSUM_VARIANT_DIRECT_LDS, ss.SPINSUM_VARIANT_REG_PIPELINE,
-            ss.SPINSUM_VARIANT_REG_ONESHOT]
+            ss.SPINSUM_VARIANT_REG_ONESHOT, ss.SPINSUM_VARIANT_LDS_PIPELINE]
 
 
-def mk(shape, stages, d, dtype=torch.float64, inplace=False, flags=0, tile=None, variant=0):
+def mk(shape, stages, d, dtype=torch.float64, inplace=False, flags=0, tile=None, variant=0,
+       item_tiles=0):
     p = ss.spinsum_plan(shape, len(shape) - d, d, stages, dtype=dtype, inplace=inplace,
                         flags=flags)
     if tile is not None:
-        ss.spinsum_plan_set_tile(p, *tile, variant=variant)
+        ss.spinsum_plan_set_tile(p, *tile, variant=variant, item_tiles=item_tiles)
     return p
 
 
@@ -159,13 +160,50 @@ def test_table2_cases(case, chain):
     shape = (3,) + (n,) * d
     flags = ss.SPINSUM_FLAG_CHAIN_STAGES if chain else 0
     for tile, variant in [((n, 1), 0), ((3, 1), 0), ((n, 1), ss.SPINSUM_VARIANT_REG_PIPELINE),
-                          ((3, 1), ss.SPINSUM_VARIANT_REG_ONESHOT)]:
+                          ((3, 1), ss.SPINSUM_VARIANT_REG_ONESHOT),
+                          ((n, 1), ss.SPINSUM_VARIANT_LDS_PIPELINE),
+                          ((2, 1), ss.SPINSUM_VARIANT_LDS_PIPELINE)]:
         p = mk(shape, stages, d, flags=flags, tile=tile, inplace=True, variant=variant)
         x = gpu_uniform(shape, case)
         y = run(p, x)
         assert nerr(y.cpu().numpy(), ref_of(x, stages, d)) <= 1e-14, tile
         xi = gpu_ints(shape, case + 100)
         np.testing.assert_array_equal(run(p, xi).cpu().numpy(), ref_of(xi, stages, d))
+
+
+GROUP_CASES = [
+    ((3, 16, 16, 16), 3, 4),     # 20 orbits of 1, 3 and 6 tiles
+    ((2, 20, 20, 20), 3, 6),     # ragged
+    ((2, 12, 12, 12, 12), 4, 6),
+    ((2, 10, 10, 10, 10), 4, 4),  # ragged 4D
+]
+
+
+@pytest.mark.parametrize("shape,d,bl", GROUP_CASES)
+@pytest.mark.parametrize("item_tiles", [1, 6, 12, 24])
+def test_orbit_groups_against_oracle(shape, d, bl, item_tiles):
+    _say("groups", shape, d, bl, item_tiles)
+    rng = np.random.default_rng(item_tiles + d)
+    terms = [(p, float(rng.integers(-3, 4))) for p in itertools.permutations(range(d))]
+    x = gpu_uniform(shape, 21)
+    ref = ref_of(x, [terms], d)
+    xi = gpu_ints(shape, 22)
+    refi = ref_of(xi, [terms], d)
+    for variant in VARIANTS:
+        for inplace in (False, True):
+            try:
+                p = mk(shape, [terms], d, inplace=inplace, tile=(bl, 1), variant=variant,
+                       item_tiles=item_tiles)
+            except ss.SpinSumError as e:
+                # the packed item needs more LDS than a workgroup has
+                assert e.status == ss.SPINSUM_ERR_UNSUPPORTED
+                assert item_tiles * bl ** d * 8 > 160 * 1024
+                continue
+            info = ss.spinsum_plan_get_info(p)
+            assert info["item_tiles"] <= max(item_tiles, 24)
+            y = run(p, x)
+            assert nerr(y.cpu().numpy(), ref) <= 1e-14, (variant, inplace)
+            np.testing.assert_array_equal(run(p, xi).cpu().numpy(), refi)
 
 
 def test_factored_form_chained_and_expanded():

@@ -287,3 +287,49 @@ def test_direct_lds_variant_uses_dense_tiles():
     assert ss.spinsum_plan_get_info(p)["variant"] == ss.SPINSUM_VARIANT_REG_ONESHOT
     q = plan((3, 5, 5, 5), [[((0, 1, 2), 1.0)]])
     assert ss.spinsum_plan_get_info(q)["variant"] == ss.SPINSUM_VARIANT_REG_ONESHOT
+
+
+@pytest.mark.parametrize("d,n,bl", [(3, 32, 8), (3, 13, 4), (4, 12, 6), (4, 10, 4), (2, 16, 4),
+                                    (3, 24, 6)])
+def test_orbit_groups_cover_every_orbit(d, n, bl):
+    """Work items are single tile orbits by default; with item_tiles > 0 the
+    orbits of a cube are packed into items of at most max(item_tiles,
+    largest orbit) tiles, and every element is still owned exactly once."""
+    p = plan((2,) + (n,) * d, [[(tuple(range(d)), 1.0)]], d=d)
+    ss.spinsum_plan_set_tile(p, bl)
+    info = ss.spinsum_plan_get_info(p)
+    norb, biggest = info["norbits"], info["max_tiles"]
+    assert info["items_per_cube"] == norb
+    assert info["nitems"] == 2 * norb
+    tiles_per_cube = (-(-n // bl)) ** d
+    for cap in (1, biggest, 2 * biggest, 24):
+        ss.spinsum_plan_set_tile(p, bl, item_tiles=cap)
+        info = ss.spinsum_plan_get_info(p)
+        eff = min(max(cap, biggest), 24)
+        assert info["item_tiles"] <= eff
+        assert info["items_per_cube"] >= -(-tiles_per_cube // eff)
+        assert info["items_per_cube"] <= norb
+        assert info["norbits"] == norb
+        ok, why = ss.spinsum_plan_check_ownership(p)
+        assert ok, (cap, why)
+
+
+def test_lds_pipeline_variant_needs_two_buffers():
+    """The double-buffered kernel holds two item buffers plus every
+    representative table in LDS; it falls back to the one-shot direct-LDS
+    kernel when they do not fit, and to registers without 16-byte rows."""
+    V = ss.SPINSUM_VARIANT_LDS_PIPELINE
+    p = plan((2, 32, 32, 32), [[((0, 1, 2), 1.0)]])
+    ss.spinsum_plan_set_tile(p, 8, lds_pad=1, variant=V)
+    info = ss.spinsum_plan_get_info(p)
+    assert info["variant"] == V and info["lds_pad"] == 0
+    ok, why = ss.spinsum_plan_check_ownership(p)
+    assert ok, why
+    ss.spinsum_plan_set_tile(p, 16, variant=V)  # 2 x 3 x 32 KiB > 160 KiB
+    assert ss.spinsum_plan_get_info(p)["variant"] == ss.SPINSUM_VARIANT_DIRECT_LDS
+    q = plan((2, 32, 32, 32), [[((0, 1, 2), 1.0)]], dtype="f32")
+    ss.spinsum_plan_set_tile(q, 16, variant=V)  # 2 x 3 x 16 KiB fits
+    assert ss.spinsum_plan_get_info(q)["variant"] == V
+    r = plan((2, 12, 12, 12), [[((0, 1, 2), 1.0)]])
+    ss.spinsum_plan_set_tile(r, 3, variant=V)  # 24-byte rows
+    assert ss.spinsum_plan_get_info(r)["variant"] == ss.SPINSUM_VARIANT_REG_ONESHOT
