@@ -47,20 +47,26 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(name: str, algo_bytes: float):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
-    was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"{name}.traffic.json")
+def traffic_from_profile(name: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy's reading), or
+    None when the counters were taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{name}.traffic.txt")
     if not os.path.exists(path):
         return None
-    try:
-        with open(path) as f:
-            rec = json.load(f)
-    except (OSError, ValueError):
-        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#") or ":" not in line:
+                continue
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    try:
+        return float(rec["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def kernel_name(info, dtype="double"):
@@ -68,10 +74,12 @@ def kernel_name(info, dtype="double"):
     d = info["d"]
     v = info["variant"]
     if v == 1:
-        return f"k_lds<{dtype},{d},false>"
+        return f"k_lds<{dtype}, {d}, false, true>"
+    if v == 4:
+        return f"k_ldsp<{dtype}, {d}, false, true>"
     if v == 2:
-        return f"k_pipe<{dtype},{d},{info['vector_width']},false,*>"
-    return f"k_exec<{dtype},{d},{info['vector_width']},false,true>"
+        return f"k_pipe<{dtype}, {d}, {info['vector_width']}, false, *>"
+    return f"k_exec<{dtype}, {d}, {info['vector_width']}, false, true>"
 
 
 def timed(fn, reps, stream):
@@ -186,8 +194,7 @@ def main():
                    "work_items_per_cube": info["items_per_cube"], "tiles_per_item": info["item_tiles"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_GBPS, 4),
-                     "traffic": traffic_from_profile("spinsum_3d_v64_o32_inplace",
-                                                     algo_per_launch),
+                     "traffic": traffic_from_profile("spinsum_3d_v64_o32_inplace"),
                      "kernel": kernel_name(info),
                      "algorithmic_bytes_per_launch": algo_per_launch,
                      "avg_launch_ms": round(launch_ms, 4)},
