@@ -310,6 +310,8 @@ class PointerArrays:
             raise SpinSumError(SPINSUM_ERR_INVALID_ARG, "one tensor per block expected")
         pin = [_tensor_ptr(t, plan, s, "input") for t, s in zip(ins, plan.shapes)]
         pout = [_tensor_ptr(t, plan, s, "output") for t, s in zip(outs, plan.shapes)]
+        if any(p & 15 for p in pin + pout):
+            raise SpinSumError(SPINSUM_ERR_MISALIGNED, "block tensors must be 16-byte aligned")
         for k, (a, b) in enumerate(zip(pin, pout)):
             nbytes = ins[k].numel() * ins[k].element_size()
             if plan.inplace and a != b:

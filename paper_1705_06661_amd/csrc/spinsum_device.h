@@ -159,6 +159,9 @@ struct BatchArgs {
   const BatchBlock* blocks;
   const BatchItem* items;
   int64_t nitems;
+  int64_t xcd_per;         // > 0: items grouped per XCD (items per XCD range)
+  int32_t lds_tile_bytes;  // start of the representative lists in LDS
+  int32_t pad;
 };
 
 // w_tau = sum_sigma a(tau^-1 o sigma) v_sigma, sigma in lexicographic
@@ -368,14 +371,10 @@ __global__ void __launch_bounds__(kThreads) k_exec(const ExecArgs<T> a) {
 }
 
 // Chunk c (VW elements) of a full tile, chunks in row-major order: its
-// element offset inside the cube.  *ok is false for chunks past the tile and
-// for chunks outside the extent of a ragged tile (ext packs one byte per
-// index).
+// local coordinates l (l[D-1] is the first element of the chunk).
 template <int D, int VW>
-__device__ __forceinline__ int tile_chunk(const Geom& g, uint32_t c, uint32_t cpt, int ext,
-                                          bool ragged, bool* ok) {
+__device__ __forceinline__ void chunk_coords(const Geom& g, uint32_t c, int (&l)[D]) {
   uint32_t q = fdiv(c, g.fd_vpr);
-  int l[D];
   l[D - 1] = (int)(c - q * (uint32_t)g.vpr) * VW;
   if constexpr (D == 2) {
     l[0] = (int)q;
@@ -389,24 +388,25 @@ __device__ __forceinline__ int tile_chunk(const Geom& g, uint32_t c, uint32_t cp
     }
     l[0] = (int)r;
   }
-  bool in = c < cpt;
-  if (ragged) {
+}
+
+// Inside the extent of a ragged tile (ext packs one byte per index)?
+template <int D>
+__device__ __forceinline__ bool chunk_inside(const int (&l)[D], int ext) {
+  bool in = true;
 #pragma unroll
-    for (int m = 0; m < D; ++m) in = in && (l[m] < ((ext >> (8 * m)) & 255));
-  }
-  *ok = in;
-  int off = 0;
-#pragma unroll
-  for (int m = 0; m < D; ++m) off += l[m] * g.gst[m];
-  return off;
+  for (int m = 0; m < D; ++m) in = in && (l[m] < ((ext >> (8 * m)) & 255));
+  return in;
 }
 
 // Issue the loads of one item straight into LDS (global_load_lds_dwordx4:
 // lane i of a wave writes 16 bytes at the wave's LDS base + 16 i).  LDS
 // holds the tiles densely in chunk order: tile t at element t * ts, chunk c
-// at c * VW.  Returns, uniformly over the wave, how many load instructions
-// this wave issued with at least one active lane -- a lower bound on the
-// vector-memory operations the item added to the wave's vmcnt.
+// at c * VW.  A chunk has the same position in every tile, so its address
+// arithmetic is done once and reused for all tiles of the item.  Returns,
+// uniformly over the wave, how many load instructions this wave issued with
+// at least one active lane -- a lower bound on the vector-memory operations
+// the item added to the wave's vmcnt.
 template <typename T, int D>
 __device__ __forceinline__ int issue_item_lds(const Geom& g, cptr<GroupDev> od, bool whole,
                                               int ntl, bool ragged, const T* src,
@@ -416,12 +416,16 @@ __device__ __forceinline__ int issue_item_lds(const Geom& g, cptr<GroupDev> od, 
   const uint32_t tid = threadIdx.x;
   const uint32_t wave_bytes = (tid >> 6) * 1024u;
   int issued = 0;
-  for (int t = 0; t < ntl; ++t) {
-    const int toff = whole ? t * (int)g.cube_elems : od->tile_off[t];
-    const int text = whole ? 0 : od->tile_ext[t];
-    for (uint32_t c0 = 0; c0 < cpt; c0 += kThreads) {
-      bool ok;
-      const int off = tile_chunk<D, VW>(g, c0 + tid, cpt, text, ragged, &ok);
+  for (uint32_t c0 = 0; c0 < cpt; c0 += kThreads) {
+    int l[D];
+    chunk_coords<D, VW>(g, c0 + tid, l);
+    int off = 0;
+#pragma unroll
+    for (int m = 0; m < D; ++m) off += l[m] * g.gst[m];
+    const bool in = c0 + tid < cpt;
+    for (int t = 0; t < ntl; ++t) {
+      const int toff = whole ? t * (int)g.cube_elems : od->tile_off[t];
+      const bool ok = in && (!ragged || chunk_inside<D>(l, od->tile_ext[t]));
       const uint32_t lbyte = (uint32_t)(t * g.ts + (int)c0 * VW) * (uint32_t)sizeof(T) + wave_bytes;
       if (ok)
         __builtin_amdgcn_global_load_lds(
@@ -431,6 +435,94 @@ __device__ __forceinline__ int issue_item_lds(const Geom& g, cptr<GroupDev> od, 
     }
   }
   return __builtin_amdgcn_readfirstlane(issued);
+}
+
+// Whole-cube items are one contiguous run of m elements starting at src.
+// It is copied into LDS as it lies in memory, shifted so that 16-byte
+// chunks of memory land on 16-byte chunks of LDS: with p0 = src rounded
+// down to 16 bytes, element src + e goes to LDS element shift + e, where
+// shift = (src - p0) / sizeof(T).  Whole chunks inside the run go
+// global->LDS directly (global_load_lds_dwordx4); the partial chunks at
+// either end (fewer than 16 / sizeof(T) elements each) go through
+// registers.  Nothing outside the run is read.  Returns shift.
+template <typename T>
+__device__ __forceinline__ int flat_issue(const T* src, uint32_t m, unsigned char* lds) {
+  constexpr uint32_t E = 16 / sizeof(T);
+  const uintptr_t p = (uintptr_t)src;
+  const uintptr_t p0 = p & ~(uintptr_t)15;
+  const uintptr_t pend = p + (uintptr_t)m * sizeof(T);
+  uintptr_t pc = (p + 15) & ~(uintptr_t)15;
+  if (pc > pend) pc = pend;
+  const uint32_t nfull = (uint32_t)((pend - pc) >> 4);
+  const uintptr_t pf = pc + ((uintptr_t)nfull << 4);
+  const uint32_t head = (uint32_t)((pc - p) / sizeof(T));
+  const uint32_t tail = (uint32_t)((pend - pf) / sizeof(T));
+  const uint32_t shift = (uint32_t)((p - p0) / sizeof(T));
+  const uint32_t tid = threadIdx.x;
+  T* ldsT = reinterpret_cast<T*>(lds);
+  // partial chunks through registers (at most E - 1 elements each)
+  if (tid < head) ldsT[shift + tid] = src[tid];
+  if (tid >= 32 && tid - 32 < tail) {
+    const uint32_t e = (uint32_t)((pf - p) / sizeof(T)) + (tid - 32);
+    ldsT[shift + e] = src[e];
+  }
+  (void)E;
+  const uint32_t lds0 = (uint32_t)(pc - p0);
+  const uint32_t wave_bytes = (tid >> 6) * 1024u;
+  for (uint32_t c0 = 0; c0 < nfull; c0 += kThreads) {
+    if (c0 + tid < nfull)
+      __builtin_amdgcn_global_load_lds(
+          (const void*)(pc + ((uintptr_t)(c0 + tid) << 4)),
+          (__attribute__((address_space(3))) void*)(lds + lds0 + c0 * 16u + wave_bytes), 16, 0, 0);
+  }
+  return (int)shift;
+}
+
+template <typename T>
+__device__ __forceinline__ int flat_shift(const T* p) {
+  return (int)(((uintptr_t)p & 15u) / sizeof(T));
+}
+
+// Store a whole-cube item from its LDS copy, whose element 0 sits at LDS
+// element in_shift (as flat_issue left it): whole 16-byte chunks with vector
+// stores (non-temporal when NTS), the partial chunks at either end element
+// by element.  If dst is aligned differently from the loaded source, every
+// element is stored on its own.
+template <typename T, bool NTS>
+__device__ __forceinline__ void flat_store(T* dst, uint32_t m, const unsigned char* lds,
+                                           int in_shift) {
+  typedef typename VecT<T, 16 / sizeof(T)>::type V;
+  if (flat_shift(dst) != in_shift) {
+    const T* ldsT = reinterpret_cast<const T*>(lds) + in_shift;
+    for (uint32_t e = threadIdx.x; e < m; e += kThreads) dst[e] = ldsT[e];
+    return;
+  }
+  const uintptr_t p = (uintptr_t)dst;
+  const uintptr_t p0 = p & ~(uintptr_t)15;
+  const uintptr_t pend = p + (uintptr_t)m * sizeof(T);
+  uintptr_t pc = (p + 15) & ~(uintptr_t)15;
+  if (pc > pend) pc = pend;
+  const uint32_t nfull = (uint32_t)((pend - pc) >> 4);
+  const uintptr_t pf = pc + ((uintptr_t)nfull << 4);
+  const uint32_t head = (uint32_t)((pc - p) / sizeof(T));
+  const uint32_t tail = (uint32_t)((pend - pf) / sizeof(T));
+  const uint32_t shift = (uint32_t)((p - p0) / sizeof(T));
+  const uint32_t tid = threadIdx.x;
+  const T* ldsT = reinterpret_cast<const T*>(lds);
+  if (tid < head) dst[tid] = ldsT[shift + tid];
+  if (tid >= 32 && tid - 32 < tail) {
+    const uint32_t e = (uint32_t)((pf - p) / sizeof(T)) + (tid - 32);
+    dst[e] = ldsT[shift + e];
+  }
+  const uint32_t lds0 = (uint32_t)(pc - p0);
+  for (uint32_t c = tid; c < nfull; c += kThreads) {
+    const V val = *reinterpret_cast<const V*>(lds + lds0 + c * 16u);
+    V* q = reinterpret_cast<V*>(pc + ((uintptr_t)c << 4));
+    if constexpr (NTS)
+      __builtin_nontemporal_store(val, q);
+    else
+      *q = val;
+  }
 }
 
 // Issue the loads of an item's representative lists straight into LDS
@@ -462,13 +554,17 @@ __device__ __forceinline__ void store_item_lds(const Geom& g, cptr<GroupDev> od,
   constexpr int VW = 16 / sizeof(T);
   typedef typename VecT<T, VW>::type V;
   const uint32_t cpt = (uint32_t)g.rows * (uint32_t)g.vpr;
-  for (int t = 0; t < ntl; ++t) {
-    const int toff = whole ? t * (int)g.cube_elems : od->tile_off[t];
-    const int text = whole ? 0 : od->tile_ext[t];
-    for (uint32_t c0 = 0; c0 < cpt; c0 += kThreads) {
-      bool ok;
-      const uint32_t c = c0 + threadIdx.x;
-      const int off = tile_chunk<D, VW>(g, c, cpt, text, ragged, &ok);
+  for (uint32_t c0 = 0; c0 < cpt; c0 += kThreads) {
+    const uint32_t c = c0 + threadIdx.x;
+    int l[D];
+    chunk_coords<D, VW>(g, c, l);
+    int off = 0;
+#pragma unroll
+    for (int m = 0; m < D; ++m) off += l[m] * g.gst[m];
+    const bool in = c < cpt;
+    for (int t = 0; t < ntl; ++t) {
+      const int toff = whole ? t * (int)g.cube_elems : od->tile_off[t];
+      const bool ok = in && (!ragged || chunk_inside<D>(l, od->tile_ext[t]));
       if (ok) {
         const V val = *reinterpret_cast<const V*>(lds + t * g.ts + (int)c * VW);
         V* p = reinterpret_cast<V*>(dst + toff + off);
@@ -552,16 +648,24 @@ __global__ void __launch_bounds__(kThreads) k_lds(const ExecArgs<T> a) {
   // 1. tiles and representative lists straight into LDS, all in flight
   //    together
   unsigned char* rep_lds = smem + a.lds_tile_bytes;
-  issue_item_lds<T, D>(g, od, whole, ntl, ragged, a.in + cube0 * g.cube_elems, smem);
+  const uint32_t span = (uint32_t)ncub * (uint32_t)g.cube_elems;
+  int shift = 0;
+  if (whole)
+    shift = flat_issue<T>(a.in + cube0 * g.cube_elems, span, smem);
+  else
+    issue_item_lds<T, D>(g, od, whole, ntl, ragged, a.in + cube0 * g.cube_elems, smem);
   issue_reps_lds(od, a.reps, rep_lds);
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): everything is in LDS
   __syncthreads();
   // 2. combine
   combine_item<T, D, CHAIN, true>(g, od, reinterpret_cast<const uint32_t*>(rep_lds),
-                                  as_const(a.coef), a.nstages, ncub, lds);
+                                  as_const(a.coef), a.nstages, ncub, lds + shift);
   __syncthreads();
-  // 3. store
-  store_item_lds<T, D, NTS>(g, od, whole, ntl, ragged, a.out + cube0 * g.cube_elems, lds);
+  // 3. store (the output may be shifted differently from the input)
+  if (whole)
+    flat_store<T, NTS>(a.out + cube0 * g.cube_elems, span, smem, shift);
+  else
+    store_item_lds<T, D, NTS>(g, od, whole, ntl, ragged, a.out + cube0 * g.cube_elems, lds);
 }
 
 // Persistent, double-buffered direct-LDS loads: while item k is combined
@@ -747,48 +851,70 @@ __global__ void __launch_bounds__(kThreads) k_pipe(const ExecArgs<T> a) {
   }
 }
 
+// Batched: one work item of the cost-sorted list per workgroup (the
+// hardware dispatcher is the queue), XCD-grouped like the single-tensor
+// kernels.  Whole-cube items (every block whose cube fits) are copied as one
+// contiguous run straight into LDS, with their representative lists behind
+// them; tile-orbit items of larger cubes go through registers.
 template <typename T, int D, int VW>
 __global__ void __launch_bounds__(kThreads) k_batched(const BatchArgs<T> a) {
   typedef typename VecT<T, VW>::type V;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  __shared__ int32_t tinfo[2 * kMaxDF];
   T* lds = reinterpret_cast<T*>(smem);
-  for (int64_t it = blockIdx.x; it < a.nitems; it += gridDim.x) {
-    const cptr<BatchItem> item = as_const(a.items) + it;
-    const int blk = item->block;
-    const int64_t icube0 = item->cube0;
-    const int incubes = item->ncubes;
-    const Geom g = load_geom(as_const(a.blocks)[blk].g);
-    const T* src = as_const(a.in)[blk] + icube0 * g.cube_elems;
-    T* dst = as_const(a.out)[blk] + icube0 * g.cube_elems;
-    const GroupDev* od = a.orbits + item->group;
-    cptr<GroupDev> cod = as_const(od);
-    stage_tinfo(tinfo, od);
+  int64_t it;
+  if (a.xcd_per > 0)
+    it = (int64_t)(blockIdx.x & 7u) * a.xcd_per + (int64_t)(blockIdx.x >> 3);
+  else
+    it = blockIdx.x;
+  if (it >= a.nitems) return;
+  const cptr<BatchItem> item = as_const(a.items) + it;
+  const int blk = item->block;
+  const int64_t icube0 = item->cube0;
+  const int incubes = item->ncubes;
+  const Geom g = load_geom(as_const(a.blocks)[blk].g);
+  const T* src = as_const(a.in)[blk] + icube0 * g.cube_elems;
+  T* dst = as_const(a.out)[blk] + icube0 * g.cube_elems;
+  const GroupDev* od = a.orbits + item->group;
+  cptr<GroupDev> cod = as_const(od);
+  const cptr<T> coef = as_const(a.coef);
+  unsigned char* rep_lds = smem + a.lds_tile_bytes;
+  if (g.bl == g.n) {
+    const uint32_t span = (uint32_t)incubes * (uint32_t)g.cube_elems;
+    const int shift = flat_issue<T>(src, span, smem);
+    issue_reps_lds(cod, a.reps, rep_lds);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): everything is in LDS
     __syncthreads();
-    const int ntiles = cod->ntiles;
-    const bool ragged = cod->ragged != 0;
-    const uint32_t nchunks =
-        (uint32_t)incubes * (uint32_t)ntiles * (uint32_t)g.rows * (uint32_t)g.vpr;
-    for (uint32_t c0 = 0; c0 < nchunks; c0 += kUnroll * kThreads) {
-      V buf[kUnroll];
-      int lo[kUnroll];
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        uint32_t c = c0 + threadIdx.x + u * kThreads;
-        int go = 0;
-        int l = 0;
-        bool ok = (c < nchunks) && chunk_addr<D, VW>(g, c, ntiles, tinfo, tinfo + kMaxDF, ragged, &go, &l);
-        lo[u] = ok ? l : -1;
-        if (ok) buf[u] = *reinterpret_cast<const V*>(src + go);
-      }
-      fill_lds<T, VW, kUnroll>(buf, lo, lds);
-    }
+    combine_item<T, D, false, true>(g, cod, reinterpret_cast<const uint32_t*>(rep_lds), coef, 1,
+                                    incubes, lds + shift);
     __syncthreads();
-    combine_item<T, D, false, false>(g, cod, a.reps, as_const(a.coef), 1, incubes, lds);
-    __syncthreads();
-    store_item<T, D, VW, true>(g, tinfo, ntiles, ragged, nchunks, dst, lds);
-    __syncthreads();
+    flat_store<T, true>(dst, span, smem, shift);
+    return;
   }
+  int32_t* tinfo = reinterpret_cast<int32_t*>(rep_lds);  // tile table (no lists needed)
+  stage_tinfo(tinfo, od);
+  __syncthreads();
+  const int ntiles = cod->ntiles;
+  const bool ragged = cod->ragged != 0;
+  const uint32_t nchunks =
+      (uint32_t)incubes * (uint32_t)ntiles * (uint32_t)g.rows * (uint32_t)g.vpr;
+  for (uint32_t c0 = 0; c0 < nchunks; c0 += kUnroll * kThreads) {
+    V buf[kUnroll];
+    int lo[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      uint32_t c = c0 + threadIdx.x + u * kThreads;
+      int go = 0;
+      int l = 0;
+      bool ok = (c < nchunks) && chunk_addr<D, VW>(g, c, ntiles, tinfo, tinfo + kMaxDF, ragged, &go, &l);
+      lo[u] = ok ? l : -1;
+      if (ok) buf[u] = *reinterpret_cast<const V*>(src + go);
+    }
+    fill_lds<T, VW, kUnroll>(buf, lo, lds);
+  }
+  __syncthreads();
+  combine_item<T, D, false, false>(g, cod, a.reps, coef, 1, incubes, lds);
+  __syncthreads();
+  store_item<T, D, VW, true>(g, tinfo, ntiles, ragged, nchunks, dst, lds);
 }
 
 // ------------------------------------------------------------ dispatch

@@ -149,13 +149,21 @@ spinsum_status launch_batched(spinsum_plan_s* P, const void* const* in, void* co
   a.blocks = reinterpret_cast<const BatchBlock*>(P->d_blocks);
   a.items = reinterpret_cast<const BatchItem*>(P->d_items);
   a.nitems = (int64_t)P->items.size();
+  a.lds_tile_bytes = (int32_t)(((size_t)P->batch_lds_elems * sizeof(T) + 15) / 16 * 16);
   const void* k = pick_batched<T>(P->d, P->batch_vw);
-  const size_t shmem = (size_t)P->batch_lds_elems * sizeof(T);
+  const size_t shmem = (size_t)a.lds_tile_bytes + (size_t)P->batch_rep_bytes;
   spinsum_status st = prepare_kernel(P, k, shmem);
   if (st != SPINSUM_OK) return st;
+  int64_t grid;
+  if (P->flags & SPINSUM_FLAG_NO_XCD_REMAP) {
+    a.xcd_per = 0;
+    grid = a.nitems;
+  } else {
+    a.xcd_per = (a.nitems + 7) / 8;
+    grid = a.xcd_per * 8;
+  }
   void* kargs[] = {&a};
-  hipError_t e =
-      hipLaunchKernel(k, dim3((unsigned)P->batch_grid), dim3(kThreads), kargs, shmem, stream);
+  hipError_t e = hipLaunchKernel(k, dim3((unsigned)grid), dim3(kThreads), kargs, shmem, stream);
   if (e != hipSuccess) return hip_error(P, e);
   return SPINSUM_OK;
 }

@@ -348,7 +348,9 @@ spinsum_status build_tiling(const spinsum_plan_s& P, int n, int64_t ncubes,
   g.fd_ngroups = make_fastdiv((uint32_t)g.ngroups);
   T.nb = nb;
   T.vw = vw;
-  T.lds_elems = (bl == n) ? (int64_t)cpw * g.ts : (int64_t)T.max_tiles * g.ts;
+  // whole cubes: plus one 16-byte chunk for the alignment shift of the
+  // contiguous copy
+  T.lds_elems = (bl == n) ? (int64_t)cpw * g.ts + 16 / elem_size(P) : (int64_t)T.max_tiles * g.ts;
   T.nitems = (bl == n) ? (ncubes + cpw - 1) / cpw : ncubes * g.ngroups;
   {
     int64_t chunks = (int64_t)((bl == n) ? cpw : T.max_tiles) * g.rows * g.vpr;
@@ -542,14 +544,17 @@ static spinsum_status apply_tile(spinsum_plan_s* P, const spinsum_tile_t* req) {
   if (t.threads != 256 && t.threads != 0) return SPINSUM_ERR_UNSUPPORTED;
   t.threads = 256;
   if (t.variant < 0 || t.variant > SPINSUM_VARIANT_LDS_PIPELINE) return SPINSUM_ERR_INVALID_ARG;
-  // kernel variant: loads straight into LDS need whole 16-byte rows
+  // kernel variant: loads straight into LDS need whole 16-byte rows, except
+  // for whole cubes, which the one-shot kernel copies as one contiguous run
   const int bl = t.bl <= 0 ? std::max(1, P->n) : std::min(t.bl, std::max(1, P->n));
-  const bool direct_ok = vw_for(std::max(1, P->n), bl, vmax) * elem_size(*P) == 16 &&
-                         !(P->flags & SPINSUM_FLAG_NO_DIRECT_LDS);
+  const bool no_direct = (P->flags & SPINSUM_FLAG_NO_DIRECT_LDS) != 0;
+  const bool rows_ok = vw_for(std::max(1, P->n), bl, vmax) * elem_size(*P) == 16 && !no_direct;
+  const bool direct_ok = rows_ok || (bl >= P->n && !no_direct);
   if (t.variant == SPINSUM_VARIANT_AUTO)
     t.variant = direct_ok ? SPINSUM_VARIANT_DIRECT_LDS : SPINSUM_VARIANT_REG_ONESHOT;
-  const bool direct = t.variant == SPINSUM_VARIANT_DIRECT_LDS || t.variant == SPINSUM_VARIANT_LDS_PIPELINE;
-  if (direct && !direct_ok) t.variant = SPINSUM_VARIANT_REG_ONESHOT;
+  if (t.variant == SPINSUM_VARIANT_LDS_PIPELINE && !rows_ok)
+    t.variant = direct_ok ? SPINSUM_VARIANT_DIRECT_LDS : SPINSUM_VARIANT_REG_ONESHOT;
+  if (t.variant == SPINSUM_VARIANT_DIRECT_LDS && !direct_ok) t.variant = SPINSUM_VARIANT_REG_ONESHOT;
   if (t.variant == SPINSUM_VARIANT_DIRECT_LDS || t.variant == SPINSUM_VARIANT_LDS_PIPELINE)
     t.lds_pad = 0;  // dense chunk-order layout
   Tiling T;
@@ -671,9 +676,20 @@ extern "C" spinsum_status spinsum_plan_batched(spinsum_plan_t* plan, int nblocks
     return st;
   }
   query_device(P);
-  int vmax = 16 / elem_size(*P);
+  // tiles: whole cubes when they fit (copied as one contiguous run, any
+  // extent), packed up to the largest cube of the batch (at least 8 KiB, at
+  // most 40 KiB) so that every workgroup moves about the same bytes; tile
+  // orbits through registers otherwise, with one vector width for all such
+  // blocks
+  const int esz = elem_size(*P);
+  int64_t target = 8 * 1024;
   for (int b = 0; b < nblocks; ++b)
-    if (ns[b] > 0 && cs[b] > 0) vmax = std::min(vmax, max_vector_width(*P, ns[b]));
+    if (ns[b] > 0 && cs[b] > 0 && ipow(ns[b], d) * esz <= 40 * 1024)
+      target = std::max<int64_t>(target, ipow(ns[b], d) * esz);
+  int vmax = 16 / esz;
+  for (int b = 0; b < nblocks; ++b)
+    if (ns[b] > 0 && cs[b] > 0 && ipow(ns[b], d) * esz > 40 * 1024)
+      vmax = std::min(vmax, max_vector_width(*P, ns[b]));
   P->batch_vw = vmax;
   P->btil.resize(nblocks);
   P->blocks.resize(nblocks);
@@ -682,8 +698,16 @@ extern "C" spinsum_status spinsum_plan_batched(spinsum_plan_t* plan, int nblocks
   for (int b = 0; b < nblocks; ++b) {
     spinsum_tile_t t{};
     if (ns[b] > 0 && cs[b] > 0) {
-      st = choose_tile(*P, ns[b], cs[b], vmax, &t);
-      if (st == SPINSUM_OK && t.bl % vmax != 0) st = SPINSUM_ERR_UNSUPPORTED;
+      const int64_t cube_bytes = ipow(ns[b], d) * esz;
+      if (cube_bytes <= 40 * 1024) {
+        t.bl = ns[b];
+        t.cubes_per_wg = (int)std::max<int64_t>(1, std::min<int64_t>(target / cube_bytes, cs[b]));
+        t.threads = 256;
+        t.lds_pad = 0;
+      } else {
+        st = choose_tile(*P, ns[b], cs[b], vmax, &t);
+        if (st == SPINSUM_OK && t.bl % vmax != 0) st = SPINSUM_ERR_UNSUPPORTED;
+      }
     }
     if (st == SPINSUM_OK) st = build_tiling(*P, ns[b], cs[b], t, vmax, &P->btil[b]);
     if (st != SPINSUM_OK) {
@@ -698,6 +722,7 @@ extern "C" spinsum_status spinsum_plan_batched(spinsum_plan_t* plan, int nblocks
     P->elems += P->block_elems[b];
     P->ncubes += cs[b];
     P->batch_lds_elems = std::max(P->batch_lds_elems, T.lds_elems);
+    P->batch_rep_bytes = std::max<int64_t>(P->batch_rep_bytes, (int64_t)T.max_rep_cnt * 4);
     // items of this block
     const Geom& g = T.g;
     if (T.nitems > 0) {
@@ -737,14 +762,14 @@ extern "C" spinsum_status spinsum_plan_batched(spinsum_plan_t* plan, int nblocks
     delete P;
     return SPINSUM_ERR_UNSUPPORTED;
   }
-  if (P->batch_lds_elems * elem_size(*P) + 512 > P->lds_limit) {
+  // behind the tiles: the representative lists (whole cubes) or the tile
+  // table (tile orbits)
+  P->batch_rep_bytes = std::max<int64_t>(P->batch_rep_bytes, 2 * kMaxDF * 4);
+  if ((P->batch_lds_elems * elem_size(*P) + 15) / 16 * 16 + P->batch_rep_bytes > P->lds_limit) {
     delete P;
     return SPINSUM_ERR_UNSUPPORTED;
   }
-  int64_t lds_b = std::max<int64_t>(1, P->batch_lds_elems * elem_size(*P) + 512);
-  int per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(8, P->lds_limit / lds_b));
-  P->batch_grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)P->items.size(),
-                                                               (int64_t)P->num_cus * per_cu));
+  P->batch_grid = (int)std::min<int64_t>((int64_t)P->items.size(), INT32_MAX);
   st = upload_tables(P);
   if (st != SPINSUM_OK) {
     free_device(P);
@@ -815,7 +840,7 @@ extern "C" spinsum_status spinsum_plan_get_info(spinsum_plan_t P, spinsum_plan_i
     }
     info->norbits = norb;
     info->max_tiles = mt;
-    info->fits_lds = P->batch_lds_elems * elem_size(*P) + 512 <= P->lds_limit;
+    info->fits_lds = (P->batch_lds_elems * elem_size(*P) + 15) / 16 * 16 + P->batch_rep_bytes <= P->lds_limit;
   }
   return SPINSUM_OK;
 }
@@ -840,6 +865,45 @@ extern "C" spinsum_status spinsum_plan_expanded(spinsum_plan_t P, int cap, int* 
 // Replays, on the host, the addresses one work item computes on the device
 // (load, combine, store) with the kernels' own index functions, and checks
 // that they stay in bounds and agree with each other.
+// Combine step of a work item: for every orbit of the group, the LDS
+// address of sigma . x (plus the item's LDS shift) holds global element
+// sigma . x.
+template <int D>
+static bool check_combine(const Tiling& T, const GroupDev& gd, int ncub,
+                          const std::vector<int64_t>& lds_of, int shift, std::string* why) {
+  const Geom& g = T.g;
+  const int d = D;
+  for (int k = 0; k < gd.norb; ++k) {
+    const uint32_t nrep = (uint32_t)ncub * (uint32_t)gd.rep_cnt[k];
+    int x0[D];  // origin of the orbit's identity tile
+    {
+      int64_t o0 = gd.tile_off[gd.slot_base[k][0] / g.ts];
+      for (int m = 0; m < d; ++m) x0[m] = (int)((o0 / g.gst[m]) % g.n);
+    }
+    for (uint32_t i = 0; i < nrep; ++i) {
+      uint32_t ci = (ncub == 1) ? 0u : fdiv(i, gd.fd_rep[k]);
+      uint32_t ri = i - ci * (uint32_t)gd.rep_cnt[k];
+      if (ci >= (uint32_t)ncub || ri >= (uint32_t)gd.rep_cnt[k]) { *why = "bad representative index"; return false; }
+      uint32_t pk = T.reps[gd.rep_off[k] + ri];
+      int l[D];
+      for (int m = 0; m < d; ++m) l[m] = (int)((pk >> (8 * m)) & 255u);
+      int x[D];
+      for (int m = 0; m < d; ++m) x[m] = x0[m] + l[m];
+      int addrs[kMaxDF];
+      orbit_addrs<D>(g, (int)ci * g.cube_lds, gd.slot_base[k], l, addrs,
+                     std::make_integer_sequence<int, Fact<D>()>{});
+      for (int r = 0; r < Fact<D>(); ++r) {
+        int a = addrs[r] + shift;
+        if (a < 0 || a >= T.lds_elems) { *why = "combine address out of bounds"; return false; }
+        int64_t want = (int64_t)ci * g.cube_elems;
+        for (int m = 0; m < d; ++m) want += (int64_t)x[lex_perm(D, r, m)] * g.gst[m];
+        if (lds_of[a] != want) { *why = "combine address does not hold sigma . x"; return false; }
+      }
+    }
+  }
+  return true;
+}
+
 template <int D, int VW>
 static bool emulate_item(const Tiling& T, const GroupDev& gd, int ncub, std::string* why) {
   const Geom& g = T.g;
@@ -881,41 +945,26 @@ static bool emulate_item(const Tiling& T, const GroupDev& gd, int ncub, std::str
         if (loaded[off] != 1) { *why = "tile element not loaded exactly once"; return false; }
       }
     }
-  // combine: for every orbit of the group, the LDS address of sigma . x
-  // holds global element sigma . x
-  for (int k = 0; k < gd.norb; ++k) {
-    const uint32_t nrep = (uint32_t)ncub * (uint32_t)gd.rep_cnt[k];
-    int x0[D];  // origin of the orbit's identity tile
-    {
-      int64_t o0 = gd.tile_off[gd.slot_base[k][0] / g.ts];
-      for (int m = 0; m < d; ++m) x0[m] = (int)((o0 / g.gst[m]) % g.n);
-    }
-    for (uint32_t i = 0; i < nrep; ++i) {
-      uint32_t ci = (ncub == 1) ? 0u : fdiv(i, gd.fd_rep[k]);
-      uint32_t ri = i - ci * (uint32_t)gd.rep_cnt[k];
-      if (ci >= (uint32_t)ncub || ri >= (uint32_t)gd.rep_cnt[k]) { *why = "bad representative index"; return false; }
-      uint32_t pk = T.reps[gd.rep_off[k] + ri];
-      int l[D];
-      for (int m = 0; m < d; ++m) l[m] = (int)((pk >> (8 * m)) & 255u);
-      int x[D];
-      for (int m = 0; m < d; ++m) x[m] = x0[m] + l[m];
-      int addrs[kMaxDF];
-      orbit_addrs<D>(g, (int)ci * g.cube_lds, gd.slot_base[k], l, addrs,
-                     std::make_integer_sequence<int, Fact<D>()>{});
-      for (int r = 0; r < Fact<D>(); ++r) {
-        int a = addrs[r];
-        if (a < 0 || a >= T.lds_elems) { *why = "combine address out of bounds"; return false; }
-        int64_t want = (int64_t)ci * g.cube_elems;
-        for (int m = 0; m < d; ++m) want += (int64_t)x[lex_perm(D, r, m)] * g.gst[m];
-        if (lds_of[a] != want) { *why = "combine address does not hold sigma . x"; return false; }
-      }
-    }
+  return check_combine<D>(T, gd, ncub, lds_of, 0, why);
+}
+
+// Whole-cube item copied as one contiguous run (direct-LDS kernel): element
+// e of the run sits at LDS element shift + e, for every alignment shift the
+// copy can take.
+template <int D>
+static bool emulate_flat(const Tiling& T, const GroupDev& gd, int ncub, int esz, std::string* why) {
+  const int64_t span = (int64_t)ncub * T.g.cube_elems;
+  for (int shift = 0; shift < 16 / esz; ++shift) {
+    if (shift + span > T.lds_elems) { *why = "contiguous copy exceeds the LDS tile area"; return false; }
+    std::vector<int64_t> lds_of(T.lds_elems, -1);
+    for (int64_t e = 0; e < span; ++e) lds_of[shift + e] = e;
+    if (!check_combine<D>(T, gd, ncub, lds_of, shift, why)) return false;
   }
   return true;
 }
 
 template <int D>
-static bool emulate_all(const Tiling& T, std::string* why) {
+static bool emulate_all(const Tiling& T, std::string* why, bool flat, int esz) {
   const Geom& g = T.g;
   std::vector<int> ncubs;
   if (g.bl == g.n) {
@@ -927,6 +976,7 @@ static bool emulate_all(const Tiling& T, std::string* why) {
   for (const GroupDev& gd : T.groups)
     for (int nc : ncubs) {
       bool ok = false;
+      if (flat && !emulate_flat<D>(T, gd, nc, esz, why)) return false;
       if (T.vw == 4) ok = emulate_item<D, 4>(T, gd, nc, why);
       else if (T.vw == 2) ok = emulate_item<D, 2>(T, gd, nc, why);
       else ok = emulate_item<D, 1>(T, gd, nc, why);
@@ -1003,7 +1053,14 @@ extern "C" spinsum_status spinsum_plan_check_ownership(spinsum_plan_t P, int blo
   for (int64_t e = 0; e < g.cube_elems; ++e)
     if (owner[e] == -1) return fail("element not owned");
   std::string w;
-  bool ok = (d == 2) ? emulate_all<2>(T, &w) : (d == 3) ? emulate_all<3>(T, &w) : emulate_all<4>(T, &w);
+  // whole cubes are also copied as one contiguous run by the direct-LDS
+  // kernels (single tensors) and by the batched kernel
+  const bool flat = (g.bl == g.n) &&
+                    (P->batched || P->tile.variant == SPINSUM_VARIANT_DIRECT_LDS);
+  const int esz = elem_size(*P);
+  bool ok = (d == 2)   ? emulate_all<2>(T, &w, flat, esz)
+            : (d == 3) ? emulate_all<3>(T, &w, flat, esz)
+                       : emulate_all<4>(T, &w, flat, esz);
   if (!ok) return fail(w);
   return SPINSUM_OK;
 }

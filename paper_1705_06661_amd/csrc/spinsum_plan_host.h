@@ -79,6 +79,7 @@ struct spinsum_plan_s {
   std::vector<int64_t> block_elems;
   int batch_vw = 1;
   int64_t batch_lds_elems = 0;
+  int64_t batch_rep_bytes = 0;  // LDS behind the tiles: representative lists / tile table
   int batch_grid = 0;
 
   // device

@@ -326,6 +326,29 @@ def test_autograd_gradcheck_and_dense_matrix(shape, gf, d):
                                    M @ x.detach().cpu().numpy().ravel(), rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_whole_cube_runs_at_every_alignment(dtype):
+    """Whole-cube items are copied as one contiguous run: odd cube sizes and
+    cube counts put item starts and ends at every offset within a 16-byte
+    chunk (head and tail elements through registers)."""
+    for shape, d in [((7, 5, 5, 5), 3), ((5, 3, 3, 3), 3), ((9, 3, 3, 3, 3), 4),
+                     ((11, 7, 7), 2), ((3, 1, 1, 1), 3), ((6, 2, 2, 2), 3)]:
+        n = shape[1]
+        rng = np.random.default_rng(sum(shape))
+        terms = [(p, float(rng.integers(-3, 4))) for p in itertools.permutations(range(d))]
+        x = gpu_uniform(shape, 31, dtype)
+        ref = ref_of(x, [terms], d)
+        xi = gpu_ints(shape, 32, dtype)
+        refi = ref_of(xi, [terms], d)
+        for cpw in (1, 2, 3, 5):
+            for inplace in (False, True):
+                p = mk(shape, [terms], d, dtype=dtype, inplace=inplace, tile=(n, cpw))
+                info = ss.spinsum_plan_get_info(p)
+                assert info["variant"] == ss.SPINSUM_VARIANT_DIRECT_LDS
+                assert nerr(run(p, x).cpu().numpy(), ref) <= TOL[dtype], (shape, cpw, inplace)
+                np.testing.assert_array_equal(run(p, xi).cpu().numpy().astype(np.float64), refi)
+
+
 # ----------------------------------------------------------------- batched
 def _small_blocks():
     rng = np.random.default_rng(5)

@@ -281,12 +281,18 @@ def test_direct_lds_variant_uses_dense_tiles():
         assert info["variant"] == ss.SPINSUM_VARIANT_DIRECT_LDS and info["lds_pad"] == 0
         ok, why = ss.spinsum_plan_check_ownership(p)
         assert ok, why
-    # rows that are not 16 bytes fall back to the register one-shot kernel
-    p = plan((3, 6, 6, 6), [[((0, 1, 2), 1.0)]], dtype="f32")
+    # tile rows that are not 16 bytes fall back to the register one-shot kernel
+    p = plan((3, 12, 12, 12), [[((0, 1, 2), 1.0)]], dtype="f32")
     ss.spinsum_plan_set_tile(p, 6, variant=ss.SPINSUM_VARIANT_DIRECT_LDS)
     assert ss.spinsum_plan_get_info(p)["variant"] == ss.SPINSUM_VARIANT_REG_ONESHOT
-    q = plan((3, 5, 5, 5), [[((0, 1, 2), 1.0)]])
-    assert ss.spinsum_plan_get_info(q)["variant"] == ss.SPINSUM_VARIANT_REG_ONESHOT
+    # whole cubes of any extent are copied as one contiguous run
+    for shape, dtype in [((3, 5, 5, 5), "f64"), ((3, 6, 6, 6), "f32"), ((7, 3, 3, 3, 3), "f64")]:
+        q = plan(shape, [[(tuple(range(len(shape) - 1)), 1.0)]], d=len(shape) - 1, dtype=dtype)
+        info = ss.spinsum_plan_get_info(q)
+        assert info["bl"] == shape[1]
+        assert info["variant"] == ss.SPINSUM_VARIANT_DIRECT_LDS
+        ok, why = ss.spinsum_plan_check_ownership(q)
+        assert ok, why
 
 
 @pytest.mark.parametrize("d,n,bl", [(3, 32, 8), (3, 13, 4), (4, 12, 6), (4, 10, 4), (2, 16, 4),
