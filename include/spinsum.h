@@ -90,9 +90,12 @@ typedef struct spinsum_graph_s* spinsum_graph_t;
 /* Tile configuration (the blocking of Alg. 5a/5b, Sec. 4.5).
  * bl: tile edge along every group axis, 1 <= bl <= N; bl == N processes whole
  *     cubes.  cubes_per_wg: whole-cube mode only, spectator cubes per
- *     workgroup (>= 1).  threads: workgroup size (256).  lds_pad: 1 = odd
- *     LDS strides (register variants only).  variant: SPINSUM_VARIANT_*.
- *     0 in bl / cubes_per_wg / threads / variant means "choose". */
+ *     workgroup (>= 1).  threads: workgroup size, 256, 512 or 1024 for
+ *     SPINSUM_VARIANT_DIRECT_LDS (0: chosen so that the workgroups that fit
+ *     a CU's LDS hold about 16 waves), always 256 for the other variants.
+ *     lds_pad: 1 = odd LDS strides (register variants only).  variant:
+ *     SPINSUM_VARIANT_*.  0 in bl / cubes_per_wg / threads / variant means
+ *     "choose". */
 typedef struct {
   int bl;
   int cubes_per_wg;

@@ -191,7 +191,7 @@ class Plan:
 
     def __del__(self):
         h, self._h = getattr(self, "_h", None), None
-        if h:
+        if h and _c_destroy is not None:  # module globals may be gone at exit
             _c_destroy(h)
 
     def info(self) -> dict:
@@ -226,7 +226,7 @@ def spinsum_plan_batched(shapes: Sequence[Sequence[int]], d: int, stages, dtype=
 
 
 def spinsum_plan_set_tile(plan: Plan, bl: int, cubes_per_wg: int = 1, lds_pad: int = 1,
-                          threads: int = 256, variant: int = SPINSUM_VARIANT_AUTO,
+                          threads: int = 0, variant: int = SPINSUM_VARIANT_AUTO,
                           item_tiles: int = 0):
     t = _Tile(int(bl), int(cubes_per_wg), int(threads), int(lds_pad), int(variant),
               int(item_tiles))
@@ -339,7 +339,7 @@ class Graph:
 
     def __del__(self):
         h, self._h = getattr(self, "_h", None), None
-        if h:
+        if h and _c_graph_destroy is not None:
             _c_graph_destroy(h)
 
 

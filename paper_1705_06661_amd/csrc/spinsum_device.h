@@ -37,7 +37,8 @@
 namespace spinsum {
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 256;     // workgroup size of every kernel but k_lds
+constexpr int kMaxThreads = 1024; // k_lds, k_ldsp: 256, 512 or 1024 (blockDim.x)
 constexpr int kUnroll = 4;
 
 template <int D>
@@ -164,12 +165,17 @@ struct BatchArgs {
   int32_t pad;
 };
 
+// Fused multiply-add in the storage type (a float FMA for float: the
+// generic builtin would promote to double).
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // w_tau = sum_sigma a(tau^-1 o sigma) v_sigma, sigma in lexicographic
 // order, every index a compile-time constant
 template <typename T, int D, int TAU, int... S>
 __device__ __forceinline__ T orbit_row(const T* a, const T* v, std::integer_sequence<int, S...>) {
   T acc = T(0);
-  ((acc = __builtin_fma(a[GinvMul<D, TAU, S>::value], v[S], acc)), ...);
+  ((acc = fma_t(a[GinvMul<D, TAU, S>::value], v[S], acc)), ...);
   return acc;
 }
 
@@ -183,6 +189,17 @@ template <typename T, int D>
 __device__ __forceinline__ void orbit_product(const T (&a)[Fact<D>::v], const T (&v)[Fact<D>::v],
                                               T (&w)[Fact<D>::v]) {
   orbit_rows<T, D>(a, v, w, std::make_integer_sequence<int, Fact<D>::v>{});
+}
+
+// The same product, each w_tau written to LDS as soon as it is formed (all
+// v_sigma are already in registers, so the in-place writes are safe); only
+// a few accumulators are live at a time.  (One FMA chain per row is fine:
+// a wave64 FMA occupies its SIMD for four cycles, which covers the
+// dependency latency.)
+template <typename T, int D, int... TAU>
+__device__ __forceinline__ void orbit_rows_store(const T* a, const T* v, T* lds, const int* addr,
+                                                 std::integer_sequence<int, TAU...>) {
+  ((lds[addr[TAU]] = orbit_row<T, D, TAU>(a, v, std::make_integer_sequence<int, Fact<D>::v>{})), ...);
 }
 
 // 2. combine every element orbit of the item in LDS
@@ -209,7 +226,7 @@ __device__ __forceinline__ void combine_item(const Geom& g, cptr<GroupDev> gd,
     const uint32_t nrep = (uint32_t)ncub * rep_cnt;
     const FastDiv fdr = load_fd(gd->fd_rep[k]);
     const uint32_t* rp = reps + (REPS_IN_LDS ? gd->rep_base[k] : gd->rep_off[k]);
-    for (uint32_t i = threadIdx.x; i < nrep; i += kThreads) {
+    for (uint32_t i = threadIdx.x; i < nrep; i += blockDim.x) {
       uint32_t ci = (ncub == 1) ? 0u : fdiv(i, fdr);
       uint32_t ri = i - ci * rep_cnt;
       uint32_t pk = rp[ri];
@@ -219,13 +236,13 @@ __device__ __forceinline__ void combine_item(const Geom& g, cptr<GroupDev> gd,
       const int base = (int)ci * g.cube_lds;
       int addr[DF];
       T v[DF];
-      T w[DF];
       orbit_addrs<D>(g, base, sb, l, addr, std::make_integer_sequence<int, DF>{});
 #pragma unroll
       for (int r = 0; r < DF; ++r) v[r] = lds[addr[r]];
       if constexpr (!CHAIN) {
-        orbit_product<T, D>(a, v, w);
+        orbit_rows_store<T, D>(a, v, lds, addr, std::make_integer_sequence<int, DF>{});
       } else {
+        T w[DF];
         for (int s = 0; s < nstages; ++s) {
 #pragma unroll
           for (int r = 0; r < DF; ++r) a[r] = coef[s * DF + r];
@@ -234,10 +251,8 @@ __device__ __forceinline__ void combine_item(const Geom& g, cptr<GroupDev> gd,
           for (int r = 0; r < DF; ++r) v[r] = w[r];
         }
 #pragma unroll
-        for (int r = 0; r < DF; ++r) w[r] = v[r];
+        for (int r = 0; r < DF; ++r) lds[addr[r]] = v[r];
       }
-#pragma unroll
-      for (int r = 0; r < DF; ++r) lds[addr[r]] = w[r];
     }
   }
 }
@@ -416,7 +431,7 @@ __device__ __forceinline__ int issue_item_lds(const Geom& g, cptr<GroupDev> od, 
   const uint32_t tid = threadIdx.x;
   const uint32_t wave_bytes = (tid >> 6) * 1024u;
   int issued = 0;
-  for (uint32_t c0 = 0; c0 < cpt; c0 += kThreads) {
+  for (uint32_t c0 = 0; c0 < cpt; c0 += blockDim.x) {
     int l[D];
     chunk_coords<D, VW>(g, c0 + tid, l);
     int off = 0;
@@ -469,7 +484,7 @@ __device__ __forceinline__ int flat_issue(const T* src, uint32_t m, unsigned cha
   (void)E;
   const uint32_t lds0 = (uint32_t)(pc - p0);
   const uint32_t wave_bytes = (tid >> 6) * 1024u;
-  for (uint32_t c0 = 0; c0 < nfull; c0 += kThreads) {
+  for (uint32_t c0 = 0; c0 < nfull; c0 += blockDim.x) {
     if (c0 + tid < nfull)
       __builtin_amdgcn_global_load_lds(
           (const void*)(pc + ((uintptr_t)(c0 + tid) << 4)),
@@ -494,7 +509,7 @@ __device__ __forceinline__ void flat_store(T* dst, uint32_t m, const unsigned ch
   typedef typename VecT<T, 16 / sizeof(T)>::type V;
   if (flat_shift(dst) != in_shift) {
     const T* ldsT = reinterpret_cast<const T*>(lds) + in_shift;
-    for (uint32_t e = threadIdx.x; e < m; e += kThreads) dst[e] = ldsT[e];
+    for (uint32_t e = threadIdx.x; e < m; e += blockDim.x) dst[e] = ldsT[e];
     return;
   }
   const uintptr_t p = (uintptr_t)dst;
@@ -515,7 +530,7 @@ __device__ __forceinline__ void flat_store(T* dst, uint32_t m, const unsigned ch
     dst[e] = ldsT[shift + e];
   }
   const uint32_t lds0 = (uint32_t)(pc - p0);
-  for (uint32_t c = tid; c < nfull; c += kThreads) {
+  for (uint32_t c = tid; c < nfull; c += blockDim.x) {
     const V val = *reinterpret_cast<const V*>(lds + lds0 + c * 16u);
     V* q = reinterpret_cast<V*>(pc + ((uintptr_t)c << 4));
     if constexpr (NTS)
@@ -537,7 +552,7 @@ __device__ __forceinline__ void issue_reps_lds(cptr<GroupDev> od, const uint32_t
     const uint32_t cnt = (uint32_t)od->rep_cnt[k];
     const uint32_t* src = reps + od->rep_off[k];
     unsigned char* dst = rep_lds + (uint32_t)od->rep_base[k] * 4u;
-    for (uint32_t i0 = 0; i0 < cnt; i0 += kThreads) {
+    for (uint32_t i0 = 0; i0 < cnt; i0 += blockDim.x) {
       if (i0 + tid < cnt)
         __builtin_amdgcn_global_load_lds(
             (const void*)(src + i0 + tid),
@@ -554,7 +569,7 @@ __device__ __forceinline__ void store_item_lds(const Geom& g, cptr<GroupDev> od,
   constexpr int VW = 16 / sizeof(T);
   typedef typename VecT<T, VW>::type V;
   const uint32_t cpt = (uint32_t)g.rows * (uint32_t)g.vpr;
-  for (uint32_t c0 = 0; c0 < cpt; c0 += kThreads) {
+  for (uint32_t c0 = 0; c0 < cpt; c0 += blockDim.x) {
     const uint32_t c = c0 + threadIdx.x;
     int l[D];
     chunk_coords<D, VW>(g, c, l);
@@ -627,7 +642,7 @@ __device__ __forceinline__ void wait_vmcnt_atmost(int n) {
 // way, so the combine step issues no global loads.
 // LDS: [tiles (lds_tile_bytes) | representatives (rep_total entries)].
 template <typename T, int D, bool CHAIN, bool NTS>
-__global__ void __launch_bounds__(kThreads) k_lds(const ExecArgs<T> a) {
+__global__ void __launch_bounds__(kMaxThreads) k_lds(const ExecArgs<T> a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
   int64_t item;
@@ -676,7 +691,7 @@ __global__ void __launch_bounds__(kThreads) k_lds(const ExecArgs<T> a) {
 // workgroups of one XCD work on neighbouring items at any time.
 // LDS: [representatives (nreps, padded to 16 bytes) | buffer 0 | buffer 1].
 template <typename T, int D, bool CHAIN, bool NTS>
-__global__ void __launch_bounds__(kThreads) k_ldsp(const ExecArgs<T> a) {
+__global__ void __launch_bounds__(kMaxThreads) k_ldsp(const ExecArgs<T> a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const Geom& g = a.g;
   uint32_t* rep_lds = reinterpret_cast<uint32_t*>(smem);
@@ -699,7 +714,7 @@ __global__ void __launch_bounds__(kThreads) k_ldsp(const ExecArgs<T> a) {
   };
   int64_t it = item_at(0);
   if (it < 0) return;
-  for (int i = threadIdx.x; i < a.nreps; i += kThreads) rep_lds[i] = a.reps[i];
+  for (int i = threadIdx.x; i < a.nreps; i += blockDim.x) rep_lds[i] = a.reps[i];
   const bool whole = (g.bl == g.n);
   const cptr<T> coef = as_const(a.coef);
   int64_t cube0;

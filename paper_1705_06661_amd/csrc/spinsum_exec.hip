@@ -60,14 +60,15 @@ spinsum_status prepare_kernel(spinsum_plan_s* P, const void* k, size_t shmem) {
 
 // Workgroups of a persistent launch: the occupancy of the kernel times the
 // CUs, rounded down to a multiple of 8 (one share per XCD).
-spinsum_status persistent_grid(spinsum_plan_s* P, const void* k, size_t shmem, int64_t nitems,
-                               int64_t* grid) {
-  if (P->occ_kernel != k || P->occ_shmem != (int64_t)shmem) {
+spinsum_status persistent_grid(spinsum_plan_s* P, const void* k, int threads, size_t shmem,
+                               int64_t nitems, int64_t* grid) {
+  if (P->occ_kernel != k || P->occ_shmem != (int64_t)shmem || P->occ_threads != threads) {
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kThreads, shmem);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, shmem);
     if (e != hipSuccess) return hip_error(P, e);
     P->occ_kernel = k;
     P->occ_shmem = (int64_t)shmem;
+    P->occ_threads = threads;
     P->occ_blocks = std::max(1, per_cu);
   }
   int64_t g = (int64_t)P->occ_blocks * P->num_cus;
@@ -117,9 +118,12 @@ spinsum_status launch_exec(spinsum_plan_s* P, const void* in, void* out, hipStre
     shmem = ((size_t)a.nreps * 4 + 15) / 16 * 16 + 2 * (size_t)a.lds_tile_bytes;
   spinsum_status st = prepare_kernel(P, k, shmem);
   if (st != SPINSUM_OK) return st;
+  const int threads = (kind == SPINSUM_VARIANT_DIRECT_LDS || kind == SPINSUM_VARIANT_LDS_PIPELINE)
+                          ? P->tile.threads
+                          : kThreads;
   int64_t grid;
   if (kind == SPINSUM_VARIANT_REG_PIPELINE || kind == SPINSUM_VARIANT_LDS_PIPELINE) {
-    st = persistent_grid(P, k, shmem, Tl.nitems, &grid);
+    st = persistent_grid(P, k, threads, shmem, Tl.nitems, &grid);
     if (st != SPINSUM_OK) return st;
     a.xcd_per = (P->flags & SPINSUM_FLAG_NO_XCD_REMAP) ? 0 : (Tl.nitems + 7) / 8;
   } else if (P->flags & SPINSUM_FLAG_NO_XCD_REMAP) {
@@ -130,7 +134,7 @@ spinsum_status launch_exec(spinsum_plan_s* P, const void* in, void* out, hipStre
     grid = a.xcd_per * 8;
   }
   void* kargs[] = {&a};
-  hipError_t e = hipLaunchKernel(k, dim3((unsigned)grid), dim3(kThreads), kargs, shmem, stream);
+  hipError_t e = hipLaunchKernel(k, dim3((unsigned)grid), dim3(threads), kargs, shmem, stream);
   if (e != hipSuccess) return hip_error(P, e);
   return SPINSUM_OK;
 }

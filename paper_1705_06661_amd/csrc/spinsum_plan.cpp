@@ -131,6 +131,14 @@ static int64_t tile_lds_bytes(const spinsum_plan_s& P, int n, int bl, int cpw, i
   return (int64_t)tiles * ts * elem_size(P) + ipow(bl, P.d) * 4;
 }
 
+// Default tile (measured on MI355X; spinsum_autotune searches more).
+//  1. Cubes up to 64 KiB are processed whole, several per workgroup up to
+//     about 8 KiB, as one contiguous copy (any extent).
+//  2. Larger cubes use tile orbits whose rows (also the short rows of
+//     ragged edge tiles) are whole 16-byte chunks, for the direct-LDS kernel,
+//     and whose largest orbit takes at most 32 KiB of LDS; among those, the
+//     widest rows win, then the smaller LDS footprint.
+//  3. Otherwise the largest tile that fits, through registers.
 spinsum_status choose_tile(const spinsum_plan_s& P, int n, int64_t ncubes, int vw,
                            spinsum_tile_t* tile) {
   const int esz = elem_size(P);
@@ -138,12 +146,12 @@ spinsum_status choose_tile(const spinsum_plan_s& P, int n, int64_t ncubes, int v
   const int pad = (P.flags & SPINSUM_FLAG_NO_LDS_PAD) ? 0 : 1;
   const int64_t budget = P.lds_limit - 512;
   spinsum_tile_t t{};
-  t.threads = 256;
+  t.threads = 0;  // chosen once the variant is known
   t.lds_pad = pad;
   const int64_t cube_bytes = ipow(n, d) * esz;
-  if (cube_bytes <= 40 * 1024) {
+  if (cube_bytes <= 64 * 1024 && cube_bytes + 16 + ipow(n, d) * 4 <= budget) {
     t.bl = n;
-    int cpw = (int)std::max<int64_t>(1, (32 * 1024) / std::max<int64_t>(1, cube_bytes));
+    int cpw = (int)std::max<int64_t>(1, (8 * 1024) / std::max<int64_t>(1, cube_bytes));
     // keep at least ~8 workgroups per CU of work when the tensor allows it
     int64_t cap = std::max<int64_t>(1, ncubes / (8 * (int64_t)P.num_cus));
     cpw = (int)std::min<int64_t>(cpw, cap);
@@ -152,23 +160,32 @@ spinsum_status choose_tile(const spinsum_plan_s& P, int n, int64_t ncubes, int v
     return SPINSUM_OK;
   }
   t.cubes_per_wg = 1;
-  struct Pass {
-    int min_row_bytes;
-    int64_t max_lds;
-  };
-  const Pass passes[] = {{64, 48 * 1024}, {32, 80 * 1024}, {0, budget}};
-  for (const Pass& ps : passes) {
-    for (int bl = n - 1; bl >= 1; --bl) {
-      if (n % bl != 0 && ps.min_row_bytes > 0) continue;
-      if (vw > 1 && bl % vw != 0 && ps.min_row_bytes > 0) continue;
-      if (bl * esz < ps.min_row_bytes) continue;
-      if (bl > 255) continue;
-      int64_t lb = tile_lds_bytes(P, n, bl, 1, pad);
-      if (lb > std::min<int64_t>(ps.max_lds, budget)) continue;
-      t.bl = bl;
-      *tile = t;
-      return SPINSUM_OK;
+  const int64_t orbit_cap = 32 * 1024;
+  int best = 0;
+  int64_t best_lds = 0;
+  for (int bl = n - 1; bl >= 1; --bl) {
+    if (bl > 255) continue;
+    const int row = bl * esz;
+    if (vw_for(n, bl, vw) * esz != 16) continue;
+    const int64_t lb = tile_lds_bytes(P, n, bl, 1, 0);
+    if (lb > std::min(orbit_cap, budget)) continue;
+    if (best == 0 || row > best * esz || (row == best * esz && lb < best_lds)) {
+      best = bl;
+      best_lds = lb;
     }
+  }
+  if (best > 0) {
+    t.bl = best;
+    *tile = t;
+    return SPINSUM_OK;
+  }
+  for (int bl = n - 1; bl >= 1; --bl) {
+    if (bl > 255) continue;
+    if (vw > 1 && bl % vw != 0) continue;
+    if (tile_lds_bytes(P, n, bl, 1, pad) > budget) continue;
+    t.bl = bl;
+    *tile = t;
+    return SPINSUM_OK;
   }
   return SPINSUM_ERR_UNSUPPORTED;
 }
@@ -533,7 +550,7 @@ static spinsum_status apply_tile(spinsum_plan_s* P, const spinsum_tile_t* req) {
   const int vmax = max_vector_width(*P, std::max(1, P->n));
   if (req && req->bl > 0) {
     t = *req;
-    if (t.threads <= 0) t.threads = 256;
+    if (t.threads < 0) t.threads = 0;
     if (t.cubes_per_wg <= 0) t.cubes_per_wg = 1;
   } else if (P->n > 0 && P->ncubes > 0) {
     if (!cache_lookup(*P, &t)) {
@@ -541,8 +558,8 @@ static spinsum_status apply_tile(spinsum_plan_s* P, const spinsum_tile_t* req) {
       if (st != SPINSUM_OK) return st;
     }
   }
-  if (t.threads != 256 && t.threads != 0) return SPINSUM_ERR_UNSUPPORTED;
-  t.threads = 256;
+  if (t.threads != 0 && t.threads != 256 && t.threads != 512 && t.threads != 1024)
+    return SPINSUM_ERR_UNSUPPORTED;
   if (t.variant < 0 || t.variant > SPINSUM_VARIANT_LDS_PIPELINE) return SPINSUM_ERR_INVALID_ARG;
   // kernel variant: loads straight into LDS need whole 16-byte rows, except
   // for whole cubes, which the one-shot kernel copies as one contiguous run
@@ -567,6 +584,20 @@ static spinsum_status apply_tile(spinsum_plan_s* P, const spinsum_tile_t* req) {
       (((int64_t)T.reps.size() * 4 + 15) / 16 * 16 + 2 * ((T.lds_elems * elem_size(*P) + 15) / 16 * 16) >
        P->lds_limit))
     t.variant = SPINSUM_VARIANT_DIRECT_LDS;
+  // workgroup size: the direct-LDS kernels take 256, 512 or 1024 threads;
+  // by default enough that the workgroups LDS lets onto a CU hold about 16
+  // waves (the combine step of big items then spreads over more waves);
+  // the register kernels run 256
+  if (t.variant != SPINSUM_VARIANT_DIRECT_LDS && t.variant != SPINSUM_VARIANT_LDS_PIPELINE) {
+    t.threads = 256;
+  } else if (t.threads == 0) {
+    const int64_t tiles = (T.lds_elems * elem_size(*P) + 15) / 16 * 16;
+    const int64_t wg_lds = (t.variant == SPINSUM_VARIANT_DIRECT_LDS)
+                               ? tiles + (int64_t)T.max_rep_cnt * 4
+                               : 2 * tiles + ((int64_t)T.reps.size() * 4 + 15) / 16 * 16;
+    const int64_t per_cu = std::max<int64_t>(1, P->lds_limit / std::max<int64_t>(1, wg_lds));
+    t.threads = per_cu >= 4 ? 256 : per_cu >= 2 ? 512 : 1024;
+  }
   P->tile = t;
   P->T = std::move(T);
   return SPINSUM_OK;
@@ -810,7 +841,7 @@ extern "C" spinsum_status spinsum_plan_get_info(spinsum_plan_t P, spinsum_plan_i
   info->nblocks = P->nblocks;
   info->dtype = P->dtype;
   info->inplace = P->inplace;
-  info->threads = 256;
+  info->threads = P->batched ? 256 : P->tile.threads;
   if (!P->batched) {
     info->bl = P->T.g.bl;
     info->variant = P->tile.variant;

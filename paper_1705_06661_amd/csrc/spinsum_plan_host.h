@@ -95,6 +95,7 @@ struct spinsum_plan_s {
   int last_hip_error = 0;
   const void* occ_kernel = nullptr;  // occupancy cache of the persistent kernel
   int64_t occ_shmem = -1;
+  int occ_threads = 0;
   int occ_blocks = 1;
   std::string why;
 };

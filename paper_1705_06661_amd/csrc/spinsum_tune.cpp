@@ -134,7 +134,11 @@ extern "C" spinsum_status spinsum_autotune(spinsum_plan_t P, void* in, void* out
     spinsum_tile_t t = sh;
     t.lds_pad = 0;
     t.variant = SPINSUM_VARIANT_DIRECT_LDS;
-    cands.push_back(t);
+    for (int th : {256, 512, 1024}) {
+      t.threads = th;
+      cands.push_back(t);
+    }
+    t.threads = 256;
     t.variant = SPINSUM_VARIANT_LDS_PIPELINE;
     cands.push_back(t);
     for (int pad = 1; pad >= 0; --pad) {

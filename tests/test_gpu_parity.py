@@ -349,6 +349,34 @@ def test_whole_cube_runs_at_every_alignment(dtype):
                 np.testing.assert_array_equal(run(p, xi).cpu().numpy().astype(np.float64), refi)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_direct_lds_thread_counts(dtype):
+    """The direct-LDS kernels (one-shot and pipelined) at 256, 512 and 1024
+    threads: the same result (bitwise), within tolerance of the oracle."""
+    for shape, d, bl in [((3, 16, 16, 16), 3, 16), ((2, 20, 20, 20), 3, 8), ((2, 12, 12, 12, 12), 4, 4),
+                         ((2, 12, 12, 12, 12), 4, 6), ((5, 7, 7, 7), 3, 7), ((1, 24, 24, 24), 3, 24)]:
+        rng = np.random.default_rng(len(shape) + bl)
+        terms = [(p, float(rng.integers(-3, 4))) for p in itertools.permutations(range(d))]
+        x = gpu_uniform(shape, 41, dtype)
+        ref = ref_of(x, [terms], d)
+        base = None
+        for threads, inplace, variant in itertools.product(
+                (256, 512, 1024), (False, True),
+                (ss.SPINSUM_VARIANT_DIRECT_LDS, ss.SPINSUM_VARIANT_LDS_PIPELINE)):
+            if True:
+                p = ss.spinsum_plan(shape, len(shape) - d, d, [terms], dtype=dtype, inplace=inplace)
+                ss.spinsum_plan_set_tile(p, bl, threads=threads, variant=variant)
+                info = ss.spinsum_plan_get_info(p)
+                if info["variant"] != variant:
+                    continue
+                assert info["threads"] == threads
+                y = run(p, x)
+                assert nerr(y.cpu().numpy(), ref) <= TOL[dtype], (shape, bl, threads, inplace)
+                if base is None:
+                    base = y
+                assert torch.equal(y, base), (shape, bl, threads, inplace)
+
+
 # ----------------------------------------------------------------- batched
 def _small_blocks():
     rng = np.random.default_rng(5)

@@ -205,7 +205,7 @@ def test_lds_footprint_matches_eq11():
 
 
 @pytest.mark.parametrize("name,bl,whole", [("3d_v16_o8", 8, True), ("3d_v64_o32_slab", 8, False),
-                                           ("4d_v24_o12_slab", 6, False), ("3d_v48_o24", 8, False)])
+                                           ("4d_v24_o12_slab", 4, False), ("3d_v48_o24", 8, False)])
 def test_default_tiles_of_the_workloads(name, bl, whole):
     w = workloads.WORKLOADS[name]
     p = ss.spinsum_plan(w["shape"], w["group_first"], w["d"], [workloads.CONFIG_3D_ALPHA] if w["d"] == 3
@@ -216,6 +216,23 @@ def test_default_tiles_of_the_workloads(name, bl, whole):
     assert info["lds_bytes"] <= 160 * 1024
     assert info["vector_width"] == 2
     assert info["elems"] == int(np.prod(w["shape"]))
+
+
+def test_default_tiles_follow_the_measured_rules():
+    """Cubes up to 64 KiB whole (8 KiB per workgroup when small); larger
+    cubes in tile orbits of 16-byte-chunk rows within 32 KiB, widest rows
+    first (ragged edge tiles allowed)."""
+    alpha = [workloads.CONFIG_3D_ALPHA]
+    for shape, dtype, bl, cpw in [((64, 64, 64, 8, 8, 8), "f64", 8, 2),
+                                  ((48, 48, 48, 24, 24, 24), "f32", 24, 1),
+                                  ((40, 40, 40, 20, 20, 20), "f64", 20, 1),
+                                  ((32, 32, 32, 28, 28, 28), "f64", 8, 1),
+                                  ((16, 16, 16, 40, 40, 40), "f64", 8, 1),
+                                  ((64, 64, 8, 32, 32, 32), "f32", 8, 1)]:
+        p = plan(shape, alpha, dtype=dtype)
+        info = ss.spinsum_plan_get_info(p)
+        assert (info["bl"], info["cubes_per_wg"]) == (bl, cpw), shape
+        assert info["variant"] == ss.SPINSUM_VARIANT_DIRECT_LDS
 
 
 def test_batched_plan_tables():
