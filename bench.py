@@ -103,20 +103,21 @@ def form_entry(nbytes, ms, ref_gbps=None):
     return d
 
 
-def cpu_baseline(seconds: float):
-    """The oracle on a bounded sample of the headline workload: whole
-    32^3 spectator cubes of slab 0, regenerated on the host."""
+def cpu_baseline(seconds: float, nslabs: int):
+    """The oracle on a bounded sample of the headline workload: consecutive
+    whole 32^3 spectator cubes of the slabs, regenerated on the host from
+    the same seeds, until about `seconds` of oracle time."""
     import numpy as np
     import oracle
     import workloads
     cube = 32 ** 3
+    per_slab = 64 * 64 * 8
     threads = max(1, min(16, os.cpu_count() or 1))
-
-    # consecutive chunks of cubes of slab 0 until about `seconds` of CPU work
     chunk = 1024
     done, total = 0, 0.0
-    while total < seconds and done < 32768:
-        x = workloads.uniform_numpy(chunk * cube, 1000, offset=done * cube).reshape(chunk, 32, 32, 32)
+    while total < seconds and done < nslabs * per_slab:
+        slab, c0 = divmod(done, per_slab)
+        x = workloads.uniform_numpy(chunk * cube, 1000 + slab, offset=c0 * cube).reshape(chunk, 32, 32, 32)
         t0 = time.perf_counter()
         oracle.spinsum(x, workloads.CONFIG_3D_ALPHA, 1, 3, nthreads=threads)
         total += time.perf_counter() - t0
@@ -124,8 +125,9 @@ def cpu_baseline(seconds: float):
     elems = done * cube
     return {"value": round(2 * elems * 8 / total / 1e9, 4), "unit": "GB/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"first {done} of the 32768 spectator cubes (32^3 each, {elems} elements, fp64) "
-                      f"of slab 0 of the v=64 o=32 in-place workload, {total:.1f} s of oracle time"}
+            "sample": f"the first {done} spectator cubes (32^3 each, {elems} elements, fp64) of the "
+                      f"{nslabs} slabs of the v=64 o=32 in-place workload, in slab order, "
+                      f"{total:.1f} s of oracle time on {threads} threads"}
 
 
 def main():
@@ -285,7 +287,7 @@ def main():
 
     if not args.no_cpu_baseline:
         log("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, nslabs)
     print(json.dumps(out), flush=True)
 
 

@@ -1,31 +1,35 @@
-// spinsum_kernels.hip -- gfx950 kernels of libspinsum and the exec entry
-// points of the C-ABI.
+// spinsum_device.h -- gfx950 kernels of libspinsum (instantiated per storage
+// type and group size in spinsum_kern_<type>_d<d>.hip).
 //
 // A work item is a run of whole spectator cubes, or one tile orbit
-// {sigma . B} of one cube (the macro-kernel of Alg. 5b/6).  A workgroup
-//   1. loads every tile of the item from HBM once, with 16-byte vector loads
-//      along the fastest (stride-one) axis, into LDS (padded strides);
-//   2. combines every element orbit in registers: each thread takes
-//      representatives x, reads v_sigma = tile[sigma . x] for all sigma in
-//      S_d, forms w_tau = sum_sigma a(tau^-1 o sigma) v_sigma (a = the
-//      coefficient of each permutation in the operator, held in scalar
-//      registers; with stage chaining the stages are applied one after the
-//      other) and writes w_tau to tile[tau . x];
+// {sigma . B} of one cube (the macro-kernel of Alg. 5b/6), optionally
+// several tile orbits of a cube.  A workgroup
+//   1. loads every tile of the item from HBM once, in 16-byte chunks along
+//      the fastest (stride-one) axis, into LDS;
+//   2. combines every element orbit: each thread takes representatives x,
+//      reads v_sigma = tile[sigma . x] for all sigma in S_d, forms
+//      w_tau = sum_sigma a(tau^-1 o sigma) v_sigma (a = the coefficient of
+//      each permutation in the operator, in scalar registers; with stage
+//      chaining the stages are applied one after the other) and writes w_tau
+//      to tile[tau . x];
 //   3. stores the tiles back once with 16-byte stores, non-temporal by
 //      default (Sec. 4.6.3), in place (Sec. 4.6.5) or to the output.
 // Every element belongs to exactly one item, and inside an item to the
 // element orbit of exactly one representative, so in-place needs only the
 // workgroup barriers.
 //
-// The main kernel (k_pipe) is persistent and software-pipelined: while an
-// item is combined and stored, the loads of the workgroup's next item are
-// already in flight in registers.  Items are grouped per XCD: the workgroups
-// of XCD x (blockIdx % 8 == x) sweep a contiguous range of items, so the
-// tile orbits of one cube -- which share 128-byte lines along the fastest
-// axis -- meet in the same L2.  k_exec is the one-shot form (one item per
-// workgroup), used for items too large for the register prefetch buffer and
-// as an ablation.  The work is HBM-bound (0.75 flop/byte in 3D, 3 in 4D):
-// no matrix cores are used.
+// Kernels:
+//   k_lds     one item per workgroup, loads straight into LDS
+//             (global_load_lds), 256/512/1024 threads -- the default;
+//   k_ldsp    persistent, two LDS buffers, next item's loads in flight;
+//   k_exec    one item per workgroup, loads through registers into padded
+//             LDS (rows that are not whole 16-byte chunks);
+//   k_pipe    persistent, next item prefetched into registers;
+//   k_batched many tensors, one item of the cost-sorted list per workgroup.
+// One-shot grids are XCD-grouped: the workgroups of XCD x (blockIdx % 8 == x)
+// take a contiguous range of items, so the tile orbits of one cube -- which
+// share cache lines along the fastest axis -- meet in the same L2.  The work
+// is HBM-bound (0.75 flop/byte in 3D, 3 in 4D): no matrix cores are used.
 #pragma once
 #include <hip/hip_runtime.h>
 
