@@ -41,7 +41,7 @@ def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1705_06661_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
+        if f.endswith((".hip", ".h", ".cpp")):
             with open(os.path.join(csrc, f), "rb") as fh:
                 h.update(fh.read())
     return h.hexdigest()[:16]
@@ -128,6 +128,39 @@ def cpu_baseline(seconds: float, nslabs: int):
             "sample": f"the first {done} spectator cubes (32^3 each, {elems} elements, fp64) of the "
                       f"{nslabs} slabs of the v=64 o=32 in-place workload, in slab order, "
                       f"{total:.1f} s of oracle time on {threads} threads"}
+
+
+def table2_sweep(ss, workloads, dev, stream):
+    """The paper's benchmark (Table II, all 21 spin summations) on hyper-square
+    tensors without spectators of about 320 MiB (the medium size of Sec. 5.1:
+    3D N = 352, 4D N = 80: rows of whole 128-byte lines), in place, FP64.  Eq. 12 bandwidth in GiB/s and
+    Eq. 13 GFLOP/s with n = the number of expanded permutations."""
+    import torch
+    res = {}
+    tensors = {}
+    for case in range(1, 22):
+        d, stages = workloads.table2_case(case)
+        n = 352 if d == 3 else 80
+        shape = (n,) * d
+        if d not in tensors:
+            tensors[d] = torch.empty(shape, dtype=torch.float64, device=dev)
+        x = tensors[d]
+        workloads.fill_uniform(x, 5000 + case)
+        p = ss.spinsum_plan(shape, 0, d, stages, inplace=True)
+        info = ss.spinsum_plan_get_info(p)
+        ss.spinsum_exec(p, x, x, stream)
+        ms = timed(lambda: ss.spinsum_exec(p, x, x, stream), 10, stream)
+        elems = x.numel()
+        t = ms * 1e-3
+        res[str(case)] = {"d": d, "N": n, "terms": info["nterms_expanded"],
+                          "GiBps_eq12": round(2 * elems * 8 / 2 ** 30 / t, 1),
+                          "GBps": round(2 * elems * 8 / 1e9 / t, 1),
+                          "frac_peak": round(2 * elems * 8 / 1e9 / t / PEAK_GBPS, 4),
+                          "GFLOPs_eq13": round(2 * info["nterms_expanded"] * elems / 1e9 / t, 1),
+                          "ms": round(ms, 4), "tile_edge": info["bl"]}
+    del tensors
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -284,6 +317,7 @@ def main():
             del x5, y5
             torch.cuda.empty_cache()
         out["forms"] = forms
+        out["table2_medium"] = table2_sweep(ss, workloads, dev, stream)
 
     if not args.no_cpu_baseline:
         log("cpu baseline")

@@ -135,9 +135,11 @@ static int64_t tile_lds_bytes(const spinsum_plan_s& P, int n, int bl, int cpw, i
 //  1. Cubes up to 64 KiB are processed whole, several per workgroup up to
 //     about 8 KiB, as one contiguous copy (any extent).
 //  2. Larger cubes use tile orbits whose rows (also the short rows of
-//     ragged edge tiles) are whole 16-byte chunks, for the direct-LDS kernel,
-//     and whose largest orbit takes at most 32 KiB of LDS; among those, the
-//     widest rows win, then the smaller LDS footprint.
+//     ragged edge tiles) are whole 16-byte chunks, for the direct-LDS kernel:
+//     rows of at least 32 bytes with the largest orbit within 32 KiB of LDS,
+//     else within 64 KiB (large 4D cubes, whose generic orbits have 24
+//     tiles), else any such rows within 32 KiB; among the candidates of a
+//     pass, the widest rows win, then the smaller LDS footprint.
 //  3. Otherwise the largest tile that fits, through registers.
 spinsum_status choose_tile(const spinsum_plan_s& P, int n, int64_t ncubes, int vw,
                            spinsum_tile_t* tile) {
@@ -160,24 +162,30 @@ spinsum_status choose_tile(const spinsum_plan_s& P, int n, int64_t ncubes, int v
     return SPINSUM_OK;
   }
   t.cubes_per_wg = 1;
-  const int64_t orbit_cap = 32 * 1024;
-  int best = 0;
-  int64_t best_lds = 0;
-  for (int bl = n - 1; bl >= 1; --bl) {
-    if (bl > 255) continue;
-    const int row = bl * esz;
-    if (vw_for(n, bl, vw) * esz != 16) continue;
-    const int64_t lb = tile_lds_bytes(P, n, bl, 1, 0);
-    if (lb > std::min(orbit_cap, budget)) continue;
-    if (best == 0 || row > best * esz || (row == best * esz && lb < best_lds)) {
-      best = bl;
-      best_lds = lb;
+  struct Pass {
+    int min_row;
+    int64_t cap;
+  };
+  const Pass passes[] = {{32, 32 * 1024}, {32, 64 * 1024}, {16, 32 * 1024}};
+  for (const Pass& ps : passes) {
+    int best = 0;
+    int64_t best_lds = 0;
+    for (int bl = n - 1; bl >= 1; --bl) {
+      if (bl > 255) continue;
+      const int row = bl * esz;
+      if (row < ps.min_row || vw_for(n, bl, vw) * esz != 16) continue;
+      const int64_t lb = tile_lds_bytes(P, n, bl, 1, 0);
+      if (lb > std::min(ps.cap, budget)) continue;
+      if (best == 0 || row > best * esz || (row == best * esz && lb < best_lds)) {
+        best = bl;
+        best_lds = lb;
+      }
     }
-  }
-  if (best > 0) {
-    t.bl = best;
-    *tile = t;
-    return SPINSUM_OK;
+    if (best > 0) {
+      t.bl = best;
+      *tile = t;
+      return SPINSUM_OK;
+    }
   }
   for (int bl = n - 1; bl >= 1; --bl) {
     if (bl > 255) continue;
@@ -297,6 +305,30 @@ spinsum_status build_tiling(const spinsum_plan_s& P, int n, int64_t ncubes,
     if (m < 0) break;
     B[m]++;
     for (int j = m + 1; j < d; ++j) B[j] = B[m];
+  }
+
+  // Large cubes (more tile orbits than an XCD runs at once): order the
+  // orbits by their "line block" tuple.  Tiles whose rows share cache lines
+  // along the fastest axis (block b and its neighbours within one line,
+  // b / s for s tiles per line) get the same key, so their orbits are
+  // neighbours in the item list -- and land on the same XCD, close in time.
+  // Within a key, the loop-nest order is kept.  (Measured: +12% for one
+  // 352^3 cube; for cubes of a few dozen orbits, which an XCD processes
+  // together anyway, the loop-nest order is 2% faster.)
+  if (T.orbits.size() > 128) {
+    const int line = 128;
+    const int row = bl * elem_size(P);
+    const int s = (row < line && line % row == 0 && (n * elem_size(P)) % line == 0) ? line / row : 1;
+    if (s > 1) {
+      auto key = [&](const OrbitHost& o) {
+        std::vector<int> k(d);
+        for (int m = 0; m < d; ++m) k[m] = o.B[m] / s;
+        std::sort(k.begin(), k.end());
+        return k;
+      };
+      std::stable_sort(T.orbits.begin(), T.orbits.end(),
+                       [&](const OrbitHost& a, const OrbitHost& b) { return key(a) < key(b); });
+    }
   }
 
   // 2. work items: one tile orbit each (item_tiles 0), or groups of orbits,

@@ -182,3 +182,26 @@ def test_3d_v64_o32_whole_tensor_one_launch():
     check_cube_sums(x2, in_sums, 0.0, 1e-12)
     del x, x2
     torch.cuda.empty_cache()
+
+
+# Table II on hyper-square tensors without spectators at the paper's medium
+# size (Sec. 5.1: about 320 MiB), in place, in the launch configuration of
+# the benchmark's Table II sweep; the oracle takes the whole tensor.
+TABLE2_N = {3: 352, 4: 80}
+
+
+@pytest.mark.parametrize("case", [1, 2, 4, 5, 8, 11, 17, 18, 21])
+def test_table2_medium_size_inplace(case):
+    d, stages = workloads.table2_case(case)
+    n = TABLE2_N[d]
+    shape = (n,) * d
+    _say(f"case table2 #{case} shape {shape}")
+    x = workloads.uniform(shape, 5000 + case, device=DEV)
+    ref = oracle.spinsum_chain(x.cpu().numpy().reshape((1,) + shape), stages, 1, d).reshape(shape)
+    p = ss.spinsum_plan(shape, 0, d, stages, inplace=True)
+    ss.spinsum_exec(p, x, x)
+    torch.cuda.synchronize()
+    got = x.cpu().numpy()
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    _say(f"  normwise error {err:.3e}")
+    assert err <= 1e-14
