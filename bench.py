@@ -256,6 +256,14 @@ def main():
                                  flags=flags)
             fms = timed(lambda: ss.spinsum_exec(pf, big[0], big[0], stream), 5, stream)
             forms[name] = form_entry(2 * big[0].numel() * 8, fms, value)
+        # coefficient gradient <g, pi_p(x)> for all 6 permutations: two slabs
+        # read once (no writes)
+        cg = timed(lambda: ss.spinsum_coef_grad(plan, big[0], big[1], stream), 5, stream)
+        forms["3d_coef_grad"] = form_entry(2 * big[0].numel() * 8, cg, value)
+        # antisymmetrisation (every permutation weighted by its sign), slab 0
+        pa = ss.spinsum_plan(slab_shape, 3, 3, [workloads.antisymmetrizer(3)], inplace=True)
+        ams = timed(lambda: ss.spinsum_exec(pa, big[0], big[0], stream), 5, stream)
+        forms["3d_antisymmetrize"] = form_entry(2 * big[0].numel() * 8, ams, value)
         for name, flags in [("3d_no_nt_stores", ss.SPINSUM_FLAG_NO_NT_STORES),
                             ("3d_no_xcd_grouping", ss.SPINSUM_FLAG_NO_XCD_REMAP)]:
             pf = ss.spinsum_plan(slab_shape, 3, 3, alpha, inplace=True, flags=flags)

@@ -191,6 +191,19 @@ spinsum_status spinsum_exec_batched(spinsum_plan_t plan, const void* const* in,
 spinsum_status spinsum_adjoint(spinsum_plan_t plan, const void* grad_out, void* grad_in,
                                void* stream);
 
+/* Coefficient gradient (not in the paper; the derivative of <g, S(x)> with
+ * respect to the coefficient of each permutation, Def. 2-3): grad[r] =
+ * <g, pi_r(x)> for the r-th permutation of the group in lexicographic order
+ * (d! values, r = 0 the identity), for the plan's tensor shape.  x and g are
+ * device tensors of the plan's shape and dtype (16-byte aligned); grad is a
+ * device array of d! doubles (8-byte aligned), overwritten.  The sums are
+ * accumulated in double with atomic adds, so the last bits may differ from
+ * run to run.  Needs the direct-LDS tile layout (whole cubes, or tile rows
+ * of whole 16-byte chunks): SPINSUM_ERR_UNSUPPORTED otherwise.  Asynchronous
+ * on `stream`. */
+spinsum_status spinsum_coef_grad(spinsum_plan_t plan, const void* x, const void* g,
+                                 double* grad, void* stream);
+
 /* Capture one spinsum_exec_batched launch into a hipGraph (captured on a
  * private stream) and instantiate it.  The pointer arrays must stay valid
  * for the life of the graph. */

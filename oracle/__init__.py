@@ -154,6 +154,19 @@ def _inverse(p: Sequence[int]) -> Tuple[int, ...]:
     return tuple(inv)
 
 
+def coef_grad(x: np.ndarray, g: np.ndarray, group_first: int, d: int,
+              nthreads: int = 1) -> np.ndarray:
+    """<g, pi_p(x)> for every permutation p of the group in lexicographic
+    order: the derivative of <g, S(x)> with respect to the coefficient of p
+    (S is linear in its coefficients, Def. 3), each term by the oracle's own
+    single-term summation."""
+    out = []
+    for p in itertools.permutations(range(d)):
+        y = spinsum(x, [(p, 1.0)], group_first, d, nthreads)
+        out.append(float(np.sum(np.asarray(g, dtype=np.float64) * y, dtype=np.float64)))
+    return np.array(out)
+
+
 def spinsum_numpy(x: np.ndarray, terms: Stage, group_first: int, d: int) -> np.ndarray:
     """sum_t alpha_t * transpose(A) in float64 (second, independent route)."""
     x = np.asarray(x, dtype=np.float64)

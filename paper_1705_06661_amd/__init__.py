@@ -17,6 +17,8 @@ A coefficient set is given as a list of stages, each a list of
 from __future__ import annotations
 
 import ctypes
+import math
+import itertools
 import os
 from typing import List, Optional, Sequence, Tuple
 
@@ -112,6 +114,7 @@ _c_check = _decl("spinsum_plan_check_ownership", [_vp, ctypes.c_int,
 _c_exec = _decl("spinsum_exec", [_vp, _vp, _vp, _vp])
 _c_exec_batched = _decl("spinsum_exec_batched", [_vp, _vp, _vp, _vp])
 _c_adjoint = _decl("spinsum_adjoint", [_vp, _vp, _vp, _vp])
+_c_coef_grad = _decl("spinsum_coef_grad", [_vp, _vp, _vp, _vp, _vp])
 _c_graph_create = _decl("spinsum_graph_create", [_vp, _vp, _vp, ctypes.POINTER(_vp)])
 _c_graph_launch = _decl("spinsum_graph_launch", [_vp, _vp])
 _c_graph_destroy = _decl("spinsum_graph_destroy", [_vp], None)
@@ -125,7 +128,8 @@ _c_version = _decl("spinsum_version", [], ctypes.c_char_p)
 
 EXPORTED = ["spinsum_plan", "spinsum_plan_batched", "spinsum_plan_set_tile",
             "spinsum_plan_get_info", "spinsum_plan_expanded", "spinsum_plan_check_ownership",
-            "spinsum_exec", "spinsum_exec_batched", "spinsum_adjoint", "spinsum_graph_create",
+            "spinsum_exec", "spinsum_exec_batched", "spinsum_adjoint", "spinsum_coef_grad",
+            "spinsum_graph_create",
             "spinsum_graph_launch", "spinsum_graph_destroy", "spinsum_autotune",
             "spinsum_stream_copy", "spinsum_plan_last_hip_error", "spinsum_plan_destroy",
             "spinsum_status_string", "spinsum_version"]
@@ -302,6 +306,17 @@ def spinsum_adjoint(plan: Plan, grad_out: torch.Tensor, grad_in: torch.Tensor, s
     return grad_in
 
 
+def spinsum_coef_grad(plan: Plan, x: torch.Tensor, g: torch.Tensor, stream=None) -> torch.Tensor:
+    """<g, pi_r(x)> for every permutation r of the group (lexicographic
+    order, d! float64 values on the device): the gradient of <g, S(x)> with
+    respect to the coefficient of each permutation."""
+    a = _tensor_ptr(x, plan, plan.shape, "x")
+    b = _tensor_ptr(g, plan, plan.shape, "g")
+    out = torch.empty(math.factorial(plan.d), dtype=torch.float64, device=x.device)
+    _check(_c_coef_grad(plan._h, a, b, out.data_ptr(), _stream(stream)), "spinsum_coef_grad", plan)
+    return out
+
+
 class PointerArrays:
     """Device-resident arrays of block pointers for the batched entry points."""
 
@@ -428,5 +443,44 @@ class SpinSumFunction(torch.autograd.Function):
         return gi, None
 
 
+class SpinSumCoefFunction(torch.autograd.Function):
+    """Out = sum_t alpha_t pi_t(x) with the coefficients as a tensor: the
+    gradient flows to x (adjoint kernel) and to alpha (coefficient-gradient
+    kernel).  perms: the d-tuples of the terms (distinct); a plan is made
+    from the current coefficient values on every call (single stage,
+    out-of-place)."""
+
+    @staticmethod
+    def forward(ctx, x, alpha, perms, group_first):
+        d = len(perms[0])
+        terms = [(tuple(p), float(a)) for p, a in zip(perms, alpha.detach().cpu().tolist())]
+        if len(set(tuple(p) for p in perms)) != len(perms):
+            raise SpinSumError(SPINSUM_ERR_INVALID_ARG, "permutations must be distinct")
+        plan = spinsum_plan(tuple(x.shape), group_first, d, [terms], dtype=x.dtype, inplace=False)
+        out = torch.empty_like(x)
+        spinsum_exec(plan, x.contiguous(), out)
+        ctx.plan = plan
+        ctx.perms = [tuple(p) for p in perms]
+        ctx.save_for_backward(x)
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        (x,) = ctx.saved_tensors
+        plan = ctx.plan
+        g = g.contiguous()
+        gx = None
+        if ctx.needs_input_grad[0]:
+            gx = torch.empty_like(g)
+            spinsum_adjoint(plan, g, gx)
+        ga = None
+        if ctx.needs_input_grad[1]:
+            c = spinsum_coef_grad(plan, x.contiguous(), g)
+            d = len(ctx.perms[0])
+            rank = {p: r for r, p in enumerate(itertools.permutations(range(d)))}
+            ga = torch.stack([c[rank[p]] for p in ctx.perms]).to(x.dtype)
+        return gx, ga, None, None
+
+
 __all__ = EXPORTED + ["Plan", "Graph", "PointerArrays", "SpinSumError", "SpinSumFunction",
-                      "apply"]
+                      "SpinSumCoefFunction", "apply"]

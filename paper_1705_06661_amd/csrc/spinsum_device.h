@@ -155,6 +155,20 @@ struct ExecArgs {
 };
 
 template <typename T>
+struct CGradArgs {
+  const T* x;
+  const T* gr;             // upstream gradient
+  double* grad;            // d! sums, lexicographic permutation order
+  const GroupDev* orbits;
+  const uint32_t* reps;
+  Geom g;
+  int64_t nitems;
+  int64_t xcd_per;
+  int32_t lds_tile_bytes;  // one tile region (x or gr)
+  int32_t pad;
+};
+
+template <typename T>
 struct BatchArgs {
   const T* const* in;
   T* const* out;
@@ -936,6 +950,129 @@ __global__ void __launch_bounds__(kThreads) k_batched(const BatchArgs<T> a) {
   store_item<T, D, VW, true>(g, tinfo, ntiles, ragged, nchunks, dst, lds);
 }
 
+// Coefficient gradient: c_p = <gr, P_p x> for every permutation p of the
+// group -- the derivative of <gr, S(x)> with respect to the coefficient of p.
+// Over one element orbit, with v_sigma = x[sigma . r] and u_tau =
+// gr[tau . r], the terms are sum_tau u_tau v_(tau o p); every element of the
+// orbit appears |H| times among the tau (H: the permutations that fix r),
+// so the orbit's share is that sum / |H|.
+template <int D, int P, int... TAU>
+__device__ __forceinline__ double cgrad_row(const double* u, const double* v,
+                                           std::integer_sequence<int, TAU...>) {
+  double s = 0.0;
+  ((s = fma_t(u[TAU], v[Compose<D, TAU, P>::value], s)), ...);
+  return s;
+}
+
+template <int D, int... P>
+__device__ __forceinline__ void cgrad_rows(double* acc, const double* u, const double* v, double w,
+                                           std::integer_sequence<int, P...>) {
+  ((acc[P] = fma_t(w, cgrad_row<D, P>(u, v, std::make_integer_sequence<int, Fact<D>::v>{}), acc[P])),
+   ...);
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kThreads) k_cgrad(const CGradArgs<T> a) {
+  constexpr int DF = Fact<D>::v;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  int64_t item;
+  if (a.xcd_per > 0)
+    item = (int64_t)(blockIdx.x & 7u) * a.xcd_per + (int64_t)(blockIdx.x >> 3);
+  else
+    item = blockIdx.x;
+  if (item >= a.nitems) return;
+  const Geom& g = a.g;
+  int64_t cube0;
+  int orbit, ncub;
+  decode_item(g, item, &cube0, &orbit, &ncub);
+  const cptr<GroupDev> od = as_const(a.orbits + orbit);
+  const bool whole = (g.bl == g.n);
+  const int ntl = whole ? ncub : od->ntiles;
+  const bool ragged = od->ragged != 0;
+  unsigned char* ldsx = smem;
+  unsigned char* ldsg = smem + a.lds_tile_bytes;
+  unsigned char* rep_lds = smem + 2 * a.lds_tile_bytes;
+  const uint32_t span = (uint32_t)ncub * (uint32_t)g.cube_elems;
+  int sx = 0, sg = 0;
+  if (whole) {
+    sx = flat_issue<T>(a.x + cube0 * g.cube_elems, span, ldsx);
+    sg = flat_issue<T>(a.gr + cube0 * g.cube_elems, span, ldsg);
+  } else {
+    issue_item_lds<T, D>(g, od, false, ntl, ragged, a.x + cube0 * g.cube_elems, ldsx);
+    issue_item_lds<T, D>(g, od, false, ntl, ragged, a.gr + cube0 * g.cube_elems, ldsg);
+  }
+  issue_reps_lds(od, a.reps, rep_lds);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): everything is in LDS
+  __syncthreads();
+  const T* X = reinterpret_cast<const T*>(ldsx) + sx;
+  const T* U = reinterpret_cast<const T*>(ldsg) + sg;
+  const uint32_t* reps = reinterpret_cast<const uint32_t*>(rep_lds);
+  double acc[DF];
+#pragma unroll
+  for (int p = 0; p < DF; ++p) acc[p] = 0.0;
+  const int norb = od->norb;
+  for (int k = 0; k < norb; ++k) {
+    int32_t sb[DF];
+#pragma unroll
+    for (int r = 0; r < DF; ++r) sb[r] = od->slot_base[k][r];
+    const uint32_t rep_cnt = (uint32_t)od->rep_cnt[k];
+    const uint32_t nrep = (uint32_t)ncub * rep_cnt;
+    const FastDiv fdr = load_fd(od->fd_rep[k]);
+    const uint32_t* rp = reps + od->rep_base[k];
+    const int eq = od->eqmask[k];
+    for (uint32_t i = threadIdx.x; i < nrep; i += blockDim.x) {
+      uint32_t ci = (ncub == 1) ? 0u : fdiv(i, fdr);
+      uint32_t ri = i - ci * rep_cnt;
+      uint32_t pk = rp[ri];
+      int l[D];
+#pragma unroll
+      for (int m = 0; m < D; ++m) l[m] = (int)((pk >> (8 * m)) & 255u);
+      int addr[DF];
+      orbit_addrs<D>(g, (int)ci * g.cube_lds, sb, l, addr, std::make_integer_sequence<int, DF>{});
+      double v[DF], u[DF];
+#pragma unroll
+      for (int r = 0; r < DF; ++r) {
+        v[r] = (double)X[addr[r]];
+        u[r] = (double)U[addr[r]];
+      }
+      // |H|: equal global coordinates are neighbours in a representative
+      // (equal blocks, local coordinates non-decreasing within them)
+      int h = 1, run = 1;
+#pragma unroll
+      for (int m = 1; m < D; ++m) {
+        if (((eq >> (m - 1)) & 1) && l[m] == l[m - 1]) {
+          ++run;
+          h *= run;
+        } else {
+          run = 1;
+        }
+      }
+      cgrad_rows<D>(acc, u, v, 1.0 / (double)h, std::make_integer_sequence<int, DF>{});
+    }
+  }
+  // workgroup sum: within each wave, then across the waves through LDS
+  __syncthreads();  // every wave is done with the tiles
+  double* red = reinterpret_cast<double*>(smem);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int p = 0; p < DF; ++p) {
+    double s = acc[p];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) red[wave * DF + p] = s;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < DF) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w * DF + threadIdx.x];
+    unsafeAtomicAdd(a.grad + threadIdx.x, s);
+  }
+}
+
+__global__ void k_zero_f64(double* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0.0;
+}
+
 // ------------------------------------------------------------ dispatch
 template <typename T, int D, bool CHAIN, bool NTS>
 const void* exec_kernel(int vw) {
@@ -982,6 +1119,11 @@ const void* pick_d(int kind, int vw, bool chain, bool nts, int maxc) {
 }
 
 template <typename T, int D>
+const void* cgrad_kernel() {
+  return (const void*)k_cgrad<T, D>;
+}
+
+template <typename T, int D>
 const void* batched_kernel(int vw) {
   if constexpr (sizeof(T) == 8) {
     if (vw == 2) return (const void*)k_batched<T, D, 2>;
@@ -999,7 +1141,8 @@ const void* batched_kernel(int vw) {
 // spinsum_kern_<type>_d<d>.hip.
 #define SPINSUM_DECLARE_PICK(tag, d)                                                    \
   const void* pick_##tag##_d##d(int kind, int vw, bool chain, bool nts, int maxc);     \
-  const void* pick_batched_##tag##_d##d(int vw);
+  const void* pick_batched_##tag##_d##d(int vw);                                       \
+  const void* pick_cgrad_##tag##_d##d();
 SPINSUM_DECLARE_PICK(f64, 2)
 SPINSUM_DECLARE_PICK(f64, 3)
 SPINSUM_DECLARE_PICK(f64, 4)

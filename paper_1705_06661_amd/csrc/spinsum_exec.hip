@@ -44,6 +44,19 @@ const void* pick_batched(int d, int vw) {
   }
 }
 
+template <typename T>
+const void* pick_cgrad(int d) {
+  if constexpr (sizeof(T) == 8) {
+    if (d == 2) return pick_cgrad_f64_d2();
+    if (d == 3) return pick_cgrad_f64_d3();
+    return pick_cgrad_f64_d4();
+  } else {
+    if (d == 2) return pick_cgrad_f32_d2();
+    if (d == 3) return pick_cgrad_f32_d3();
+    return pick_cgrad_f32_d4();
+  }
+}
+
 spinsum_status hip_error(spinsum_plan_s* P, hipError_t e) {
   P->last_hip_error = (int)e;
   (void)hipGetLastError();
@@ -218,6 +231,78 @@ extern "C" spinsum_status spinsum_adjoint(spinsum_plan_t P, const void* grad_out
   if (P->dtype == SPINSUM_F32)
     return launch_exec<float>(P, grad_out, grad_in, (hipStream_t)stream, true);
   return launch_exec<double>(P, grad_out, grad_in, (hipStream_t)stream, true);
+}
+
+namespace spinsum {
+namespace {
+
+template <typename T>
+spinsum_status launch_cgrad(spinsum_plan_s* P, const void* x, const void* g, double* grad,
+                            hipStream_t stream) {
+  const Tiling& Tl = P->T;
+  CGradArgs<T> a;
+  std::memset(&a, 0, sizeof(a));
+  a.x = reinterpret_cast<const T*>(x);
+  a.gr = reinterpret_cast<const T*>(g);
+  a.grad = grad;
+  a.orbits = reinterpret_cast<const GroupDev*>(P->d_orbits);
+  a.reps = reinterpret_cast<const uint32_t*>(P->d_reps);
+  a.g = Tl.g;
+  a.nitems = Tl.nitems;
+  a.lds_tile_bytes = (int32_t)(((size_t)Tl.lds_elems * sizeof(T) + 15) / 16 * 16);
+  const int df = P->G.df;
+  // LDS: x tiles | gradient tiles | representative lists; the partial sums
+  // of the waves reuse it at the end
+  const size_t shmem = std::max<size_t>(2 * (size_t)a.lds_tile_bytes + (size_t)Tl.max_rep_cnt * 4,
+                                        (size_t)(kThreads / 64) * df * sizeof(double));
+  if ((int64_t)shmem > P->lds_limit) return SPINSUM_ERR_UNSUPPORTED;
+  const void* k = pick_cgrad<T>(P->d);
+  spinsum_status st = prepare_kernel(P, k, shmem);
+  if (st != SPINSUM_OK) return st;
+  hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, stream, grad, df);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_error(P, e);
+  int64_t grid;
+  if (P->flags & SPINSUM_FLAG_NO_XCD_REMAP) {
+    a.xcd_per = 0;
+    grid = Tl.nitems;
+  } else {
+    a.xcd_per = (Tl.nitems + 7) / 8;
+    grid = a.xcd_per * 8;
+  }
+  void* kargs[] = {&a};
+  e = hipLaunchKernel(k, dim3((unsigned)grid), dim3(kThreads), kargs, shmem, stream);
+  if (e != hipSuccess) return hip_error(P, e);
+  return SPINSUM_OK;
+}
+
+}  // namespace
+}  // namespace spinsum
+
+extern "C" spinsum_status spinsum_coef_grad(spinsum_plan_t P, const void* x, const void* g,
+                                            double* grad, void* stream) {
+  if (P == nullptr || P->batched || grad == nullptr) return SPINSUM_ERR_INVALID_ARG;
+  if (!P->has_dev) return SPINSUM_ERR_NO_DEVICE;
+  if (((uintptr_t)grad) & 7u) return SPINSUM_ERR_MISALIGNED;
+  if (P->elems == 0) {
+    spinsum_status st = check_device(P);
+    if (st != SPINSUM_OK) return st;
+    hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, (hipStream_t)stream, grad, P->G.df);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SPINSUM_OK : hip_error(P, e);
+  }
+  if (x == nullptr || g == nullptr) return SPINSUM_ERR_INVALID_ARG;
+  if ((((uintptr_t)x) | ((uintptr_t)g)) & 15u) return SPINSUM_ERR_MISALIGNED;
+  spinsum_status st = check_device(P);
+  if (st != SPINSUM_OK) return st;
+  // the direct-LDS layout: whole cubes, or tiles whose rows are whole
+  // 16-byte chunks, unpadded
+  const Tiling& Tl = P->T;
+  const bool whole = Tl.g.bl == Tl.g.n;
+  const bool rows = Tl.vw * elem_size(*P) == 16;
+  if (P->tile.lds_pad != 0 || !(whole || rows)) return SPINSUM_ERR_UNSUPPORTED;
+  if (P->dtype == SPINSUM_F32) return launch_cgrad<float>(P, x, g, grad, (hipStream_t)stream);
+  return launch_cgrad<double>(P, x, g, grad, (hipStream_t)stream);
 }
 
 extern "C" spinsum_status spinsum_exec_batched(spinsum_plan_t P, const void* const* in,

@@ -70,6 +70,7 @@ struct alignas(16) GroupDev {
   int32_t rep_base[kMaxGroupOrbits]; // prefix sum of rep_cnt
   FastDiv fd_rep[kMaxGroupOrbits];   // / rep_cnt[k]
   int32_t slot_base[kMaxGroupOrbits][kMaxDF];  // LDS element offset of tile sigma . B_k
+  int32_t eqmask[kMaxGroupOrbits];   // bit m: blocks m and m+1 of B_k are equal
 };
 
 // Geometry of one tensor (or one block of a batch).
@@ -165,6 +166,14 @@ __host__ __device__ constexpr int ginv_mul(int d, int t, int s) {
   return lex_rank(d, c);
 }
 
+// Rank of t o p ((a o b)[m] = a[b[m]]): with v_sigma = In[sigma . x], the
+// term with permutation p reads v_(tau o p) for the output at tau . x.
+__host__ __device__ constexpr int compose(int d, int t, int p) {
+  int c[4] = {0, 0, 0, 0};
+  for (int m = 0; m < d; ++m) c[m] = lex_perm(d, t, lex_perm(d, p, m));
+  return lex_rank(d, c);
+}
+
 // Chunk c of a work item (one VW-vector of one tile row) -> global element
 // offset from the item's first cube (32 bits: an item spans less than 2^31
 // bytes) and LDS element offset; false if the chunk lies outside a ragged
@@ -221,6 +230,10 @@ struct LexPerm {
 template <int D, int T, int S>
 struct GinvMul {
   static constexpr int value = ginv_mul(D, T, S);
+};
+template <int D, int T, int P>
+struct Compose {
+  static constexpr int value = compose(D, T, P);
 };
 
 // LDS element offset of sigma_R . x for representative x = l[] of a cube

@@ -382,6 +382,8 @@ spinsum_status build_tiling(const spinsum_plan_s& P, int n, int64_t ncubes,
       gd.rep_cnt[k] = oh.rep_cnt;
       gd.rep_base[k] = rbase;
       gd.fd_rep[k] = make_fastdiv((uint32_t)std::max(1, oh.rep_cnt));
+      for (int m = 0; m + 1 < d; ++m)
+        if (oh.B[m] == oh.B[m + 1]) gd.eqmask[k] |= 1 << m;
       gd.ragged |= oh.ragged;
       tbase += oh.ntiles;
       rbase += oh.rep_cnt;

@@ -377,6 +377,28 @@ def test_direct_lds_thread_counts(dtype):
                 assert torch.equal(y, base), (shape, bl, threads, inplace)
 
 
+@pytest.mark.parametrize("d", [2, 3, 4])
+def test_symmetrizer_and_antisymmetrizer(d):
+    """(Anti)symmetrisation, the sums of transpositions adjacent to spin
+    summation: against the oracle, and the output is (anti)symmetric under
+    every transposition of the group, and applying it twice scales by d!."""
+    n = {2: 24, 3: 12, 4: 6}[d]
+    shape = (3,) + (n,) * d
+    x = gpu_uniform(shape, 70 + d)
+    for stage, sign in [(workloads.symmetrizer(d), 1.0), (workloads.antisymmetrizer(d), -1.0)]:
+        p = mk(shape, [stage], d, inplace=False)
+        y = run(p, x)
+        assert nerr(y.cpu().numpy(), ref_of(x, [stage], d)) <= 1e-14
+        for a, b in itertools.combinations(range(d), 2):
+            axes = list(range(d + 1))
+            axes[1 + a], axes[1 + b] = axes[1 + b], axes[1 + a]
+            sw = y.permute(*axes)
+            assert torch.allclose(sw, sign * y, rtol=0, atol=1e-12 * float(y.abs().max()))
+        yy = run(p, y)
+        fact = float(np.prod(range(1, d + 1)))
+        assert torch.allclose(yy, fact * y, rtol=0, atol=1e-12 * fact * float(y.abs().max()))
+
+
 # ----------------------------------------------------------------- batched
 def _small_blocks():
     rng = np.random.default_rng(5)
@@ -455,3 +477,74 @@ def test_autotune_and_cache(tmp_path):
         assert ss.spinsum_plan_get_info(q)["bl"] == best["bl"]
     finally:
         del os.environ["SPINSUM_AUTOTUNE_CACHE"]
+
+
+# ----------------------------------------------------------- coefficient gradient
+COEF_GRAD_CASES = [
+    ((3, 8, 8, 8), 3, None),        # whole cubes
+    ((2, 16, 16, 16), 3, (8, 1)),   # tile orbits
+    ((2, 20, 20, 20), 3, (8, 1)),   # ragged tiles
+    ((5, 7, 7, 7), 3, None),        # odd whole cubes (alignment shifts)
+    ((2, 12, 12, 12, 12), 4, (4, 1)),
+    ((3, 5, 5, 5, 5), 4, None),
+    ((4, 24, 24), 2, (8, 1)),
+    ((1, 1, 1, 1), 3, None),
+]
+
+
+@pytest.mark.parametrize("shape,d,tile", COEF_GRAD_CASES)
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_coef_grad_against_oracle(shape, d, tile, dtype):
+    _say("coef grad", shape, d, tile, dtype)
+    x = gpu_uniform(shape, 81, dtype)
+    g = gpu_uniform(shape, 82, dtype)
+    p = mk(shape, [workloads.CONFIG_3D_ALPHA if d == 3 else [(tuple(range(d)), 1.0)]], d,
+           dtype=dtype, tile=tile)
+    got = ss.spinsum_coef_grad(p, x, g).cpu().numpy()
+    ref = oracle.coef_grad(x.double().cpu().numpy(), g.double().cpu().numpy(), 1, d)
+    scale = float(np.sum(np.abs(g.double().cpu().numpy()) * np.abs(x.double().cpu().numpy()).max()))
+    # products and sums in double for both storage types
+    assert np.max(np.abs(got - ref)) <= 1e-12 * max(1.0, scale), (got, ref)
+    # integer inputs: every partial sum is an exact integer
+    xi, gi = gpu_ints(shape, 83, dtype), gpu_ints(shape, 84, dtype)
+    goti = ss.spinsum_coef_grad(p, xi, gi).cpu().numpy()
+    refi = oracle.coef_grad(xi.double().cpu().numpy(), gi.double().cpu().numpy(), 1, d)
+    np.testing.assert_array_equal(goti, refi)
+
+
+def test_coef_grad_errors_and_empty():
+    x = gpu_uniform((2, 8, 8, 8), 1)
+    p = mk((2, 8, 8, 8), [workloads.CONFIG_3D_ALPHA], 3)
+    with pytest.raises(ss.SpinSumError):
+        ss.spinsum_coef_grad(p, x.float(), x)  # dtype mismatch
+    pe = mk((0, 8, 8, 8), [workloads.CONFIG_3D_ALPHA], 3)
+    e = torch.empty((0, 8, 8, 8), dtype=torch.float64, device=DEV)
+    assert torch.equal(ss.spinsum_coef_grad(pe, e, e).cpu(), torch.zeros(6, dtype=torch.float64))
+    # register-only tile layouts are refused
+    q = mk((2, 12, 12, 12), [workloads.CONFIG_3D_ALPHA], 3, tile=(3, 1))
+    y = gpu_uniform((2, 12, 12, 12), 2)
+    with pytest.raises(ss.SpinSumError) as ei:
+        ss.spinsum_coef_grad(q, y, y)
+    assert ei.value.status == ss.SPINSUM_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("d", [3, 4])
+def test_autograd_through_coefficients(d):
+    """SpinSumCoefFunction: gradcheck in x and alpha (the map is bilinear, so
+    central differences are exact up to rounding), and the alpha gradient
+    equals the oracle's <g, pi_t(x)>."""
+    n = {3: 5, 4: 3}[d]
+    shape = (2,) + (n,) * d
+    perms = list(itertools.permutations(range(d)))[: (6 if d == 3 else 9)]
+    x = gpu_uniform(shape, 91).requires_grad_(True)
+    alpha = torch.tensor([float(k % 5 - 2) for k in range(len(perms))], dtype=torch.float64,
+                         device=DEV, requires_grad=True)
+    f = lambda xx, aa: ss.SpinSumCoefFunction.apply(xx, aa, perms, 1)
+    assert torch.autograd.gradcheck(f, (x, alpha), eps=1.0, atol=1e-10, rtol=1e-10)
+    g = gpu_uniform(shape, 92)
+    y = f(x, alpha)
+    (y * g).sum().backward()
+    full = oracle.coef_grad(x.detach().cpu().numpy(), g.cpu().numpy(), 1, d)
+    rank = {p: r for r, p in enumerate(itertools.permutations(range(d)))}
+    want = np.array([full[rank[p]] for p in perms])
+    np.testing.assert_allclose(alpha.grad.cpu().numpy(), want, rtol=1e-12, atol=1e-12)

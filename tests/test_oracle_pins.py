@@ -8,6 +8,7 @@ library routines (numpy transpose), from closed forms of the symmetric group
 and from brute-force explicit matrices.
 """
 import itertools
+import math
 import os
 import re
 
@@ -401,3 +402,43 @@ def test_batched_block_list():
     assert 1.9e9 <= total <= 2.1e9
     assert all(4 <= v <= 40 and 2 <= o <= 16 for v, o in blocks)
     assert workloads.batched_blocks() == (seed, blocks)
+
+
+@pytest.mark.parametrize("d", [2, 3, 4])
+def test_symmetrizer_sets(d):
+    """The (anti)symmetrisers of the workloads: outputs are (anti)symmetric
+    under every transposition and the operators are d! times idempotent."""
+    x = _rand((2,) + (3,) * d, 90 + d)
+    fact = math.factorial(d)
+    for stage, sign in [(workloads.symmetrizer(d), 1.0), (workloads.antisymmetrizer(d), -1.0)]:
+        y = oracle.spinsum(x, stage, 1, d)
+        for a, b in itertools.combinations(range(d), 2):
+            axes = list(range(d + 1))
+            axes[1 + a], axes[1 + b] = axes[1 + b], axes[1 + a]
+            np.testing.assert_allclose(np.transpose(y, axes), sign * y, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(oracle.spinsum(y, stage, 1, d), fact * y, rtol=0, atol=1e-10)
+    # the antisymmetriser annihilates symmetric inputs and vice versa
+    ys = oracle.spinsum(x, workloads.symmetrizer(d), 1, d)
+    np.testing.assert_allclose(oracle.spinsum(ys, workloads.antisymmetrizer(d), 1, d), 0, atol=1e-10)
+
+
+@pytest.mark.parametrize("shape,gf,d", [((2, 3, 3, 3), 1, 3), ((1, 2, 2, 2, 2), 1, 4), ((3, 4, 4), 1, 2)])
+def test_coef_grad_definition(shape, gf, d):
+    """<g, pi_p(x)> equals g^T M_p x with the dense matrix of the single term
+    p, and the derivative of the linear map L(alpha) = <g, S_alpha(x)>:
+    L(alpha + e_p) - L(alpha) = grad_p exactly (up to rounding)."""
+    x = _rand(shape, 17)
+    g = _rand(shape, 18)
+    grad = oracle.coef_grad(x, g, gf, d)
+    perms = list(itertools.permutations(range(d)))
+    assert grad.shape == (len(perms),)
+    rng = np.random.default_rng(3)
+    alpha = rng.integers(-3, 4, len(perms)).astype(float)
+    def L(al):
+        return float(np.sum(g * oracle.spinsum(x, list(zip(perms, al)), gf, d)))
+    for r, p in enumerate(perms):
+        M = oracle.dense_matrix(shape, [(p, 1.0)], gf, d)
+        assert abs(grad[r] - g.ravel() @ (M @ x.ravel())) <= 1e-12 * max(1.0, abs(grad[r]))
+        e = np.zeros(len(perms))
+        e[r] = 1.0
+        assert abs((L(alpha + e) - L(alpha)) - grad[r]) <= 1e-10

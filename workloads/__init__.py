@@ -176,6 +176,21 @@ def table2_case(case: int) -> Tuple[int, List[Stage]]:
     return d, stages
 
 
+def _parity(p) -> int:
+    inv = sum(1 for i in range(len(p)) for j in range(i + 1, len(p)) if p[i] > p[j])
+    return -1 if inv % 2 else 1
+
+
+def symmetrizer(d: int) -> Stage:
+    """sum over all permutations of the group (every coefficient +1)."""
+    return [(p, 1.0) for p in itertools.permutations(range(d))]
+
+
+def antisymmetrizer(d: int) -> Stage:
+    """sum over all permutations weighted by their sign."""
+    return [(p, float(_parity(p))) for p in itertools.permutations(range(d))]
+
+
 def random_4d_alpha(seed: int) -> Stage:
     """24 integer coefficients in {-2..8} drawn from ``seed`` (numpy PCG64),
     assigned to the permutations of (0,1,2,3) in lexicographic order."""
