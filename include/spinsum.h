@@ -34,6 +34,11 @@
  *   - exec/adjoint calls are asynchronous and stream-ordered, allocate
  *     nothing and never synchronise, so they may be captured in a hipGraph;
  *   - a plan is bound to the device that was current when it was made;
+ *   - a plan is not changed by exec/adjoint/exec_batched, so their calls may
+ *     overlap on several streams; spinsum_plan_set_tile, spinsum_autotune
+ *     and spinsum_plan_destroy need exclusive use of the plan, and
+ *     spinsum_coef_grad calls on one plan must not overlap (they share the
+ *     plan's partial-sum buffer);
  *   - HIP failures return SPINSUM_ERR_HIP and the hipError_t is kept on the
  *     plan (spinsum_plan_last_hip_error).
  */
@@ -197,8 +202,9 @@ spinsum_status spinsum_adjoint(spinsum_plan_t plan, const void* grad_out, void* 
  * (d! values, r = 0 the identity), for the plan's tensor shape.  x and g are
  * device tensors of the plan's shape and dtype (16-byte aligned); grad is a
  * device array of d! doubles (8-byte aligned), overwritten.  The sums are
- * accumulated in double with atomic adds, so the last bits may differ from
- * run to run.  Needs the direct-LDS tile layout (whole cubes, or tile rows
+ * accumulated in double (per workgroup, then atomically into 2048 partial
+ * sums per permutation held by the plan, then one reduction), so the last
+ * bits may differ from run to run; calls on one plan must not overlap.  Needs the direct-LDS tile layout (whole cubes, or tile rows
  * of whole 16-byte chunks): SPINSUM_ERR_UNSUPPORTED otherwise.  Asynchronous
  * on `stream`. */
 spinsum_status spinsum_coef_grad(spinsum_plan_t plan, const void* x, const void* g,

@@ -158,7 +158,7 @@ template <typename T>
 struct CGradArgs {
   const T* x;
   const T* gr;             // upstream gradient
-  double* grad;            // d! sums, lexicographic permutation order
+  double* grad;            // kGradSlots x d! partial sums, lexicographic permutation order
   const GroupDev* orbits;
   const uint32_t* reps;
   Geom g;
@@ -1065,12 +1065,30 @@ __global__ void __launch_bounds__(kThreads) k_cgrad(const CGradArgs<T> a) {
   if ((int)threadIdx.x < DF) {
     double s = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w * DF + threadIdx.x];
-    unsafeAtomicAdd(a.grad + threadIdx.x, s);
+    // one of kGradSlots partial sums per permutation: spreads the atomic
+    // adds of the workgroups over many addresses
+    unsafeAtomicAdd(a.grad + (blockIdx.x & (kGradSlots - 1)) * DF + threadIdx.x, s);
   }
 }
 
-__global__ void k_zero_f64(double* p, int n) {
-  if ((int)threadIdx.x < n) p[threadIdx.x] = 0.0;
+// Zero n doubles (grid-stride).
+__global__ void __launch_bounds__(kThreads) k_zero_f64(double* p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0.0;
+}
+
+// grad[p] = sum over the kGradSlots partial sums of p (workgroup p).
+__global__ void __launch_bounds__(kThreads) k_grad_reduce(const double* part, double* grad, int df) {
+  __shared__ double red[kThreads];
+  const int p = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < kGradSlots; i += kThreads) s += part[i * df + p];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) grad[p] = red[0];
 }
 
 // ------------------------------------------------------------ dispatch

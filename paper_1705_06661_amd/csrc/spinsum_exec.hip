@@ -244,7 +244,7 @@ spinsum_status launch_cgrad(spinsum_plan_s* P, const void* x, const void* g, dou
   std::memset(&a, 0, sizeof(a));
   a.x = reinterpret_cast<const T*>(x);
   a.gr = reinterpret_cast<const T*>(g);
-  a.grad = grad;
+  a.grad = reinterpret_cast<double*>(P->d_grad_part);
   a.orbits = reinterpret_cast<const GroupDev*>(P->d_orbits);
   a.reps = reinterpret_cast<const uint32_t*>(P->d_reps);
   a.g = Tl.g;
@@ -259,7 +259,7 @@ spinsum_status launch_cgrad(spinsum_plan_s* P, const void* x, const void* g, dou
   const void* k = pick_cgrad<T>(P->d);
   spinsum_status st = prepare_kernel(P, k, shmem);
   if (st != SPINSUM_OK) return st;
-  hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, stream, grad, df);
+  hipLaunchKernelGGL(k_zero_f64, dim3(64), dim3(kThreads), 0, stream, a.grad, kGradSlots * df);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_error(P, e);
   int64_t grid;
@@ -272,6 +272,10 @@ spinsum_status launch_cgrad(spinsum_plan_s* P, const void* x, const void* g, dou
   }
   void* kargs[] = {&a};
   e = hipLaunchKernel(k, dim3((unsigned)grid), dim3(kThreads), kargs, shmem, stream);
+  if (e != hipSuccess) return hip_error(P, e);
+  hipLaunchKernelGGL(k_grad_reduce, dim3(df), dim3(kThreads), 0, stream,
+                     (const double*)a.grad, grad, df);
+  e = hipGetLastError();
   if (e != hipSuccess) return hip_error(P, e);
   return SPINSUM_OK;
 }
@@ -287,7 +291,7 @@ extern "C" spinsum_status spinsum_coef_grad(spinsum_plan_t P, const void* x, con
   if (P->elems == 0) {
     spinsum_status st = check_device(P);
     if (st != SPINSUM_OK) return st;
-    hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, (hipStream_t)stream, grad, P->G.df);
+    hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(kThreads), 0, (hipStream_t)stream, grad, P->G.df);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? SPINSUM_OK : hip_error(P, e);
   }

@@ -51,6 +51,7 @@ inline FastDiv make_fastdiv(uint32_t d) {
   return f;
 }
 
+constexpr int kGradSlots = 2048;     // partial sums of the coefficient gradient (power of 2)
 constexpr int kMaxGroupTiles = 24;   // tiles of one work item
 constexpr int kMaxGroupOrbits = 8;   // tile orbits of one work item
 

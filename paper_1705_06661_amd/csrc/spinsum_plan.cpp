@@ -424,7 +424,7 @@ static spinsum_status hip_fail(spinsum_plan_s* P, hipError_t e) {
 }
 
 void free_device(spinsum_plan_s* P) {
-  void** ptrs[] = {&P->d_orbits, &P->d_reps, &P->d_mats, &P->d_blocks, &P->d_items};
+  void** ptrs[] = {&P->d_orbits, &P->d_reps, &P->d_mats, &P->d_blocks, &P->d_items, &P->d_grad_part};
   for (void** p : ptrs) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
@@ -470,6 +470,9 @@ spinsum_status upload_tables(spinsum_plan_s* P) {
     st = upload(P, &P->d_orbits, P->T.groups.data(), P->T.groups.size());
     if (st != SPINSUM_OK) return st;
     st = upload(P, &P->d_reps, P->T.reps.data(), P->T.reps.size());
+    if (st != SPINSUM_OK) return st;
+    std::vector<double> part((size_t)kGradSlots * P->G.df, 0.0);
+    st = upload(P, &P->d_grad_part, part.data(), part.size());
     if (st != SPINSUM_OK) return st;
   } else {
     std::vector<GroupDev> groups;

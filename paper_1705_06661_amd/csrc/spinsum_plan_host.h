@@ -92,6 +92,7 @@ struct spinsum_plan_s {
   void* d_mats = nullptr;   // M | MT | SM | SMT in the storage type
   void* d_blocks = nullptr;
   void* d_items = nullptr;
+  void* d_grad_part = nullptr;  // kGradSlots x d! doubles (spinsum_coef_grad)
   int last_hip_error = 0;
   const void* occ_kernel = nullptr;  // occupancy cache of the persistent kernel
   int64_t occ_shmem = -1;
