@@ -26,6 +26,13 @@ Conventions (Def. 1-2): a permutation is a 0-based tuple ``p`` with
 permuted group is the ``d`` dimensions starting at ``group_first``; the
 dimensions before it are outer spectators and those after it inner
 spectators.  A stage list is applied first-to-last (stage 0 innermost).
+
+Index-pair form (``pairs=True``): the coupled-cluster quantities the paper's
+summations act on (Sec. 1) carry their indices in pairs, e.g. T[a,b,c,i,j,k]
+with (a,i), (b,j), (c,k) together.  Then the ``d`` dimensions right before
+the group are permuted by the same ``p``:
+``B[.., a_0..a_{d-1}, i_0..i_{d-1}, ..] += alpha *
+A[.., a_{p[0]}..a_{p[d-1]}, i_{p[0]}..i_{p[d-1]}, ..]``.
 """
 from __future__ import annotations
 
@@ -71,6 +78,11 @@ def _load():
             f.restype = ctypes.c_int
             f.argtypes = [ctypes.c_int, i64p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                           ip, ip, dp, dp, dp, ctypes.c_int]
+        for name in ("oracle_spinsum_chain_ex", "oracle_spinsum_chain_adjoint_ex"):
+            f = getattr(lib, name)
+            f.restype = ctypes.c_int
+            f.argtypes = [ctypes.c_int, i64p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                          ctypes.c_int, ip, ip, dp, dp, dp, ctypes.c_int]
         lib.oracle_max_threads.restype = ctypes.c_int
         lib.oracle_max_threads.argtypes = []
         _lib = lib
@@ -110,7 +122,7 @@ def _flatten(stages: Sequence[Stage], d: int):
 
 
 def _call(fn_name: str, x: np.ndarray, stages: Sequence[Stage], group_first: int,
-          d: int, nthreads: int) -> np.ndarray:
+          d: int, nthreads: int, pairs: bool = False) -> np.ndarray:
     lib = _load()
     x = np.ascontiguousarray(x, dtype=np.float64)
     out = np.empty_like(x)
@@ -120,30 +132,31 @@ def _call(fn_name: str, x: np.ndarray, stages: Sequence[Stage], group_first: int
     pp = (ctypes.c_int * max(1, len(perms)))(*perms)
     aa = (ctypes.c_double * max(1, len(alpha)))(*alpha)
     dp = ctypes.POINTER(ctypes.c_double)
-    st = getattr(lib, fn_name)(x.ndim, ext, group_first, d, len(stages), nt, pp, aa,
-                               x.ctypes.data_as(dp), out.ctypes.data_as(dp), int(nthreads))
+    st = getattr(lib, fn_name + "_ex")(x.ndim, ext, group_first, d, int(bool(pairs)),
+                                       len(stages), nt, pp, aa, x.ctypes.data_as(dp),
+                                       out.ctypes.data_as(dp), int(nthreads))
     if st != 0:
         raise ValueError(f"{fn_name} failed with status {st}")
     return out
 
 
 def spinsum(x: np.ndarray, terms: Stage, group_first: int, d: int,
-            nthreads: int = 1) -> np.ndarray:
+            nthreads: int = 1, pairs: bool = False) -> np.ndarray:
     """B = sum_t alpha_t pi_t(A)  (Def. 3, Eq. 4)."""
-    return _call("oracle_spinsum_chain", x, [terms], group_first, d, nthreads)
+    return _call("oracle_spinsum_chain", x, [terms], group_first, d, nthreads, pairs)
 
 
 def spinsum_chain(x: np.ndarray, stages: Sequence[Stage], group_first: int, d: int,
-                  nthreads: int = 1) -> np.ndarray:
+                  nthreads: int = 1, pairs: bool = False) -> np.ndarray:
     """B = S_K(...S_1(A)) through full temporaries (Def. 4, Eq. 5-6; Alg. 3)."""
-    return _call("oracle_spinsum_chain", x, list(stages), group_first, d, nthreads)
+    return _call("oracle_spinsum_chain", x, list(stages), group_first, d, nthreads, pairs)
 
 
 def spinsum_chain_adjoint(g: np.ndarray, stages: Sequence[Stage], group_first: int,
-                          d: int, nthreads: int = 1) -> np.ndarray:
+                          d: int, nthreads: int = 1, pairs: bool = False) -> np.ndarray:
     """S^T g for the chain (transpose of the linear map of Def. 3-4)."""
     return _call("oracle_spinsum_chain_adjoint", g, list(stages), group_first, d,
-                 nthreads)
+                 nthreads, pairs)
 
 
 # ------------------------------------------------------------- numpy route
@@ -155,19 +168,20 @@ def _inverse(p: Sequence[int]) -> Tuple[int, ...]:
 
 
 def coef_grad(x: np.ndarray, g: np.ndarray, group_first: int, d: int,
-              nthreads: int = 1) -> np.ndarray:
+              nthreads: int = 1, pairs: bool = False) -> np.ndarray:
     """<g, pi_p(x)> for every permutation p of the group in lexicographic
     order: the derivative of <g, S(x)> with respect to the coefficient of p
     (S is linear in its coefficients, Def. 3), each term by the oracle's own
     single-term summation."""
     out = []
     for p in itertools.permutations(range(d)):
-        y = spinsum(x, [(p, 1.0)], group_first, d, nthreads)
+        y = spinsum(x, [(p, 1.0)], group_first, d, nthreads, pairs)
         out.append(float(np.sum(np.asarray(g, dtype=np.float64) * y, dtype=np.float64)))
     return np.array(out)
 
 
-def spinsum_numpy(x: np.ndarray, terms: Stage, group_first: int, d: int) -> np.ndarray:
+def spinsum_numpy(x: np.ndarray, terms: Stage, group_first: int, d: int,
+                  pairs: bool = False) -> np.ndarray:
     """sum_t alpha_t * transpose(A) in float64 (second, independent route)."""
     x = np.asarray(x, dtype=np.float64)
     out = np.zeros_like(x)
@@ -176,22 +190,26 @@ def spinsum_numpy(x: np.ndarray, terms: Stage, group_first: int, d: int) -> np.n
         if a == 0.0:
             continue
         q = _inverse(p)
-        axes = (list(range(group_first)) + [group_first + v for v in q]
-                + list(range(group_first + d, nd)))
+        axes = list(range(nd))
+        for m in range(d):
+            axes[group_first + m] = group_first + q[m]
+            if pairs:
+                axes[group_first - d + m] = group_first - d + q[m]
         out += a * np.transpose(x, axes)
     return out
 
 
 def spinsum_chain_numpy(x: np.ndarray, stages: Sequence[Stage], group_first: int,
-                        d: int) -> np.ndarray:
+                        d: int, pairs: bool = False) -> np.ndarray:
     y = np.asarray(x, dtype=np.float64)
     for s in stages:
-        y = spinsum_numpy(y, s, group_first, d)
+        y = spinsum_numpy(y, s, group_first, d, pairs)
     return y
 
 
 # ------------------------------------------------------------ dense matrix
-def dense_matrix(shape: Sequence[int], terms: Stage, group_first: int, d: int) -> np.ndarray:
+def dense_matrix(shape: Sequence[int], terms: Stage, group_first: int, d: int,
+                 pairs: bool = False) -> np.ndarray:
     """Explicit matrix M with vec(B) = M vec(A), row-major vec (tiny shapes).
 
     Built straight from Eq. 3: for every output multi-index and every term,
@@ -208,19 +226,22 @@ def dense_matrix(shape: Sequence[int], terms: Stage, group_first: int, d: int) -
     for idx in itertools.product(*[range(s) for s in shape]):
         row = sum(i * s for i, s in zip(idx, strides))
         grp = idx[group_first:group_first + d]
+        prt = idx[group_first - d:group_first] if pairs else ()
         for p, a in terms:
             src = list(idx)
             for m in range(d):
                 src[group_first + m] = grp[p[m]]
+                if pairs:
+                    src[group_first - d + m] = prt[p[m]]
             col = sum(i * s for i, s in zip(src, strides))
             M[row, col] += a
     return M
 
 
 def dense_chain_matrix(shape: Sequence[int], stages: Sequence[Stage], group_first: int,
-                       d: int) -> np.ndarray:
+                       d: int, pairs: bool = False) -> np.ndarray:
     size = int(np.prod(shape))
     M = np.eye(size)
     for s in stages:
-        M = dense_matrix(shape, s, group_first, d) @ M
+        M = dense_matrix(shape, s, group_first, d, pairs) @ M
     return M

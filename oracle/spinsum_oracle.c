@@ -25,6 +25,15 @@
  * spectator indices are carried through unchanged.  All group extents must
  * be equal (hyper-square, Sec. 3.1).
  *
+ * Index-pair form: the coupled-cluster quantities whose spin summations the
+ * paper targets (Sec. 1) carry indices in pairs, e.g. T[a,b,c,i,j,k] with
+ * (a,i), (b,j), (c,k) belonging together.  With `pairs` set, the d
+ * dimensions right before the group (extent V each) are permuted by the
+ * same permutation as the group:
+ *     B[.., a_0..a_{d-1}, i_0..i_{d-1}, ..] +=
+ *         alpha_t * A[.., a_{p[0]}..a_{p[d-1]}, i_{p[0]}..i_{p[d-1]}, ..].
+ * Here this is evaluated literally, on the 2d-tuple (a, i).
+ *
  * Arithmetic: each output element is accumulated in long double (x87
  * extended precision on x86-64) with no reordering beyond the term order,
  * and rounded to double once at the end.  Chain temporaries are kept in
@@ -57,30 +66,44 @@
 #define ORACLE_MAX_D 8
 
 typedef struct {
-    int64_t outer;   /* product of the extents before the group */
-    int64_t n;       /* common group extent N                    */
-    int64_t inner;   /* product of the extents after the group   */
-    int64_t group;   /* N^d                                      */
+    int64_t outer;   /* product of the extents before the permuted dims */
+    int64_t inner;   /* product of the extents after the group          */
+    int64_t group;   /* product of the permuted extents (N^d, or V^d N^d) */
+    int64_t ext[2 * ORACLE_MAX_D];  /* extents of the permuted dims     */
     int d;
+    int nidx;        /* permuted dims: d, or 2d in the index-pair form  */
 } layout_t;
 
-static int make_layout(int ndim, const int64_t* extents, int group_first, int d,
+static int make_layout(int ndim, const int64_t* extents, int group_first, int d, int pairs,
                        layout_t* L) {
     if (ndim < 1 || extents == NULL || d < 1 || d > ORACLE_MAX_D) return ORACLE_ERR_ARG;
     if (group_first < 0 || group_first + d > ndim) return ORACLE_ERR_ARG;
+    if (pairs && group_first < d) return ORACLE_ERR_ARG;
     for (int k = 0; k < ndim; ++k)
         if (extents[k] < 0) return ORACLE_ERR_ARG;
+    const int first = pairs ? group_first - d : group_first;
     L->d = d;
-    L->n = extents[group_first];
+    L->nidx = pairs ? 2 * d : d;
+    for (int m = 0; m < L->nidx; ++m) L->ext[m] = extents[first + m];
     for (int m = 1; m < d; ++m)
-        if (extents[group_first + m] != L->n) return ORACLE_ERR_EXTENT;
+        if (extents[group_first + m] != extents[group_first]) return ORACLE_ERR_EXTENT;
+    if (pairs)
+        for (int m = 1; m < d; ++m)
+            if (extents[first + m] != extents[first]) return ORACLE_ERR_EXTENT;
     L->outer = 1;
-    for (int k = 0; k < group_first; ++k) L->outer *= extents[k];
+    for (int k = 0; k < first; ++k) L->outer *= extents[k];
     L->inner = 1;
     for (int k = group_first + d; k < ndim; ++k) L->inner *= extents[k];
     L->group = 1;
-    for (int m = 0; m < d; ++m) L->group *= L->n;
+    for (int m = 0; m < L->nidx; ++m) L->group *= L->ext[m];
     return ORACLE_OK;
+}
+
+/* Position read for permuted dim m by a term with group permutation p: the
+ * group part (and the partner part of the index-pair form) follow p. */
+static int read_pos(const layout_t* L, const int* p, int m) {
+    if (L->nidx == L->d) return p[m];
+    return (m < L->d) ? p[m] : L->d + p[m - L->d];
 }
 
 static int check_perms(int d, int nterms, const int* perms) {
@@ -96,11 +119,11 @@ static int check_perms(int d, int nterms, const int* perms) {
     return ORACLE_OK;
 }
 
-/* Offset (in units of the inner block) of the group tuple idx[0..d-1]
- * inside one outer slice: row-major, idx[d-1] fastest. */
-static int64_t group_offset(const int64_t* idx, int d, int64_t n) {
+/* Offset (in units of the inner block) of the permuted-dims tuple
+ * idx[0..nidx-1] inside one outer slice: row-major, last fastest. */
+static int64_t group_offset(const layout_t* L, const int64_t* idx) {
     int64_t off = 0;
-    for (int m = 0; m < d; ++m) off = off * n + idx[m];
+    for (int m = 0; m < L->nidx; ++m) off = off * L->ext[m] + idx[m];
     return off;
 }
 
@@ -109,33 +132,32 @@ static int64_t group_offset(const int64_t* idx, int d, int64_t n) {
 static void stage_ld(const layout_t* L, int nterms, const int* perms,
                      const double* alpha, const long double* src,
                      long double* dst, int nthreads) {
-    const int d = L->d;
+    const int d = L->d, nidx = L->nidx;
     (void)nthreads;
 #ifdef _OPENMP
 #pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
 #endif
     for (int64_t b = 0; b < L->outer; ++b) {
-        int64_t idx[ORACLE_MAX_D];
-        int64_t read[ORACLE_MAX_D];
+        int64_t idx[2 * ORACLE_MAX_D];
+        int64_t read[2 * ORACLE_MAX_D];
         const long double* s = src + b * L->group * L->inner;
         long double* o = dst + b * L->group * L->inner;
-        for (int m = 0; m < d; ++m) idx[m] = 0;
+        for (int m = 0; m < nidx; ++m) idx[m] = 0;
         for (int64_t g = 0; g < L->group; ++g) {
-            /* idx is the tuple (i_0..i_{d-1}) of linear group index g */
+            /* idx is the tuple of permuted indices of linear index g */
             for (int64_t r = 0; r < L->inner; ++r) {
                 long double acc = 0.0L;
                 for (int t = 0; t < nterms; ++t) {
                     if (alpha[t] == 0.0) continue;
                     const int* p = perms + t * d;
-                    for (int m = 0; m < d; ++m) read[m] = idx[p[m]];
-                    acc += (long double)alpha[t] *
-                           s[group_offset(read, d, L->n) * L->inner + r];
+                    for (int m = 0; m < nidx; ++m) read[m] = idx[read_pos(L, p, m)];
+                    acc += (long double)alpha[t] * s[group_offset(L, read) * L->inner + r];
                 }
                 o[g * L->inner + r] = acc;
             }
             /* advance the odometer, last index fastest */
-            for (int m = d - 1; m >= 0; --m) {
-                if (++idx[m] < L->n) break;
+            for (int m = nidx - 1; m >= 0; --m) {
+                if (++idx[m] < L->ext[m]) break;
                 idx[m] = 0;
             }
         }
@@ -146,30 +168,30 @@ static void stage_ld(const layout_t* L, int nterms, const int* perms,
 static void stage_adjoint_ld(const layout_t* L, int nterms, const int* perms,
                              const double* alpha, const long double* gout,
                              long double* gin, int nthreads) {
-    const int d = L->d;
+    const int d = L->d, nidx = L->nidx;
     (void)nthreads;
 #ifdef _OPENMP
 #pragma omp parallel for schedule(static) num_threads(nthreads > 0 ? nthreads : 1)
 #endif
     for (int64_t b = 0; b < L->outer; ++b) {
-        int64_t idx[ORACLE_MAX_D];
-        int64_t read[ORACLE_MAX_D];
+        int64_t idx[2 * ORACLE_MAX_D];
+        int64_t read[2 * ORACLE_MAX_D];
         const long double* go = gout + b * L->group * L->inner;
         long double* gi = gin + b * L->group * L->inner;
         for (int64_t e = 0; e < L->group * L->inner; ++e) gi[e] = 0.0L;
-        for (int m = 0; m < d; ++m) idx[m] = 0;
+        for (int m = 0; m < nidx; ++m) idx[m] = 0;
         for (int64_t g = 0; g < L->group; ++g) {
             for (int64_t r = 0; r < L->inner; ++r) {
                 for (int t = 0; t < nterms; ++t) {
                     if (alpha[t] == 0.0) continue;
                     const int* p = perms + t * d;
-                    for (int m = 0; m < d; ++m) read[m] = idx[p[m]];
-                    gi[group_offset(read, d, L->n) * L->inner + r] +=
+                    for (int m = 0; m < nidx; ++m) read[m] = idx[read_pos(L, p, m)];
+                    gi[group_offset(L, read) * L->inner + r] +=
                         (long double)alpha[t] * go[g * L->inner + r];
                 }
             }
-            for (int m = d - 1; m >= 0; --m) {
-                if (++idx[m] < L->n) break;
+            for (int m = nidx - 1; m >= 0; --m) {
+                if (++idx[m] < L->ext[m]) break;
                 idx[m] = 0;
             }
         }
@@ -177,11 +199,11 @@ static void stage_adjoint_ld(const layout_t* L, int nterms, const int* perms,
 }
 
 static int run_chain(int adjoint, int ndim, const int64_t* extents, int group_first,
-                     int d, int nstages, const int* nterms, const int* perms,
+                     int d, int pairs, int nstages, const int* nterms, const int* perms,
                      const double* alpha, const double* in, double* out,
                      int nthreads) {
     layout_t L;
-    int st = make_layout(ndim, extents, group_first, d, &L);
+    int st = make_layout(ndim, extents, group_first, d, pairs, &L);
     if (st != ORACLE_OK) return st;
     if (nstages < 1 || nterms == NULL || in == NULL || out == NULL) return ORACLE_ERR_ARG;
     int total = 0;
@@ -239,15 +261,25 @@ int oracle_spinsum_chain(int ndim, const int64_t* extents, int group_first, int 
                          int nstages, const int* nterms, const int* perms,
                          const double* alpha, const double* in, double* out,
                          int nthreads) {
-    return run_chain(0, ndim, extents, group_first, d, nstages, nterms, perms, alpha,
+    return run_chain(0, ndim, extents, group_first, d, 0, nstages, nterms, perms, alpha,
                      in, out, nthreads);
+}
+
+/* The same with the index-pair form selectable (pairs = 1: the d dims before
+ * the group are permuted along with it). */
+int oracle_spinsum_chain_ex(int ndim, const int64_t* extents, int group_first, int d,
+                            int pairs, int nstages, const int* nterms, const int* perms,
+                            const double* alpha, const double* in, double* out,
+                            int nthreads) {
+    return run_chain(0, ndim, extents, group_first, d, pairs != 0, nstages, nterms, perms,
+                     alpha, in, out, nthreads);
 }
 
 /* Single stage convenience form. */
 int oracle_spinsum(int ndim, const int64_t* extents, int group_first, int d,
                    int nterms, const int* perms, const double* alpha,
                    const double* in, double* out, int nthreads) {
-    return run_chain(0, ndim, extents, group_first, d, 1, &nterms, perms, alpha, in, out,
+    return run_chain(0, ndim, extents, group_first, d, 0, 1, &nterms, perms, alpha, in, out,
                      nthreads);
 }
 
@@ -257,8 +289,17 @@ int oracle_spinsum_chain_adjoint(int ndim, const int64_t* extents, int group_fir
                                  const int* perms, const double* alpha,
                                  const double* grad_out, double* grad_in,
                                  int nthreads) {
-    return run_chain(1, ndim, extents, group_first, d, nstages, nterms, perms, alpha,
+    return run_chain(1, ndim, extents, group_first, d, 0, nstages, nterms, perms, alpha,
                      grad_out, grad_in, nthreads);
+}
+
+int oracle_spinsum_chain_adjoint_ex(int ndim, const int64_t* extents, int group_first,
+                                    int d, int pairs, int nstages, const int* nterms,
+                                    const int* perms, const double* alpha,
+                                    const double* grad_out, double* grad_in,
+                                    int nthreads) {
+    return run_chain(1, ndim, extents, group_first, d, pairs != 0, nstages, nterms, perms,
+                     alpha, grad_out, grad_in, nthreads);
 }
 
 int oracle_max_threads(void) {

@@ -442,3 +442,86 @@ def test_coef_grad_definition(shape, gf, d):
         e = np.zeros(len(perms))
         e[r] = 1.0
         assert abs((L(alpha + e) - L(alpha)) - grad[r]) <= 1e-10
+
+
+# ------------------------------------------------------- index-pair form
+def _interleave(x, first, d):
+    """[.., a_0..a_{d-1}, i_0..i_{d-1}, ..] -> [.., (a_0 i_0), .., (a_{d-1} i_{d-1}), ..]:
+    each pair (a_m, i_m) becomes one index a_m * N + i_m of extent V * N."""
+    nd = x.ndim
+    axes = list(range(first))
+    for m in range(d):
+        axes += [first + m, first + d + m]
+    axes += list(range(first + 2 * d, nd))
+    y = np.transpose(x, axes)
+    V, N = x.shape[first], x.shape[first + d]
+    return np.ascontiguousarray(y).reshape(x.shape[:first] + (V * N,) * d + x.shape[first + 2 * d:])
+
+
+def _deinterleave(y, first, d, V, N):
+    shp = y.shape[:first] + tuple(v for _ in range(d) for v in (V, N)) + y.shape[first + d:]
+    z = y.reshape(shp)
+    nd = z.ndim
+    axes = list(range(first)) + [first + 2 * m for m in range(d)] + \
+        [first + 2 * m + 1 for m in range(d)] + list(range(first + 2 * d, nd))
+    return np.ascontiguousarray(np.transpose(z, axes))
+
+
+@pytest.mark.parametrize("shape,gf,d", [((3, 3, 2, 2), 2, 2), ((2, 3, 3, 3, 2, 2, 2), 4, 3),
+                                        ((2, 2, 2, 2, 2, 2, 2, 2), 4, 4),
+                                        ((2, 4, 4, 2, 2, 3), 3, 2), ((1, 3, 3, 3, 3, 3, 3, 2), 4, 3)])
+def test_pairs_match_numpy_transpose_and_interleaved_group(shape, gf, d):
+    """Index-pair form: (i) the same as the numpy transpose of both index
+    sets; (ii) conjugate to the ordinary summation over the combined indices
+    c_m = a_m * N + i_m (the pairs (a_m, i_m) permuted together are exactly
+    the permuted tuple of combined indices), which pins it to the already
+    pinned group form; bitwise, since both evaluate the same terms in the same
+    order."""
+    rng = np.random.default_rng(sum(shape))
+    terms = [(p, float(rng.normal())) for p in itertools.permutations(range(d))]
+    x = _rand(shape, 71)
+    got = oracle.spinsum(x, terms, gf, d, pairs=True)
+    np.testing.assert_allclose(got, oracle.spinsum_numpy(x, terms, gf, d, pairs=True),
+                               rtol=0, atol=1e-13)
+    first = gf - d
+    V, N = shape[first], shape[gf]
+    comb = oracle.spinsum(_interleave(x, first, d), terms, first, d)
+    np.testing.assert_array_equal(_deinterleave(comb, first, d, V, N), got)
+    adj = oracle.spinsum_chain_adjoint(x, [terms], gf, d, pairs=True)
+    comb_adj = oracle.spinsum_chain_adjoint(_interleave(x, first, d), [terms], first, d)
+    np.testing.assert_array_equal(_deinterleave(comb_adj, first, d, V, N), adj)
+
+
+@pytest.mark.parametrize("shape,gf,d", [((2, 2, 3, 3), 2, 2), ((2, 2, 2, 2, 2, 2), 3, 3),
+                                        ((2, 3, 3, 2, 2, 2), 3, 2)])
+def test_pairs_dense_matrix_forward_and_adjoint(shape, gf, d):
+    rng = np.random.default_rng(5)
+    perms = list(itertools.permutations(range(d)))
+    stages = [[(perms[k], float(rng.normal())) for k in rng.choice(len(perms), min(3, len(perms)), replace=False)]
+              for _ in range(2)]
+    M = oracle.dense_chain_matrix(shape, stages, gf, d, pairs=True)
+    x = _rand(shape, 72)
+    g = _rand(shape, 73)
+    np.testing.assert_allclose(oracle.spinsum_chain(x, stages, gf, d, pairs=True).ravel(),
+                               M @ x.ravel(), rtol=0, atol=1e-13)
+    np.testing.assert_allclose(oracle.spinsum_chain_adjoint(g, stages, gf, d, pairs=True).ravel(),
+                               M.T @ g.ravel(), rtol=0, atol=1e-13)
+
+
+def test_pairs_worked_example_and_special_cases():
+    """A[a,b,i,j] = 1000a + 100b + 10i + j under the swap (21) gives
+    B[a,b,i,j] = 1000b + 100a + 10j + i.  With V = 1 the form is the
+    ordinary summation; with N = 1 it is the ordinary summation over the
+    partner dims."""
+    V, N = 3, 4
+    enc = np.fromfunction(lambda a, b, i, j: 1000 * a + 100 * b + 10 * i + j, (V, V, N, N))
+    got = oracle.spinsum(enc, [(P("21"), 1.0)], 2, 2, pairs=True)
+    want = np.fromfunction(lambda a, b, i, j: 1000 * b + 100 * a + 10 * j + i, (V, V, N, N))
+    np.testing.assert_array_equal(got, want)
+    terms = [(p, float(k + 1)) for k, p in enumerate(itertools.permutations(range(3)))]
+    x = _rand((2, 1, 1, 1, 4, 4, 4), 74)
+    np.testing.assert_array_equal(oracle.spinsum(x, terms, 4, 3, pairs=True),
+                                  oracle.spinsum(x, terms, 4, 3))
+    x = _rand((2, 4, 4, 4, 1, 1, 1, 3), 75)
+    np.testing.assert_array_equal(oracle.spinsum(x, terms, 4, 3, pairs=True),
+                                  oracle.spinsum(x, terms, 1, 3))
