@@ -20,10 +20,12 @@
  *                     hyper-square groups.
  *
  * Tensor layout: C-contiguous (row-major, last index fastest), extents
- * [outer spectators..., N x d]: the permuted group is the trailing d
- * dimensions, all of extent N (Sec. 3.1 "hyper-square"); every spectator
- * index selects one "cube" of N^d contiguous elements.  A group followed by
- * further (inner) dimensions is rejected with SPINSUM_ERR_UNSUPPORTED.
+ * [outer spectators..., N x d, inner spectators...]: the permuted group is d
+ * consecutive dimensions, all of extent N (Sec. 3.1 "hyper-square"); every
+ * outer spectator index selects one "cube" of N^d * R contiguous elements,
+ * R being the product of the inner spectator extents (1 when the group is
+ * trailing).  Inner spectators are not permuted: each group position holds
+ * a contiguous run of R elements that moves as a whole.
  *
  * Conventions shared by every entry point:
  *   - every function returns a spinsum_status; no exception crosses the ABI;
@@ -56,7 +58,7 @@ typedef enum {
   SPINSUM_ERR_INVALID_ARG = -1,      /* null pointer, bad count, bad dim, wrong device */
   SPINSUM_ERR_NOT_PERMUTATION = -2,  /* a term is not a bijection of 0..d-1 */
   SPINSUM_ERR_EXTENT_MISMATCH = -3,  /* group extents differ (not hyper-square) */
-  SPINSUM_ERR_UNSUPPORTED = -4,      /* d not in {2,3,4}, inner spectators, tile too big */
+  SPINSUM_ERR_UNSUPPORTED = -4,      /* d not in {2,3,4}, sizes beyond the limits, tile too big */
   SPINSUM_ERR_ALIASING = -5,         /* out-of-place buffers overlap */
   SPINSUM_ERR_MISALIGNED = -6,       /* tensor pointer not 16-byte aligned */
   SPINSUM_ERR_OUT_OF_MEMORY = -7,    /* host or device allocation failed */
@@ -77,6 +79,10 @@ typedef enum { SPINSUM_F64 = 0, SPINSUM_F32 = 1 } spinsum_dtype;
 #define SPINSUM_FLAG_REVERSE_ORDER 0x10u /* process work items in reverse order (ownership test) */
 #define SPINSUM_FLAG_NO_LDS_PAD 0x20u    /* unpadded LDS tiles (bank-conflict ablation) */
 #define SPINSUM_FLAG_NO_DIRECT_LDS 0x40u /* never use the direct-LDS variant (ablation)  */
+#define SPINSUM_FLAG_INDEX_PAIRS 0x80u   /* index-pair form: the d dims right before the group
+                                            (the partner indices, extent V each) are permuted
+                                            by the same permutation as the group, e.g.
+                                            T[a,b,c,i,j,k] with (a,i), (b,j), (c,k) as pairs */
 
 typedef struct spinsum_plan_s* spinsum_plan_t;
 typedef struct spinsum_graph_s* spinsum_graph_t;
@@ -129,12 +135,16 @@ typedef struct {
   int item_tiles;        /* tiles of the largest work item                 */
   int chunks_per_thread; /* 16-byte loads per thread for the largest item */
   int64_t rep_lds_bytes; /* LDS for the element-orbit representatives      */
+  int inner;             /* elements of the inner spectator run (1: trailing group) */
+  int pair_extent;       /* index-pair form: partner extent V, else 0    */
 } spinsum_plan_info_t;
 
 /* Create a plan for Out = S_K(...S_1(In)) (Def. 3-4; in-place: Sec. 4.6.5).
  *   ndim, extents : tensor shape, C-contiguous, all extents >= 0.
  *   group_first, d: the permuted group is dims [group_first, group_first+d);
- *                   d in {2,3,4}; group_first + d must equal ndim.
+ *                   d in {2,3,4}; dims after it are inner spectators
+ *                   (N^d times their product must stay below 2^31
+ *                   elements).
  *   nstages >= 1, nterms[k] >= 0 terms in stage k; perms holds sum(nterms)
  *                   rows of d 0-based entries; alpha holds sum(nterms)
  *                   coefficients.  Duplicate permutations within a stage are

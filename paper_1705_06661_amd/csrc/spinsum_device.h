@@ -130,6 +130,9 @@ __device__ __forceinline__ Geom load_geom(const __attribute__((address_space(4))
   g.cube_lds = s.cube_lds;
   g.rows = s.rows;
   g.vpr = s.vpr;
+  g.inner = s.inner;
+  g.pad0 = 0;
+  g.fd_inner = load_fd(s.fd_inner);
   g.fd_vpr = load_fd(s.fd_vpr);
   g.fd_rows = load_fd(s.fd_rows);
   g.fd_bl = load_fd(s.fd_bl);
@@ -183,6 +186,23 @@ struct BatchArgs {
   int32_t pad;
 };
 
+template <typename T>
+struct PairArgs {
+  const T* in;
+  T* out;
+  const uint64_t* orbits;  // sorted combined blocks of each tile orbit, 16 bits each
+  const uint32_t* reps;    // representative pool (lists selected by pair_key)
+  const T* coef;
+  Geom g;
+  PairGeom pg;
+  int64_t nitems;
+  int64_t xcd_per;
+  int32_t nstages;
+  int32_t reverse;
+  int32_t lds_tile_bytes;  // start of the representative list in LDS
+  int32_t pad;
+};
+
 // Fused multiply-add in the storage type (a float FMA for float: the
 // generic builtin would promote to double).
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -220,6 +240,63 @@ __device__ __forceinline__ void orbit_rows_store(const T* a, const T* v, T* lds,
   ((lds[addr[TAU]] = orbit_row<T, D, TAU>(a, v, std::make_integer_sequence<int, Fact<D>::v>{})), ...);
 }
 
+// Unit i of an orbit's combine loop -> cube of the item ci, representative
+// ri and inner spectator index s: units run over (cube, representative,
+// inner index) with the inner index fastest, so that the lanes of a wave
+// read neighbouring LDS words when inner > 1.
+__device__ __forceinline__ void split_unit(const Geom& g, uint32_t i, uint32_t rep_cnt,
+                                           const FastDiv& fdr, int ncub, uint32_t* ci,
+                                           uint32_t* ri, uint32_t* s) {
+  uint32_t j = i;
+  *s = 0;
+  if (g.inner != 1) {
+    j = fdiv(i, g.fd_inner);
+    *s = i - j * (uint32_t)g.inner;
+  }
+  *ci = (ncub == 1) ? 0u : fdiv(j, fdr);
+  *ri = j - *ci * rep_cnt;
+}
+
+// Combine the element orbits of one tile orbit: sb[sigma] = LDS offset of
+// tile sigma . B, rp = its representative list (rep_cnt entries, local
+// coordinates packed one byte per axis), for ncub cubes of the item.
+template <typename T, int D, bool CHAIN>
+__device__ __forceinline__ void combine_orbit(const Geom& g, const int32_t (&sb)[Fact<D>::v],
+                                              const uint32_t* rp, uint32_t rep_cnt,
+                                              const FastDiv& fdr, int ncub, cptr<T> coef,
+                                              int nstages, T (&a)[Fact<D>::v], T* lds) {
+  constexpr int DF = Fact<D>::v;
+  const uint32_t nrep = (uint32_t)ncub * rep_cnt * (uint32_t)g.inner;
+  for (uint32_t i = threadIdx.x; i < nrep; i += blockDim.x) {
+    uint32_t ci, ri, si;
+    split_unit(g, i, rep_cnt, fdr, ncub, &ci, &ri, &si);
+    uint32_t pk = rp[ri];
+    int l[D];
+#pragma unroll
+    for (int m = 0; m < D; ++m) l[m] = (int)((pk >> (8 * m)) & 255u);
+    const int base = (int)ci * g.cube_lds + (int)si;
+    int addr[DF];
+    T v[DF];
+    orbit_addrs<D>(g, base, sb, l, addr, std::make_integer_sequence<int, DF>{});
+#pragma unroll
+    for (int r = 0; r < DF; ++r) v[r] = lds[addr[r]];
+    if constexpr (!CHAIN) {
+      orbit_rows_store<T, D>(a, v, lds, addr, std::make_integer_sequence<int, DF>{});
+    } else {
+      T w[DF];
+      for (int s = 0; s < nstages; ++s) {
+#pragma unroll
+        for (int r = 0; r < DF; ++r) a[r] = coef[s * DF + r];
+        orbit_product<T, D>(a, v, w);
+#pragma unroll
+        for (int r = 0; r < DF; ++r) v[r] = w[r];
+      }
+#pragma unroll
+      for (int r = 0; r < DF; ++r) lds[addr[r]] = v[r];
+    }
+  }
+}
+
 // 2. combine every element orbit of the item in LDS
 // Combine every element orbit of a work item.  The item's tile orbits are
 // visited in turn (uniform loop); their representatives come from global
@@ -240,38 +317,10 @@ __device__ __forceinline__ void combine_item(const Geom& g, cptr<GroupDev> gd,
     int32_t sb[DF];
 #pragma unroll
     for (int r = 0; r < DF; ++r) sb[r] = gd->slot_base[k][r];
-    const uint32_t rep_cnt = (uint32_t)gd->rep_cnt[k];
-    const uint32_t nrep = (uint32_t)ncub * rep_cnt;
     const FastDiv fdr = load_fd(gd->fd_rep[k]);
     const uint32_t* rp = reps + (REPS_IN_LDS ? gd->rep_base[k] : gd->rep_off[k]);
-    for (uint32_t i = threadIdx.x; i < nrep; i += blockDim.x) {
-      uint32_t ci = (ncub == 1) ? 0u : fdiv(i, fdr);
-      uint32_t ri = i - ci * rep_cnt;
-      uint32_t pk = rp[ri];
-      int l[D];
-#pragma unroll
-      for (int m = 0; m < D; ++m) l[m] = (int)((pk >> (8 * m)) & 255u);
-      const int base = (int)ci * g.cube_lds;
-      int addr[DF];
-      T v[DF];
-      orbit_addrs<D>(g, base, sb, l, addr, std::make_integer_sequence<int, DF>{});
-#pragma unroll
-      for (int r = 0; r < DF; ++r) v[r] = lds[addr[r]];
-      if constexpr (!CHAIN) {
-        orbit_rows_store<T, D>(a, v, lds, addr, std::make_integer_sequence<int, DF>{});
-      } else {
-        T w[DF];
-        for (int s = 0; s < nstages; ++s) {
-#pragma unroll
-          for (int r = 0; r < DF; ++r) a[r] = coef[s * DF + r];
-          orbit_product<T, D>(a, v, w);
-#pragma unroll
-          for (int r = 0; r < DF; ++r) v[r] = w[r];
-        }
-#pragma unroll
-        for (int r = 0; r < DF; ++r) lds[addr[r]] = v[r];
-      }
-    }
+    combine_orbit<T, D, CHAIN>(g, sb, rp, (uint32_t)gd->rep_cnt[k], fdr, ncub, coef, nstages, a,
+                               lds);
   }
 }
 
@@ -404,7 +453,8 @@ __global__ void __launch_bounds__(kThreads) k_exec(const ExecArgs<T> a) {
 }
 
 // Chunk c (VW elements) of a full tile, chunks in row-major order: its
-// local coordinates l (l[D-1] is the first element of the chunk).
+// local coordinates l (l[D-1] is the chunk's first element inside its row
+// of bl * inner elements).
 template <int D, int VW>
 __device__ __forceinline__ void chunk_coords(const Geom& g, uint32_t c, int (&l)[D]) {
   uint32_t q = fdiv(c, g.fd_vpr);
@@ -425,11 +475,21 @@ __device__ __forceinline__ void chunk_coords(const Geom& g, uint32_t c, int (&l)
 
 // Inside the extent of a ragged tile (ext packs one byte per index)?
 template <int D>
-__device__ __forceinline__ bool chunk_inside(const int (&l)[D], int ext) {
+__device__ __forceinline__ bool chunk_inside(const int (&l)[D], int ext, int inner) {
   bool in = true;
 #pragma unroll
-  for (int m = 0; m < D; ++m) in = in && (l[m] < ((ext >> (8 * m)) & 255));
-  return in;
+  for (int m = 0; m < D - 1; ++m) in = in && (l[m] < ((ext >> (8 * m)) & 255));
+  return in && (l[D - 1] < ((ext >> (8 * (D - 1))) & 255) * inner);
+}
+
+// Element offset of a chunk inside its tile (the last coordinate counts
+// elements of the row).
+template <int D>
+__device__ __forceinline__ int chunk_offset(const Geom& g, const int (&l)[D]) {
+  int off = l[D - 1];
+#pragma unroll
+  for (int m = 0; m < D - 1; ++m) off += l[m] * g.gst[m];
+  return off;
 }
 
 // Issue the loads of one item straight into LDS (global_load_lds_dwordx4:
@@ -452,13 +512,11 @@ __device__ __forceinline__ int issue_item_lds(const Geom& g, cptr<GroupDev> od, 
   for (uint32_t c0 = 0; c0 < cpt; c0 += blockDim.x) {
     int l[D];
     chunk_coords<D, VW>(g, c0 + tid, l);
-    int off = 0;
-#pragma unroll
-    for (int m = 0; m < D; ++m) off += l[m] * g.gst[m];
+    const int off = chunk_offset<D>(g, l);
     const bool in = c0 + tid < cpt;
     for (int t = 0; t < ntl; ++t) {
       const int toff = whole ? t * (int)g.cube_elems : od->tile_off[t];
-      const bool ok = in && (!ragged || chunk_inside<D>(l, od->tile_ext[t]));
+      const bool ok = in && (!ragged || chunk_inside<D>(l, od->tile_ext[t], g.inner));
       const uint32_t lbyte = (uint32_t)(t * g.ts + (int)c0 * VW) * (uint32_t)sizeof(T) + wave_bytes;
       if (ok)
         __builtin_amdgcn_global_load_lds(
@@ -591,13 +649,11 @@ __device__ __forceinline__ void store_item_lds(const Geom& g, cptr<GroupDev> od,
     const uint32_t c = c0 + threadIdx.x;
     int l[D];
     chunk_coords<D, VW>(g, c, l);
-    int off = 0;
-#pragma unroll
-    for (int m = 0; m < D; ++m) off += l[m] * g.gst[m];
+    const int off = chunk_offset<D>(g, l);
     const bool in = c < cpt;
     for (int t = 0; t < ntl; ++t) {
       const int toff = whole ? t * (int)g.cube_elems : od->tile_off[t];
-      const bool ok = in && (!ragged || chunk_inside<D>(l, od->tile_ext[t]));
+      const bool ok = in && (!ragged || chunk_inside<D>(l, od->tile_ext[t], g.inner));
       if (ok) {
         const V val = *reinterpret_cast<const V*>(lds + t * g.ts + (int)c * VW);
         V* p = reinterpret_cast<V*>(dst + toff + off);
@@ -699,6 +755,194 @@ __global__ void __launch_bounds__(kMaxThreads) k_lds(const ExecArgs<T> a) {
     flat_store<T, NTS>(a.out + cube0 * g.cube_elems, span, smem, shift);
   else
     store_item_lds<T, D, NTS>(g, od, whole, ntl, ragged, a.out + cube0 * g.cube_elems, lds);
+}
+
+// Index-pair form: one tile orbit {sigma . c} of one pair block per
+// workgroup, c the orbit's sorted combined blocks (c_m = a_m * nb + b_m).
+// Lane r of wave 0 forms sigma_r . c; tiles are numbered in the order of
+// their first sigma, and slot r of the combine step is the tile of
+// sigma_r . c.  Tiles then go straight into LDS: whole group cubes (bl == N)
+// as one contiguous run each, with the run's 16-byte alignment shift folded
+// into the slot offsets; otherwise in 16-byte chunks of rows, as in k_lds.
+// LDS: [tiles (lds_tile_bytes) | representatives]; the tile list (PairInfo)
+// in a static LDS block.
+
+// Entry k of the unrolled permutation table: element m of permutation r
+// (lexicographic) as a select chain, so that no register array is indexed
+// with a lane-dependent value.
+template <int D, int M, int... R>
+__device__ __forceinline__ int perm_entry(int r, std::integer_sequence<int, R...>) {
+  int v = 0;
+  ((v = (r == R) ? LexPerm<D, R, M>::value : v), ...);
+  return v;
+}
+
+template <int D>
+__device__ __forceinline__ int pick(const int (&c)[D], int k) {
+  int v = c[0];
+#pragma unroll
+  for (int j = 1; j < D; ++j) v = (k == j) ? c[j] : v;
+  return v;
+}
+
+template <int D, int... M>
+__device__ __forceinline__ void permuted_tuple(const int (&c)[D], int r, int (&t)[D],
+                                               std::integer_sequence<int, M...>) {
+  ((t[M] = pick<D>(c, perm_entry<D, M>(r, std::make_integer_sequence<int, Fact<D>::v>{}))), ...);
+}
+
+template <typename T, int D, bool CHAIN, bool NTS>
+__global__ void __launch_bounds__(kMaxThreads) k_pair(const PairArgs<T> a) {
+  constexpr int DF = Fact<D>::v;
+  constexpr int VW = 16 / sizeof(T);
+  typedef typename VecT<T, VW>::type V;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  __shared__ PairInfo info;
+  T* lds = reinterpret_cast<T*>(smem);
+  int64_t item;
+  if (a.xcd_per > 0)
+    item = (int64_t)(blockIdx.x & 7u) * a.xcd_per + (int64_t)(blockIdx.x >> 3);
+  else
+    item = blockIdx.x;
+  if (item >= a.nitems) return;
+  if (a.reverse) item = a.nitems - 1 - item;
+  const Geom& g = a.g;
+  const PairGeom& pg = a.pg;
+  const uint32_t q = fdiv((uint32_t)item, pg.fd_norb);
+  const int64_t cube0 = q;
+  const int64_t orb = item - (int64_t)q * pg.norb;
+  const T* src = a.in + cube0 * g.cube_elems;
+  T* dst = a.out + cube0 * g.cube_elems;
+  // 1. the orbit's tile list
+  if (threadIdx.x < 64) {
+    const uint64_t pk = as_const(a.orbits)[orb];
+    int c[D];
+#pragma unroll
+    for (int m = 0; m < D; ++m) c[m] = (int)((pk >> (16 * m)) & 0xFFFFu);
+    const int r = (int)threadIdx.x;
+    const bool act = r < DF;
+    int t[D];
+    permuted_tuple<D>(c, act ? r : 0, t, std::make_integer_sequence<int, D>{});
+    uint64_t key = 0;
+#pragma unroll
+    for (int m = 0; m < D; ++m) key |= (uint64_t)t[m] << (16 * m);
+    int first = r;
+    for (int r2 = DF - 1; r2 >= 0; --r2) {
+      const uint64_t k2 = ((uint64_t)(uint32_t)__shfl((int)(key >> 32), r2, 64) << 32) |
+                          (uint32_t)__shfl((int)(uint32_t)key, r2, 64);
+      if (r2 < r && k2 == key) first = r2;
+    }
+    const bool isfirst = act && first == r;
+    const uint64_t mask = __builtin_amdgcn_ballot_w64(isfirst);
+    const int slot = __builtin_popcountll(mask & ((1ull << first) - 1ull));
+    int shift = 0;
+    if (isfirst) {
+      int64_t off;
+      int32_t ext;
+      pair_tile(g, pg, D, t, &off, &ext);
+      if (pg.flat) shift = flat_shift<T>(src + off);
+      info.toff[slot] = off;
+      info.text[slot] = ext;
+      info.shift[slot] = shift;
+    }
+    const int fshift = __shfl(shift, act ? first : 0, 64);
+    if (act) info.sb[r] = slot * pg.tile_stride + fshift;
+    if (r == 0) {
+      info.ntiles = __builtin_popcountll(mask);
+      const int k = pair_key(g, pg, D, c);
+      info.rep_off = pg.rep_off[k];
+      info.rep_cnt = pg.rep_cnt[k];
+    }
+  }
+  __syncthreads();
+  const int ntl = __builtin_amdgcn_readfirstlane(info.ntiles);
+  const uint32_t rep_cnt = (uint32_t)__builtin_amdgcn_readfirstlane(info.rep_cnt);
+  const uint32_t rep_off = (uint32_t)__builtin_amdgcn_readfirstlane(info.rep_off);
+  // 2. tiles and the representative list straight into LDS
+  const uint32_t tid = threadIdx.x;
+  const uint32_t wave_bytes = (tid >> 6) * 1024u;
+  const int64_t tile_elems = (int64_t)g.rows * g.bl * g.inner;
+  if (pg.flat) {
+    for (int t = 0; t < ntl; ++t) {
+      const int64_t toff = info.toff[t];
+      flat_issue<T>(src + toff, (uint32_t)tile_elems,
+                    smem + (size_t)t * pg.tile_stride * sizeof(T));
+    }
+  } else {
+    const uint32_t cpt = (uint32_t)g.rows * (uint32_t)g.vpr;
+    for (uint32_t c0 = 0; c0 < cpt; c0 += blockDim.x) {
+      int l[D];
+      chunk_coords<D, VW>(g, c0 + tid, l);
+      const int off = chunk_offset<D>(g, l);
+      const bool in = c0 + tid < cpt;
+      for (int t = 0; t < ntl; ++t) {
+        const int64_t toff = info.toff[t];
+        const bool ok = in && chunk_inside<D>(l, info.text[t], g.inner);
+        const uint32_t lbyte =
+            (uint32_t)(t * pg.tile_stride + (int)c0 * VW) * (uint32_t)sizeof(T) + wave_bytes;
+        if (ok)
+          __builtin_amdgcn_global_load_lds(
+              (const void*)(src + toff + off),
+              (__attribute__((address_space(3))) void*)(smem + lbyte), 16, 0, 0);
+      }
+    }
+  }
+  unsigned char* rep_lds = smem + a.lds_tile_bytes;
+  {
+    const uint32_t wave0 = tid & ~63u;
+    for (uint32_t i0 = 0; i0 < rep_cnt; i0 += blockDim.x)
+      if (i0 + tid < rep_cnt)
+        __builtin_amdgcn_global_load_lds(
+            (const void*)(a.reps + rep_off + i0 + tid),
+            (__attribute__((address_space(3))) void*)(rep_lds + (i0 + wave0) * 4u), 4, 0, 0);
+  }
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): everything is in LDS
+  __syncthreads();
+  // 3. combine
+  {
+    T co[DF];
+    const cptr<T> coef = as_const(a.coef);
+    if constexpr (!CHAIN) {
+#pragma unroll
+      for (int r = 0; r < DF; ++r) co[r] = coef[r];
+    }
+    int32_t sb[DF];
+#pragma unroll
+    for (int r = 0; r < DF; ++r) sb[r] = __builtin_amdgcn_readfirstlane(info.sb[r]);
+    const FastDiv one{1u, 0u, 0u, 0u};
+    combine_orbit<T, D, CHAIN>(g, sb, reinterpret_cast<const uint32_t*>(rep_lds), rep_cnt, one, 1,
+                               coef, a.nstages, co, lds);
+  }
+  __syncthreads();
+  // 4. store
+  if (pg.flat) {
+    for (int t = 0; t < ntl; ++t) {
+      const int64_t toff = info.toff[t];
+      flat_store<T, NTS>(dst + toff, (uint32_t)tile_elems,
+                         smem + (size_t)t * pg.tile_stride * sizeof(T), info.shift[t]);
+    }
+  } else {
+    const uint32_t cpt = (uint32_t)g.rows * (uint32_t)g.vpr;
+    for (uint32_t c0 = 0; c0 < cpt; c0 += blockDim.x) {
+      const uint32_t c = c0 + tid;
+      int l[D];
+      chunk_coords<D, VW>(g, c, l);
+      const int off = chunk_offset<D>(g, l);
+      const bool in = c < cpt;
+      for (int t = 0; t < ntl; ++t) {
+        const int64_t toff = info.toff[t];
+        const bool ok = in && chunk_inside<D>(l, info.text[t], g.inner);
+        if (ok) {
+          const V val = *reinterpret_cast<const V*>(lds + t * pg.tile_stride + (int)c * VW);
+          V* p = reinterpret_cast<V*>(dst + toff + off);
+          if constexpr (NTS)
+            __builtin_nontemporal_store(val, p);
+          else
+            *p = val;
+        }
+      }
+    }
+  }
 }
 
 // Persistent, double-buffered direct-LDS loads: while item k is combined
@@ -1016,19 +1260,20 @@ __global__ void __launch_bounds__(kThreads) k_cgrad(const CGradArgs<T> a) {
 #pragma unroll
     for (int r = 0; r < DF; ++r) sb[r] = od->slot_base[k][r];
     const uint32_t rep_cnt = (uint32_t)od->rep_cnt[k];
-    const uint32_t nrep = (uint32_t)ncub * rep_cnt;
+    const uint32_t nrep = (uint32_t)ncub * rep_cnt * (uint32_t)g.inner;
     const FastDiv fdr = load_fd(od->fd_rep[k]);
     const uint32_t* rp = reps + od->rep_base[k];
     const int eq = od->eqmask[k];
     for (uint32_t i = threadIdx.x; i < nrep; i += blockDim.x) {
-      uint32_t ci = (ncub == 1) ? 0u : fdiv(i, fdr);
-      uint32_t ri = i - ci * rep_cnt;
+      uint32_t ci, ri, si;
+      split_unit(g, i, rep_cnt, fdr, ncub, &ci, &ri, &si);
       uint32_t pk = rp[ri];
       int l[D];
 #pragma unroll
       for (int m = 0; m < D; ++m) l[m] = (int)((pk >> (8 * m)) & 255u);
       int addr[DF];
-      orbit_addrs<D>(g, (int)ci * g.cube_lds, sb, l, addr, std::make_integer_sequence<int, DF>{});
+      orbit_addrs<D>(g, (int)ci * g.cube_lds + (int)si, sb, l, addr,
+                     std::make_integer_sequence<int, DF>{});
       double v[DF], u[DF];
 #pragma unroll
       for (int r = 0; r < DF; ++r) {
@@ -1117,9 +1362,14 @@ const void* pipe_kernel(int vw) {
 }
 
 // kind: 1 direct-LDS one-shot, 2 register-prefetch persistent (maxc = 8 or
-// 16), 3 register one-shot, 4 direct-LDS double-buffered persistent
+// 16), 3 register one-shot, 4 direct-LDS double-buffered persistent,
+// 5 index-pair form (direct-LDS one-shot)
 template <typename T, int D>
 const void* pick_d(int kind, int vw, bool chain, bool nts, int maxc) {
+  if (kind == 5) {
+    if (chain) return nts ? (const void*)k_pair<T, D, true, true> : (const void*)k_pair<T, D, true, false>;
+    return nts ? (const void*)k_pair<T, D, false, true> : (const void*)k_pair<T, D, false, false>;
+  }
   if (kind == 1) {
     if (chain) return nts ? (const void*)k_lds<T, D, true, true> : (const void*)k_lds<T, D, true, false>;
     return nts ? (const void*)k_lds<T, D, false, true> : (const void*)k_lds<T, D, false, false>;

@@ -152,6 +152,54 @@ spinsum_status launch_exec(spinsum_plan_s* P, const void* in, void* out, hipStre
   return SPINSUM_OK;
 }
 
+// Index-pair form: one tile orbit of one pair block per workgroup.
+template <typename T>
+spinsum_status launch_pair(spinsum_plan_s* P, const void* in, void* out, hipStream_t stream,
+                           bool adjoint) {
+  const Tiling& Tl = P->T;
+  if (Tl.nitems <= 0) return SPINSUM_OK;
+  const int df = P->G.df;
+  const int K = (int)P->stage_a.size();
+  const bool chain = (P->flags & SPINSUM_FLAG_CHAIN_STAGES) != 0;
+  const bool nts = (P->flags & SPINSUM_FLAG_NO_NT_STORES) == 0;
+  const T* coef = reinterpret_cast<const T*>(P->d_mats);
+  PairArgs<T> a;
+  std::memset(&a, 0, sizeof(a));
+  a.in = reinterpret_cast<const T*>(in);
+  a.out = reinterpret_cast<T*>(out);
+  a.orbits = reinterpret_cast<const uint64_t*>(P->d_orbits);
+  a.reps = reinterpret_cast<const uint32_t*>(P->d_reps);
+  if (!chain) {
+    a.coef = coef + (adjoint ? df : 0);
+    a.nstages = 1;
+  } else {
+    a.coef = coef + 2 * df + (adjoint ? (size_t)K * df : 0);
+    a.nstages = K;
+  }
+  a.g = Tl.g;
+  a.pg = P->pg;
+  a.nitems = Tl.nitems;
+  a.reverse = (P->flags & SPINSUM_FLAG_REVERSE_ORDER) ? 1 : 0;
+  a.lds_tile_bytes = (int32_t)(((size_t)Tl.lds_elems * sizeof(T) + 15) / 16 * 16);
+  const void* k = pick_kernel<T>(P->d, 5, Tl.vw, chain, nts, 0);
+  const size_t shmem = (size_t)a.lds_tile_bytes + (size_t)Tl.max_rep_cnt * 4;
+  spinsum_status st = prepare_kernel(P, k, shmem);
+  if (st != SPINSUM_OK) return st;
+  int64_t grid;
+  if (P->flags & SPINSUM_FLAG_NO_XCD_REMAP) {
+    a.xcd_per = 0;
+    grid = Tl.nitems;
+  } else {
+    a.xcd_per = (Tl.nitems + 7) / 8;
+    grid = a.xcd_per * 8;
+  }
+  void* kargs[] = {&a};
+  hipError_t e =
+      hipLaunchKernel(k, dim3((unsigned)grid), dim3(P->tile.threads), kargs, shmem, stream);
+  if (e != hipSuccess) return hip_error(P, e);
+  return SPINSUM_OK;
+}
+
 template <typename T>
 spinsum_status launch_batched(spinsum_plan_s* P, const void* const* in, void* const* out,
                               hipStream_t stream) {
@@ -219,6 +267,10 @@ using namespace spinsum;
 extern "C" spinsum_status spinsum_exec(spinsum_plan_t P, const void* in, void* out, void* stream) {
   spinsum_status st = check_tensor_args(P, in, out);
   if (st != SPINSUM_OK || P->elems == 0) return st;
+  if (P->pair) {
+    if (P->dtype == SPINSUM_F32) return launch_pair<float>(P, in, out, (hipStream_t)stream, false);
+    return launch_pair<double>(P, in, out, (hipStream_t)stream, false);
+  }
   if (P->dtype == SPINSUM_F32)
     return launch_exec<float>(P, in, out, (hipStream_t)stream, false);
   return launch_exec<double>(P, in, out, (hipStream_t)stream, false);
@@ -228,6 +280,11 @@ extern "C" spinsum_status spinsum_adjoint(spinsum_plan_t P, const void* grad_out
                                           void* stream) {
   spinsum_status st = check_tensor_args(P, grad_out, grad_in);
   if (st != SPINSUM_OK || P->elems == 0) return st;
+  if (P->pair) {
+    if (P->dtype == SPINSUM_F32)
+      return launch_pair<float>(P, grad_out, grad_in, (hipStream_t)stream, true);
+    return launch_pair<double>(P, grad_out, grad_in, (hipStream_t)stream, true);
+  }
   if (P->dtype == SPINSUM_F32)
     return launch_exec<float>(P, grad_out, grad_in, (hipStream_t)stream, true);
   return launch_exec<double>(P, grad_out, grad_in, (hipStream_t)stream, true);
@@ -288,6 +345,7 @@ extern "C" spinsum_status spinsum_coef_grad(spinsum_plan_t P, const void* x, con
   if (P == nullptr || P->batched || grad == nullptr) return SPINSUM_ERR_INVALID_ARG;
   if (!P->has_dev) return SPINSUM_ERR_NO_DEVICE;
   if (((uintptr_t)grad) & 7u) return SPINSUM_ERR_MISALIGNED;
+  if (P->pair) return SPINSUM_ERR_UNSUPPORTED;
   if (P->elems == 0) {
     spinsum_status st = check_device(P);
     if (st != SPINSUM_OK) return st;

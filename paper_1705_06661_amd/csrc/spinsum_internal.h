@@ -16,6 +16,15 @@
 //     M[tau][sigma] = a(tau^-1 o sigma) and a() is the coefficient of each
 //     permutation in the (expanded) operator -- Alg. 2's d! update
 //     statements of one element orbit, written as one d! x d! product.
+//
+// Index-pair form ([.., V x d partner dims, N x d group, inner..], the same
+// permutation applied to both index sets): the pair (a_m, i_m) of axis m
+// acts as one combined index, and a tile as one combined block
+// c_m = a_m * nb + b_m (partner index a_m, group block b_m).  The tile orbits
+// are the multisets of d combined blocks; the kernel obtains its orbit by
+// reading its sorted combined blocks from a table (8 bytes per orbit,
+// against at least 8 * bl^d bytes of data per orbit) and builds the orbit's
+// tile list itself.
 #pragma once
 #include <stdint.h>
 
@@ -75,9 +84,12 @@ struct alignas(16) GroupDev {
 };
 
 // Geometry of one tensor (or one block of a batch).
+// A "cube" is the N^d group block of one outer spectator index, each group
+// element being a contiguous run of `inner` elements (the inner spectators,
+// 1 when the group is trailing).
 struct alignas(16) Geom {
-  int64_t cube_elems;  // N^d
-  int64_t ncubes;      // spectator cubes
+  int64_t cube_elems;  // N^d * inner
+  int64_t ncubes;      // outer spectator cubes
   int32_t n;           // group extent N
   int32_t bl;          // tile edge
   int32_t ngroups;     // work items (groups of tile orbits) per cube
@@ -87,11 +99,14 @@ struct alignas(16) Geom {
   int32_t ts;          // LDS elements per tile slot
   int32_t cube_lds;    // LDS elements per cube in whole-cube mode
   int32_t rows;        // bl^(d-1) rows per tile
-  int32_t vpr;         // vectors per row, bl / VW
+  int32_t vpr;         // vectors per row, bl * inner / VW
+  int32_t inner;       // inner spectator run per group element
+  int32_t pad0;
   FastDiv fd_vpr;      // / vpr
   FastDiv fd_rows;     // / rows
   FastDiv fd_bl;       // / bl
   FastDiv fd_ngroups;  // / ngroups
+  FastDiv fd_inner;    // / inner
 };
 
 // One item of a batched launch: a run of whole cubes, or one tile orbit of
@@ -109,6 +124,35 @@ struct alignas(16) BatchBlock {
   int32_t group_base;
   int32_t pad[3];
 };
+
+// Index-pair form: geometry beyond Geom (whose cube is one pair block of
+// V^d N^d inner elements, its group strides gst those of the N^d group).
+constexpr int kPairKeys = 1 << (2 * kMaxD - 1);  // (equal-neighbour mask, last-block mask)
+struct alignas(16) PairGeom {
+  int64_t pstride[kMaxD];  // element stride of partner axis m inside a pair block
+  int64_t norb;            // tile orbits per pair block: multisets of d combined blocks
+                           // (sorted combined blocks of orbit o: 16 bits each in table[o])
+  int32_t nc;              // combined blocks per axis, V * nb
+  int32_t nb;              // tile blocks per group axis
+  int32_t last_ext;        // extent of the last block of a group axis (bl if N % bl == 0)
+  int32_t flat;            // 1: bl == N, every tile is one contiguous group cube
+  int32_t tile_stride;     // LDS elements per tile slot (flat: plus the alignment shift)
+  int32_t pad;
+  FastDiv fd_nb;           // / nb
+  FastDiv fd_norb;         // / norb (norb < 2^31)
+  int32_t rep_off[kPairKeys];  // representative list of each key in the pool
+  int32_t rep_cnt[kPairKeys];
+};
+
+// Tile list of one index-pair work item, built by the workgroup in LDS.
+struct PairInfo {
+  int64_t toff[kMaxDF];   // element offset of each tile in the pair block
+  int32_t text[kMaxDF];   // packed extents
+  int32_t shift[kMaxDF];  // alignment shift of each tile's LDS copy (whole cubes)
+  int32_t sb[kMaxDF];     // LDS offset of tile sigma_r . c, sigma_r in lexicographic order
+  int32_t ntiles, rep_off, rep_cnt, pad;
+};
+
 
 // ------------------------------------------------------------------------
 // Index arithmetic shared by the kernels and by the host-side checker of the
@@ -179,6 +223,9 @@ __host__ __device__ constexpr int compose(int d, int t, int p) {
 // offset from the item's first cube (32 bits: an item spans less than 2^31
 // bytes) and LDS element offset; false if the chunk lies outside a ragged
 // tile.  toff/text: tile origins and packed extents of the item's orbit.
+// A tile row is bl * inner contiguous elements (bl group positions along
+// the last group axis, each a run of `inner` elements); l[D-1] is the
+// chunk's first element inside its row.
 template <int D, int VW>
 __host__ __device__ inline bool chunk_addr(const Geom& g, uint32_t c, int ntiles,
                                            const int32_t* toff, const int32_t* text,
@@ -207,12 +254,13 @@ __host__ __device__ inline bool chunk_addr(const Geom& g, uint32_t c, int ntiles
   if (ragged) {
     int ext = text[s];
 #pragma unroll
-    for (int m = 0; m < D; ++m) ok = ok && (l[m] < ((ext >> (8 * m)) & 255));
+    for (int m = 0; m < D - 1; ++m) ok = ok && (l[m] < ((ext >> (8 * m)) & 255));
+    ok = ok && (l[D - 1] < ((ext >> (8 * (D - 1))) & 255) * g.inner);
   }
-  int go = toff[s];
-  int lo = s * g.ts;
+  int go = toff[s] + l[D - 1];
+  int lo = s * g.ts + l[D - 1];
 #pragma unroll
-  for (int m = 0; m < D; ++m) {
+  for (int m = 0; m < D - 1; ++m) {
     go += l[m] * g.gst[m];
     lo += l[m] * g.lst[m];
   }
@@ -238,7 +286,8 @@ struct Compose {
 };
 
 // LDS element offset of sigma_R . x for representative x = l[] of a cube
-// whose LDS image starts at `base` (combine phase).
+// whose LDS image starts at `base` (combine phase; base includes the inner
+// spectator index, lst[d-1] = inner).
 template <int D, int R, int... M>
 __host__ __device__ inline int orbit_addr_one(const Geom& g, int base, int32_t slot_base_r,
                                               const int* l, std::integer_sequence<int, M...>) {
@@ -252,6 +301,50 @@ __host__ __device__ inline void orbit_addrs(const Geom& g, int base, const int32
                                             std::integer_sequence<int, R...>) {
   ((addr[R] = orbit_addr_one<D, R>(g, base, slot_base[R], l, std::make_integer_sequence<int, D>{})),
    ...);
+}
+
+// Number of non-decreasing L-tuples over m values, C(m + L - 1, L), or -1
+// if it exceeds 2^62.
+inline int64_t multiset_count(int64_t m, int L) {
+  if (L == 0) return 1;
+  if (m <= 0) return 0;
+  const int64_t x = m + L - 1;
+  int64_t r = 1;
+  for (int k = 0; k < L; ++k) {
+    if (r > ((int64_t)1 << 62) / (x - k)) return -1;
+    r = r * (x - k) / (k + 1);  // C(x, k + 1), exact
+  }
+  return r;
+}
+
+// Origin (element offset inside the pair block) and packed extents of the
+// tile with combined blocks t[0..d-1].
+__host__ __device__ inline void pair_tile(const Geom& g, const PairGeom& pg, int d, const int* t,
+                                          int64_t* off, int32_t* ext) {
+  int64_t o = 0;
+  int32_t e = 0;
+  for (int m = 0; m < d; ++m) {
+    const int a = (int)fdiv((uint32_t)t[m], pg.fd_nb);
+    const int b = t[m] - a * pg.nb;
+    o += (int64_t)a * pg.pstride[m] + (int64_t)b * g.bl * g.gst[m];
+    e |= ((b == pg.nb - 1) ? pg.last_ext : g.bl) << (8 * m);
+  }
+  *off = o;
+  *ext = e;
+}
+
+// Key of the representative list of the orbit with sorted combined blocks
+// c: bit m (m < d-1) if c[m] == c[m+1]; bit d-1+m if c[m] is a ragged last
+// block.
+__host__ __device__ inline int pair_key(const Geom& g, const PairGeom& pg, int d, const int* c) {
+  int k = 0;
+  for (int m = 0; m + 1 < d; ++m) k |= (c[m] == c[m + 1]) ? (1 << m) : 0;
+  for (int m = 0; m < d; ++m) {
+    const int a = (int)fdiv((uint32_t)c[m], pg.fd_nb);
+    const int b = c[m] - a * pg.nb;
+    if (b == pg.nb - 1 && pg.last_ext != g.bl) k |= 1 << (d - 1 + m);
+  }
+  return k;
 }
 
 }  // namespace spinsum

@@ -19,6 +19,8 @@ using spinsum::BatchItem;
 using spinsum::Geom;
 using spinsum::GroupDev;
 using spinsum::OrbitHost;
+using spinsum::PairGeom;
+using spinsum::PairInfo;
 using spinsum::Tiling;
 
 namespace spinsum {
@@ -74,20 +76,27 @@ static int64_t ipow(int64_t b, int e) {
   return r;
 }
 
-int max_vector_width(const spinsum_plan_s& P, int n) {
+// Widest vector (elements, at most 16 bytes) dividing a cube row of `row`
+// elements (N * inner).
+int max_vector_width(const spinsum_plan_s& P, int64_t row) {
   int v = 16 / elem_size(P);
-  while (v > 1 && (n % v) != 0) v /= 2;
+  while (v > 1 && (row % v) != 0) v /= 2;
   return v;
 }
 
-static int vw_for(int n, int bl, int vmax) {
+// Widest vector dividing both the cube row (n * inner elements) and the tile
+// row (bl * inner elements).
+static int vw_for(int64_t n_row, int64_t bl_row, int vmax) {
   int v = vmax;
-  while (v > 1 && ((n % v) != 0 || (bl % v) != 0)) v /= 2;
+  while (v > 1 && ((n_row % v) != 0 || (bl_row % v) != 0)) v /= 2;
   return v;
 }
 
-static void lds_strides(int d, int bl, int pad, int32_t* lst, int32_t* ts) {
-  lst[d - 1] = 1;
+// LDS strides of a tile: the last group axis has stride `inner` (each group
+// position holds a run of inner spectator elements), rows padded by one
+// element when pad is set.
+static void lds_strides(int d, int bl, int pad, int inner, int32_t* lst, int32_t* ts) {
+  lst[d - 1] = inner;
   for (int m = d - 2; m >= 0; --m) {
     int64_t s = (int64_t)lst[m + 1] * bl;
     if (pad && (s % 2) == 0) s += 1;
@@ -124,7 +133,7 @@ static int max_orbit_tiles(const SymGroup& G, int nb) {
 
 static int64_t tile_lds_bytes(const spinsum_plan_s& P, int n, int bl, int cpw, int pad) {
   int32_t lst[kMaxD], ts;
-  lds_strides(P.d, bl, pad, lst, &ts);
+  lds_strides(P.d, bl, pad, P.inner, lst, &ts);
   int nb = (n + bl - 1) / bl;
   int tiles = (bl == n) ? cpw : max_orbit_tiles(P.G, nb);
   // plus the representative copy of the pipelined kernel (at most bl^d)
@@ -150,7 +159,7 @@ spinsum_status choose_tile(const spinsum_plan_s& P, int n, int64_t ncubes, int v
   spinsum_tile_t t{};
   t.threads = 0;  // chosen once the variant is known
   t.lds_pad = pad;
-  const int64_t cube_bytes = ipow(n, d) * esz;
+  const int64_t cube_bytes = ipow(n, d) * P.inner * esz;
   if (cube_bytes <= 64 * 1024 && cube_bytes + 16 + ipow(n, d) * 4 <= budget) {
     t.bl = n;
     int cpw = (int)std::max<int64_t>(1, (8 * 1024) / std::max<int64_t>(1, cube_bytes));
@@ -172,11 +181,12 @@ spinsum_status choose_tile(const spinsum_plan_s& P, int n, int64_t ncubes, int v
     int64_t best_lds = 0;
     for (int bl = n - 1; bl >= 1; --bl) {
       if (bl > 255) continue;
-      const int row = bl * esz;
-      if (row < ps.min_row || vw_for(n, bl, vw) * esz != 16) continue;
+      const int64_t row = (int64_t)bl * P.inner * esz;
+      if (row < ps.min_row || vw_for((int64_t)n * P.inner, (int64_t)bl * P.inner, vw) * esz != 16)
+        continue;
       const int64_t lb = tile_lds_bytes(P, n, bl, 1, 0);
       if (lb > std::min(ps.cap, budget)) continue;
-      if (best == 0 || row > best * esz || (row == best * esz && lb < best_lds)) {
+      if (best == 0 || bl > best || (bl == best && lb < best_lds)) {
         best = bl;
         best_lds = lb;
       }
@@ -189,7 +199,7 @@ spinsum_status choose_tile(const spinsum_plan_s& P, int n, int64_t ncubes, int v
   }
   for (int bl = n - 1; bl >= 1; --bl) {
     if (bl > 255) continue;
-    if (vw > 1 && bl % vw != 0) continue;
+    if (vw > 1 && ((int64_t)bl * P.inner) % vw != 0) continue;
     if (tile_lds_bytes(P, n, bl, 1, pad) > budget) continue;
     t.bl = bl;
     *tile = t;
@@ -206,6 +216,8 @@ spinsum_status build_tiling(const spinsum_plan_s& P, int n, int64_t ncubes,
   if (n <= 0 || ncubes <= 0) {
     T.g.ncubes = std::max<int64_t>(0, ncubes);
     T.g.n = n;
+    T.g.inner = std::max(1, P.inner);
+    T.g.fd_inner = make_fastdiv((uint32_t)T.g.inner);
     *out = T;
     return SPINSUM_OK;
   }
@@ -213,10 +225,11 @@ spinsum_status build_tiling(const spinsum_plan_s& P, int n, int64_t ncubes,
   if (bl > 255) return SPINSUM_ERR_UNSUPPORTED;
   const int pad = tile.lds_pad ? 1 : 0;
   const int cpw = (bl == n) ? std::max(1, tile.cubes_per_wg) : 1;
-  const int64_t cube_elems = ipow(n, d);
+  const int inner = P.inner;
+  const int64_t cube_elems = ipow(n, d) * inner;
   if (cube_elems * elem_size(P) >= (1ll << 31)) return SPINSUM_ERR_UNSUPPORTED;
   const int nb = (n + bl - 1) / bl;
-  const int vw = vw_for(n, bl, vmax);
+  const int vw = vw_for((int64_t)n * inner, (int64_t)bl * inner, vmax);
 
   Geom& g = T.g;
   g.cube_elems = cube_elems;
@@ -225,14 +238,17 @@ spinsum_status build_tiling(const spinsum_plan_s& P, int n, int64_t ncubes,
   g.bl = bl;
   g.cpw = cpw;
   for (int m = 0; m < kMaxD; ++m) g.gst[m] = 0;
-  for (int m = 0; m < d; ++m) g.gst[m] = (int32_t)ipow(n, d - 1 - m);
-  lds_strides(d, bl, pad, g.lst, &g.ts);
+  for (int m = 0; m < d; ++m) g.gst[m] = (int32_t)(ipow(n, d - 1 - m) * inner);
+  lds_strides(d, bl, pad, inner, g.lst, &g.ts);
   g.cube_lds = g.ts;
   g.rows = (int32_t)ipow(bl, d - 1);
-  g.vpr = bl / vw;
+  g.vpr = bl * inner / vw;
+  g.inner = inner;
+  g.pad0 = 0;
   g.fd_vpr = make_fastdiv((uint32_t)g.vpr);
   g.fd_rows = make_fastdiv((uint32_t)g.rows);
   g.fd_bl = make_fastdiv((uint32_t)bl);
+  g.fd_inner = make_fastdiv((uint32_t)inner);
 
   // 1. tile orbits: one per sorted block tuple B (the loop nest of Alg. 5a)
   std::map<std::vector<int>, std::pair<int, int>> rep_index;  // shared representative lists
@@ -317,8 +333,10 @@ spinsum_status build_tiling(const spinsum_plan_s& P, int n, int64_t ncubes,
   // together anyway, the loop-nest order is 2% faster.)
   if (T.orbits.size() > 128) {
     const int line = 128;
-    const int row = bl * elem_size(P);
-    const int s = (row < line && line % row == 0 && (n * elem_size(P)) % line == 0) ? line / row : 1;
+    const int64_t row = (int64_t)bl * inner * elem_size(P);
+    const int s = (row < line && line % row == 0 && ((int64_t)n * inner * elem_size(P)) % line == 0)
+                      ? (int)(line / row)
+                      : 1;
     if (s > 1) {
       auto key = [&](const OrbitHost& o) {
         std::vector<int> k(d);
@@ -466,7 +484,12 @@ spinsum_status upload_tables(spinsum_plan_s* P) {
     st = upload(P, &P->d_mats, all.data(), all.size());
   }
   if (st != SPINSUM_OK) return st;
-  if (!P->batched) {
+  if (P->pair) {
+    st = upload(P, &P->d_orbits, P->pair_orbits.data(), P->pair_orbits.size());
+    if (st != SPINSUM_OK) return st;
+    st = upload(P, &P->d_reps, P->T.reps.data(), P->T.reps.size());
+    if (st != SPINSUM_OK) return st;
+  } else if (!P->batched) {
     st = upload(P, &P->d_orbits, P->T.groups.data(), P->T.groups.size());
     if (st != SPINSUM_OK) return st;
     st = upload(P, &P->d_reps, P->T.reps.data(), P->T.reps.size());
@@ -582,9 +605,204 @@ static void query_device(spinsum_plan_s* P) {
   (void)hipGetLastError();
 }
 
-static spinsum_status apply_tile(spinsum_plan_s* P, const spinsum_tile_t* req) {
+// ---------------------------------------------------------- index-pair form
+// Tensor [outer.., V x d partners, N x d group, inner..], term p applied to
+// both index sets.  Axis m carries the pair (a_m, i_m); with the group cut
+// into nb blocks of edge bl, a tile is one combined block c_m = a_m * nb + b_m
+// per axis: the bl^d group positions of block tuple b under the partner
+// tuple a.  A permutation maps tile c to tile sigma . c and element l of it
+// to sigma . l, exactly as in the group form, so the tile orbits are the
+// multisets of d combined blocks and the element orbits inside a tile are
+// those of its equal-block pattern (Alg. 5a/5b on combined indices).
+
+// LDS bytes the index-pair kernel needs for tile edge bl (0 if bl is not
+// usable: a partial cube whose rows are not whole 16-byte chunks).
+static int64_t pair_lds_bytes(const spinsum_plan_s& P, int bl, int* vw_out) {
+  const int n = P.n, d = P.d, esz = elem_size(P), inner = P.inner;
+  const bool flat = (bl == n);
+  int vw = vw_for((int64_t)n * inner, (int64_t)bl * inner, 16 / esz);
+  if (!flat && vw * esz != 16) return 0;
+  const int nb = (n + bl - 1) / bl;
+  const int64_t nc = (int64_t)P.pv * nb;
+  const int tiles = max_orbit_tiles(P.G, (int)std::min<int64_t>(nc, 64));
+  int64_t ts = ipow(bl, d) * inner;
+  if (flat) ts = (ts + 16 / esz + 16 / esz - 1) / (16 / esz) * (16 / esz);
+  if (vw_out) *vw_out = vw;
+  return ((int64_t)tiles * ts * esz + 15) / 16 * 16 + ipow(bl, d) * 4 +
+         (int64_t)sizeof(PairInfo);
+}
+
+// Default tile edge: the largest usable bl whose orbit fits 32 KiB of LDS,
+// else 64 KiB, else the LDS of a CU (the rules of the group form).
+static spinsum_status choose_pair_tile(const spinsum_plan_s& P, spinsum_tile_t* tile) {
+  const int64_t budget = P.lds_limit - 512;
+  for (int64_t cap : {(int64_t)32 * 1024, (int64_t)64 * 1024, budget}) {
+    for (int bl = std::min(P.n, 255); bl >= 1; --bl) {
+      const int64_t b = pair_lds_bytes(P, bl, nullptr);
+      if (b > 0 && b <= std::min(cap, budget)) {
+        spinsum_tile_t t{};
+        t.bl = bl;
+        t.cubes_per_wg = 1;
+        t.variant = SPINSUM_VARIANT_DIRECT_LDS;
+        *tile = t;
+        return SPINSUM_OK;
+      }
+    }
+  }
+  return SPINSUM_ERR_UNSUPPORTED;
+}
+
+static spinsum_status build_pair_tiling(spinsum_plan_s* P, const spinsum_tile_t& tile) {
+  const int n = P->n, d = P->d, inner = P->inner, esz = elem_size(*P);
+  const int64_t V = P->pv;
+  Tiling T;
+  PairGeom pg;
+  std::memset(&pg, 0, sizeof(pg));
+  std::vector<uint64_t> orbits;
+  const int bl = tile.bl <= 0 ? n : std::min(tile.bl, n);
+  if (bl < 1 || bl > 255) return SPINSUM_ERR_UNSUPPORTED;
+  int vw = 1;
+  const int64_t lds_bytes = pair_lds_bytes(*P, bl, &vw);
+  if (lds_bytes == 0) return SPINSUM_ERR_UNSUPPORTED;
+  const bool flat = (bl == n);
+  const int nb = (n + bl - 1) / bl;
+  const int64_t nc = V * nb;
+  if (nc > 16000) return SPINSUM_ERR_UNSUPPORTED;  // 16-bit combined blocks
+  Geom& g = T.g;
+  g.ncubes = P->ncubes;
+  g.n = n;
+  g.bl = bl;
+  g.cpw = 1;
+  g.ngroups = 1;
+  for (int m = 0; m < kMaxD; ++m) g.gst[m] = 0;
+  for (int m = 0; m < d; ++m) g.gst[m] = (int32_t)(ipow(n, d - 1 - m) * inner);
+  lds_strides(d, bl, 0, inner, g.lst, &g.ts);
+  g.cube_lds = g.ts;
+  g.rows = (int32_t)ipow(bl, d - 1);
+  g.vpr = flat ? 1 : bl * inner / vw;
+  g.inner = inner;
+  g.fd_vpr = make_fastdiv((uint32_t)g.vpr);
+  g.fd_rows = make_fastdiv((uint32_t)g.rows);
+  g.fd_bl = make_fastdiv((uint32_t)bl);
+  g.fd_ngroups = make_fastdiv(1);
+  g.fd_inner = make_fastdiv((uint32_t)inner);
+  const int64_t group_elems = ipow(n, d) * inner;
+  int64_t block = group_elems;
+  for (int m = 0; m < d; ++m) {
+    if (block > ((int64_t)1 << 62) / V) return SPINSUM_ERR_UNSUPPORTED;
+    block *= V;
+  }
+  g.cube_elems = block;
+  for (int m = 0; m < d; ++m) pg.pstride[m] = ipow(V, d - 1 - m) * group_elems;
+  pg.nc = (int32_t)nc;
+  pg.nb = nb;
+  pg.last_ext = n - (nb - 1) * bl;
+  pg.flat = flat ? 1 : 0;
+  pg.tile_stride = flat ? (int32_t)((g.ts + 16 / esz + 16 / esz - 1) / (16 / esz) * (16 / esz)) : g.ts;
+  pg.fd_nb = make_fastdiv((uint32_t)nb);
+  pg.norb = multiset_count(nc, d);
+  if (pg.norb <= 0 || pg.norb >= (1ll << 31)) return SPINSUM_ERR_UNSUPPORTED;
+  pg.fd_norb = make_fastdiv((uint32_t)pg.norb);
+  T.nitems = P->ncubes * pg.norb;
+  if (T.nitems >= (1ll << 31) - 8) return SPINSUM_ERR_UNSUPPORTED;
+  // the orbit table: sorted combined-block tuples in lexicographic order
+  orbits.reserve((size_t)pg.norb);
+  {
+    std::vector<int> c(d, 0);
+    while (true) {
+      uint64_t pk = 0;
+      for (int m = 0; m < d; ++m) pk |= (uint64_t)c[m] << (16 * m);
+      orbits.push_back(pk);
+      int m = d - 1;
+      while (m >= 0 && c[m] == nc - 1) --m;
+      if (m < 0) break;
+      c[m]++;
+      for (int j = m + 1; j < d; ++j) c[j] = c[m];
+    }
+  }
+  if ((int64_t)orbits.size() != pg.norb) return SPINSUM_ERR_UNSUPPORTED;
+  // representative lists per key (equal-neighbour mask, ragged-block mask)
+  for (int key = 0; key < (1 << (2 * d - 1)); ++key) {
+    int ext[kMaxD];
+    bool consistent = true;
+    for (int m = 0; m < d; ++m) ext[m] = ((key >> (d - 1 + m)) & 1) ? pg.last_ext : bl;
+    for (int m = 0; m + 1 < d; ++m)
+      if (((key >> m) & 1) && ext[m] != ext[m + 1]) consistent = false;
+    pg.rep_off[key] = (int32_t)T.reps.size();
+    if (consistent) {
+      int64_t box = 1;
+      for (int m = 0; m < d; ++m) box *= ext[m];
+      std::vector<int> l(d, 0);
+      for (int64_t e = 0; e < box; ++e) {
+        int64_t rem = e;
+        for (int m = d - 1; m >= 0; --m) {
+          l[m] = (int)(rem % ext[m]);
+          rem /= ext[m];
+        }
+        bool ok = true;
+        for (int m = 0; m + 1 < d; ++m)
+          if (((key >> m) & 1) && l[m] > l[m + 1]) ok = false;
+        if (!ok) continue;
+        uint32_t pk = 0;
+        for (int m = 0; m < d; ++m) pk |= (uint32_t)l[m] << (8 * m);
+        T.reps.push_back(pk);
+      }
+    }
+    pg.rep_cnt[key] = (int32_t)T.reps.size() - pg.rep_off[key];
+    T.max_rep_cnt = std::max(T.max_rep_cnt, pg.rep_cnt[key]);
+  }
+  T.nb = nb;
+  T.vw = vw;
+  T.ragged = (pg.last_ext != bl) ? 1 : 0;
+  T.max_orbit_tiles = max_orbit_tiles(P->G, (int)std::min<int64_t>(nc, 64));
+  T.max_tiles = T.max_orbit_tiles;
+  T.lds_elems = (int64_t)T.max_tiles * pg.tile_stride;
+  T.chunks_per_thread = (int)(((int64_t)T.max_tiles * g.rows * g.vpr + 255) / 256);
+  T.fits = (lds_bytes <= P->lds_limit) ? 1 : 0;
+  if (!T.fits && !(P->flags & SPINSUM_FLAG_HOST_ONLY)) return SPINSUM_ERR_UNSUPPORTED;
+  P->T = std::move(T);
+  P->pg = pg;
+  P->pair_orbits = std::move(orbits);
+  return SPINSUM_OK;
+}
+
+static spinsum_status apply_pair_tile(spinsum_plan_s* P, const spinsum_tile_t* req) {
   spinsum_tile_t t{};
-  const int vmax = max_vector_width(*P, std::max(1, P->n));
+  if (req && req->bl > 0) {
+    t = *req;
+    if (t.threads < 0) t.threads = 0;
+  } else if (P->ncubes > 0 && P->elems > 0) {
+    spinsum_status st = choose_pair_tile(*P, &t);
+    if (st != SPINSUM_OK) return st;
+  } else {
+    t.bl = std::max(1, P->n);
+  }
+  if (t.threads != 0 && t.threads != 256 && t.threads != 512 && t.threads != 1024)
+    return SPINSUM_ERR_UNSUPPORTED;
+  if (t.variant != SPINSUM_VARIANT_AUTO && t.variant != SPINSUM_VARIANT_DIRECT_LDS)
+    return SPINSUM_ERR_UNSUPPORTED;
+  if (P->flags & SPINSUM_FLAG_NO_DIRECT_LDS) return SPINSUM_ERR_UNSUPPORTED;
+  t.variant = SPINSUM_VARIANT_DIRECT_LDS;
+  t.lds_pad = 0;
+  t.cubes_per_wg = 1;
+  t.item_tiles = 0;
+  if (P->ncubes > 0 && P->elems > 0) {
+    spinsum_status st = build_pair_tiling(P, t);
+    if (st != SPINSUM_OK) return st;
+  }
+  if (t.threads == 0) {
+    const int64_t wg = pair_lds_bytes(*P, P->T.g.bl > 0 ? P->T.g.bl : std::max(1, P->n), nullptr);
+    const int64_t per_cu = std::max<int64_t>(1, P->lds_limit / std::max<int64_t>(1, wg));
+    t.threads = per_cu >= 4 ? 256 : per_cu >= 2 ? 512 : 1024;
+  }
+  P->tile = t;
+  return SPINSUM_OK;
+}
+
+static spinsum_status apply_tile(spinsum_plan_s* P, const spinsum_tile_t* req) {
+  if (P->pair) return apply_pair_tile(P, req);
+  spinsum_tile_t t{};
+  const int vmax = max_vector_width(*P, (int64_t)std::max(1, P->n) * P->inner);
   if (req && req->bl > 0) {
     t = *req;
     if (t.threads < 0) t.threads = 0;
@@ -602,7 +820,9 @@ static spinsum_status apply_tile(spinsum_plan_s* P, const spinsum_tile_t* req) {
   // for whole cubes, which the one-shot kernel copies as one contiguous run
   const int bl = t.bl <= 0 ? std::max(1, P->n) : std::min(t.bl, std::max(1, P->n));
   const bool no_direct = (P->flags & SPINSUM_FLAG_NO_DIRECT_LDS) != 0;
-  const bool rows_ok = vw_for(std::max(1, P->n), bl, vmax) * elem_size(*P) == 16 && !no_direct;
+  const bool rows_ok =
+      vw_for((int64_t)std::max(1, P->n) * P->inner, (int64_t)bl * P->inner, vmax) * elem_size(*P) == 16 &&
+      !no_direct;
   const bool direct_ok = rows_ok || (bl >= P->n && !no_direct);
   if (t.variant == SPINSUM_VARIANT_AUTO)
     t.variant = direct_ok ? SPINSUM_VARIANT_DIRECT_LDS : SPINSUM_VARIANT_REG_ONESHOT;
@@ -647,23 +867,35 @@ static spinsum_status common_checks(int d, spinsum_dtype dtype, int inplace) {
   return SPINSUM_OK;
 }
 
+// Group extent N, outer spectator cubes (product of the dims before the
+// group) and inner spectator run (product of the dims after it; 1 if none).
+// An empty inner run makes the tensor empty (no cubes).
 static spinsum_status shape_info(int ndim, const int64_t* extents, int group_first, int d,
-                                 int* n, int64_t* ncubes) {
+                                 int* n, int64_t* ncubes, int* inner) {
   if (ndim < 1 || ndim > 64 || extents == nullptr) return SPINSUM_ERR_INVALID_ARG;
   if (group_first < 0 || group_first + d > ndim) return SPINSUM_ERR_INVALID_ARG;
   for (int k = 0; k < ndim; ++k)
     if (extents[k] < 0) return SPINSUM_ERR_INVALID_ARG;
   for (int m = 1; m < d; ++m)
     if (extents[group_first + m] != extents[group_first]) return SPINSUM_ERR_EXTENT_MISMATCH;
-  if (group_first + d != ndim) return SPINSUM_ERR_UNSUPPORTED;  // inner spectators
   if (extents[group_first] > 255 * 255) return SPINSUM_ERR_UNSUPPORTED;
   *n = (int)extents[group_first];
+  int64_t r = 1;
+  for (int k = group_first + d; k < ndim; ++k) {
+    if (extents[k] > 0 && r > (1ll << 31) / extents[k]) return SPINSUM_ERR_UNSUPPORTED;
+    r *= extents[k];
+  }
   int64_t c = 1;
   for (int k = 0; k < group_first; ++k) {
     if (extents[k] > 0 && c > (1ll << 62) / extents[k]) return SPINSUM_ERR_UNSUPPORTED;
     c *= extents[k];
   }
+  if (r == 0) {
+    r = 1;
+    c = 0;
+  }
   *ncubes = c;
+  *inner = (int)r;
   return SPINSUM_OK;
 }
 
@@ -675,14 +907,37 @@ extern "C" spinsum_status spinsum_plan(spinsum_plan_t* plan, int ndim, const int
   *plan = nullptr;
   spinsum_status st = common_checks(d, dtype, inplace);
   if (st != SPINSUM_OK) return st;
-  int n = 0;
+  int n = 0, inner = 1;
   int64_t ncubes = 0;
-  st = shape_info(ndim, extents, group_first, d, &n, &ncubes);
+  st = shape_info(ndim, extents, group_first, d, &n, &ncubes, &inner);
   if (st != SPINSUM_OK) return st;
+  // index-pair form: the d dims before the group are its partners
+  bool pair = false;
+  int64_t V = 1;
+  if (flags & SPINSUM_FLAG_INDEX_PAIRS) {
+    if (group_first < d) return SPINSUM_ERR_INVALID_ARG;
+    V = extents[group_first - d];
+    for (int m = 1; m < d; ++m)
+      if (extents[group_first - d + m] != V) return SPINSUM_ERR_EXTENT_MISMATCH;
+    if (V > 1 && n == 1) {
+      // a group of extent 1: the ordinary summation over the partners
+      st = shape_info(ndim, extents, group_first - d, d, &n, &ncubes, &inner);
+      if (st != SPINSUM_OK) return st;
+    } else if (V > 1 && n > 1) {
+      if (V > 16000) return SPINSUM_ERR_UNSUPPORTED;
+      pair = true;
+      ncubes = 1;
+      for (int k = 0; k < group_first - d; ++k) ncubes *= extents[k];
+    }
+    // V <= 1 or an empty group: the ordinary summation over the group
+  }
   spinsum_plan_s* P = new (std::nothrow) spinsum_plan_s();
   if (!P) return SPINSUM_ERR_OUT_OF_MEMORY;
   P->d = d;
   P->n = n;
+  P->inner = inner;
+  P->pair = pair;
+  P->pv = (int)V;
   P->ndim = ndim;
   P->extents.assign(extents, extents + ndim);
   P->ncubes = ncubes;
@@ -690,11 +945,19 @@ extern "C" spinsum_status spinsum_plan(spinsum_plan_t* plan, int ndim, const int
   P->inplace = inplace;
   P->flags = flags;
   P->G.init(d);
-  if (n > 0 && ipow(n, d) >= (1ll << 31)) {
+  if (n > 0 && ipow(n, d) * inner >= (1ll << 31)) {
     delete P;
     return SPINSUM_ERR_UNSUPPORTED;
   }
-  P->elems = ncubes * ipow(n, d);
+  P->elems = ncubes * ipow(n, d) * inner;
+  if (pair) {
+    const int64_t vd = ipow(V, d);
+    if (P->elems > 0 && vd > ((int64_t)1 << 62) / P->elems) {
+      delete P;
+      return SPINSUM_ERR_UNSUPPORTED;
+    }
+    P->elems *= vd;
+  }
   st = set_terms(P, nstages, nterms, perms, alpha);
   if (st == SPINSUM_OK) {
     query_device(P);
@@ -725,7 +988,8 @@ extern "C" spinsum_status spinsum_plan_batched(spinsum_plan_t* plan, int nblocks
   std::vector<int64_t> cs(nblocks);
   for (int b = 0; b < nblocks; ++b) {
     if (ndims[b] < d) return SPINSUM_ERR_INVALID_ARG;
-    st = shape_info(ndims[b], extents[b], ndims[b] - d, d, &ns[b], &cs[b]);
+    int inner_b = 1;
+    st = shape_info(ndims[b], extents[b], ndims[b] - d, d, &ns[b], &cs[b], &inner_b);
     if (st != SPINSUM_OK) return st;
     if (ns[b] > 0 && ipow(ns[b], d) >= (1ll << 31)) return SPINSUM_ERR_UNSUPPORTED;
   }
@@ -853,11 +1117,15 @@ extern "C" spinsum_status spinsum_plan_set_tile(spinsum_plan_t P, const spinsum_
   if (tile->bl < 0 || tile->cubes_per_wg < 0) return SPINSUM_ERR_INVALID_ARG;
   spinsum_tile_t keep = P->tile;
   Tiling keepT = P->T;
+  const PairGeom keep_pg = P->pg;
+  const std::vector<uint64_t> keep_orbits = P->pair_orbits;
   spinsum_status st = apply_tile(P, tile);
   if (st == SPINSUM_OK) st = upload_tables(P);
   if (st != SPINSUM_OK) {
     P->tile = keep;
     P->T = keepT;
+    P->pg = keep_pg;
+    P->pair_orbits = keep_orbits;
     spinsum_status st2 = upload_tables(P);
     (void)st2;
   }
@@ -879,6 +1147,8 @@ extern "C" spinsum_status spinsum_plan_get_info(spinsum_plan_t P, spinsum_plan_i
   info->dtype = P->dtype;
   info->inplace = P->inplace;
   info->threads = P->batched ? 256 : P->tile.threads;
+  info->inner = P->inner;
+  info->pair_extent = P->pair ? P->pv : 0;
   if (!P->batched) {
     info->bl = P->T.g.bl;
     info->variant = P->tile.variant;
@@ -896,6 +1166,10 @@ extern "C" spinsum_status spinsum_plan_get_info(spinsum_plan_t P, spinsum_plan_i
     info->fits_lds = P->T.fits;
     info->rep_lds_bytes = (int64_t)P->T.max_rep_cnt * 4;
     info->chunks_per_thread = P->T.chunks_per_thread;
+    if (P->pair) {
+      info->norbits = (int)std::min<int64_t>(P->pg.norb, INT32_MAX);
+      info->items_per_cube = info->norbits;
+    }
   } else {
     info->lds_bytes = P->batch_lds_elems * elem_size(*P);
     info->nitems = (int64_t)P->items.size();
@@ -948,9 +1222,12 @@ static bool check_combine(const Tiling& T, const GroupDev& gd, int ncub,
       int64_t o0 = gd.tile_off[gd.slot_base[k][0] / g.ts];
       for (int m = 0; m < d; ++m) x0[m] = (int)((o0 / g.gst[m]) % g.n);
     }
-    for (uint32_t i = 0; i < nrep; ++i) {
-      uint32_t ci = (ncub == 1) ? 0u : fdiv(i, gd.fd_rep[k]);
-      uint32_t ri = i - ci * (uint32_t)gd.rep_cnt[k];
+    for (uint32_t i = 0; i < nrep * (uint32_t)g.inner; ++i) {
+      // unit -> (cube, representative, inner index), inner index fastest
+      const uint32_t j = fdiv(i, g.fd_inner);
+      const uint32_t si = i - j * (uint32_t)g.inner;
+      uint32_t ci = (ncub == 1) ? 0u : fdiv(j, gd.fd_rep[k]);
+      uint32_t ri = j - ci * (uint32_t)gd.rep_cnt[k];
       if (ci >= (uint32_t)ncub || ri >= (uint32_t)gd.rep_cnt[k]) { *why = "bad representative index"; return false; }
       uint32_t pk = T.reps[gd.rep_off[k] + ri];
       int l[D];
@@ -958,12 +1235,12 @@ static bool check_combine(const Tiling& T, const GroupDev& gd, int ncub,
       int x[D];
       for (int m = 0; m < d; ++m) x[m] = x0[m] + l[m];
       int addrs[kMaxDF];
-      orbit_addrs<D>(g, (int)ci * g.cube_lds, gd.slot_base[k], l, addrs,
+      orbit_addrs<D>(g, (int)ci * g.cube_lds + (int)si, gd.slot_base[k], l, addrs,
                      std::make_integer_sequence<int, Fact<D>()>{});
       for (int r = 0; r < Fact<D>(); ++r) {
         int a = addrs[r] + shift;
         if (a < 0 || a >= T.lds_elems) { *why = "combine address out of bounds"; return false; }
-        int64_t want = (int64_t)ci * g.cube_elems;
+        int64_t want = (int64_t)ci * g.cube_elems + si;
         for (int m = 0; m < d; ++m) want += (int64_t)x[lex_perm(D, r, m)] * g.gst[m];
         if (lds_of[a] != want) { *why = "combine address does not hold sigma . x"; return false; }
       }
@@ -1010,7 +1287,8 @@ static bool emulate_item(const Tiling& T, const GroupDev& gd, int ncub, std::str
           off += (rem % ext[m]) * g.gst[m];
           rem /= ext[m];
         }
-        if (loaded[off] != 1) { *why = "tile element not loaded exactly once"; return false; }
+        for (int si = 0; si < g.inner; ++si)
+          if (loaded[off + si] != 1) { *why = "tile element not loaded exactly once"; return false; }
       }
     }
   return check_combine<D>(T, gd, ncub, lds_of, 0, why);
@@ -1053,6 +1331,108 @@ static bool emulate_all(const Tiling& T, std::string* why, bool flat, int esz) {
   return true;
 }
 
+// Index-pair form: replays every work item of one pair block -- the tile
+// list in first-sigma order, the loads (contiguous copies of whole cubes at
+// varied alignment shifts, else the 16-byte row chunks of chunk_addr), the
+// combine addresses -- and checks that the LDS slot read for sigma holds
+// element sigma . x and that every element of the block belongs to exactly
+// one element orbit.
+template <int D, int VW>
+static bool check_pair(const spinsum_plan_s& P, std::string* why) {
+  constexpr int DF = Fact<D>();
+  const Tiling& T = P.T;
+  const Geom& g = T.g;
+  const PairGeom& pg = P.pg;
+  const int64_t blk = g.cube_elems;
+  if (blk > (1 << 24)) { *why = "pair block too large for the checker"; return false; }
+  const int64_t tile_elems = (int64_t)g.rows * g.bl * g.inner;
+  std::vector<int64_t> owner((size_t)blk, -1);
+  int64_t next_id = 0;
+  for (int64_t o = 0; o < pg.norb; ++o) {
+    int c[D];
+    for (int m = 0; m < D; ++m) c[m] = (int)((P.pair_orbits[o] >> (16 * m)) & 0xFFFFu);
+    for (int m = 0; m + 1 < D; ++m)
+      if (c[m] > c[m + 1] || c[D - 1] >= pg.nc) { *why = "orbit table not sorted"; return false; }
+    int slot[DF], nt = 0;
+    int64_t toff[DF];
+    int32_t text[DF];
+    uint64_t keys[DF];
+    for (int r = 0; r < DF; ++r) {
+      int t[D];
+      uint64_t key = 0;
+      for (int m = 0; m < D; ++m) {
+        t[m] = c[lex_perm(D, r, m)];
+        key |= (uint64_t)t[m] << (16 * m);
+      }
+      int s = -1;
+      for (int j = 0; j < nt; ++j)
+        if (keys[j] == key) s = j;
+      if (s < 0) {
+        pair_tile(g, pg, D, t, &toff[nt], &text[nt]);
+        keys[nt] = key;
+        s = nt++;
+      }
+      slot[r] = s;
+    }
+    if (nt > T.max_tiles) { *why = "orbit has more tiles than planned"; return false; }
+    std::vector<int64_t> lds_of((size_t)T.lds_elems, -1);
+    int shift[DF];
+    for (int t = 0; t < nt; ++t) {
+      const int64_t base = (int64_t)t * pg.tile_stride;
+      shift[t] = pg.flat ? (int)((t + o) % VW) : 0;
+      if (pg.flat) {
+        if (shift[t] + tile_elems > pg.tile_stride) { *why = "tile copy exceeds its slot"; return false; }
+        if (toff[t] < 0 || toff[t] + tile_elems > blk) { *why = "tile outside the pair block"; return false; }
+        for (int64_t e = 0; e < tile_elems; ++e) lds_of[base + shift[t] + e] = toff[t] + e;
+        continue;
+      }
+      const int32_t zero = 0;
+      int64_t loaded = 0;
+      for (uint32_t ch = 0; ch < (uint32_t)(g.rows * g.vpr); ++ch) {
+        int go = 0, lo = 0;
+        if (!chunk_addr<D, VW>(g, ch, 1, &zero, &text[t], true, &go, &lo)) continue;
+        if (lo != (int)ch * VW) { *why = "LDS chunk not in chunk order"; return false; }
+        if (toff[t] + go < 0 || toff[t] + go + VW > blk) { *why = "global chunk out of bounds"; return false; }
+        for (int k = 0; k < VW; ++k) {
+          if (lds_of[base + lo + k] != -1) { *why = "LDS slot written twice"; return false; }
+          lds_of[base + lo + k] = toff[t] + go + k;
+        }
+        loaded += VW;
+      }
+      int64_t want = g.inner;
+      for (int m = 0; m < D; ++m) want *= (text[t] >> (8 * m)) & 255;
+      if (loaded != want) { *why = "tile not loaded exactly once"; return false; }
+    }
+    const int key = pair_key(g, pg, D, c);
+    const int cnt = pg.rep_cnt[key];
+    if (cnt <= 0) { *why = "empty representative list"; return false; }
+    int32_t sb[DF];
+    for (int r = 0; r < DF; ++r) sb[r] = slot[r] * pg.tile_stride + shift[slot[r]];
+    for (int i = 0; i < cnt; ++i) {
+      const uint32_t pk = T.reps[pg.rep_off[key] + i];
+      int l[D];
+      for (int m = 0; m < D; ++m) l[m] = (int)((pk >> (8 * m)) & 255u);
+      for (int si = 0; si < g.inner; ++si) {
+        int addrs[DF];
+        orbit_addrs<D>(g, si, sb, l, addrs, std::make_integer_sequence<int, DF>{});
+        const int64_t id = next_id++;
+        for (int r = 0; r < DF; ++r) {
+          const int a = addrs[r];
+          if (a < 0 || a >= T.lds_elems) { *why = "combine address out of bounds"; return false; }
+          int64_t want = toff[slot[r]] + si;
+          for (int m = 0; m < D; ++m) want += (int64_t)l[lex_perm(D, r, m)] * g.gst[m];
+          if (lds_of[a] != want) { *why = "combine address does not hold sigma . x"; return false; }
+          if (owner[want] != -1 && owner[want] != id) { *why = "element owned twice"; return false; }
+          owner[want] = id;
+        }
+      }
+    }
+  }
+  for (int64_t e = 0; e < blk; ++e)
+    if (owner[e] == -1) { *why = "element not owned"; return false; }
+  return true;
+}
+
 extern "C" spinsum_status spinsum_plan_check_ownership(spinsum_plan_t P, int block, const char** why) {
   static thread_local std::string msg;
   auto fail = [&](const std::string& m) {
@@ -1066,11 +1446,21 @@ extern "C" spinsum_status spinsum_plan_check_ownership(spinsum_plan_t P, int blo
   const Tiling& T = P->batched ? P->btil[block] : P->T;
   const Geom& g = T.g;
   if (g.n <= 0 || g.ncubes <= 0) return SPINSUM_OK;
+  if (P->pair) {
+    std::string w;
+    const int vw = 16 / elem_size(*P);
+    bool ok;
+    if (P->d == 2) ok = (vw == 2) ? check_pair<2, 2>(*P, &w) : check_pair<2, 4>(*P, &w);
+    else if (P->d == 3) ok = (vw == 2) ? check_pair<3, 2>(*P, &w) : check_pair<3, 4>(*P, &w);
+    else ok = (vw == 2) ? check_pair<4, 2>(*P, &w) : check_pair<4, 4>(*P, &w);
+    if (!ok) return fail(w);
+    return SPINSUM_OK;
+  }
   const int d = P->d, df = P->G.df, n = g.n, bl = g.bl;
   // every orbit of the cube belongs to exactly one work item
   std::vector<int> orbit_in(T.orbits.size(), 0);
   std::vector<int64_t> owner((size_t)g.cube_elems, -1);
-  int64_t orbit_id = 0;
+  int64_t next_id = 0;  // one per element orbit (representative, inner index)
   for (const GroupDev& gd : T.groups) {
     int tiles = 0;
     for (int k = 0; k < gd.norb; ++k) {
@@ -1104,15 +1494,16 @@ extern "C" spinsum_status spinsum_plan_check_ownership(spinsum_plan_t P, int blo
           if (l >= std::min(bl, n - B[m] * bl)) return fail("representative outside its tile");
           x[m] = B[m] * bl + l;
         }
-        int64_t id = orbit_id * (1ll << 32) + i;
-        for (int r = 0; r < df; ++r) {
-          int64_t e = 0;
-          for (int m = 0; m < d; ++m) e += (int64_t)x[P->G.p[r][m]] * g.gst[m];
-          if (owner[e] != -1 && owner[e] != id) return fail("element owned twice");
-          owner[e] = id;
+        for (int si = 0; si < g.inner; ++si) {
+          const int64_t id = next_id++;
+          for (int r = 0; r < df; ++r) {
+            int64_t e = si;
+            for (int m = 0; m < d; ++m) e += (int64_t)x[P->G.p[r][m]] * g.gst[m];
+            if (owner[e] != -1 && owner[e] != id) return fail("element owned twice");
+            owner[e] = id;
+          }
         }
       }
-      ++orbit_id;
     }
     if (tiles != gd.ntiles) return fail("work item tile count");
   }

@@ -55,6 +55,7 @@ struct Tiling {
 struct spinsum_plan_s {
   // problem
   int d = 0, n = 0;
+  int inner = 1;  // elements of the inner spectators (dims after the group)
   int ndim = 0;
   std::vector<int64_t> extents;
   int64_t ncubes = 0, elems = 0;
@@ -69,6 +70,14 @@ struct spinsum_plan_s {
   // tiling (single tensor)
   spinsum_tile_t tile{};
   spinsum::Tiling T;
+
+  // index-pair form (SPINSUM_FLAG_INDEX_PAIRS): T.g describes one pair
+  // block, T.reps holds the representative pool, T.nb / T.vw / T.ragged /
+  // T.max_tiles / T.max_rep_cnt / T.lds_elems / T.nitems as for tile orbits
+  bool pair = false;
+  int pv = 0;                             // partner extent V
+  spinsum::PairGeom pg{};
+  std::vector<uint64_t> pair_orbits;      // sorted combined blocks per tile orbit
 
   // batch
   bool batched = false;
@@ -107,7 +116,7 @@ spinsum_status build_tiling(const spinsum_plan_s& P, int n, int64_t ncubes,
                             const spinsum_tile_t& tile, int vw, Tiling* out);
 spinsum_status choose_tile(const spinsum_plan_s& P, int n, int64_t ncubes, int vw,
                            spinsum_tile_t* tile);
-int max_vector_width(const spinsum_plan_s& P, int n);
+int max_vector_width(const spinsum_plan_s& P, int64_t row);
 spinsum_status upload_tables(spinsum_plan_s* P);
 void free_device(spinsum_plan_s* P);
 int elem_size(const spinsum_plan_s& P);

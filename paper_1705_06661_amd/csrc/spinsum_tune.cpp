@@ -105,6 +105,7 @@ extern "C" spinsum_status spinsum_autotune(spinsum_plan_t P, void* in, void* out
                                            float* best_ms) {
   if (P == nullptr || P->batched) return SPINSUM_ERR_INVALID_ARG;
   if (!P->has_dev) return SPINSUM_ERR_NO_DEVICE;
+  if (P->pair) return SPINSUM_ERR_UNSUPPORTED;
   if (P->elems == 0) return SPINSUM_OK;
   hipStream_t s = (hipStream_t)stream;
   const int esz = elem_size(*P);

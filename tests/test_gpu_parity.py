@@ -548,3 +548,145 @@ def test_autograd_through_coefficients(d):
     rank = {p: r for r, p in enumerate(itertools.permutations(range(d)))}
     want = np.array([full[rank[p]] for p in perms])
     np.testing.assert_allclose(alpha.grad.cpu().numpy(), want, rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------ inner spectators (group not last)
+INNER_CASES = [
+    # shape, group_first, d, tile (None: default)
+    ((4, 6, 6, 6, 3), 1, 3, None),          # whole cubes, inner run 3
+    ((5, 11, 11, 11, 3), 1, 3, None),       # odd whole cubes (alignment shifts)
+    ((2, 16, 16, 16, 3), 1, 3, None),       # tile orbits
+    ((1, 30, 30, 30, 2), 1, 3, (8, 1)),     # ragged tile orbits
+    ((20, 20, 20, 5), 0, 3, None),          # no outer spectators, odd inner run
+    ((3, 12, 12, 12, 12, 2), 1, 4, None),
+    ((2, 7, 7, 7, 7, 3), 1, 4, None),
+    ((2, 100, 100, 2), 1, 2, None),
+    ((2, 9, 9, 9, 2, 3), 1, 3, None),       # two inner dims
+]
+
+
+def _random_terms(d, seed):
+    rng = np.random.default_rng(seed)
+    return [(p, float(rng.integers(-3, 4))) for p in itertools.permutations(range(d))]
+
+
+@pytest.mark.parametrize("shape,gf,d,tile", INNER_CASES)
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_inner_spectators_against_oracle(shape, gf, d, tile, dtype):
+    _say("inner spectators", shape, gf, d, tile, dtype)
+    terms = _random_terms(d, sum(shape))
+    x = gpu_uniform(shape, 91, dtype)
+    xh = x.cpu().to(torch.float64).numpy()
+    ref = oracle.spinsum(xh, terms, gf, d, nthreads=8)
+    refa = oracle.spinsum_chain_adjoint(xh, [terms], gf, d, nthreads=8)
+    xi = gpu_ints(shape, 92, dtype)
+    refi = oracle.spinsum(xi.cpu().to(torch.float64).numpy(), terms, gf, d, nthreads=8)
+    variants = [0] if tile is None else VARIANTS
+    for variant in variants:
+        outs = []
+        for inplace in (False, True):
+            p = ss.spinsum_plan(shape, gf, d, [terms], dtype=dtype, inplace=inplace)
+            if tile is not None:
+                ss.spinsum_plan_set_tile(p, *tile, variant=variant)
+            y = run(p, x)
+            assert nerr(y.cpu().numpy(), ref) <= TOL[dtype], (variant, inplace)
+            outs.append(y)
+            yi = run(p, xi)
+            np.testing.assert_array_equal(yi.cpu().numpy().astype(np.float64), refi)
+            ga = torch.empty_like(x) if not inplace else x.clone()
+            ss.spinsum_adjoint(p, x if not inplace else ga, ga)
+            torch.cuda.synchronize()
+            assert nerr(ga.cpu().numpy(), refa) <= TOL[dtype], (variant, inplace)
+        assert torch.equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("shape,gf,d", [((4, 6, 6, 6, 3), 1, 3), ((2, 16, 16, 16, 3), 1, 3),
+                                        ((2, 7, 7, 7, 7, 3), 1, 4), ((20, 20, 20, 5), 0, 3)])
+def test_inner_spectators_coef_grad(shape, gf, d):
+    _say("inner coef grad", shape, gf, d)
+    x = gpu_uniform(shape, 93)
+    g = gpu_uniform(shape, 94)
+    p = ss.spinsum_plan(shape, gf, d, [_random_terms(d, 5)])
+    got = ss.spinsum_coef_grad(p, x, g).cpu().numpy()
+    xh, gh = x.cpu().numpy(), g.cpu().numpy()
+    ref = oracle.coef_grad(xh, gh, gf, d)
+    scale = float(np.sum(np.abs(gh)) * np.abs(xh).max())
+    assert np.max(np.abs(got - ref)) <= 1e-12 * max(1.0, scale), (got, ref)
+
+
+# ------------------------------------------------------- index-pair form
+PAIR_CASES = [
+    # shape, group_first, d, tile edge (None: default)
+    ((3, 3, 4, 4), 2, 2, None),
+    ((5, 5, 5, 8, 8, 8), 3, 3, None),             # whole group cubes
+    ((2, 4, 4, 4, 6, 6, 6), 4, 3, None),          # outer spectator, odd alignment shifts
+    ((4, 4, 4, 12, 12, 12), 3, 3, None),          # tiles with a ragged last block
+    ((4, 4, 4, 12, 12, 12), 3, 3, 4),             # tiles, even (16-byte rows in FP32 too)
+    ((3, 3, 3, 5, 5, 5, 2), 3, 3, None),          # inner spectators
+    ((2, 2, 2, 2, 3, 3, 3, 3), 4, 4, None),       # V < d
+    ((3, 3, 3, 3, 6, 6, 6, 6), 4, 4, None),
+    ((2, 6, 6, 6, 10, 10, 10, 3), 4, 3, None),    # tiles, inner and outer spectators
+    ((16, 16, 16, 8, 8, 8), 3, 3, None),          # the 3D v=16, o=8 amplitude shape
+]
+
+
+@pytest.mark.parametrize("shape,gf,d,bl", PAIR_CASES)
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_index_pairs_against_oracle(shape, gf, d, bl, dtype):
+    _say("index pairs", shape, gf, d, bl, dtype)
+    terms = _random_terms(d, sum(shape) + 1)
+    flags = ss.SPINSUM_FLAG_INDEX_PAIRS
+    x = gpu_uniform(shape, 95, dtype)
+    xh = x.cpu().to(torch.float64).numpy()
+    ref = oracle.spinsum(xh, terms, gf, d, nthreads=8, pairs=True)
+    refa = oracle.spinsum_chain_adjoint(xh, [terms], gf, d, nthreads=8, pairs=True)
+    xi = gpu_ints(shape, 96, dtype)
+    refi = oracle.spinsum(xi.cpu().to(torch.float64).numpy(), terms, gf, d, nthreads=8, pairs=True)
+    outs = []
+    for inplace in (False, True):
+        p = ss.spinsum_plan(shape, gf, d, [terms], dtype=dtype, inplace=inplace, flags=flags)
+        if bl is not None:
+            ss.spinsum_plan_set_tile(p, bl)
+        assert ss.spinsum_plan_get_info(p)["pair_extent"] == shape[gf - d]
+        y = run(p, x)
+        assert nerr(y.cpu().numpy(), ref) <= TOL[dtype], inplace
+        outs.append(y)
+        yi = run(p, xi)
+        np.testing.assert_array_equal(yi.cpu().numpy().astype(np.float64), refi)
+        ga = x.clone() if inplace else torch.empty_like(x)
+        ss.spinsum_adjoint(p, ga if inplace else x, ga)
+        torch.cuda.synchronize()
+        assert nerr(ga.cpu().numpy(), refa) <= TOL[dtype], inplace
+    assert torch.equal(outs[0], outs[1])
+
+
+def test_index_pairs_chain_and_schedule_flags():
+    """Chained stages, reverse item order, plain workgroup order and cached
+    stores give the same bits as the default schedule."""
+    shape, gf, d = (4, 4, 4, 12, 12, 12), 3, 3
+    stages = workloads.FACTORED_PIJ_PJK
+    x = gpu_uniform(shape, 97)
+    ref = oracle.spinsum_chain(x.cpu().numpy(), stages, gf, d, nthreads=8, pairs=True)
+    base = None
+    for extra in (0, ss.SPINSUM_FLAG_CHAIN_STAGES, ss.SPINSUM_FLAG_REVERSE_ORDER,
+                  ss.SPINSUM_FLAG_NO_XCD_REMAP, ss.SPINSUM_FLAG_NO_NT_STORES):
+        p = ss.spinsum_plan(shape, gf, d, stages, flags=ss.SPINSUM_FLAG_INDEX_PAIRS | extra)
+        y = run(p, x)
+        assert nerr(y.cpu().numpy(), ref) <= TOL[torch.float64], extra
+        if extra in (ss.SPINSUM_FLAG_REVERSE_ORDER, ss.SPINSUM_FLAG_NO_XCD_REMAP,
+                     ss.SPINSUM_FLAG_NO_NT_STORES):
+            assert torch.equal(y, base), extra
+        if extra == 0:
+            base = y
+
+
+def test_index_pairs_unsupported_calls():
+    p = ss.spinsum_plan((3, 3, 3, 4, 4, 4), 3, 3, [workloads.CONFIG_3D_ALPHA],
+                        flags=ss.SPINSUM_FLAG_INDEX_PAIRS)
+    x = gpu_uniform((3, 3, 3, 4, 4, 4), 98)
+    with pytest.raises(ss.SpinSumError) as e:
+        ss.spinsum_coef_grad(p, x, x)
+    assert e.value.status == ss.SPINSUM_ERR_UNSUPPORTED
+    with pytest.raises(ss.SpinSumError) as e:
+        ss.spinsum_plan_set_tile(p, 4, variant=ss.SPINSUM_VARIANT_REG_ONESHOT)
+    assert e.value.status == ss.SPINSUM_ERR_UNSUPPORTED

@@ -20,6 +20,8 @@ from workloads import P
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HOST = ss.SPINSUM_FLAG_HOST_ONLY
+VARIANTS_ALL = [ss.SPINSUM_VARIANT_DIRECT_LDS, ss.SPINSUM_VARIANT_REG_PIPELINE,
+                ss.SPINSUM_VARIANT_REG_ONESHOT, ss.SPINSUM_VARIANT_LDS_PIPELINE]
 
 
 def plan(shape, stages, d=None, dtype="f64", inplace=False, flags=0):
@@ -66,10 +68,97 @@ def test_plan_rejects_bad_arguments(shape, stages, d, code):
     assert e.value.status == code
 
 
-def test_inner_spectators_are_unsupported():
+@pytest.mark.parametrize("shape,gf,d,dtype", [
+    ((4, 6, 6, 6, 3), 1, 3, "f64"), ((2, 8, 8, 8, 5), 1, 3, "f32"),
+    ((3, 5, 5, 5, 5, 2), 1, 4, "f64"), ((3, 7, 7, 2, 3), 1, 2, "f64"),
+    ((2, 12, 12, 12, 4), 1, 3, "f64"), ((9, 9, 9, 2), 0, 3, "f32"),
+    ((13, 13, 13, 2), 0, 3, "f64"), ((1, 10, 10, 10, 2, 3), 1, 3, "f64"),
+])
+def test_inner_spectator_addresses_replayed(shape, gf, d, dtype):
+    """Groups followed by inner spectator dims: tiles hold runs of `inner`
+    elements per group position.  Every tile edge and kernel variant the
+    planner accepts has its load/combine/store addresses replayed."""
+    terms = [[(p, 1.0 + i) for i, p in enumerate(itertools.permutations(range(d)))]]
+    p = ss.spinsum_plan(shape, gf, d, terms, dtype=dtype, flags=HOST)
+    ok, why = ss.spinsum_plan_check_ownership(p)
+    assert ok, why
+    n = shape[gf]
+    accepted = 0
+    for bl in range(1, n + 1):
+        for pad in (0, 1):
+            for variant in VARIANTS_ALL:
+                try:
+                    ss.spinsum_plan_set_tile(p, bl, cubes_per_wg=2, lds_pad=pad, variant=variant)
+                except ss.SpinSumError:
+                    continue
+                accepted += 1
+                ok, why = ss.spinsum_plan_check_ownership(p)
+                assert ok, (bl, pad, variant, why)
+    assert accepted > 0
+
+
+@pytest.mark.parametrize("shape,gf,d,dtype", [
+    ((3, 3, 4, 4), 2, 2, "f64"), ((2, 4, 4, 4, 6, 6, 6), 4, 3, "f64"),
+    ((3, 3, 3, 5, 5, 5, 2), 3, 3, "f32"), ((2, 2, 2, 2, 3, 3, 3, 3), 4, 4, "f64"),
+    ((4, 4, 4, 12, 12, 12), 3, 3, "f64"), ((3, 3, 3, 3, 6, 6, 6, 6), 4, 4, "f32"),
+    ((2, 6, 6, 6, 10, 10, 10, 3), 4, 3, "f64"), ((5, 5, 9, 9), 2, 2, "f32"),
+])
+def test_index_pair_items_replayed(shape, gf, d, dtype):
+    """Index-pair form: every work item's tile list, loads, combine addresses
+    and element ownership replayed on the host for every usable tile edge."""
+    terms = [[(p, 1.0) for p in itertools.permutations(range(d))]]
+    flags = HOST | ss.SPINSUM_FLAG_INDEX_PAIRS
+    p = ss.spinsum_plan(shape, gf, d, terms, dtype=dtype, flags=flags)
+    info = ss.spinsum_plan_get_info(p)
+    V, n = shape[gf - d], shape[gf]
+    nb = info["nb"]
+    assert info["pair_extent"] == V and info["variant"] == ss.SPINSUM_VARIANT_DIRECT_LDS
+    assert info["norbits"] == math.comb(V * nb + d - 1, d)   # multisets of combined blocks
+    assert info["elems"] == int(np.prod(shape))
+    accepted = 0
+    for bl in range(1, n + 1):
+        try:
+            ss.spinsum_plan_set_tile(p, bl)
+        except ss.SpinSumError:
+            continue
+        accepted += 1
+        ok, why = ss.spinsum_plan_check_ownership(p)
+        assert ok, (bl, why)
+    assert accepted > 0
+
+
+def test_index_pair_reductions_and_errors():
+    terms = [workloads.CONFIG_3D_ALPHA]
+    fl = HOST | ss.SPINSUM_FLAG_INDEX_PAIRS
+    # V == 1: the ordinary summation over the group
+    i1 = ss.spinsum_plan_get_info(ss.spinsum_plan((1, 1, 1, 5, 5, 5), 3, 3, terms, flags=fl))
+    assert i1["pair_extent"] == 0 and i1["n"] == 5
+    # N == 1: the ordinary summation over the partners
+    i2 = ss.spinsum_plan_get_info(ss.spinsum_plan((5, 5, 5, 1, 1, 1), 3, 3, terms, flags=fl))
+    assert i2["pair_extent"] == 0 and i2["n"] == 5
     with pytest.raises(ss.SpinSumError) as e:
-        ss.spinsum_plan((4, 3, 3, 3, 2), 1, 3, [workloads.CONFIG_3D_ALPHA], flags=HOST)
+        ss.spinsum_plan((4, 4, 4, 4, 4), 2, 3, terms, flags=fl)   # no room for partners
+    assert e.value.status == ss.SPINSUM_ERR_INVALID_ARG
+    with pytest.raises(ss.SpinSumError) as e:
+        ss.spinsum_plan((3, 3, 2, 4, 4, 4), 3, 3, terms, flags=fl)
+    assert e.value.status == ss.SPINSUM_ERR_EXTENT_MISMATCH
+    p = ss.spinsum_plan((3, 3, 3, 4, 4, 4), 3, 3, terms, flags=fl)
+    with pytest.raises(ss.SpinSumError) as e:
+        ss.spinsum_plan_set_tile(p, 2, variant=ss.SPINSUM_VARIANT_REG_PIPELINE)
     assert e.value.status == ss.SPINSUM_ERR_UNSUPPORTED
+
+
+def test_inner_spectator_geometry():
+    """A cube of [.., N^d, inner] is N^d * inner contiguous elements; rows
+    along the last group axis hold bl * inner elements."""
+    p = ss.spinsum_plan((3, 16, 16, 16, 3), 1, 3, [workloads.CONFIG_3D_ALPHA], flags=HOST)
+    info = ss.spinsum_plan_get_info(p)
+    assert info["elems"] == 3 * 16 ** 3 * 3 and info["ncubes"] == 3
+    assert info["bl"] < 16 and info["bl"] % 2 == 0      # 16-byte rows: bl * 3 * 8 % 16 == 0
+    assert info["vector_width"] == 2
+    # an empty inner dim empties the tensor
+    p0 = ss.spinsum_plan((3, 4, 4, 4, 0), 1, 3, [workloads.CONFIG_3D_ALPHA], flags=HOST)
+    assert ss.spinsum_plan_get_info(p0)["elems"] == 0
 
 
 def test_host_only_plan_refuses_exec():
