@@ -309,6 +309,29 @@ def main():
         del xs, graph, singles
         torch.cuda.empty_cache()
 
+        # groups not in the last position: the slab with its group moved in
+        # front of an inner spectator run of 8, [64, 64, 32, 32, 32, 8], in place
+        xin = workloads.uniform((64, 64, 32, 32, 32, 8), 5000, device=dev)
+        pin = ss.spinsum_plan(tuple(xin.shape), 2, 3, alpha, inplace=True)
+        ss.spinsum_exec(pin, xin, xin, stream)
+        ims = timed(lambda: ss.spinsum_exec(pin, xin, xin, stream), 5, stream)
+        forms["3d_inner_run8_inplace"] = form_entry(2 * xin.numel() * 8, ims, value)
+        forms["3d_inner_run8_inplace"]["tile_edge"] = ss.spinsum_plan_get_info(pin)["bl"]
+        del xin
+        torch.cuda.empty_cache()
+        # index-pair form T[a,b,c,i,j,k], v=48, o=24: (a,i), (b,j), (c,k)
+        # permuted together, in place
+        w5 = workloads.WORKLOADS["3d_v48_o24"]
+        xp = workloads.uniform(w5["shape"], 5100, device=dev)
+        pp = ss.spinsum_plan(w5["shape"], 3, 3, alpha, inplace=True,
+                             flags=ss.SPINSUM_FLAG_INDEX_PAIRS)
+        ss.spinsum_exec(pp, xp, xp, stream)
+        pms_ = timed(lambda: ss.spinsum_exec(pp, xp, xp, stream), 5, stream)
+        forms["3d_pairs_v48_o24_inplace"] = form_entry(2 * xp.numel() * 8, pms_, value)
+        forms["3d_pairs_v48_o24_inplace"]["tile_edge"] = ss.spinsum_plan_get_info(pp)["bl"]
+        del xp
+        torch.cuda.empty_cache()
+
         # adjoint and FP32: v=48, o=24, forward and backward (autograd form)
         w5 = workloads.WORKLOADS["3d_v48_o24"]
         st5 = workloads.FACTORED_PIJ_PJK

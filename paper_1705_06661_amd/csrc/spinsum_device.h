@@ -858,13 +858,24 @@ __global__ void __launch_bounds__(kMaxThreads) k_pair(const PairArgs<T> a) {
   const int ntl = __builtin_amdgcn_readfirstlane(info.ntiles);
   const uint32_t rep_cnt = (uint32_t)__builtin_amdgcn_readfirstlane(info.rep_cnt);
   const uint32_t rep_off = (uint32_t)__builtin_amdgcn_readfirstlane(info.rep_off);
+  // lane t of every wave holds tile t's origin and extents; the tile loops
+  // below take them with v_readlane (uniform index) instead of one LDS read
+  // per tile and chunk
+  const int lane = (int)(threadIdx.x & 63u);
+  const int64_t my_toff = (lane < ntl) ? info.toff[lane] : 0;
+  const int32_t my_text = (lane < ntl) ? info.text[lane] : 0;
+  auto tile_off = [&](int t) -> int64_t {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)my_toff, t);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(my_toff >> 32), t);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+  };
   // 2. tiles and the representative list straight into LDS
   const uint32_t tid = threadIdx.x;
   const uint32_t wave_bytes = (tid >> 6) * 1024u;
   const int64_t tile_elems = (int64_t)g.rows * g.bl * g.inner;
   if (pg.flat) {
     for (int t = 0; t < ntl; ++t) {
-      const int64_t toff = info.toff[t];
+      const int64_t toff = tile_off(t);
       flat_issue<T>(src + toff, (uint32_t)tile_elems,
                     smem + (size_t)t * pg.tile_stride * sizeof(T));
     }
@@ -876,8 +887,8 @@ __global__ void __launch_bounds__(kMaxThreads) k_pair(const PairArgs<T> a) {
       const int off = chunk_offset<D>(g, l);
       const bool in = c0 + tid < cpt;
       for (int t = 0; t < ntl; ++t) {
-        const int64_t toff = info.toff[t];
-        const bool ok = in && chunk_inside<D>(l, info.text[t], g.inner);
+        const int64_t toff = tile_off(t);
+        const bool ok = in && chunk_inside<D>(l, __builtin_amdgcn_readlane(my_text, t), g.inner);
         const uint32_t lbyte =
             (uint32_t)(t * pg.tile_stride + (int)c0 * VW) * (uint32_t)sizeof(T) + wave_bytes;
         if (ok)
@@ -917,7 +928,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_pair(const PairArgs<T> a) {
   // 4. store
   if (pg.flat) {
     for (int t = 0; t < ntl; ++t) {
-      const int64_t toff = info.toff[t];
+      const int64_t toff = tile_off(t);
       flat_store<T, NTS>(dst + toff, (uint32_t)tile_elems,
                          smem + (size_t)t * pg.tile_stride * sizeof(T), info.shift[t]);
     }
@@ -930,8 +941,8 @@ __global__ void __launch_bounds__(kMaxThreads) k_pair(const PairArgs<T> a) {
       const int off = chunk_offset<D>(g, l);
       const bool in = c < cpt;
       for (int t = 0; t < ntl; ++t) {
-        const int64_t toff = info.toff[t];
-        const bool ok = in && chunk_inside<D>(l, info.text[t], g.inner);
+        const int64_t toff = tile_off(t);
+        const bool ok = in && chunk_inside<D>(l, __builtin_amdgcn_readlane(my_text, t), g.inner);
         if (ok) {
           const V val = *reinterpret_cast<const V*>(lds + t * pg.tile_stride + (int)c * VW);
           V* p = reinterpret_cast<V*>(dst + toff + off);

@@ -721,6 +721,37 @@ static spinsum_status build_pair_tiling(spinsum_plan_s* P, const spinsum_tile_t&
     }
   }
   if ((int64_t)orbits.size() != pg.norb) return SPINSUM_ERR_UNSUPPORTED;
+  // Orbits whose tiles share cache lines along the fastest axis get
+  // neighbouring item numbers (same XCD, close in time): key = the multiset
+  // of (a_m, b_m / s) with s blocks per 128-byte line, or every block of the
+  // axis when group rows are not whole lines.  Loop-nest order within a key.
+  if (!flat && orbits.size() > 128) {
+    const int64_t row = (int64_t)bl * inner * esz;
+    const int64_t line = 128;
+    int s = nb;
+    if (((int64_t)n * inner * esz) % line == 0 && row < line && line % row == 0) s = (int)(line / row);
+    if (s > 1) {
+      struct Keyed {
+        uint32_t k[kMaxD];
+        uint64_t v;
+      };
+      std::vector<Keyed> kv(orbits.size());
+      for (size_t i = 0; i < orbits.size(); ++i) {
+        Keyed& e = kv[i];
+        for (int m = 0; m < kMaxD; ++m) e.k[m] = 0;
+        for (int m = 0; m < d; ++m) {
+          const int cm = (int)((orbits[i] >> (16 * m)) & 0xFFFFu);
+          e.k[m] = ((uint32_t)(cm / nb) << 16) | (uint32_t)((cm % nb) / s);
+        }
+        std::sort(e.k, e.k + d);
+        e.v = orbits[i];
+      }
+      std::stable_sort(kv.begin(), kv.end(), [](const Keyed& x, const Keyed& y) {
+        return std::lexicographical_compare(x.k, x.k + kMaxD, y.k, y.k + kMaxD);
+      });
+      for (size_t i = 0; i < orbits.size(); ++i) orbits[i] = kv[i].v;
+    }
+  }
   // representative lists per key (equal-neighbour mask, ragged-block mask)
   for (int key = 0; key < (1 << (2 * d - 1)); ++key) {
     int ext[kMaxD];
