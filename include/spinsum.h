@@ -153,6 +153,18 @@ typedef struct {
  *   dtype         : storage and accumulation type (coefficients are rounded
  *                   to it).  inplace: 1 = exec requires in == out.
  *   flags         : SPINSUM_FLAG_*.
+ * Index-pair form (SPINSUM_FLAG_INDEX_PAIRS; the paired indices of the
+ * coupled-cluster quantities of Sec. 1): dims [group_first - d, group_first)
+ * are the partners, all of one extent V (group_first >= d, else
+ * SPINSUM_ERR_INVALID_ARG; unequal partner extents give
+ * SPINSUM_ERR_EXTENT_MISMATCH), and a term (p, alpha) adds
+ *   alpha * In[.., a_{p[0]}..a_{p[d-1]}, i_{p[0]}..i_{p[d-1]}, ..]
+ * to Out[.., a_0..a_{d-1}, i_0..i_{d-1}, ..].  Dims before the partners are
+ * outer spectators, dims after the group inner spectators.  V <= 1 or
+ * N <= 1 reduce to the plain form (over the group, or over the partners).
+ * Pair plans run the direct-LDS kernel only, need V * ceil(N / bl) <= 16000
+ * and fewer than 2^31 work items, and have no coefficient gradient or
+ * autotuner (SPINSUM_ERR_UNSUPPORTED).
  * Host arrays are copied; the caller keeps ownership.  On error *plan is set
  * to NULL. */
 spinsum_status spinsum_plan(spinsum_plan_t* plan, int ndim, const int64_t* extents,
@@ -214,9 +226,10 @@ spinsum_status spinsum_adjoint(spinsum_plan_t plan, const void* grad_out, void* 
  * device array of d! doubles (8-byte aligned), overwritten.  The sums are
  * accumulated in double (per workgroup, then atomically into 2048 partial
  * sums per permutation held by the plan, then one reduction), so the last
- * bits may differ from run to run; calls on one plan must not overlap.  Needs the direct-LDS tile layout (whole cubes, or tile rows
- * of whole 16-byte chunks): SPINSUM_ERR_UNSUPPORTED otherwise.  Asynchronous
- * on `stream`. */
+ * bits may differ from run to run; calls on one plan must not overlap.
+ * Needs the direct-LDS tile layout (whole cubes, or tile rows of whole
+ * 16-byte chunks) and a plan without SPINSUM_FLAG_INDEX_PAIRS:
+ * SPINSUM_ERR_UNSUPPORTED otherwise.  Asynchronous on `stream`. */
 spinsum_status spinsum_coef_grad(spinsum_plan_t plan, const void* x, const void* g,
                                  double* grad, void* stream);
 
@@ -232,7 +245,8 @@ void spinsum_graph_destroy(spinsum_graph_t graph);
  * buffers (their contents are overwritten with unspecified values), keep
  * the fastest in the plan and, if cache_path is not NULL, record it in that
  * cache file (one "key value" line per configuration).  *best_ms receives
- * the best time of one exec.  Synchronises the stream. */
+ * the best time of one exec.  Synchronises the stream.  Index-pair plans:
+ * SPINSUM_ERR_UNSUPPORTED. */
 spinsum_status spinsum_autotune(spinsum_plan_t plan, void* in, void* out, void* stream,
                                 const char* cache_path, spinsum_tile_t* best,
                                 float* best_ms);
