@@ -79,6 +79,8 @@ typedef enum { SPINSUM_F64 = 0, SPINSUM_F32 = 1 } spinsum_dtype;
 #define SPINSUM_FLAG_REVERSE_ORDER 0x10u /* process work items in reverse order (ownership test) */
 #define SPINSUM_FLAG_NO_LDS_PAD 0x20u    /* unpadded LDS tiles (bank-conflict ablation) */
 #define SPINSUM_FLAG_NO_DIRECT_LDS 0x40u /* never use the direct-LDS variant (ablation)  */
+#define SPINSUM_FLAG_NT_STORES 0x100u    /* non-temporal stores even where the planner would
+                                            use cached ones (see spinsum_plan_info_t.nt_stores) */
 #define SPINSUM_FLAG_INDEX_PAIRS 0x80u   /* index-pair form: the d dims right before the group
                                             (the partner indices, extent V each) are permuted
                                             by the same permutation as the group, e.g.
@@ -137,6 +139,10 @@ typedef struct {
   int64_t rep_lds_bytes; /* LDS for the element-orbit representatives      */
   int inner;             /* elements of the inner spectator run (1: trailing group) */
   int pair_extent;       /* index-pair form: partner extent V, else 0    */
+  int nt_stores;         /* 1: non-temporal stores (default where tile rows are at least
+                            64 bytes and a cube has at most 128 tile orbits, and for whole
+                            cubes); 0: cached stores, which let the L2 merge the partial
+                            128-byte lines that short rows or far-apart items write */
 } spinsum_plan_info_t;
 
 /* Create a plan for Out = S_K(...S_1(In)) (Def. 3-4; in-place: Sec. 4.6.5).

@@ -57,6 +57,7 @@ SPINSUM_FLAG_REVERSE_ORDER = 0x10
 SPINSUM_FLAG_NO_LDS_PAD = 0x20
 SPINSUM_FLAG_NO_DIRECT_LDS = 0x40
 SPINSUM_FLAG_INDEX_PAIRS = 0x80
+SPINSUM_FLAG_NT_STORES = 0x100
 
 SPINSUM_VARIANT_AUTO = 0
 SPINSUM_VARIANT_DIRECT_LDS = 1
@@ -84,7 +85,7 @@ class _Info(ctypes.Structure):
                 ("fits_lds", ctypes.c_int), ("items_per_cube", ctypes.c_int),
                 ("item_tiles", ctypes.c_int), ("chunks_per_thread", ctypes.c_int),
                 ("rep_lds_bytes", ctypes.c_int64), ("inner", ctypes.c_int),
-                ("pair_extent", ctypes.c_int)]
+                ("pair_extent", ctypes.c_int), ("nt_stores", ctypes.c_int)]
 
 
 _vp = ctypes.c_void_p

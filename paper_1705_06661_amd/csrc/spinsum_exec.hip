@@ -99,7 +99,7 @@ spinsum_status launch_exec(spinsum_plan_s* P, const void* in, void* out, hipStre
   const int df = P->G.df;
   const int K = (int)P->stage_a.size();
   const bool chain = (P->flags & SPINSUM_FLAG_CHAIN_STAGES) != 0;
-  const bool nts = (P->flags & SPINSUM_FLAG_NO_NT_STORES) == 0;
+  const bool nts = Tl.nts != 0;
   const T* coef = reinterpret_cast<const T*>(P->d_mats);
   ExecArgs<T> a;
   std::memset(&a, 0, sizeof(a));
@@ -161,7 +161,7 @@ spinsum_status launch_pair(spinsum_plan_s* P, const void* in, void* out, hipStre
   const int df = P->G.df;
   const int K = (int)P->stage_a.size();
   const bool chain = (P->flags & SPINSUM_FLAG_CHAIN_STAGES) != 0;
-  const bool nts = (P->flags & SPINSUM_FLAG_NO_NT_STORES) == 0;
+  const bool nts = Tl.nts != 0;
   const T* coef = reinterpret_cast<const T*>(P->d_mats);
   PairArgs<T> a;
   std::memset(&a, 0, sizeof(a));

@@ -690,3 +690,28 @@ def test_index_pairs_unsupported_calls():
     with pytest.raises(ss.SpinSumError) as e:
         ss.spinsum_plan_set_tile(p, 4, variant=ss.SPINSUM_VARIANT_REG_ONESHOT)
     assert e.value.status == ss.SPINSUM_ERR_UNSUPPORTED
+
+
+def test_non_finite_inputs_with_every_term_present():
+    """Inf and NaN inputs under an operator in which every permutation has a
+    nonzero coefficient (the 3D set): the same outputs become +-Inf or NaN as
+    in the oracle, and the finite ones agree.  (The kernels form the dense
+    product over S_d, so for operators with absent permutations a non-finite
+    input also turns the outputs it does not feed into NaN; the oracle skips
+    absent terms.)"""
+    shape = (3, 12, 12, 12)
+    x = gpu_uniform(shape, 99)
+    xh = x.cpu().numpy().copy()
+    for idx, val in [((0, 1, 2, 3), np.inf), ((1, 5, 5, 7), -np.inf), ((2, 0, 9, 4), np.nan),
+                     ((2, 4, 0, 9), np.inf), ((2, 9, 4, 0), np.inf)]:
+        xh[idx] = val
+    x = torch.from_numpy(xh).to(DEV)
+    ref = oracle.spinsum(xh, workloads.CONFIG_3D_ALPHA, 1, 3)
+    for inplace in (False, True):
+        p = mk(shape, [workloads.CONFIG_3D_ALPHA], 3, inplace=inplace)
+        y = run(p, x).cpu().numpy()
+        np.testing.assert_array_equal(np.isnan(y), np.isnan(ref))
+        np.testing.assert_array_equal(np.isposinf(y), np.isposinf(ref))
+        np.testing.assert_array_equal(np.isneginf(y), np.isneginf(ref))
+        fin = np.isfinite(ref)
+        assert nerr(y[fin], ref[fin]) <= TOL[torch.float64]

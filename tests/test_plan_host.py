@@ -148,6 +148,23 @@ def test_index_pair_reductions_and_errors():
     assert e.value.status == ss.SPINSUM_ERR_UNSUPPORTED
 
 
+def test_store_mode_rule():
+    """Non-temporal stores for whole cubes and for tile rows of at least 64
+    bytes in cubes of at most 128 tile orbits; cached stores otherwise; the
+    flags override the rule."""
+    cfg3 = [workloads.CONFIG_3D_ALPHA]
+    def nt(shape, gf, d, terms, flags=0, dtype="f64"):
+        p = ss.spinsum_plan(shape, gf, d, terms, dtype=dtype, flags=flags | HOST)
+        return ss.spinsum_plan_get_info(p)["nt_stores"]
+    a4 = [(p, 1.0) for p in itertools.permutations(range(4))]
+    assert nt((2, 32, 32, 32), 1, 3, cfg3) == 1              # 64-byte rows, 20 orbits
+    assert nt((4, 8, 8, 8), 1, 3, cfg3) == 1                 # whole cubes
+    assert nt((2, 12, 12, 12, 12), 1, 4, [a4]) == 0          # 32-byte rows
+    assert nt((352, 352, 352), 0, 3, cfg3) == 0              # one cube of 1140 orbits
+    assert nt((2, 12, 12, 12, 12), 1, 4, [a4], ss.SPINSUM_FLAG_NT_STORES) == 1
+    assert nt((2, 32, 32, 32), 1, 3, cfg3, ss.SPINSUM_FLAG_NO_NT_STORES) == 0
+
+
 def test_inner_spectator_geometry():
     """A cube of [.., N^d, inner] is N^d * inner contiguous elements; rows
     along the last group axis hold bl * inner elements."""
