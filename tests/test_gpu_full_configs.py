@@ -112,6 +112,69 @@ def test_4d_v24_o12_slab_inplace():
     check_cube_sums(x2, in_sums, expanded_sum([a]), 1e-12)
 
 
+def test_3d_inner_run8_inplace():
+    """The slab with its group moved in front of an inner spectator run of
+    8: [64, 64, 32, 32, 32, 8], group dims 2..4, in place (the bench line)."""
+    shape = (64, 64, 32, 32, 32, 8)
+    _say("case 3d_inner_run8", shape)
+    stages = [workloads.CONFIG_3D_ALPHA]
+    seed = 5000
+    x = workloads.uniform(shape, seed, device=DEV)
+    cube = 32 ** 3 * 8
+    x2 = x.view(-1, cube)
+    in_sums = x2.sum(dim=1, dtype=torch.float64)
+    p = ss.spinsum_plan(shape, 2, 3, stages, inplace=True)
+    ss.spinsum_exec(p, x, x)
+    torch.cuda.synchronize()
+    worst = 0.0
+    cubes = sample_cubes(x2.shape[0], 24, 5)
+    for c in cubes:
+        xc = workloads.uniform_numpy(cube, seed, offset=c * cube).reshape(1, 32, 32, 32, 8)
+        ref = oracle.spinsum(xc, stages[0], 1, 3)
+        got = x2[c].to("cpu", torch.float64).numpy().reshape(ref.shape)
+        worst = max(worst, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+    _say(f"  sampled {len(cubes)} cubes, worst normwise error {worst:.3e}")
+    assert worst <= 1e-14
+    check_cube_sums(x2, in_sums, expanded_sum(stages), 1e-12)
+
+
+def test_3d_pairs_v48_o24_inplace():
+    """Index-pair form on T[a,b,c,i,j,k], v=48, o=24, in place (the bench
+    line).  For a set S of partner values the sub-tensor T[S,S,S,:,:,:] is
+    closed under the operator (a permutation of (a,b,c) stays in S^3), so the
+    oracle runs on that sub-tensor alone; its input is regenerated on the
+    host cube by cube."""
+    shape = (48, 48, 48, 24, 24, 24)
+    _say("case 3d_pairs_v48_o24", shape)
+    terms = workloads.CONFIG_3D_ALPHA
+    seed = 5100
+    x = workloads.uniform(shape, seed, device=DEV)
+    cube = 24 ** 3
+    total_in = float(x.sum(dtype=torch.float64))
+    p = ss.spinsum_plan(shape, 3, 3, [terms], inplace=True, flags=ss.SPINSUM_FLAG_INDEX_PAIRS)
+    ss.spinsum_exec(p, x, x)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for S in ([0, 1, 47], [3, 20], [11], [5, 46, 47], [0, 24, 36]):
+        k = len(S)
+        xs = np.empty((k, k, k, 24, 24, 24))
+        got = np.empty_like(xs)
+        for ia, a in enumerate(S):
+            for ib, b in enumerate(S):
+                for ic, c in enumerate(S):
+                    off = ((a * 48 + b) * 48 + c) * cube
+                    xs[ia, ib, ic] = workloads.uniform_numpy(cube, seed, offset=off).reshape(24, 24, 24)
+                    got[ia, ib, ic] = x[a, b, c].to("cpu", torch.float64).numpy()
+        ref = oracle.spinsum(xs, terms, 3, 3, pairs=True, nthreads=8)
+        worst = max(worst, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+    _say(f"  sampled partner sets, worst normwise error {worst:.3e}")
+    assert worst <= 1e-14
+    # whole-tensor sum invariant: sum(Out) = (sum of coefficients) * sum(In)
+    total_out = float(x.sum(dtype=torch.float64))
+    coef_sum = sum(a for _, a in terms)
+    assert abs(total_out - coef_sum * total_in) <= 1e-9 * float(x.abs().sum(dtype=torch.float64))
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_3d_v48_o24_forward_and_adjoint(dtype):
     w = workloads.WORKLOADS["3d_v48_o24"]
