@@ -130,17 +130,23 @@ def cpu_baseline(seconds: float, nslabs: int):
                       f"{total:.1f} s of oracle time on {threads} threads"}
 
 
-def table2_sweep(ss, workloads, dev, stream):
+# The paper's three tensor sizes (Sec. 5.1: about 70, 320 and 1200 MiB),
+# hyper-square, no spectators: 3D N = 208 / 352 / 544 (rows of whole
+# 128-byte lines), 4D N = 54 / 80 / 112.
+TABLE2_SIZES = {"small": {3: 208, 4: 54}, "medium": {3: 352, 4: 80}, "large": {3: 544, 4: 112}}
+
+
+def table2_sweep(ss, workloads, dev, stream, size="medium"):
     """The paper's benchmark (Table II, all 21 spin summations) on hyper-square
-    tensors without spectators of about 320 MiB (the medium size of Sec. 5.1:
-    3D N = 352, 4D N = 80: rows of whole 128-byte lines), in place, FP64.  Eq. 12 bandwidth in GiB/s and
-    Eq. 13 GFLOP/s with n = the number of expanded permutations."""
+    tensors without spectators at one of the sizes of Sec. 5.1, in place,
+    FP64.  Eq. 12 bandwidth in GiB/s and Eq. 13 GFLOP/s with n = the number
+    of expanded permutations."""
     import torch
     res = {}
     tensors = {}
     for case in range(1, 22):
         d, stages = workloads.table2_case(case)
-        n = 352 if d == 3 else 80
+        n = TABLE2_SIZES[size][d]
         shape = (n,) * d
         if d not in tensors:
             tensors[d] = torch.empty(shape, dtype=torch.float64, device=dev)
@@ -348,7 +354,8 @@ def main():
             del x5, y5
             torch.cuda.empty_cache()
         out["forms"] = forms
-        out["table2_medium"] = table2_sweep(ss, workloads, dev, stream)
+        for size in ("small", "medium", "large"):
+            out[f"table2_{size}"] = table2_sweep(ss, workloads, dev, stream, size)
 
     if not args.no_cpu_baseline:
         log("cpu baseline")

@@ -253,6 +253,41 @@ def test_3d_v64_o32_whole_tensor_one_launch():
 TABLE2_N = {3: 352, 4: 80}
 
 
+# The small (about 70 MiB) and large (about 1200 MiB) sizes: for a set S of
+# indices (with 0 and N-1) the sub-tensor In[S, .., S] is closed under every
+# permutation of the group, so Out on it is the oracle on that sub-tensor
+# alone; its input is regenerated on the host at those positions.
+TABLE2_OTHER = {"small": {3: 208, 4: 54}, "large": {3: 544, 4: 112}}
+
+
+@pytest.mark.parametrize("size", ["small", "large"])
+@pytest.mark.parametrize("case", [1, 3, 5, 9, 18])
+def test_table2_small_and_large_inplace(size, case):
+    d, stages = workloads.table2_case(case)
+    n = TABLE2_OTHER[size][d]
+    shape = (n,) * d
+    _say(f"case table2 #{case} {size} shape {shape}")
+    seed = 6000 + case
+    x = workloads.uniform(shape, seed, device=DEV)
+    p = ss.spinsum_plan(shape, 0, d, stages, inplace=True)
+    ss.spinsum_exec(p, x, x)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(case)
+    k = 24 if d == 3 else 14
+    S = np.unique(np.concatenate([[0, n - 1], rng.choice(n, k - 2, replace=False)]))
+    grids = np.meshgrid(*([S] * d), indexing="ij")
+    lin = np.zeros(grids[0].shape, dtype=np.int64)
+    for gmat in grids:
+        lin = lin * n + gmat
+    xs = workloads.uniform_numpy_at(lin.astype(np.uint64), seed)
+    ref = oracle.spinsum_chain(xs.reshape((1,) + xs.shape), stages, 1, d).reshape(xs.shape)
+    idx = torch.from_numpy(lin.reshape(-1)).to(DEV)
+    got = x.view(-1)[idx].cpu().numpy().reshape(xs.shape)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    _say(f"  {len(S)}^{d} sub-tensor, normwise error {err:.3e}")
+    assert err <= 1e-14
+
+
 @pytest.mark.parametrize("case", [1, 2, 4, 5, 8, 11, 17, 18, 21])
 def test_table2_medium_size_inplace(case):
     d, stages = workloads.table2_case(case)

@@ -100,8 +100,13 @@ def integers(shape: Sequence[int], seed: int, device="cpu", dtype=torch.float64,
 
 def uniform_numpy(n: int, seed: int, offset: int = 0) -> np.ndarray:
     """The same stream computed with numpy uint64 (well-defined wrap-around)."""
+    return uniform_numpy_at(np.arange(offset, offset + n, dtype=np.uint64), seed)
+
+
+def uniform_numpy_at(index: np.ndarray, seed: int) -> np.ndarray:
+    """The stream at arbitrary linear indices (any shape)."""
     with np.errstate(over="ignore"):
-        k = np.arange(offset, offset + n, dtype=np.uint64) + np.uint64(
+        k = np.asarray(index, dtype=np.uint64) + np.uint64(
             (seed << _SEED_SHIFT) + 1)
         z = k * np.uint64(_GOLDEN)
         z = (z ^ (z >> np.uint64(30))) * np.uint64(_M1)
