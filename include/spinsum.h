@@ -168,7 +168,8 @@ typedef struct {
  * to Out[.., a_0..a_{d-1}, i_0..i_{d-1}, ..].  Dims before the partners are
  * outer spectators, dims after the group inner spectators.  V <= 1 or
  * N <= 1 reduce to the plain form (over the group, or over the partners).
- * Pair plans run the direct-LDS kernel only, need V * ceil(N / bl) <= 16000
+ * Pair plans run the direct-LDS kernel only, need V * ceil(N / bl) <= 16000,
+ * at most 2^26 tile orbits per pair block (their table takes 8 bytes each)
  * and fewer than 2^31 work items, and have no coefficient gradient or
  * autotuner (SPINSUM_ERR_UNSUPPORTED).
  * Host arrays are copied; the caller keeps ownership.  On error *plan is set

@@ -701,7 +701,8 @@ static spinsum_status build_pair_tiling(spinsum_plan_s* P, const spinsum_tile_t&
   pg.tile_stride = flat ? (int32_t)((g.ts + 16 / esz + 16 / esz - 1) / (16 / esz) * (16 / esz)) : g.ts;
   pg.fd_nb = make_fastdiv((uint32_t)nb);
   pg.norb = multiset_count(nc, d);
-  if (pg.norb <= 0 || pg.norb >= (1ll << 31)) return SPINSUM_ERR_UNSUPPORTED;
+  // host table of 8 bytes per orbit (plus the sort for the line order)
+  if (pg.norb <= 0 || pg.norb > (1ll << 26)) return SPINSUM_ERR_UNSUPPORTED;
   pg.fd_norb = make_fastdiv((uint32_t)pg.norb);
   T.nitems = P->ncubes * pg.norb;
   if (T.nitems >= (1ll << 31) - 8) return SPINSUM_ERR_UNSUPPORTED;
