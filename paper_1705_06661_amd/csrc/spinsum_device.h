@@ -777,18 +777,15 @@ __device__ __forceinline__ int perm_entry(int r, std::integer_sequence<int, R...
   return v;
 }
 
-template <int D>
-__device__ __forceinline__ int pick(const int (&c)[D], int k) {
-  int v = c[0];
-#pragma unroll
-  for (int j = 1; j < D; ++j) v = (k == j) ? c[j] : v;
-  return v;
-}
-
+// t = sigma_r . c for the packed tuple pk (16 bits per entry): entry m of
+// the result is entry sigma_r[m] of c, taken with a variable shift (no
+// register array indexed per lane).
 template <int D, int... M>
-__device__ __forceinline__ void permuted_tuple(const int (&c)[D], int r, int (&t)[D],
+__device__ __forceinline__ void permuted_tuple(uint64_t pk, int r, int (&t)[D],
                                                std::integer_sequence<int, M...>) {
-  ((t[M] = pick<D>(c, perm_entry<D, M>(r, std::make_integer_sequence<int, Fact<D>::v>{}))), ...);
+  ((t[M] = (int)((pk >> (16 * perm_entry<D, M>(r, std::make_integer_sequence<int, Fact<D>::v>{}))) &
+                 0xFFFFu)),
+   ...);
 }
 
 template <typename T, int D, bool CHAIN, bool NTS>
@@ -822,7 +819,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_pair(const PairArgs<T> a) {
     const int r = (int)threadIdx.x;
     const bool act = r < DF;
     int t[D];
-    permuted_tuple<D>(c, act ? r : 0, t, std::make_integer_sequence<int, D>{});
+    permuted_tuple<D>(pk, act ? r : 0, t, std::make_integer_sequence<int, D>{});
     uint64_t key = 0;
 #pragma unroll
     for (int m = 0; m < D; ++m) key |= (uint64_t)t[m] << (16 * m);
