@@ -8,7 +8,7 @@
 //
 // Cache file: plain text, one line per configuration:
 //   <key> <bl> <cubes_per_wg> <threads> <lds_pad> <variant> <item_tiles> <ms>
-// key = d<d>_n<N>_<f64|f32>_ip<0|1>_c<floor(log2(ncubes))>_<arch>.
+// key = d<d>_n<N>_r<inner run>_<f64|f32>_ip<0|1>_c<floor(log2(ncubes))>_<arch>.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,8 +41,9 @@ static std::string cache_key(const spinsum_plan_s& P) {
   int lg = 0;
   while ((1ll << (lg + 1)) <= P.ncubes) ++lg;
   std::ostringstream os;
-  os << "d" << P.d << "_n" << P.n << "_" << (P.dtype == SPINSUM_F32 ? "f32" : "f64") << "_ip"
-     << P.inplace << "_c" << lg << "_" << arch_name(P.device);
+  os << "d" << P.d << "_n" << P.n << "_r" << P.inner << "_"
+     << (P.dtype == SPINSUM_F32 ? "f32" : "f64") << "_ip" << P.inplace << "_c" << lg << "_"
+     << arch_name(P.device);
   return os.str();
 }
 

@@ -468,7 +468,7 @@ def test_autotune_and_cache(tmp_path):
     cache = str(tmp_path / "tune.txt")
     best, ms = ss.spinsum_autotune(p, x, out, cache_path=cache)
     assert ms > 0 and best["bl"] in (24, 12, 8, 6, 4)
-    assert os.path.exists(cache) and "d3_n24_f64_ip0" in open(cache).read()
+    assert os.path.exists(cache) and "d3_n24_r1_f64_ip0" in open(cache).read()
     y = run(p, x)
     assert nerr(y.cpu().numpy(), ref_of(x, [workloads.CONFIG_3D_ALPHA], 3)) <= 1e-14
     os.environ["SPINSUM_AUTOTUNE_CACHE"] = cache
