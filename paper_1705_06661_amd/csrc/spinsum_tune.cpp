@@ -111,7 +111,7 @@ extern "C" spinsum_status spinsum_autotune(spinsum_plan_t P, void* in, void* out
   hipStream_t s = (hipStream_t)stream;
   const int esz = elem_size(*P);
   const int n = P->n, d = P->d;
-  int64_t cube_bytes = esz;
+  int64_t cube_bytes = (int64_t)esz * P->inner;
   for (int m = 0; m < d; ++m) cube_bytes *= n;
   // candidates: kernel variant x tile edge (x cubes per workgroup)
   std::vector<spinsum_tile_t> shapes;
@@ -122,7 +122,7 @@ extern "C" spinsum_status spinsum_autotune(spinsum_plan_t P, void* in, void* out
   }
   for (int bl = n - 1; bl >= 2; --bl) {
     if (n % bl != 0) continue;
-    if (bl * esz < 32) continue;
+    if ((int64_t)bl * P->inner * esz < 32) continue;
     shapes.push_back({bl, 1, 256, 0, 0, 0});
     // work items packing several orbits: up to one and two largest orbits
     spinsum_tile_t probe{bl, 1, 256, 0, 0, 0};
