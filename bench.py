@@ -232,6 +232,13 @@ def main():
     achieved = algo_per_launch / (launch_ms * 1e-3) / 1e9
     assert bool(torch.isfinite(big[0, 0, 0]).all()), "non-finite output"
     log(f"headline: {ms_step:.3f} ms/step, {value:.1f} GB/s")
+    # single launches, after the timed region: each slab (8.6 GB) is far
+    # larger than the L2 and MALL, so every launch runs on cold caches
+    singles = []
+    for _ in range(max(1, min(3, args.steps))):
+        for s in range(nslabs):
+            singles.append(timed(lambda: ss.spinsum_exec(plan, big[s], big[s], stream), 1, stream))
+    singles.sort()
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "GB/s", "n_gpus": 1,
@@ -247,6 +254,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_GBPS, 4),
                      "traffic": traffic_from_profile("spinsum_3d_v64_o32_inplace"),
+                     "single_launch_ms_min": round(singles[0], 4),
+                     "single_launch_ms_median": round(singles[len(singles) // 2], 4),
                      "kernel": kernel_name(info),
                      "algorithmic_bytes_per_launch": algo_per_launch,
                      "avg_launch_ms": round(launch_ms, 4)},
