@@ -12,8 +12,12 @@
 //      each permutation in the operator, in scalar registers; with stage
 //      chaining the stages are applied one after the other) and writes w_tau
 //      to tile[tau . x];
-//   3. stores the tiles back once with 16-byte stores, non-temporal by
-//      default (Sec. 4.6.3), in place (Sec. 4.6.5) or to the output.
+//   3. stores the tiles back once with 16-byte stores, non-temporal where
+//      the planner chooses them (Sec. 4.6.3), in place (Sec. 4.6.5) or to
+//      the output.
+// With inner spectators every group position is a run of `inner` elements:
+// tile rows are bl * inner elements long and the combine step runs over
+// (representative, inner index) pairs.
 // Every element belongs to exactly one item, and inside an item to the
 // element orbit of exactly one representative, so in-place needs only the
 // workgroup barriers.
@@ -25,7 +29,10 @@
 //   k_exec    one item per workgroup, loads through registers into padded
 //             LDS (rows that are not whole 16-byte chunks);
 //   k_pipe    persistent, next item prefetched into registers;
-//   k_batched many tensors, one item of the cost-sorted list per workgroup.
+//   k_batched many tensors, one item of the cost-sorted list per workgroup;
+//   k_pair    index-pair form: one tile orbit of combined (partner, group)
+//             blocks per workgroup, its tile list built in the workgroup;
+//   k_cgrad   coefficient gradient (x and the upstream gradient in LDS).
 // One-shot grids are XCD-grouped: the workgroups of XCD x (blockIdx % 8 == x)
 // take a contiguous range of items, so the tile orbits of one cube -- which
 // share cache lines along the fastest axis -- meet in the same L2.  The work
