@@ -726,7 +726,7 @@ static spinsum_status build_pair_tiling(spinsum_plan_s* P, const spinsum_tile_t&
   // neighbouring item numbers (same XCD, close in time): key = the multiset
   // of (a_m, b_m / s) with s blocks per 128-byte line, or every block of the
   // axis when group rows are not whole lines.  Loop-nest order within a key.
-  if (!flat && orbits.size() > 128) {
+  if (!flat && orbits.size() > 128 && orbits.size() <= ((size_t)1 << 24)) {  // sort buffer <= 384 MiB
     const int64_t row = (int64_t)bl * inner * esz;
     const int64_t line = 128;
     int s = nb;
