@@ -303,3 +303,26 @@ def test_table2_medium_size_inplace(case):
     err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
     _say(f"  normwise error {err:.3e}")
     assert err <= 1e-14
+
+
+def test_3d_coef_grad_full_size():
+    """The coefficient gradient on two full slabs (the bench line): grad_p =
+    <g, pi_p(x)> for every permutation p, checked against the plain sum of
+    g * x.permute(...) taken in double by the library (the definition of the
+    gradient, Def. 2-3, at a size the oracle cannot take)."""
+    import itertools
+    shape = workloads.WORKLOADS["3d_v64_o32_slab"]["shape"]
+    _say("case 3d_coef_grad full slab", shape)
+    x = workloads.uniform(shape, 1000, device=DEV)
+    g = workloads.uniform(shape, 1001, device=DEV)
+    p = ss.spinsum_plan(shape, 3, 3, [workloads.CONFIG_3D_ALPHA])
+    got = ss.spinsum_coef_grad(p, x, g).cpu().numpy()
+    scale = float((g.abs().sum(dtype=torch.float64) * x.abs().max()).cpu())
+    for r, perm in enumerate(itertools.permutations(range(3))):
+        q = [0] * 3
+        for m, v in enumerate(perm):
+            q[v] = m
+        y = x.permute(0, 1, 2, 3 + q[0], 3 + q[1], 3 + q[2])
+        ref = float((g * y).sum(dtype=torch.float64))
+        _say(f"  p={perm} gpu {got[r]:.12e} ref {ref:.12e}")
+        assert abs(got[r] - ref) <= 1e-12 * scale
