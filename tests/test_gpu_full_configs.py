@@ -73,7 +73,8 @@ def expanded_sum(stages):
     return float(np.prod([sum(a for _, a in s) for s in stages]))
 
 
-@pytest.mark.parametrize("form", ["expanded", "factored_chained", "table2_1_chained"])
+@pytest.mark.parametrize("form", ["expanded", "factored_chained", "table2_1_chained",
+                                  "antisymmetrizer"])
 def test_3d_v64_o32_slab_inplace(form):
     w = workloads.WORKLOADS["3d_v64_o32_slab"]
     shape = w["shape"]
@@ -82,8 +83,10 @@ def test_3d_v64_o32_slab_inplace(form):
         stages, flags = [workloads.CONFIG_3D_ALPHA], 0
     elif form == "factored_chained":
         stages, flags = workloads.FACTORED_PIJ_PJK, ss.SPINSUM_FLAG_CHAIN_STAGES
-    else:
+    elif form == "table2_1_chained":
         stages, flags = workloads.table2_case(1)[1], ss.SPINSUM_FLAG_CHAIN_STAGES
+    else:
+        stages, flags = [workloads.antisymmetrizer(3)], 0
     seed = 1000
     x = workloads.uniform(shape, seed, device=DEV)
     cube = 32 ** 3
