@@ -715,3 +715,32 @@ def test_non_finite_inputs_with_every_term_present():
         np.testing.assert_array_equal(np.isneginf(y), np.isneginf(ref))
         fin = np.isfinite(ref)
         assert nerr(y[fin], ref[fin]) <= TOL[torch.float64]
+
+
+@pytest.mark.parametrize("shape,gf,d,pairs", [((2, 3, 3, 3, 2), 1, 3, False),
+                                              ((3, 3, 3, 3, 3), 0, 4, False),
+                                              ((2, 2, 3, 3), 2, 2, True),
+                                              ((2, 2, 2, 2, 2, 2), 3, 3, True)])
+def test_autograd_inner_runs_and_index_pairs(shape, gf, d, pairs):
+    """SpinSumFunction through groups with inner spectators and through the
+    index-pair form: gradcheck, and forward / backward against the dense
+    matrix of the chain."""
+    stages = workloads.FACTORED_PIJ_PJK if d == 3 else (
+        workloads.table2_case(6)[1] if d == 4 else [[((1, 0), 2.0), ((0, 1), -1.0)]])
+    flags = ss.SPINSUM_FLAG_INDEX_PAIRS if pairs else 0
+    M = oracle.dense_chain_matrix(shape, stages, gf, d, pairs=pairs)
+    for inplace in (False, True):
+        p = ss.spinsum_plan(shape, gf, d, stages, inplace=inplace, flags=flags)
+
+        def f(x):
+            return ss.SpinSumFunction.apply(x.clone() if inplace else x, p)
+
+        x = gpu_uniform(shape, 43).requires_grad_(True)
+        assert torch.autograd.gradcheck(f, (x,), eps=1.0, atol=1e-12, rtol=1e-12)
+        g = gpu_uniform(shape, 44)
+        y = f(x)
+        (gx,) = torch.autograd.grad(y, x, g)
+        np.testing.assert_allclose(gx.detach().cpu().numpy().ravel(), M.T @ g.cpu().numpy().ravel(),
+                                   rtol=0, atol=1e-12)
+        np.testing.assert_allclose(y.detach().cpu().numpy().ravel(),
+                                   M @ x.detach().cpu().numpy().ravel(), rtol=0, atol=1e-12)
