@@ -182,7 +182,7 @@ spinsum_status spinsum_plan(spinsum_plan_t* plan, int ndim, const int64_t* exten
 /* Plan for many tensors ("blocks") that share d, the terms, dtype and the
  * in-place choice but have their own shapes: block b has ndims[b] dims with
  * extents extents[b][0..ndims[b]-1], group = its trailing d dims.  Executed
- * by one persistent kernel (spinsum_exec_batched). */
+ * by one kernel launch (spinsum_exec_batched), one work item per workgroup. */
 spinsum_status spinsum_plan_batched(spinsum_plan_t* plan, int nblocks, const int* ndims,
                                     const int64_t* const* extents, int d, int nstages,
                                     const int* nterms, const int* perms,

@@ -219,7 +219,7 @@ def spinsum_plan(extents: Sequence[int], group_first: int, d: int, stages, dtype
 
 def spinsum_plan_batched(shapes: Sequence[Sequence[int]], d: int, stages, dtype="f64",
                          inplace: bool = False, flags: int = 0) -> Plan:
-    """Plan one persistent launch over many tensors (group = trailing d dims)."""
+    """Plan one launch over many tensors (group = trailing d dims)."""
     nb = len(shapes)
     ndims = (ctypes.c_int * nb)(*[len(s) for s in shapes])
     rows = [(ctypes.c_int64 * len(s))(*[int(e) for e in s]) for s in shapes]
@@ -343,7 +343,7 @@ class PointerArrays:
 
 
 def spinsum_exec_batched(plan: Plan, ins, outs, stream=None, arrays: Optional[PointerArrays] = None):
-    """One persistent launch over all blocks of a batched plan."""
+    """One launch over all blocks of a batched plan."""
     arrays = arrays or PointerArrays(plan, ins, outs)
     _check(_c_exec_batched(plan._h, arrays.d_in.data_ptr(), arrays.d_out.data_ptr(),
                            _stream(stream)), "spinsum_exec_batched", plan)
@@ -362,7 +362,7 @@ class Graph:
 
 
 def spinsum_graph_create(plan: Plan, ins, outs) -> Graph:
-    """Capture one exec (batched: one persistent launch) into a hipGraph."""
+    """Capture one exec (batched: one launch) into a hipGraph."""
     h = _vp()
     if plan.batched:
         arrays = PointerArrays(plan, ins, outs)

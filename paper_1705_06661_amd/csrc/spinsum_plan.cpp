@@ -1130,7 +1130,7 @@ extern "C" spinsum_status spinsum_plan_batched(spinsum_plan_t* plan, int nblocks
     }
     group_base += (int)T.groups.size();
   }
-  // larger items first so the static round-robin of the persistent kernel balances
+  // larger items first: the workgroups dispatched last then get the small ones
   auto cost = [&](const BatchItem& it) {
     const Tiling& T = P->btil[it.block];
     const GroupDev& gd = T.groups[it.group - P->blocks[it.block].group_base];
