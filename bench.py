@@ -317,6 +317,8 @@ def main():
         xs = [workloads.uniform(s, 3000 + k, device=dev) for k, s in enumerate(shapes)]
         nbytes = 2 * 8 * sum(x.numel() for x in xs)
         bp = ss.spinsum_plan_batched(shapes, 3, alpha, inplace=True)
+        # item size and launch style picked by the library's autotuner
+        tuned, _ = ss.spinsum_autotune(bp, xs, xs)
         graph = ss.spinsum_graph_create(bp, xs, xs)
         ss.spinsum_graph_launch(graph, stream)
         bms = timed(lambda: ss.spinsum_graph_launch(graph, stream), 10, stream)
@@ -330,6 +332,8 @@ def main():
         pms = timed(per_block, 5, stream)
         forms["batched_graph"] = form_entry(nbytes, bms, value)
         forms["batched_graph"].update({"blocks": len(blocks), "block_seed": seed,
+                                       "item_kib": tuned["cubes_per_wg"],
+                                       "persistent": tuned["variant"],
                                        "vs_per_block_launches": round(pms / bms, 3)})
         forms["batched_per_block_launches"] = form_entry(nbytes, pms, value)
         del xs, graph, singles

@@ -139,6 +139,9 @@ typedef struct {
   int64_t rep_lds_bytes; /* LDS for the element-orbit representatives      */
   int inner;             /* elements of the inner spectator run (1: trailing group) */
   int pair_extent;       /* index-pair form: partner extent V, else 0    */
+  int64_t batch_item_bytes; /* batched: whole-cube items are packed up to this size */
+  int batch_persistent;  /* batched: 1 = persistent workgroups walk the item list,
+                            0 = one workgroup per item */
   int nt_stores;         /* 1: non-temporal stores (default where tile rows are at least
                             64 bytes and a cube has at most 128 tile orbits, and for whole
                             cubes); 0: cached stores, which let the L2 merge the partial
@@ -182,7 +185,9 @@ spinsum_status spinsum_plan(spinsum_plan_t* plan, int ndim, const int64_t* exten
 /* Plan for many tensors ("blocks") that share d, the terms, dtype and the
  * in-place choice but have their own shapes: block b has ndims[b] dims with
  * extents extents[b][0..ndims[b]-1], group = its trailing d dims.  Executed
- * by one kernel launch (spinsum_exec_batched), one work item per workgroup. */
+ * by one kernel launch (spinsum_exec_batched): one work item per workgroup,
+ * or persistent workgroups walking the item list (spinsum_autotune picks;
+ * spinsum_plan_info_t.batch_persistent). */
 spinsum_status spinsum_plan_batched(spinsum_plan_t* plan, int nblocks, const int* ndims,
                                     const int64_t* const* extents, int d, int nstages,
                                     const int* nterms, const int* perms,
@@ -242,7 +247,8 @@ spinsum_status spinsum_coef_grad(spinsum_plan_t plan, const void* x, const void*
 
 /* Capture one spinsum_exec_batched launch into a hipGraph (captured on a
  * private stream) and instantiate it.  The pointer arrays must stay valid
- * for the life of the graph. */
+ * for the life of the graph, and so must the plan's device tables: create
+ * the graph again after spinsum_plan_set_tile or spinsum_autotune. */
 spinsum_status spinsum_graph_create(spinsum_plan_t plan, const void* const* in,
                                     void* const* out, spinsum_graph_t* graph);
 spinsum_status spinsum_graph_launch(spinsum_graph_t graph, void* stream);
@@ -253,7 +259,12 @@ void spinsum_graph_destroy(spinsum_graph_t graph);
  * the fastest in the plan and, if cache_path is not NULL, record it in that
  * cache file (one "key value" line per configuration).  *best_ms receives
  * the best time of one exec.  Synchronises the stream.  Index-pair plans:
- * SPINSUM_ERR_UNSUPPORTED. */
+ * SPINSUM_ERR_UNSUPPORTED.  Batched plans: in/out are the DEVICE arrays of
+ * block pointers of spinsum_exec_batched; the candidates are the size up to
+ * which whole cubes are packed into one work item (8 to 64 KiB) and one
+ * workgroup per item against persistent workgroups walking the item list;
+ * best->cubes_per_wg receives the item size in KiB and best->variant 1 for
+ * the persistent launch, 0 otherwise. */
 spinsum_status spinsum_autotune(spinsum_plan_t plan, void* in, void* out, void* stream,
                                 const char* cache_path, spinsum_tile_t* best,
                                 float* best_ms);

@@ -85,7 +85,8 @@ class _Info(ctypes.Structure):
                 ("fits_lds", ctypes.c_int), ("items_per_cube", ctypes.c_int),
                 ("item_tiles", ctypes.c_int), ("chunks_per_thread", ctypes.c_int),
                 ("rep_lds_bytes", ctypes.c_int64), ("inner", ctypes.c_int),
-                ("pair_extent", ctypes.c_int), ("nt_stores", ctypes.c_int)]
+                ("pair_extent", ctypes.c_int), ("batch_item_bytes", ctypes.c_int64),
+                ("batch_persistent", ctypes.c_int), ("nt_stores", ctypes.c_int)]
 
 
 _vp = ctypes.c_void_p
@@ -384,11 +385,19 @@ def spinsum_graph_destroy(graph: Graph):
     graph.__del__()
 
 
-def spinsum_autotune(plan: Plan, inp: torch.Tensor, out: torch.Tensor, stream=None,
-                     cache_path: Optional[str] = None):
-    """Time tile candidates on these buffers (overwritten) and keep the best."""
-    a = _tensor_ptr(inp, plan, plan.shape, "input")
-    b = _tensor_ptr(out, plan, plan.shape, "output")
+def spinsum_autotune(plan: Plan, inp, out, stream=None, cache_path: Optional[str] = None):
+    """Time tile candidates on these buffers (overwritten) and keep the best.
+    Batched plans take one tensor per block in `inp` and `out` (lists) and
+    tune the whole-cube item size and the persistent launch; the result's
+    cubes_per_wg is the item size in KiB and variant 1 the persistent
+    launch."""
+    keep = None
+    if plan.batched:
+        keep = PointerArrays(plan, inp, out)
+        a, b = keep.d_in.data_ptr(), keep.d_out.data_ptr()
+    else:
+        a = _tensor_ptr(inp, plan, plan.shape, "input")
+        b = _tensor_ptr(out, plan, plan.shape, "output")
     best = _Tile()
     ms = ctypes.c_float(0)
     cp = cache_path.encode() if cache_path else None

@@ -1143,22 +1143,15 @@ __global__ void __launch_bounds__(kThreads) k_pipe(const ExecArgs<T> a) {
   }
 }
 
-// Batched: one work item of the cost-sorted list per workgroup (the
-// hardware dispatcher is the queue), XCD-grouped like the single-tensor
-// kernels.  Whole-cube items (every block whose cube fits) are copied as one
-// contiguous run straight into LDS, with their representative lists behind
-// them; tile-orbit items of larger cubes go through registers.
+// Batched: one work item of the cost-sorted list.  Whole-cube items (every
+// block whose cube fits) are copied as one contiguous run straight into LDS,
+// with their representative lists behind them; tile-orbit items of larger
+// cubes go through registers.
 template <typename T, int D, int VW>
-__global__ void __launch_bounds__(kThreads) k_batched(const BatchArgs<T> a) {
+__device__ __forceinline__ void batched_item(const BatchArgs<T>& a, int64_t it,
+                                             unsigned char* smem) {
   typedef typename VecT<T, VW>::type V;
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
-  int64_t it;
-  if (a.xcd_per > 0)
-    it = (int64_t)(blockIdx.x & 7u) * a.xcd_per + (int64_t)(blockIdx.x >> 3);
-  else
-    it = blockIdx.x;
-  if (it >= a.nitems) return;
   const cptr<BatchItem> item = as_const(a.items) + it;
   const int blk = item->block;
   const int64_t icube0 = item->cube0;
@@ -1207,6 +1200,41 @@ __global__ void __launch_bounds__(kThreads) k_batched(const BatchArgs<T> a) {
   combine_item<T, D, false, false>(g, cod, a.reps, coef, 1, incubes, lds);
   __syncthreads();
   store_item<T, D, VW, true>(g, tinfo, ntiles, ragged, nchunks, dst, lds);
+}
+
+// One item per workgroup (the hardware dispatcher is the queue), or, with
+// PERSIST, a grid sized to the occupancy whose workgroups walk the list:
+// workgroup j of XCD x takes items j, j + stride, ... of that XCD's
+// contiguous range (stride = workgroups per XCD), so the workgroups of one
+// XCD work on neighbouring items at any time.
+template <typename T, int D, int VW, bool PERSIST>
+__global__ void __launch_bounds__(kThreads) k_batched(const BatchArgs<T> a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  if constexpr (!PERSIST) {
+    int64_t it;
+    if (a.xcd_per > 0)
+      it = (int64_t)(blockIdx.x & 7u) * a.xcd_per + (int64_t)(blockIdx.x >> 3);
+    else
+      it = blockIdx.x;
+    if (it >= a.nitems) return;
+    batched_item<T, D, VW>(a, it, smem);
+  } else {
+    int64_t first, stride, end;
+    if (a.xcd_per > 0) {
+      const int64_t x = blockIdx.x & 7u;
+      first = x * a.xcd_per + (blockIdx.x >> 3);
+      stride = gridDim.x >> 3;
+      end = (x + 1) * a.xcd_per < a.nitems ? (x + 1) * a.xcd_per : a.nitems;
+    } else {
+      first = blockIdx.x;
+      stride = gridDim.x;
+      end = a.nitems;
+    }
+    for (int64_t it = first; it < end; it += stride) {
+      batched_item<T, D, VW>(a, it, smem);
+      __syncthreads();  // the next item's loads reuse the LDS
+    }
+  }
 }
 
 // Coefficient gradient: c_p = <gr, P_p x> for every permutation p of the
@@ -1406,16 +1434,21 @@ const void* cgrad_kernel() {
   return (const void*)k_cgrad<T, D>;
 }
 
-template <typename T, int D>
-const void* batched_kernel(int vw) {
+template <typename T, int D, bool PERSIST>
+const void* batched_kernel_p(int vw) {
   if constexpr (sizeof(T) == 8) {
-    if (vw == 2) return (const void*)k_batched<T, D, 2>;
-    return (const void*)k_batched<T, D, 1>;
+    if (vw == 2) return (const void*)k_batched<T, D, 2, PERSIST>;
+    return (const void*)k_batched<T, D, 1, PERSIST>;
   } else {
-    if (vw == 4) return (const void*)k_batched<T, D, 4>;
-    if (vw == 2) return (const void*)k_batched<T, D, 2>;
-    return (const void*)k_batched<T, D, 1>;
+    if (vw == 4) return (const void*)k_batched<T, D, 4, PERSIST>;
+    if (vw == 2) return (const void*)k_batched<T, D, 2, PERSIST>;
+    return (const void*)k_batched<T, D, 1, PERSIST>;
   }
+}
+
+template <typename T, int D>
+const void* batched_kernel(int vw, bool persist) {
+  return persist ? batched_kernel_p<T, D, true>(vw) : batched_kernel_p<T, D, false>(vw);
 }
 
 }  // namespace
@@ -1424,7 +1457,7 @@ const void* batched_kernel(int vw) {
 // spinsum_kern_<type>_d<d>.hip.
 #define SPINSUM_DECLARE_PICK(tag, d)                                                    \
   const void* pick_##tag##_d##d(int kind, int vw, bool chain, bool nts, int maxc);     \
-  const void* pick_batched_##tag##_d##d(int vw);                                       \
+  const void* pick_batched_##tag##_d##d(int vw, bool persist);                         \
   const void* pick_cgrad_##tag##_d##d();
 SPINSUM_DECLARE_PICK(f64, 2)
 SPINSUM_DECLARE_PICK(f64, 3)

@@ -32,15 +32,15 @@ const void* pick_kernel(int d, int kind, int vw, bool chain, bool nts, int maxc)
 }
 
 template <typename T>
-const void* pick_batched(int d, int vw) {
+const void* pick_batched(int d, int vw, bool persist) {
   if constexpr (sizeof(T) == 8) {
-    if (d == 2) return pick_batched_f64_d2(vw);
-    if (d == 3) return pick_batched_f64_d3(vw);
-    return pick_batched_f64_d4(vw);
+    if (d == 2) return pick_batched_f64_d2(vw, persist);
+    if (d == 3) return pick_batched_f64_d3(vw, persist);
+    return pick_batched_f64_d4(vw, persist);
   } else {
-    if (d == 2) return pick_batched_f32_d2(vw);
-    if (d == 3) return pick_batched_f32_d3(vw);
-    return pick_batched_f32_d4(vw);
+    if (d == 2) return pick_batched_f32_d2(vw, persist);
+    if (d == 3) return pick_batched_f32_d3(vw, persist);
+    return pick_batched_f32_d4(vw, persist);
   }
 }
 
@@ -215,12 +215,17 @@ spinsum_status launch_batched(spinsum_plan_s* P, const void* const* in, void* co
   a.items = reinterpret_cast<const BatchItem*>(P->d_items);
   a.nitems = (int64_t)P->items.size();
   a.lds_tile_bytes = (int32_t)(((size_t)P->batch_lds_elems * sizeof(T) + 15) / 16 * 16);
-  const void* k = pick_batched<T>(P->d, P->batch_vw);
+  const bool persist = P->batch_persistent != 0;
+  const void* k = pick_batched<T>(P->d, P->batch_vw, persist);
   const size_t shmem = (size_t)a.lds_tile_bytes + (size_t)P->batch_rep_bytes;
   spinsum_status st = prepare_kernel(P, k, shmem);
   if (st != SPINSUM_OK) return st;
   int64_t grid;
-  if (P->flags & SPINSUM_FLAG_NO_XCD_REMAP) {
+  if (persist) {
+    st = persistent_grid(P, k, kThreads, shmem, a.nitems, &grid);
+    if (st != SPINSUM_OK) return st;
+    a.xcd_per = (P->flags & SPINSUM_FLAG_NO_XCD_REMAP) ? 0 : (a.nitems + 7) / 8;
+  } else if (P->flags & SPINSUM_FLAG_NO_XCD_REMAP) {
     a.xcd_per = 0;
     grid = a.nitems;
   } else {

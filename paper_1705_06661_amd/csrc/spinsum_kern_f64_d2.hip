@@ -8,7 +8,7 @@ const void* pick_f64_d2(int kind, int vw, bool chain, bool nts, int maxc) {
   return pick_d<double, 2>(kind, vw, chain, nts, maxc);
 }
 
-const void* pick_batched_f64_d2(int vw) { return batched_kernel<double, 2>(vw); }
+const void* pick_batched_f64_d2(int vw, bool persist) { return batched_kernel<double, 2>(vw, persist); }
 
 const void* pick_cgrad_f64_d2() { return cgrad_kernel<double, 2>(); }
 

@@ -8,7 +8,7 @@ const void* pick_f64_d3(int kind, int vw, bool chain, bool nts, int maxc) {
   return pick_d<double, 3>(kind, vw, chain, nts, maxc);
 }
 
-const void* pick_batched_f64_d3(int vw) { return batched_kernel<double, 3>(vw); }
+const void* pick_batched_f64_d3(int vw, bool persist) { return batched_kernel<double, 3>(vw, persist); }
 
 const void* pick_cgrad_f64_d3() { return cgrad_kernel<double, 3>(); }
 

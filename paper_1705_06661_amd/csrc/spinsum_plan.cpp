@@ -1022,41 +1022,21 @@ extern "C" spinsum_status spinsum_plan(spinsum_plan_t* plan, int ndim, const int
   return SPINSUM_OK;
 }
 
-extern "C" spinsum_status spinsum_plan_batched(spinsum_plan_t* plan, int nblocks, const int* ndims,
-                                               const int64_t* const* extents, int d, int nstages,
-                                               const int* nterms, const int* perms,
-                                               const double* alpha, spinsum_dtype dtype,
-                                               int inplace, unsigned flags) {
-  if (plan == nullptr) return SPINSUM_ERR_INVALID_ARG;
-  *plan = nullptr;
-  spinsum_status st = common_checks(d, dtype, inplace);
-  if (st != SPINSUM_OK) return st;
-  if (nblocks < 1 || nblocks > (1 << 20) || ndims == nullptr || extents == nullptr)
-    return SPINSUM_ERR_INVALID_ARG;
-  std::vector<int> ns(nblocks);
-  std::vector<int64_t> cs(nblocks);
-  for (int b = 0; b < nblocks; ++b) {
-    if (ndims[b] < d) return SPINSUM_ERR_INVALID_ARG;
-    int inner_b = 1;
-    st = shape_info(ndims[b], extents[b], ndims[b] - d, d, &ns[b], &cs[b], &inner_b);
-    if (st != SPINSUM_OK) return st;
-    if (ns[b] > 0 && ipow(ns[b], d) >= (1ll << 31)) return SPINSUM_ERR_UNSUPPORTED;
-  }
-  spinsum_plan_s* P = new (std::nothrow) spinsum_plan_s();
-  if (!P) return SPINSUM_ERR_OUT_OF_MEMORY;
-  P->batched = true;
-  P->nblocks = nblocks;
-  P->d = d;
-  P->dtype = dtype;
-  P->inplace = inplace;
-  P->flags = flags;
-  P->G.init(d);
-  st = set_terms(P, nstages, nterms, perms, alpha);
-  if (st != SPINSUM_OK) {
-    delete P;
-    return st;
-  }
-  query_device(P);
+// Tables of a batched plan for one choice of the whole-cube item size
+// (item_bytes 0: the default rule below).  Also used by the autotuner.
+spinsum_status spinsum::build_batched(spinsum_plan_s* P, int64_t item_bytes) {
+  const int nblocks = P->nblocks, d = P->d;
+  const std::vector<int>& ns = P->bns;
+  const std::vector<int64_t>& cs = P->bcs;
+  spinsum_status st = SPINSUM_OK;
+  P->btil.clear();
+  P->blocks.clear();
+  P->block_elems.clear();
+  P->items.clear();
+  P->elems = 0;
+  P->ncubes = 0;
+  P->batch_lds_elems = 0;
+  P->batch_rep_bytes = 0;
   // tiles: whole cubes when they fit (copied as one contiguous run, any
   // extent), packed up to the largest cube of the batch (at least 8 KiB, at
   // most 40 KiB) so that every workgroup moves about the same bytes; tile
@@ -1067,6 +1047,7 @@ extern "C" spinsum_status spinsum_plan_batched(spinsum_plan_t* plan, int nblocks
   for (int b = 0; b < nblocks; ++b)
     if (ns[b] > 0 && cs[b] > 0 && ipow(ns[b], d) * esz <= 40 * 1024)
       target = std::max<int64_t>(target, ipow(ns[b], d) * esz);
+  if (item_bytes > 0) target = item_bytes;
   int vmax = 16 / esz;
   for (int b = 0; b < nblocks; ++b)
     if (ns[b] > 0 && cs[b] > 0 && ipow(ns[b], d) * esz > 40 * 1024)
@@ -1091,10 +1072,7 @@ extern "C" spinsum_status spinsum_plan_batched(spinsum_plan_t* plan, int nblocks
       }
     }
     if (st == SPINSUM_OK) st = build_tiling(*P, ns[b], cs[b], t, vmax, &P->btil[b]);
-    if (st != SPINSUM_OK) {
-      delete P;
-      return st;
-    }
+    if (st != SPINSUM_OK) return st;
     Tiling& T = P->btil[b];
     std::memset(&P->blocks[b], 0, sizeof(BatchBlock));
     P->blocks[b].g = T.g;
@@ -1139,18 +1117,64 @@ extern "C" spinsum_status spinsum_plan_batched(spinsum_plan_t* plan, int nblocks
   };
   std::stable_sort(P->items.begin(), P->items.end(),
                    [&](const BatchItem& a, const BatchItem& b) { return cost(a) > cost(b); });
-  if ((int64_t)P->items.size() >= (1ll << 31)) {
-    delete P;
-    return SPINSUM_ERR_UNSUPPORTED;
-  }
+  if ((int64_t)P->items.size() >= (1ll << 31)) return SPINSUM_ERR_UNSUPPORTED;
   // behind the tiles: the representative lists (whole cubes) or the tile
   // table (tile orbits)
   P->batch_rep_bytes = std::max<int64_t>(P->batch_rep_bytes, 2 * kMaxDF * 4);
-  if ((P->batch_lds_elems * elem_size(*P) + 15) / 16 * 16 + P->batch_rep_bytes > P->lds_limit) {
-    delete P;
+  if ((P->batch_lds_elems * elem_size(*P) + 15) / 16 * 16 + P->batch_rep_bytes > P->lds_limit)
     return SPINSUM_ERR_UNSUPPORTED;
-  }
   P->batch_grid = (int)std::min<int64_t>((int64_t)P->items.size(), INT32_MAX);
+  P->batch_item_bytes = target;
+  return SPINSUM_OK;
+}
+
+extern "C" spinsum_status spinsum_plan_batched(spinsum_plan_t* plan, int nblocks, const int* ndims,
+                                               const int64_t* const* extents, int d, int nstages,
+                                               const int* nterms, const int* perms,
+                                               const double* alpha, spinsum_dtype dtype,
+                                               int inplace, unsigned flags) {
+  if (plan == nullptr) return SPINSUM_ERR_INVALID_ARG;
+  *plan = nullptr;
+  spinsum_status st = common_checks(d, dtype, inplace);
+  if (st != SPINSUM_OK) return st;
+  if (nblocks < 1 || nblocks > (1 << 20) || ndims == nullptr || extents == nullptr)
+    return SPINSUM_ERR_INVALID_ARG;
+  std::vector<int> ns(nblocks);
+  std::vector<int64_t> cs(nblocks);
+  for (int b = 0; b < nblocks; ++b) {
+    if (ndims[b] < d) return SPINSUM_ERR_INVALID_ARG;
+    int inner_b = 1;
+    st = shape_info(ndims[b], extents[b], ndims[b] - d, d, &ns[b], &cs[b], &inner_b);
+    if (st != SPINSUM_OK) return st;
+    if (ns[b] > 0 && ipow(ns[b], d) >= (1ll << 31)) return SPINSUM_ERR_UNSUPPORTED;
+  }
+  spinsum_plan_s* P = new (std::nothrow) spinsum_plan_s();
+  if (!P) return SPINSUM_ERR_OUT_OF_MEMORY;
+  P->batched = true;
+  P->nblocks = nblocks;
+  P->d = d;
+  P->dtype = dtype;
+  P->inplace = inplace;
+  P->flags = flags;
+  P->G.init(d);
+  st = set_terms(P, nstages, nterms, perms, alpha);
+  if (st != SPINSUM_OK) {
+    delete P;
+    return st;
+  }
+  query_device(P);
+  P->bns = ns;
+  P->bcs = cs;
+  {
+    int64_t item_bytes = 0;
+    int persistent = 0;
+    if (batched_cache_lookup(*P, &item_bytes, &persistent)) P->batch_persistent = persistent;
+    st = build_batched(P, item_bytes);
+  }
+  if (st != SPINSUM_OK) {
+    delete P;
+    return st;
+  }
   st = upload_tables(P);
   if (st != SPINSUM_OK) {
     free_device(P);
@@ -1199,6 +1223,8 @@ extern "C" spinsum_status spinsum_plan_get_info(spinsum_plan_t P, spinsum_plan_i
   info->inner = P->inner;
   info->pair_extent = P->pair ? P->pv : 0;
   info->nt_stores = P->batched ? 1 : P->T.nts;
+  info->batch_item_bytes = P->batched ? P->batch_item_bytes : 0;
+  info->batch_persistent = P->batched ? P->batch_persistent : 0;
   if (!P->batched) {
     info->bl = P->T.g.bl;
     info->variant = P->tile.variant;

@@ -91,6 +91,10 @@ struct spinsum_plan_s {
   int64_t batch_lds_elems = 0;
   int64_t batch_rep_bytes = 0;  // LDS behind the tiles: representative lists / tile table
   int batch_grid = 0;
+  std::vector<int> bns;          // group extent of each block
+  std::vector<int64_t> bcs;      // spectator cubes of each block
+  int64_t batch_item_bytes = 0;  // whole-cube items are packed up to this size
+  int batch_persistent = 0;      // 1: persistent workgroups walk the item list
 
   // device
   bool has_dev = false;
@@ -119,8 +123,10 @@ spinsum_status choose_tile(const spinsum_plan_s& P, int n, int64_t ncubes, int v
                            spinsum_tile_t* tile);
 int max_vector_width(const spinsum_plan_s& P, int64_t row);
 spinsum_status upload_tables(spinsum_plan_s* P);
+spinsum_status build_batched(spinsum_plan_s* P, int64_t item_bytes);
 void free_device(spinsum_plan_s* P);
 int elem_size(const spinsum_plan_s& P);
 // Implemented in spinsum_tune.cpp
 bool cache_lookup(const spinsum_plan_s& P, spinsum_tile_t* tile);
+bool batched_cache_lookup(const spinsum_plan_s& P, int64_t* item_bytes, int* persistent);
 }  // namespace spinsum

@@ -9,6 +9,8 @@
 // Cache file: plain text, one line per configuration:
 //   <key> <bl> <cubes_per_wg> <threads> <lds_pad> <variant> <item_tiles> <ms>
 // key = d<d>_n<N>_r<inner run>_<f64|f32>_ip<0|1>_c<floor(log2(ncubes))>_<arch>.
+// Batched plans: <key> <whole-cube item KiB> <persistent 0|1> <ms>, with
+// key = batch_b<blocks>_e<elements>_d<d>_<f64|f32>_ip<0|1>_<arch>.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -47,6 +49,63 @@ static std::string cache_key(const spinsum_plan_s& P) {
   return os.str();
 }
 
+static std::string batched_key(const spinsum_plan_s& P) {
+  int64_t elems = 0;
+  for (size_t b = 0; b < P.bns.size(); ++b) {
+    int64_t c = P.bcs[b];
+    for (int m = 0; m < P.d; ++m) c *= P.bns[b];
+    elems += c;
+  }
+  std::ostringstream os;
+  os << "batch_b" << P.nblocks << "_e" << elems << "_d" << P.d << "_"
+     << (P.dtype == SPINSUM_F32 ? "f32" : "f64") << "_ip" << P.inplace << "_" << arch_name(P.device);
+  return os.str();
+}
+
+bool batched_cache_lookup(const spinsum_plan_s& P, int64_t* item_bytes, int* persistent) {
+  const char* path = std::getenv("SPINSUM_AUTOTUNE_CACHE");
+  if (path == nullptr || *path == 0) return false;
+  std::ifstream f(path);
+  if (!f) return false;
+  const std::string key = batched_key(P);
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    std::istringstream is(line);
+    std::string k;
+    int64_t kib = 0;
+    int pers = 0;
+    double ms = 0;
+    if (!(is >> k >> kib >> pers >> ms) || k != key) continue;
+    if (kib < 1 || kib > 160 || (pers != 0 && pers != 1)) continue;
+    *item_bytes = kib * 1024;
+    *persistent = pers;
+    found = true;  // the last matching line wins
+  }
+  return found;
+}
+
+static void write_cache_line(const char* path, const std::string& key, const std::string& line) {
+  std::vector<std::string> keep;
+  {
+    std::ifstream f(path);
+    std::string l;
+    while (f && std::getline(f, l)) {
+      std::istringstream is(l);
+      std::string k;
+      if (is >> k && k == key) continue;
+      if (!l.empty()) keep.push_back(l);
+    }
+  }
+  keep.push_back(line);
+  std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream o(tmp, std::ios::trunc);
+    for (const std::string& l : keep) o << l << "\n";
+  }
+  std::rename(tmp.c_str(), path);
+}
+
 bool cache_lookup(const spinsum_plan_s& P, spinsum_tile_t* tile) {
   const char* path = std::getenv("SPINSUM_AUTOTUNE_CACHE");
   if (path == nullptr || *path == 0) return false;
@@ -74,27 +133,72 @@ bool cache_lookup(const spinsum_plan_s& P, spinsum_tile_t* tile) {
 static void cache_store(const spinsum_plan_s& P, const char* path, const spinsum_tile_t& t,
                         float ms) {
   const std::string key = cache_key(P);
-  std::vector<std::string> keep;
-  {
-    std::ifstream f(path);
-    std::string line;
-    while (f && std::getline(f, line)) {
-      std::istringstream is(line);
-      std::string k;
-      if (is >> k && k == key) continue;
-      if (!line.empty()) keep.push_back(line);
-    }
-  }
   std::ostringstream os;
   os << key << " " << t.bl << " " << t.cubes_per_wg << " " << t.threads << " " << t.lds_pad << " "
      << t.variant << " " << t.item_tiles << " " << ms;
-  keep.push_back(os.str());
-  std::string tmp = std::string(path) + ".tmp";
-  {
-    std::ofstream o(tmp, std::ios::trunc);
-    for (const std::string& l : keep) o << l << "\n";
+  write_cache_line(path, key, os.str());
+}
+
+// Batched plans: the whole-cube item size (bytes each workgroup moves) and
+// one workgroup per item against persistent workgroups walking the list.
+static spinsum_status autotune_batched(spinsum_plan_t P, const void* in, void* out,
+                                       hipStream_t s, const char* cache_path,
+                                       spinsum_tile_t* best, float* best_ms) {
+  const void* const* ins = reinterpret_cast<const void* const*>(in);
+  void* const* outs = reinterpret_cast<void* const*>(out);
+  const int64_t keep_bytes = P->batch_item_bytes;
+  const int keep_pers = P->batch_persistent;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipGetLastError();
+    return SPINSUM_ERR_HIP;
   }
-  std::rename(tmp.c_str(), path);
+  bool have = false;
+  int64_t win_bytes = 0;
+  int win_pers = 0;
+  float win_ms = 0;
+  for (int pers = 0; pers <= 1; ++pers)
+    for (int64_t kib : {8, 16, 24, 32, 40, 48, 64}) {
+      P->batch_persistent = pers;
+      if (build_batched(P, kib * 1024) != SPINSUM_OK || upload_tables(P) != SPINSUM_OK) continue;
+      if (spinsum_exec_batched(P, ins, outs, s) != SPINSUM_OK) continue;  // warm-up
+      float ms_min = 1e30f;
+      bool ok = true;
+      for (int r = 0; r < 3 && ok; ++r) {
+        (void)hipEventRecord(e0, s);
+        ok = spinsum_exec_batched(P, ins, outs, s) == SPINSUM_OK;
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms_min = std::min(ms_min, ms);
+      }
+      if (ok && (!have || ms_min < win_ms)) {
+        have = true;
+        win_bytes = kib * 1024;
+        win_pers = pers;
+        win_ms = ms_min;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  P->batch_persistent = have ? win_pers : keep_pers;
+  spinsum_status st = build_batched(P, have ? win_bytes : keep_bytes);
+  if (st == SPINSUM_OK) st = upload_tables(P);
+  if (st != SPINSUM_OK) return st;
+  if (best) {
+    std::memset(best, 0, sizeof(*best));
+    best->cubes_per_wg = (int)(P->batch_item_bytes / 1024);
+    best->threads = 256;
+    best->variant = P->batch_persistent;
+  }
+  if (best_ms) *best_ms = have ? win_ms : 0.0f;
+  if (have && cache_path != nullptr && *cache_path) {
+    std::ostringstream os;
+    os << batched_key(*P) << " " << win_bytes / 1024 << " " << win_pers << " " << win_ms;
+    write_cache_line(cache_path, batched_key(*P), os.str());
+  }
+  return have ? SPINSUM_OK : SPINSUM_ERR_UNSUPPORTED;
 }
 
 }  // namespace spinsum
@@ -104,8 +208,12 @@ using namespace spinsum;
 extern "C" spinsum_status spinsum_autotune(spinsum_plan_t P, void* in, void* out, void* stream,
                                            const char* cache_path, spinsum_tile_t* best,
                                            float* best_ms) {
-  if (P == nullptr || P->batched) return SPINSUM_ERR_INVALID_ARG;
+  if (P == nullptr) return SPINSUM_ERR_INVALID_ARG;
   if (!P->has_dev) return SPINSUM_ERR_NO_DEVICE;
+  if (P->batched) {
+    if (in == nullptr || out == nullptr) return SPINSUM_ERR_INVALID_ARG;
+    return autotune_batched(P, in, out, (hipStream_t)stream, cache_path, best, best_ms);
+  }
   if (P->pair) return SPINSUM_ERR_UNSUPPORTED;
   if (P->elems == 0) return SPINSUM_OK;
   hipStream_t s = (hipStream_t)stream;

@@ -744,3 +744,37 @@ def test_autograd_inner_runs_and_index_pairs(shape, gf, d, pairs):
                                    rtol=0, atol=1e-12)
         np.testing.assert_allclose(y.detach().cpu().numpy().ravel(),
                                    M @ x.detach().cpu().numpy().ravel(), rtol=0, atol=1e-12)
+
+
+def test_batched_autotune_and_persistent_launch(tmp_path, monkeypatch):
+    """The batched autotuner (item size, persistent launch) and the
+    persistent launch itself give the per-block results bit for bit."""
+    blocks = _small_blocks()
+    shapes = [(v, v, v, o, o, o) for v, o in blocks]
+    xs = [gpu_uniform(s, 60 + k) for k, s in enumerate(shapes)]
+    singles = [run(mk(s, [workloads.CONFIG_3D_ALPHA], 3), x) for s, x in zip(shapes, xs)]
+    cache = str(tmp_path / "tune.txt")
+    bp = ss.spinsum_plan_batched(shapes, 3, [workloads.CONFIG_3D_ALPHA])
+    outs = [torch.empty_like(x) for x in xs]
+    best, ms = ss.spinsum_autotune(bp, xs, outs, cache_path=cache)
+    info = ss.spinsum_plan_get_info(bp)
+    assert ms > 0 and best["cubes_per_wg"] * 1024 == info["batch_item_bytes"]
+    assert best["variant"] == info["batch_persistent"]
+    assert "batch_b" in open(cache).read()
+    ss.spinsum_exec_batched(bp, xs, outs)
+    torch.cuda.synchronize()
+    for k in range(len(xs)):
+        assert torch.equal(outs[k], singles[k]), k
+    # the persistent launch, forced through a cache line
+    elems = sum(v ** 3 * o ** 3 for v, o in blocks)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    forced = tmp_path / "forced.txt"
+    forced.write_text(f"batch_b{len(blocks)}_e{elems}_d3_f64_ip1_{arch} 16 1 1.0\n")
+    monkeypatch.setenv("SPINSUM_AUTOTUNE_CACHE", str(forced))
+    pp = ss.spinsum_plan_batched(shapes, 3, [workloads.CONFIG_3D_ALPHA], inplace=True)
+    assert ss.spinsum_plan_get_info(pp)["batch_persistent"] == 1
+    ys = [x.clone() for x in xs]
+    ss.spinsum_exec_batched(pp, ys, ys)
+    torch.cuda.synchronize()
+    for k in range(len(xs)):
+        assert torch.equal(ys[k], singles[k]), k

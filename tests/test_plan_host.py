@@ -352,6 +352,27 @@ def test_batched_plan_tables():
     for b in (0, 17, 199):
         ok, why = ss.spinsum_plan_check_ownership(p, b)
         assert ok, why
+    # whole cubes are packed up to the largest cube of at most 40 KiB (o = 16
+    # here: 32 KiB), one workgroup per item unless a tuned cache says so
+    assert info["batch_item_bytes"] == 16 ** 3 * 8 and info["batch_persistent"] == 0
+
+
+def test_batched_plan_reads_a_tuned_cache_line(tmp_path, monkeypatch):
+    """A batched cache line (item KiB, persistent flag) is applied when the
+    plan is made; other plans' lines are ignored."""
+    blocks = [(4, 6), (5, 3), (3, 8)]
+    shapes = [(v, v, v, o, o, o) for v, o in blocks]
+    elems = sum(v ** 3 * o ** 3 for v, o in blocks)
+    cache = tmp_path / "tune.txt"
+    cache.write_text(f"batch_b3_e{elems}_d3_f64_ip1_gfx950 16 1 0.5\n"
+                     f"batch_b3_e{elems + 1}_d3_f64_ip1_gfx950 24 0 0.5\n")
+    monkeypatch.setenv("SPINSUM_AUTOTUNE_CACHE", str(cache))
+    p = ss.spinsum_plan_batched(shapes, 3, [workloads.CONFIG_3D_ALPHA], inplace=True, flags=HOST)
+    info = ss.spinsum_plan_get_info(p)
+    assert info["batch_item_bytes"] == 16 * 1024 and info["batch_persistent"] == 1
+    for b in range(3):
+        ok, why = ss.spinsum_plan_check_ownership(p, b)
+        assert ok, why
 
 
 def test_set_tile_rebuilds_and_rejects():
