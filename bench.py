@@ -103,6 +103,29 @@ def form_entry(nbytes, ms, ref_gbps=None):
     return d
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# The paper's own measurements, quoted for context with its hardware (its
+# text gives relative numbers only): Alg. 6 against the NCC / CFOUR
+# implementation on Table II, FP64.
+PAPER_CONTEXT = {
+    "speedup_over_ncc": {"all_sizes": "2.4-5.5x", "small": "2.4-4.3x", "medium": "2.4-3.8x",
+                         "large": "3.3-5.5x"},
+    "in_place_over_out_of_place": "up to 1.2x",
+    "hardware": "2x Intel Xeon E5-2680 v3, 24 threads",
+    "stream_copy_GiBps": 101.2,
+}
+
+
 def cpu_baseline(seconds: float, nslabs: int):
     """The oracle on a bounded sample of the headline workload: consecutive
     whole 32^3 spectator cubes of the slabs, regenerated on the host from
@@ -123,11 +146,19 @@ def cpu_baseline(seconds: float, nslabs: int):
         total += time.perf_counter() - t0
         done += chunk
     elems = done * cube
+    # the same oracle on one thread, over the first chunk (a few seconds)
+    x = workloads.uniform_numpy(chunk * cube, 1000, offset=0).reshape(chunk, 32, 32, 32)
+    t0 = time.perf_counter()
+    oracle.spinsum(x, workloads.CONFIG_3D_ALPHA, 1, 3, nthreads=1)
+    t1 = time.perf_counter() - t0
     return {"value": round(2 * elems * 8 / total / 1e9, 4), "unit": "GB/s", "cores": threads,
             "kind": "oracle",
+            "one_thread_value": round(2 * chunk * cube * 8 / t1 / 1e9, 4),
+            "cpu_model": cpu_model(),
             "sample": f"the first {done} spectator cubes (32^3 each, {elems} elements, fp64) of the "
                       f"{nslabs} slabs of the v=64 o=32 in-place workload, in slab order, "
-                      f"{total:.1f} s of oracle time on {threads} threads"}
+                      f"{total:.1f} s of oracle time on {threads} threads; one_thread_value: "
+                      f"the first {chunk} of them on one thread"}
 
 
 # The paper's three tensor sizes (Sec. 5.1: about 70, 320 and 1200 MiB),
@@ -381,6 +412,7 @@ def main():
         for size in ("small", "medium", "large"):
             out[f"table2_{size}"] = table2_sweep(ss, workloads, dev, stream, size)
 
+    out["paper_context"] = PAPER_CONTEXT
     if not args.no_cpu_baseline:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds, nslabs)
