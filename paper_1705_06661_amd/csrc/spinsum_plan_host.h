@@ -119,8 +119,9 @@ namespace spinsum {
 // Implemented in spinsum_plan.cpp
 spinsum_status build_tiling(const spinsum_plan_s& P, int n, int64_t ncubes,
                             const spinsum_tile_t& tile, int vw, Tiling* out);
+// single: a single-tensor plan (may pick a packed two-blocks-per-axis tile)
 spinsum_status choose_tile(const spinsum_plan_s& P, int n, int64_t ncubes, int vw,
-                           spinsum_tile_t* tile);
+                           spinsum_tile_t* tile, bool single);
 int max_vector_width(const spinsum_plan_s& P, int64_t row);
 spinsum_status upload_tables(spinsum_plan_s* P);
 spinsum_status build_batched(spinsum_plan_s* P, int64_t item_bytes);

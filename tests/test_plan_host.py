@@ -311,7 +311,7 @@ def test_lds_footprint_matches_eq11():
 
 
 @pytest.mark.parametrize("name,bl,whole", [("3d_v16_o8", 8, True), ("3d_v64_o32_slab", 8, False),
-                                           ("4d_v24_o12_slab", 4, False), ("3d_v48_o24", 8, False)])
+                                           ("4d_v24_o12_slab", 6, False), ("3d_v48_o24", 8, False)])
 def test_default_tiles_of_the_workloads(name, bl, whole):
     w = workloads.WORKLOADS[name]
     p = ss.spinsum_plan(w["shape"], w["group_first"], w["d"], [workloads.CONFIG_3D_ALPHA] if w["d"] == 3
@@ -334,11 +334,48 @@ def test_default_tiles_follow_the_measured_rules():
                                   ((40, 40, 40, 20, 20, 20), "f64", 20, 1),
                                   ((32, 32, 32, 28, 28, 28), "f64", 8, 1),
                                   ((16, 16, 16, 40, 40, 40), "f64", 8, 1),
-                                  ((64, 64, 8, 32, 32, 32), "f32", 8, 1)]:
+                                  ((64, 64, 8, 32, 32, 32), "f32", 16, 1)]:
         p = plan(shape, alpha, dtype=dtype)
         info = ss.spinsum_plan_get_info(p)
         assert (info["bl"], info["cubes_per_wg"]) == (bl, cpw), shape
         assert info["variant"] == ss.SPINSUM_VARIANT_DIRECT_LDS
+
+
+@pytest.mark.parametrize("shape,d,dtype,bl,items,tiles", [
+    ((3, 12, 12, 12, 12), 4, "f64", 6, 3, 6),     # classes 1+4 | 6 | 4+1 tiles
+    ((3, 32, 32, 32), 3, "f32", 16, 2, 4),        # classes 1+3 | 3+1 tiles
+])
+def test_two_blocks_per_axis_tiles_pack_neighbouring_classes(shape, d, dtype, bl, items, tiles):
+    """Where the first default tile has rows shorter than 64 bytes, a tile
+    with two blocks per axis and wider rows is taken if two workgroups
+    still fit a CU; its orbits (the classes by number of upper blocks) are
+    packed in order, neighbouring classes together."""
+    terms = [[(tuple(range(d)), 1.0), (tuple(reversed(range(d))), -0.5)]]
+    p = plan(shape, terms, d=d, dtype=dtype)
+    info = ss.spinsum_plan_get_info(p)
+    assert info["bl"] == bl and info["norbits"] == d + 1
+    assert info["items_per_cube"] == items and info["item_tiles"] == tiles
+    assert info["threads"] == 512 and info["lds_bytes"] <= 80 * 1024
+    ok, why = ss.spinsum_plan_check_ownership(p)
+    assert ok, why
+    # rows of 64 bytes already: no change (3D 24^3 FP64 keeps bl = 8)
+    p = plan((2, 24, 24, 24), [[((0, 1, 2), 1.0)]])
+    assert ss.spinsum_plan_get_info(p)["bl"] == 8
+
+
+def test_small_orbits_are_packed_where_few_workgroups_fit():
+    """With fewer than four workgroups per CU (4D, 24-tile orbits of 4^4
+    tiles), the planner packs consecutive orbits up to the largest one; an
+    explicit tile keeps one orbit per item."""
+    p = plan((1, 16, 16, 16, 16), [[((0, 1, 2, 3), 1.0), ((1, 0, 2, 3), 2.0)]], d=4)
+    info = ss.spinsum_plan_get_info(p)
+    assert info["bl"] == 4 and info["item_tiles"] == 24
+    assert info["items_per_cube"] < info["norbits"]
+    ok, why = ss.spinsum_plan_check_ownership(p)
+    assert ok, why
+    ss.spinsum_plan_set_tile(p, 4)
+    info = ss.spinsum_plan_get_info(p)
+    assert info["items_per_cube"] == info["norbits"]
 
 
 def test_batched_plan_tables():
