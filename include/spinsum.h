@@ -116,8 +116,11 @@ typedef struct {
   int lds_pad;
   int variant;
   int item_tiles;  /* tile-orbit mode: 0 = one tile orbit per work item; > 0 =
-                      orbits of a cube packed (first fit, decreasing size) into
-                      items of at most max(item_tiles, largest orbit) tiles */
+                      runs of consecutive orbits of a cube (in the planner's
+                      orbit order, next fit) packed into items of at most
+                      max(item_tiles, largest orbit) tiles and 8 orbits.  A
+                      tile the planner picks itself (bl == 0) may pack; see
+                      spinsum_plan_info_t.items_per_cube */
 } spinsum_tile_t;
 
 typedef struct {
