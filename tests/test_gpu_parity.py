@@ -206,6 +206,28 @@ def test_orbit_groups_against_oracle(shape, d, bl, item_tiles):
             np.testing.assert_array_equal(run(p, xi).cpu().numpy(), refi)
 
 
+@pytest.mark.parametrize("shape,d,dtype", [((3, 12, 12, 12, 12), 4, torch.float64),
+                                           ((2, 32, 32, 32), 3, torch.float32),
+                                           ((2, 16, 16, 16, 16), 4, torch.float64)])
+def test_default_packed_tiles_against_oracle(shape, d, dtype):
+    """The planner's own packed tiles: two blocks per axis with neighbouring
+    classes in one item (12^4 FP64, 32^3 FP32), and consecutive orbits packed
+    where fewer than four workgroups fit a CU (16^4 FP64, 4^4 tiles)."""
+    _say("default packed", shape, d, dtype)
+    rng = np.random.default_rng(d + 40)
+    terms = [(p, float(rng.integers(-2, 9))) for p in itertools.permutations(range(d))]
+    x = gpu_uniform(shape, 41, dtype)
+    ref = ref_of(x, [terms], d)
+    xi = gpu_ints(shape, 42, dtype)
+    refi = ref_of(xi, [terms], d)
+    for inplace in (False, True):
+        p = mk(shape, [terms], d, dtype=dtype, inplace=inplace)
+        info = ss.spinsum_plan_get_info(p)
+        assert info["items_per_cube"] < info["norbits"], info
+        assert nerr(run(p, x).cpu().numpy(), ref) <= TOL[dtype], inplace
+        np.testing.assert_array_equal(run(p, xi).cpu().numpy(), refi)
+
+
 def test_factored_form_chained_and_expanded():
     shape = (4, 16, 16, 16)
     x = gpu_uniform(shape, 9)
