@@ -766,13 +766,13 @@ __global__ void __launch_bounds__(kMaxThreads) k_lds(const ExecArgs<T> a) {
 
 // Index-pair form: one tile orbit {sigma . c} of one pair block per
 // workgroup, c the orbit's sorted combined blocks (c_m = a_m * nb + b_m).
-// Lane r of wave 0 forms sigma_r . c; tiles are numbered in the order of
-// their first sigma, and slot r of the combine step is the tile of
-// sigma_r . c.  Tiles then go straight into LDS: whole group cubes (bl == N)
-// as one contiguous run each, with the run's 16-byte alignment shift folded
-// into the slot offsets; otherwise in 16-byte chunks of rows, as in k_lds.
-// LDS: [tiles (lds_tile_bytes) | representatives]; the tile list (PairInfo)
-// in a static LDS block.
+// Every wave forms the tile list itself: lane r forms sigma_r . c; tiles are
+// numbered in the order of their first sigma, and slot r of the combine step
+// is the tile of sigma_r . c.  Tiles then go straight into LDS: whole group
+// cubes (bl == N) as one contiguous run each, with the run's 16-byte
+// alignment shift folded into the slot offsets; otherwise in 16-byte chunks
+// of rows, as in k_lds.
+// LDS: [tiles (lds_tile_bytes) | representatives].
 
 // Entry k of the unrolled permutation table: element m of permutation r
 // (lexicographic) as a select chain, so that no register array is indexed
@@ -801,7 +801,6 @@ __global__ void __launch_bounds__(kMaxThreads) k_pair(const PairArgs<T> a) {
   constexpr int VW = 16 / sizeof(T);
   typedef typename VecT<T, VW>::type V;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  __shared__ PairInfo info;
   T* lds = reinterpret_cast<T*>(smem);
   int64_t item;
   if (a.xcd_per > 0)
@@ -817,57 +816,62 @@ __global__ void __launch_bounds__(kMaxThreads) k_pair(const PairArgs<T> a) {
   const int64_t orb = item - (int64_t)q * pg.norb;
   const T* src = a.in + cube0 * g.cube_elems;
   T* dst = a.out + cube0 * g.cube_elems;
-  // 1. the orbit's tile list
-  if (threadIdx.x < 64) {
-    const uint64_t pk = as_const(a.orbits)[orb];
-    int c[D];
-#pragma unroll
-    for (int m = 0; m < D; ++m) c[m] = (int)((pk >> (16 * m)) & 0xFFFFu);
-    const int r = (int)threadIdx.x;
-    const bool act = r < DF;
-    int t[D];
-    permuted_tuple<D>(pk, act ? r : 0, t, std::make_integer_sequence<int, D>{});
-    uint64_t key = 0;
-#pragma unroll
-    for (int m = 0; m < D; ++m) key |= (uint64_t)t[m] << (16 * m);
-    int first = r;
-    for (int r2 = DF - 1; r2 >= 0; --r2) {
-      const uint64_t k2 = ((uint64_t)(uint32_t)__shfl((int)(key >> 32), r2, 64) << 32) |
-                          (uint32_t)__shfl((int)(uint32_t)key, r2, 64);
-      if (r2 < r && k2 == key) first = r2;
-    }
-    const bool isfirst = act && first == r;
-    const uint64_t mask = __builtin_amdgcn_ballot_w64(isfirst);
-    const int slot = __builtin_popcountll(mask & ((1ull << first) - 1ull));
-    int shift = 0;
-    if (isfirst) {
-      int64_t off;
-      int32_t ext;
-      pair_tile(g, pg, D, t, &off, &ext);
-      if (pg.flat) shift = flat_shift<T>(src + off);
-      info.toff[slot] = off;
-      info.text[slot] = ext;
-      info.shift[slot] = shift;
-    }
-    const int fshift = __shfl(shift, act ? first : 0, 64);
-    if (act) info.sb[r] = slot * pg.tile_stride + fshift;
-    if (r == 0) {
-      info.ntiles = __builtin_popcountll(mask);
-      const int k = pair_key(g, pg, D, c);
-      info.rep_off = pg.rep_off[k];
-      info.rep_cnt = pg.rep_cnt[k];
-    }
-  }
-  __syncthreads();
-  const int ntl = __builtin_amdgcn_readfirstlane(info.ntiles);
-  const uint32_t rep_cnt = (uint32_t)__builtin_amdgcn_readfirstlane(info.rep_cnt);
-  const uint32_t rep_off = (uint32_t)__builtin_amdgcn_readfirstlane(info.rep_off);
-  // lane t of every wave holds tile t's origin and extents; the tile loops
-  // below take them with v_readlane (uniform index) instead of one LDS read
-  // per tile and chunk
+  // 1. the orbit's tile list, formed by every wave on its own (no barrier):
+  //    lane r forms sigma_r . c, the distinct tiles are numbered in first-
+  //    sigma order with a ballot, and lane t then holds tile t's origin,
+  //    extents and alignment shift; the tile loops below take them with
+  //    v_readlane (uniform index)
   const int lane = (int)(threadIdx.x & 63u);
-  const int64_t my_toff = (lane < ntl) ? info.toff[lane] : 0;
-  const int32_t my_text = (lane < ntl) ? info.text[lane] : 0;
+  const uint64_t pk = as_const(a.orbits)[orb];
+  int c[D];
+#pragma unroll
+  for (int m = 0; m < D; ++m) c[m] = (int)((pk >> (16 * m)) & 0xFFFFu);
+  const bool act = lane < DF;
+  int tt[D];
+  permuted_tuple<D>(pk, act ? lane : 0, tt, std::make_integer_sequence<int, D>{});
+  uint64_t key = 0;
+#pragma unroll
+  for (int m = 0; m < D; ++m) key |= (uint64_t)tt[m] << (16 * m);
+  int first = lane;
+  for (int r2 = DF - 1; r2 >= 0; --r2) {
+    const uint64_t k2 = ((uint64_t)(uint32_t)__shfl((int)(key >> 32), r2, 64) << 32) |
+                        (uint32_t)__shfl((int)(uint32_t)key, r2, 64);
+    if (r2 < lane && k2 == key) first = r2;
+  }
+  const bool isfirst = act && first == lane;
+  const uint64_t mask = __builtin_amdgcn_ballot_w64(isfirst);
+  const int slot = __builtin_popcountll(mask & ((1ull << first) - 1ull));
+  int64_t off = 0;
+  int32_t ext = 0;
+  int shift = 0;
+  if (isfirst) {
+    pair_tile(g, pg, D, tt, &off, &ext);
+    if (pg.flat) shift = flat_shift<T>(src + off);
+  }
+  // LDS offset of tile sigma_r . c for lane r (the combine step's sb[r])
+  const int sb_lane = slot * pg.tile_stride + __shfl(shift, act ? first : 0, 64);
+  const int ntl = __builtin_popcountll(mask);
+  int srcl = 0;  // the lane that formed tile `lane` (the lane-th set bit of mask)
+  {
+    int cnt = 0;
+#pragma unroll
+    for (int r = 0; r < DF; ++r)
+      if ((mask >> r) & 1ull) {
+        if (cnt == lane) srcl = r;
+        ++cnt;
+      }
+  }
+  const int64_t my_toff =
+      (int64_t)(((uint64_t)(uint32_t)__shfl((int)(off >> 32), srcl, 64) << 32) |
+                (uint32_t)__shfl((int)(uint32_t)off, srcl, 64));
+  const int32_t my_text = __shfl(ext, srcl, 64);
+  const int my_shift = __shfl(shift, srcl, 64);
+  uint32_t rep_cnt, rep_off;
+  {
+    const int k = pair_key(g, pg, D, c);
+    rep_off = (uint32_t)pg.rep_off[k];
+    rep_cnt = (uint32_t)pg.rep_cnt[k];
+  }
   auto tile_off = [&](int t) -> int64_t {
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)my_toff, t);
     const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(my_toff >> 32), t);
@@ -923,7 +927,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_pair(const PairArgs<T> a) {
     }
     int32_t sb[DF];
 #pragma unroll
-    for (int r = 0; r < DF; ++r) sb[r] = __builtin_amdgcn_readfirstlane(info.sb[r]);
+    for (int r = 0; r < DF; ++r) sb[r] = __builtin_amdgcn_readlane(sb_lane, r);
     const FastDiv one{1u, 0u, 0u, 0u};
     combine_orbit<T, D, CHAIN>(g, sb, reinterpret_cast<const uint32_t*>(rep_lds), rep_cnt, one, 1,
                                coef, a.nstages, co, lds);
@@ -934,7 +938,8 @@ __global__ void __launch_bounds__(kMaxThreads) k_pair(const PairArgs<T> a) {
     for (int t = 0; t < ntl; ++t) {
       const int64_t toff = tile_off(t);
       flat_store<T, NTS>(dst + toff, (uint32_t)tile_elems,
-                         smem + (size_t)t * pg.tile_stride * sizeof(T), info.shift[t]);
+                         smem + (size_t)t * pg.tile_stride * sizeof(T),
+                         __builtin_amdgcn_readlane(my_shift, t));
     }
   } else {
     const uint32_t cpt = (uint32_t)g.rows * (uint32_t)g.vpr;

@@ -144,14 +144,6 @@ struct alignas(16) PairGeom {
   int32_t rep_cnt[kPairKeys];
 };
 
-// Tile list of one index-pair work item, built by the workgroup in LDS.
-struct PairInfo {
-  int64_t toff[kMaxDF];   // element offset of each tile in the pair block
-  int32_t text[kMaxDF];   // packed extents
-  int32_t shift[kMaxDF];  // alignment shift of each tile's LDS copy (whole cubes)
-  int32_t sb[kMaxDF];     // LDS offset of tile sigma_r . c, sigma_r in lexicographic order
-  int32_t ntiles, rep_off, rep_cnt, pad;
-};
 
 
 // ------------------------------------------------------------------------

@@ -20,7 +20,6 @@ using spinsum::Geom;
 using spinsum::GroupDev;
 using spinsum::OrbitHost;
 using spinsum::PairGeom;
-using spinsum::PairInfo;
 using spinsum::Tiling;
 
 namespace spinsum {
@@ -643,8 +642,7 @@ static int64_t pair_lds_bytes(const spinsum_plan_s& P, int bl, int* vw_out) {
   int64_t ts = ipow(bl, d) * inner;
   if (flat) ts = (ts + 16 / esz + 16 / esz - 1) / (16 / esz) * (16 / esz);
   if (vw_out) *vw_out = vw;
-  return ((int64_t)tiles * ts * esz + 15) / 16 * 16 + ipow(bl, d) * 4 +
-         (int64_t)sizeof(PairInfo);
+  return ((int64_t)tiles * ts * esz + 15) / 16 * 16 + ipow(bl, d) * 4;
 }
 
 // Default tile edge: the largest usable bl whose orbit fits 32 KiB of LDS,
