@@ -301,14 +301,15 @@ namespace {
 template <typename T>
 spinsum_status launch_cgrad(spinsum_plan_s* P, const void* x, const void* g, double* grad,
                             hipStream_t stream) {
-  const Tiling& Tl = P->T;
+  // its own packed tiling where the plan has one (see build_cgrad_tiling)
+  const Tiling& Tl = P->cg_pack ? P->Tc : P->T;
   CGradArgs<T> a;
   std::memset(&a, 0, sizeof(a));
   a.x = reinterpret_cast<const T*>(x);
   a.gr = reinterpret_cast<const T*>(g);
   a.grad = reinterpret_cast<double*>(P->d_grad_part);
-  a.orbits = reinterpret_cast<const GroupDev*>(P->d_orbits);
-  a.reps = reinterpret_cast<const uint32_t*>(P->d_reps);
+  a.orbits = reinterpret_cast<const GroupDev*>(P->cg_pack ? P->d_cg_orbits : P->d_orbits);
+  a.reps = reinterpret_cast<const uint32_t*>(P->cg_pack ? P->d_cg_reps : P->d_reps);
   a.g = Tl.g;
   a.nitems = Tl.nitems;
   a.lds_tile_bytes = (int32_t)(((size_t)Tl.lds_elems * sizeof(T) + 15) / 16 * 16);

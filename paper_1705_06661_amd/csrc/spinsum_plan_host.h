@@ -71,6 +71,11 @@ struct spinsum_plan_s {
   // tiling (single tensor)
   spinsum_tile_t tile{};
   spinsum::Tiling T;
+  // the coefficient gradient's own tiling where it differs from T: it holds
+  // two tensors in LDS, so fewer of its workgroups fit a CU and it packs
+  // consecutive orbits into items even where T does not (cg_pack)
+  spinsum::Tiling Tc;
+  bool cg_pack = false;
 
   // index-pair form (SPINSUM_FLAG_INDEX_PAIRS): T.g describes one pair
   // block, T.reps holds the representative pool, T.nb / T.vw / T.ragged /
@@ -107,6 +112,8 @@ struct spinsum_plan_s {
   void* d_blocks = nullptr;
   void* d_items = nullptr;
   void* d_grad_part = nullptr;  // kGradSlots x d! doubles (spinsum_coef_grad)
+  void* d_cg_orbits = nullptr;  // Tc.groups, Tc.reps (cg_pack)
+  void* d_cg_reps = nullptr;
   int last_hip_error = 0;
   const void* occ_kernel = nullptr;  // occupancy cache of the persistent kernel
   int64_t occ_shmem = -1;
