@@ -147,7 +147,7 @@ def cpu_baseline(seconds: float, nslabs: int):
     import workloads
     cube = 32 ** 3
     per_slab = 64 * 64 * 8
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads, nproc, allowed = cpu_threads()
     chunk = 1024
     done, total = 0, 0.0
     while total < seconds and done < nslabs * per_slab:
@@ -164,13 +164,31 @@ def cpu_baseline(seconds: float, nslabs: int):
     oracle.spinsum(x, workloads.CONFIG_3D_ALPHA, 1, 3, nthreads=1)
     t1 = time.perf_counter() - t0
     return {"value": round(2 * elems * 8 / total / 1e9, 4), "unit": "GB/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "nproc": nproc, "affinity_cpus": allowed,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
             "one_thread_value": round(2 * chunk * cube * 8 / t1 / 1e9, 4),
             "cpu_model": cpu_model(),
             "sample": f"the first {done} spectator cubes (32^3 each, {elems} elements, fp64) of the "
                       f"{nslabs} slabs of the v=64 o=32 in-place workload, in slab order, "
                       f"{total:.1f} s of oracle time on {threads} threads; one_thread_value: "
                       f"the first {chunk} of them on one thread"}
+
+
+def cpu_threads():
+    """Threads for the oracle: every CPU this process may run on
+    (sched_getaffinity), capped by OMP_NUM_THREADS where the host sets it
+    (the share of a shared GPU host's CPUs that one GPU job is given).
+    Returns (threads, os.cpu_count(), CPUs in the affinity mask)."""
+    nproc = os.cpu_count() or 1
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = nproc
+    threads = allowed
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    if omp.isdigit() and int(omp) > 0:
+        threads = min(threads, int(omp))
+    return max(1, threads), nproc, allowed
 
 
 # The paper's three tensor sizes (Sec. 5.1: about 70, 320 and 1200 MiB),
@@ -212,16 +230,109 @@ def table2_sweep(ss, workloads, dev, stream, size="medium"):
         ms_median = times[len(times) // 2]
         elems = x.numel()
         t = ms * 1e-3
-        res[str(case)] = {"d": d, "N": n, "terms": info["nterms_expanded"],
-                          "GiBps_eq12": round(2 * elems * 8 / 2 ** 30 / t, 1),
-                          "GBps": round(2 * elems * 8 / 1e9 / t, 1),
-                          "frac_peak": round(2 * elems * 8 / 1e9 / t / PEAK_GBPS, 4),
-                          "GFLOPs_eq13": round(2 * info["nterms_expanded"] * elems / 1e9 / t, 1),
-                          "ms": round(ms, 4), "ms_median": round(ms_median, 4),
-                          "tile_edge": info["bl"]}
+        # [GB/s, fraction of peak, Eq. 12 GiB/s, Eq. 13 GFLOP/s, ms (fastest),
+        #  ms (median), expanded terms, tile edge]
+        res[str(case)] = [round(2 * elems * 8 / 1e9 / t, 1),
+                          round(2 * elems * 8 / 1e9 / t / PEAK_GBPS, 4),
+                          round(2 * elems * 8 / 2 ** 30 / t, 1),
+                          round(2 * info["nterms_expanded"] * elems / 1e9 / t, 1),
+                          round(ms, 4), round(ms_median, 4), info["nterms_expanded"], info["bl"]]
+    res["columns"] = ["GBps", "frac_peak", "GiBps_eq12", "GFLOPs_eq13", "ms", "ms_median",
+                      "terms", "tile_edge"]
+    res["N"] = {"3d": TABLE2_SIZES[size][3], "4d": TABLE2_SIZES[size][4]}
     del tensors, flush
     torch.cuda.empty_cache()
     return res
+
+
+def accuracy_report(ss, workloads, dev, stream):
+    """Errors of the v=48, o=24 forward and adjoint with (2 - P_ij)(2 - P_jk)
+    (whose adjoint differs from it), all normwise, max|got - ref| / max|ref|:
+      * FP32 storage and accumulation against FP64, on the whole tensor: the
+        FP32 kernel on the FP32-rounded input against the FP64 kernel on the
+        same rounded values ("rounded", the arithmetic alone) and on the
+        unrounded input ("unrounded", storage included);
+      * the FP64 and FP32 kernels against the oracle on sampled spectator
+        cubes (inputs regenerated on the host from the seeded stream);
+      * finite differences of the linear map: <g, (S(x + h v) - S(x)) / h>
+        against <S^T g, v> (adjoint kernel) for h = 1 and 1e-3, FP64, whole
+        tensor (the gradient check of the autograd form)."""
+    import numpy as np
+    import torch
+    import oracle
+    w5 = workloads.WORKLOADS["3d_v48_o24"]
+    shape = w5["shape"]
+    st = workloads.FACTORED_PIJ_PJK
+    cube = 24 ** 3
+    ncubes = 48 ** 3
+    picks = [0, 1, 4097, 55555, 99991, ncubes - 1]
+    p64 = ss.spinsum_plan(shape, 3, 3, st, dtype=torch.float64)
+    p32 = ss.spinsum_plan(shape, 3, 3, st, dtype=torch.float32)
+
+    def nerr(a, b):
+        return float((a - b).abs().max() / b.abs().max())
+
+    rep = {"workload": "3d_v48_o24 [48,48,48,24,24,24], (2 - P_ij)(2 - P_jk), U(-1,1) seed 4000 "
+                       "(upstream gradient seed 4002, direction seed 4001)",
+           "norm": "max|got - ref| / max|ref|", "tolerance": {"fp64": 1e-14, "fp32": 2e-6}}
+    for name, fn in (("forward", ss.spinsum_exec), ("adjoint", ss.spinsum_adjoint)):
+        x = workloads.uniform(shape, 4000, device=dev)
+        x32 = x.to(torch.float32)
+        y64 = torch.empty_like(x)
+        fn(p64, x, y64, stream)
+        y32 = torch.empty_like(x32)
+        fn(p32, x32, y32, stream)
+        yr = torch.empty_like(x)
+        fn(p64, x32.to(torch.float64), yr, stream)
+        torch.cuda.synchronize()
+        y32d = y32.to(torch.float64)
+        e = {"fp32_vs_fp64_rounded_input": nerr(y32d, yr),
+             "fp32_vs_fp64_unrounded_input": nerr(y32d, y64)}
+        del x, x32, yr, y32d
+        torch.cuda.empty_cache()
+        worst64, worst32 = 0.0, 0.0
+        for c in picks:
+            xh = workloads.uniform_numpy(cube, 4000, offset=c * cube).reshape(1, 24, 24, 24)
+            x32h = xh.astype(np.float32).astype(np.float64)
+            f = oracle.spinsum_chain_adjoint if name == "adjoint" else oracle.spinsum_chain
+            ref = f(xh, st, 1, 3)
+            ref32 = f(x32h, st, 1, 3)
+            g64 = y64.view(-1, cube)[c].cpu().numpy().reshape(ref.shape)
+            g32 = y32.view(-1, cube)[c].cpu().to(torch.float64).numpy().reshape(ref.shape)
+            worst64 = max(worst64, float(np.max(np.abs(g64 - ref)) / np.max(np.abs(ref))))
+            worst32 = max(worst32, float(np.max(np.abs(g32 - ref32)) / np.max(np.abs(ref32))))
+        e["fp64_vs_oracle_sampled"] = worst64
+        e["fp32_vs_oracle_rounded_input_sampled"] = worst32
+        e["sampled_cubes"] = picks
+        rep[name] = e
+        del y64, y32
+        torch.cuda.empty_cache()
+    # finite differences (FP64)
+    x = workloads.uniform(shape, 4000, device=dev)
+    v = workloads.uniform(shape, 4001, device=dev)
+    g = workloads.uniform(shape, 4002, device=dev)
+    y0 = torch.empty_like(x)
+    ss.spinsum_exec(p64, x, y0, stream)
+    gt = torch.empty_like(g)
+    ss.spinsum_adjoint(p64, g, gt, stream)
+    torch.cuda.synchronize()
+    analytic = float((gt * v).sum(dtype=torch.float64))
+    del gt
+    fd = {}
+    for h in (1.0, 1e-3):
+        xp = x + h * v
+        y1 = torch.empty_like(x)
+        ss.spinsum_exec(p64, xp, y1, stream)
+        torch.cuda.synchronize()
+        num = float((g * (y1 - y0)).sum(dtype=torch.float64)) / h
+        fd[f"h={h:g}"] = {"fd": num, "analytic": analytic,
+                          "rel_error": abs(num - analytic) / abs(analytic)}
+        del xp, y1
+        torch.cuda.empty_cache()
+    rep["finite_differences_fp64"] = fd
+    del x, v, g, y0
+    torch.cuda.empty_cache()
+    return rep
 
 
 def main():
@@ -437,9 +548,14 @@ def main():
             forms[f"3d_v48_o24_adjoint_{tag}"] = form_entry(nb, bwd, value)
             del x5, y5
             torch.cuda.empty_cache()
-        out["forms"] = forms
+        accuracy = accuracy_report(ss, workloads, dev, stream)
+        # the Table II sweeps first: the forms, the accuracy figures and the
+        # CPU baseline then close the line
         for size in ("small", "medium", "large"):
+            log(f"table II sweep, {size}")
             out[f"table2_{size}"] = table2_sweep(ss, workloads, dev, stream, size)
+        out["forms"] = forms
+        out["accuracy"] = accuracy
 
     out["paper_context"] = PAPER_CONTEXT
     if not args.no_cpu_baseline:

@@ -36,8 +36,9 @@
  *   - exec/adjoint calls are asynchronous and stream-ordered, allocate
  *     nothing and never synchronise, so they may be captured in a hipGraph;
  *   - a plan is bound to the device that was current when it was made;
- *   - a plan is not changed by exec/adjoint/exec_batched, so their calls may
- *     overlap on several streams; spinsum_plan_set_tile, spinsum_autotune
+ *   - a plan is not changed by exec/adjoint/exec_batched (they only read
+ *     it), so their calls may overlap on several streams and host threads;
+ *     spinsum_plan_set_tile, spinsum_autotune
  *     and spinsum_plan_destroy need exclusive use of the plan, and
  *     spinsum_coef_grad calls on one plan must not overlap (they share the
  *     plan's partial-sum buffer);
@@ -186,14 +187,22 @@ spinsum_status spinsum_plan(spinsum_plan_t* plan, int ndim, const int64_t* exten
                             int inplace, unsigned flags);
 
 /* Plan for many tensors ("blocks") that share d, the terms, dtype and the
- * in-place choice but have their own shapes: block b has ndims[b] dims with
- * extents extents[b][0..ndims[b]-1], group = its trailing d dims.  Executed
- * by one kernel launch (spinsum_exec_batched): one work item per workgroup,
- * or persistent workgroups walking the item list (spinsum_autotune picks;
- * spinsum_plan_info_t.batch_persistent). */
+ * in-place choice but have their own shapes (Def. 3-4 on each block; the
+ * blocks form one task list, as the tasks of Alg. 5a): block b has ndims[b]
+ * dims with extents extents[b][0..ndims[b]-1] and its permuted group is
+ * dims [group_first, group_first + d) -- the same position in every block,
+ * with the dims after it as inner spectators -- or, with group_first = -1,
+ * the trailing d dims of each block.  Every block must satisfy the limits
+ * of spinsum_plan (N^d times the inner run below 2^31 elements).  Arrays
+ * are copied.  Executed by one kernel launch (spinsum_exec_batched): one
+ * work item per workgroup, or persistent workgroups walking the item list
+ * (spinsum_autotune picks; spinsum_plan_info_t.batch_persistent).
+ * SPINSUM_FLAG_INDEX_PAIRS is not supported (SPINSUM_ERR_UNSUPPORTED), and
+ * SPINSUM_FLAG_CHAIN_STAGES is ignored (the stages are pre-multiplied).
+ * On error *plan is set to NULL. */
 spinsum_status spinsum_plan_batched(spinsum_plan_t* plan, int nblocks, const int* ndims,
-                                    const int64_t* const* extents, int d, int nstages,
-                                    const int* nterms, const int* perms,
+                                    const int64_t* const* extents, int group_first, int d,
+                                    int nstages, const int* nterms, const int* perms,
                                     const double* alpha, spinsum_dtype dtype, int inplace,
                                     unsigned flags);
 
@@ -222,7 +231,14 @@ spinsum_status spinsum_plan_check_ownership(spinsum_plan_t plan, int block, cons
  * out-of-place plans reject overlapping buffers (SPINSUM_ERR_ALIASING). */
 spinsum_status spinsum_exec(spinsum_plan_t plan, const void* in, void* out, void* stream);
 
-/* Batched form: in/out are DEVICE arrays of nblocks device pointers. */
+/* Batched form of spinsum_exec (Def. 3-4 on every block of the plan, as one
+ * task list, Alg. 5a): in/out are DEVICE arrays of nblocks device pointers
+ * (8-byte aligned arrays; every block pointer 16-byte aligned, each block
+ * in place or not overlapping its output, as for spinsum_exec -- the
+ * pointers are read by the kernel, so these are not checked here).  The
+ * caller owns the arrays and the block buffers.  Asynchronous on `stream`,
+ * allocates nothing; SPINSUM_ERR_INVALID_ARG for a plan that is not
+ * batched or NULL arrays, SPINSUM_ERR_MISALIGNED for misaligned arrays. */
 spinsum_status spinsum_exec_batched(spinsum_plan_t plan, const void* const* in,
                                     void* const* out, void* stream);
 

@@ -159,6 +159,29 @@ def spinsum_chain_adjoint(g: np.ndarray, stages: Sequence[Stage], group_first: i
                  nthreads, pairs)
 
 
+def expanded_terms(stages: Sequence[Stage], d: int) -> Stage:
+    """The single sum that a chain of stages equals (Def. 4 multiplied out),
+    as ``[(p, alpha_p)]`` over the permutations with nonzero coefficient, in
+    lexicographic order.
+
+    Found by applying the chain itself (the C loops above) to one indicator
+    tensor: with N = d and In = 1 at the tuple (0, 1, .., d-1) only, an output
+    position x that is itself a permutation tuple reads that 1 through the
+    term p exactly when x_{p[m]} = m for every m, i.e. p is the inverse of x,
+    so Out[x] is the coefficient of inverse(x).  Integer coefficients stay
+    exact (long-double accumulation)."""
+    shape = (d,) * d
+    ind = np.zeros(shape, dtype=np.float64)
+    ind[tuple(range(d))] = 1.0
+    out = spinsum_chain(ind, stages, 0, d)
+    terms = []
+    for p in itertools.permutations(range(d)):
+        c = float(out[_inverse(p)])
+        if c != 0.0:
+            terms.append((tuple(p), c))
+    return terms
+
+
 # ------------------------------------------------------------- numpy route
 def _inverse(p: Sequence[int]) -> Tuple[int, ...]:
     inv = [0] * len(p)

@@ -108,8 +108,8 @@ _c_plan = _decl("spinsum_plan", [ctypes.POINTER(_vp), ctypes.c_int, _i64p, ctype
                                  ctypes.c_int, ctypes.c_uint])
 _c_plan_batched = _decl("spinsum_plan_batched",
                         [ctypes.POINTER(_vp), ctypes.c_int, _ip, ctypes.POINTER(_i64p),
-                         ctypes.c_int, ctypes.c_int, _ip, _ip, _dp, ctypes.c_int, ctypes.c_int,
-                         ctypes.c_uint])
+                         ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _ip, _dp, ctypes.c_int,
+                         ctypes.c_int, ctypes.c_uint])
 _c_set_tile = _decl("spinsum_plan_set_tile", [_vp, ctypes.POINTER(_Tile)])
 _c_get_info = _decl("spinsum_plan_get_info", [_vp, ctypes.POINTER(_Info)])
 _c_expanded = _decl("spinsum_plan_expanded", [_vp, ctypes.c_int, _ip, _ip, _dp])
@@ -219,8 +219,9 @@ def spinsum_plan(extents: Sequence[int], group_first: int, d: int, stages, dtype
 
 
 def spinsum_plan_batched(shapes: Sequence[Sequence[int]], d: int, stages, dtype="f64",
-                         inplace: bool = False, flags: int = 0) -> Plan:
-    """Plan one launch over many tensors (group = trailing d dims)."""
+                         inplace: bool = False, flags: int = 0, group_first: int = -1) -> Plan:
+    """Plan one launch over many tensors: the group is dims [group_first,
+    group_first + d) of every block, or its trailing d dims (group_first -1)."""
     nb = len(shapes)
     ndims = (ctypes.c_int * nb)(*[len(s) for s in shapes])
     rows = [(ctypes.c_int64 * len(s))(*[int(e) for e in s]) for s in shapes]
@@ -228,8 +229,8 @@ def spinsum_plan_batched(shapes: Sequence[Sequence[int]], d: int, stages, dtype=
     nt, pp, aa = _flatten(stages, d)
     h = _vp()
     dt = _DTYPES[dtype]
-    _check(_c_plan_batched(ctypes.byref(h), nb, ndims, ptrs, int(d), len(stages), nt, pp, aa, dt,
-                           int(bool(inplace)), int(flags)), "spinsum_plan_batched")
+    _check(_c_plan_batched(ctypes.byref(h), nb, ndims, ptrs, int(group_first), int(d), len(stages),
+                           nt, pp, aa, dt, int(bool(inplace)), int(flags)), "spinsum_plan_batched")
     return Plan(h, d, [tuple(int(e) for e in s) for s in shapes], dt, inplace, True, stages)
 
 

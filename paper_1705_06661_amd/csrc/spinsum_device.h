@@ -162,6 +162,8 @@ struct ExecArgs {
   int32_t lds_tile_bytes;  // k_pipe: start of the representative copy in LDS;
                            // k_ldsp: bytes of one tile buffer
   int32_t nreps;           // k_ldsp: entries of the shared representative table
+  uint32_t sparse;         // bit s: stage s has a zero coefficient (see combine_orbit)
+  int32_t pad;
 };
 
 template <typename T>
@@ -190,7 +192,7 @@ struct BatchArgs {
   int64_t nitems;
   int64_t xcd_per;         // > 0: items grouped per XCD (items per XCD range)
   int32_t lds_tile_bytes;  // start of the representative lists in LDS
-  int32_t pad;
+  uint32_t sparse;         // the operator has a zero coefficient (see combine_orbit)
 };
 
 template <typename T>
@@ -207,7 +209,7 @@ struct PairArgs {
   int32_t nstages;
   int32_t reverse;
   int32_t lds_tile_bytes;  // start of the representative list in LDS
-  int32_t pad;
+  uint32_t sparse;         // bit s: stage s has a zero coefficient (see combine_orbit)
 };
 
 // Fused multiply-add in the storage type (a float FMA for float: the
@@ -224,27 +226,96 @@ __device__ __forceinline__ T orbit_row(const T* a, const T* v, std::integer_sequ
   return acc;
 }
 
-template <typename T, int D, int... TAU>
-__device__ __forceinline__ void orbit_rows(const T* a, const T* v, T* w,
-                                           std::integer_sequence<int, TAU...>) {
-  ((w[TAU] = orbit_row<T, D, TAU>(a, v, std::make_integer_sequence<int, Fact<D>::v>{})), ...);
+// The same row over the operator's own terms only: a permutation whose
+// coefficient is zero is not a term of the sum (Def. 3), so its input is
+// not read at all.  For finite inputs this equals orbit_row (adding 0 * v
+// is exact); it differs where some v_sigma is Inf or NaN, which then
+// reaches only the outputs of the terms that read it.  The coefficients are
+// wave-uniform, so every test is a scalar branch.
+template <typename T, int D, int TAU, int... S>
+__device__ __forceinline__ T orbit_row_terms(const T* a, const T* v, std::integer_sequence<int, S...>) {
+  T acc = T(0);
+  ((acc = (a[GinvMul<D, TAU, S>::value] != T(0)) ? fma_t(a[GinvMul<D, TAU, S>::value], v[S], acc)
+                                                  : acc),
+   ...);
+  return acc;
 }
 
+template <typename T, int D, int... TAU>
+__device__ __forceinline__ void orbit_rows_terms(const T* a, const T* v, T* w,
+                                                 std::integer_sequence<int, TAU...>) {
+  ((w[TAU] = orbit_row_terms<T, D, TAU>(a, v, std::make_integer_sequence<int, Fact<D>::v>{})), ...);
+}
+
+// Whether an element orbit has to be redone over the operator's own terms:
+// w0 = sum_sigma a(sigma) v_sigma is formed over every sigma, zero
+// coefficients included, so one Inf or NaN among the v_sigma makes w0 Inf or
+// NaN (a * Inf is +-Inf, 0 * Inf and anything with NaN are NaN, and a sum
+// holding a non-finite term stays non-finite).  A finite w0 therefore means
+// every v_sigma is finite and the dense product is exact; a non-finite one
+// (or an overflow, which is rare and harmless) sends the whole wave to the
+// term-by-term product.  Operators with every coefficient nonzero
+// (sparse == false) never need it.
+template <typename T>
+__device__ __forceinline__ bool needs_terms(bool sparse, T w0) {
+  return sparse && __builtin_amdgcn_ballot_w64(!__builtin_isfinite(w0)) != 0ull;
+}
+
+template <typename T, int D, int... TAU>
+__device__ __forceinline__ void orbit_rows_tail(const T* a, const T* v, T* w,
+                                                std::integer_sequence<int, TAU...>) {
+  ((w[TAU + 1] = orbit_row<T, D, TAU + 1>(a, v, std::make_integer_sequence<int, Fact<D>::v>{})),
+   ...);
+}
+
+// w = the coefficient product of one element orbit (chained stages); row 0
+// is formed first and decides whether the orbit takes the term-by-term
+// product (needs_terms).
 template <typename T, int D>
 __device__ __forceinline__ void orbit_product(const T (&a)[Fact<D>::v], const T (&v)[Fact<D>::v],
-                                              T (&w)[Fact<D>::v]) {
-  orbit_rows<T, D>(a, v, w, std::make_integer_sequence<int, Fact<D>::v>{});
+                                              T (&w)[Fact<D>::v], bool sparse) {
+  constexpr int DF = Fact<D>::v;
+  const T w0 = orbit_row<T, D, 0>(a, v, std::make_integer_sequence<int, DF>{});
+  if (needs_terms<T>(sparse, w0)) {
+    orbit_rows_terms<T, D>(a, v, w, std::make_integer_sequence<int, DF>{});
+  } else {
+    w[0] = w0;
+    orbit_rows_tail<T, D>(a, v, w, std::make_integer_sequence<int, DF - 1>{});
+  }
 }
 
 // The same product, each w_tau written to LDS as soon as it is formed (all
 // v_sigma are already in registers, so the in-place writes are safe); only
 // a few accumulators are live at a time.  (One FMA chain per row is fine:
 // a wave64 FMA occupies its SIMD for four cycles, which covers the
-// dependency latency.)
+// dependency latency.)  Row 0 is formed first and decides whether the
+// orbit takes the term-by-term product (needs_terms).
 template <typename T, int D, int... TAU>
-__device__ __forceinline__ void orbit_rows_store(const T* a, const T* v, T* lds, const int* addr,
-                                                 std::integer_sequence<int, TAU...>) {
-  ((lds[addr[TAU]] = orbit_row<T, D, TAU>(a, v, std::make_integer_sequence<int, Fact<D>::v>{})), ...);
+__device__ __forceinline__ void orbit_rows_store_tail(const T* a, const T* v, T* lds, const int* addr,
+                                                      std::integer_sequence<int, TAU...>) {
+  ((lds[addr[TAU + 1]] =
+        orbit_row<T, D, TAU + 1>(a, v, std::make_integer_sequence<int, Fact<D>::v>{})),
+   ...);
+}
+
+template <typename T, int D, int... TAU>
+__device__ __forceinline__ void orbit_rows_store_terms(const T* a, const T* v, T* lds, const int* addr,
+                                                       std::integer_sequence<int, TAU...>) {
+  ((lds[addr[TAU]] = orbit_row_terms<T, D, TAU>(a, v, std::make_integer_sequence<int, Fact<D>::v>{})),
+   ...);
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void orbit_store(const T (&a)[Fact<D>::v], const T (&v)[Fact<D>::v],
+                                            T* lds, const int (&addr)[Fact<D>::v], bool sparse) {
+  constexpr int DF = Fact<D>::v;
+  const T w0 = orbit_row<T, D, 0>(a, v, std::make_integer_sequence<int, DF>{});
+  if (needs_terms<T>(sparse, w0)) {
+    orbit_rows_store_terms<T, D>(a, v, lds, addr, std::make_integer_sequence<int, DF>{});
+  } else {
+    lds[addr[0]] = w0;
+    orbit_rows_store_tail<T, D>(a, v, lds, addr, std::make_integer_sequence<int, DF - 1>{});
+  }
 }
 
 // Unit i of an orbit's combine loop -> cube of the item ci, representative
@@ -267,11 +338,15 @@ __device__ __forceinline__ void split_unit(const Geom& g, uint32_t i, uint32_t r
 // Combine the element orbits of one tile orbit: sb[sigma] = LDS offset of
 // tile sigma . B, rp = its representative list (rep_cnt entries, local
 // coordinates packed one byte per axis), for ncub cubes of the item.
+// sparse: bit s set if stage s (bit 0 alone without CHAIN: the
+// pre-multiplied operator) has a permutation of zero coefficient; stages
+// from 32 on are always treated as having one.
 template <typename T, int D, bool CHAIN>
 __device__ __forceinline__ void combine_orbit(const Geom& g, const int32_t (&sb)[Fact<D>::v],
                                               const uint32_t* rp, uint32_t rep_cnt,
                                               const FastDiv& fdr, int ncub, cptr<T> coef,
-                                              int nstages, T (&a)[Fact<D>::v], T* lds) {
+                                              int nstages, uint32_t sparse, T (&a)[Fact<D>::v],
+                                              T* lds) {
   constexpr int DF = Fact<D>::v;
   const uint32_t nrep = (uint32_t)ncub * rep_cnt * (uint32_t)g.inner;
   for (uint32_t i = threadIdx.x; i < nrep; i += blockDim.x) {
@@ -288,13 +363,13 @@ __device__ __forceinline__ void combine_orbit(const Geom& g, const int32_t (&sb)
 #pragma unroll
     for (int r = 0; r < DF; ++r) v[r] = lds[addr[r]];
     if constexpr (!CHAIN) {
-      orbit_rows_store<T, D>(a, v, lds, addr, std::make_integer_sequence<int, DF>{});
+      orbit_store<T, D>(a, v, lds, addr, (sparse & 1u) != 0u);
     } else {
       T w[DF];
       for (int s = 0; s < nstages; ++s) {
 #pragma unroll
         for (int r = 0; r < DF; ++r) a[r] = coef[s * DF + r];
-        orbit_product<T, D>(a, v, w);
+        orbit_product<T, D>(a, v, w, s >= 32 || ((sparse >> s) & 1u) != 0u);
 #pragma unroll
         for (int r = 0; r < DF; ++r) v[r] = w[r];
       }
@@ -312,7 +387,7 @@ __device__ __forceinline__ void combine_orbit(const Geom& g, const int32_t (&sb)
 template <typename T, int D, bool CHAIN, bool REPS_IN_LDS>
 __device__ __forceinline__ void combine_item(const Geom& g, cptr<GroupDev> gd,
                                              const uint32_t* reps, cptr<T> coef, int nstages,
-                                             int ncub, T* lds) {
+                                             uint32_t sparse, int ncub, T* lds) {
   constexpr int DF = Fact<D>::v;
   T a[DF];
   if constexpr (!CHAIN) {
@@ -326,8 +401,8 @@ __device__ __forceinline__ void combine_item(const Geom& g, cptr<GroupDev> gd,
     for (int r = 0; r < DF; ++r) sb[r] = gd->slot_base[k][r];
     const FastDiv fdr = load_fd(gd->fd_rep[k]);
     const uint32_t* rp = reps + (REPS_IN_LDS ? gd->rep_base[k] : gd->rep_off[k]);
-    combine_orbit<T, D, CHAIN>(g, sb, rp, (uint32_t)gd->rep_cnt[k], fdr, ncub, coef, nstages, a,
-                               lds);
+    combine_orbit<T, D, CHAIN>(g, sb, rp, (uint32_t)gd->rep_cnt[k], fdr, ncub, coef, nstages,
+                               sparse, a, lds);
   }
 }
 
@@ -454,7 +529,8 @@ __global__ void __launch_bounds__(kThreads) k_exec(const ExecArgs<T> a) {
     fill_lds<T, VW, kUnroll>(buf, lo, lds);
   }
   __syncthreads();
-  combine_item<T, D, CHAIN, false>(g, cod, a.reps, as_const(a.coef), a.nstages, ncub, lds);
+  combine_item<T, D, CHAIN, false>(g, cod, a.reps, as_const(a.coef), a.nstages, a.sparse, ncub,
+                                   lds);
   __syncthreads();
   store_item<T, D, VW, NTS>(g, tinfo, ntiles, ragged, nchunks, a.out + cube0 * g.cube_elems, lds);
 }
@@ -766,7 +842,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_lds(const ExecArgs<T> a) {
   __syncthreads();
   // 2. combine
   combine_item<T, D, CHAIN, true>(g, od, reinterpret_cast<const uint32_t*>(rep_lds),
-                                  as_const(a.coef), a.nstages, ncub, lds + shift);
+                                  as_const(a.coef), a.nstages, a.sparse, ncub, lds + shift);
   __syncthreads();
   // 3. store (the output may be shifted differently from the input)
   set_memory_priority();
@@ -944,7 +1020,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_pair(const PairArgs<T> a) {
     for (int r = 0; r < DF; ++r) sb[r] = __builtin_amdgcn_readlane(sb_lane, r);
     const FastDiv one{1u, 0u, 0u, 0u};
     combine_orbit<T, D, CHAIN>(g, sb, reinterpret_cast<const uint32_t*>(rep_lds), rep_cnt, one, 1,
-                               coef, a.nstages, co, lds);
+                               coef, a.nstages, a.sparse, co, lds);
   }
   __syncthreads();
   // 4. store
@@ -1042,7 +1118,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_ldsp(const ExecArgs<T> a) {
     wait_vmcnt_atmost(pending);
     lds_barrier();
     T* lds = reinterpret_cast<T*>(buf0 + par * bb);
-    combine_item<T, D, CHAIN, false>(g, od, rep_lds, coef, a.nstages, ncub, lds);
+    combine_item<T, D, CHAIN, false>(g, od, rep_lds, coef, a.nstages, a.sparse, ncub, lds);
     lds_barrier();
     store_item_lds<T, D, NTS>(g, od, whole, ntl, ragged, a.out + cube0 * g.cube_elems, lds);
     // the buffer is refilled two items on: every wave has read it by then
@@ -1145,7 +1221,8 @@ __global__ void __launch_bounds__(kThreads) k_pipe(const ExecArgs<T> a) {
                                   a.in + cube0n * g.cube_elems, buf, lo);
     }
     // C.
-    combine_item<T, D, CHAIN, true>(g, as_const(od), rep_lds, coef, a.nstages, ncub, lds);
+    combine_item<T, D, CHAIN, true>(g, as_const(od), rep_lds, coef, a.nstages, a.sparse, ncub,
+                                    lds);
     __syncthreads();
     // D.
     store_item<T, D, VW, true>(g, tinfo[par], ntiles, ragged, nchunks,
@@ -1192,7 +1269,7 @@ __device__ __forceinline__ void batched_item(const BatchArgs<T>& a, int64_t it,
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): everything is in LDS
     __syncthreads();
     combine_item<T, D, false, true>(g, cod, reinterpret_cast<const uint32_t*>(rep_lds), coef, 1,
-                                    incubes, lds + shift);
+                                    a.sparse, incubes, lds + shift);
     __syncthreads();
     set_memory_priority();
     flat_store<T, true>(dst, span, smem, shift);
@@ -1221,7 +1298,7 @@ __device__ __forceinline__ void batched_item(const BatchArgs<T>& a, int64_t it,
     fill_lds<T, VW, kUnroll>(buf, lo, lds);
   }
   __syncthreads();
-  combine_item<T, D, false, false>(g, cod, a.reps, coef, 1, incubes, lds);
+  combine_item<T, D, false, false>(g, cod, a.reps, coef, 1, a.sparse, incubes, lds);
   __syncthreads();
   store_item<T, D, VW, true>(g, tinfo, ntiles, ragged, nchunks, dst, lds);
 }

@@ -71,24 +71,57 @@ spinsum_status prepare_kernel(spinsum_plan_s* P, const void* k, size_t shmem) {
   return SPINSUM_OK;
 }
 
-// Workgroups of a persistent launch: the occupancy of the kernel times the
-// CUs, rounded down to a multiple of 8 (one share per XCD).
-spinsum_status persistent_grid(spinsum_plan_s* P, const void* k, int threads, size_t shmem,
-                               int64_t nitems, int64_t* grid) {
-  if (P->occ_kernel != k || P->occ_shmem != (int64_t)shmem || P->occ_threads != threads) {
-    int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, threads, shmem);
-    if (e != hipSuccess) return hip_error(P, e);
-    P->occ_kernel = k;
-    P->occ_shmem = (int64_t)shmem;
-    P->occ_threads = threads;
-    P->occ_blocks = std::max(1, per_cu);
-  }
-  int64_t g = (int64_t)P->occ_blocks * P->num_cus;
+// Kernel, dynamic LDS and workgroup size of a plan's exec / adjoint launch
+// (both launch the same kernel), and whether that kernel is persistent.
+struct LaunchCfg {
+  const void* k = nullptr;
+  size_t shmem = 0;
+  int threads = kThreads;
+  int kind = 0;
+  bool persistent = false;
+};
+
+template <typename T>
+LaunchCfg exec_cfg(const spinsum_plan_s* P) {
+  const Tiling& Tl = P->T;
+  const bool chain = (P->flags & SPINSUM_FLAG_CHAIN_STAGES) != 0;
+  const bool nts = Tl.nts != 0;
+  LaunchCfg c;
+  int kind = P->tile.variant;
+  if (!nts && kind == SPINSUM_VARIANT_REG_PIPELINE) kind = SPINSUM_VARIANT_REG_ONESHOT;
+  const int maxc = (kind == SPINSUM_VARIANT_REG_PIPELINE) ? (Tl.chunks_per_thread <= 8 ? 8 : 16) : 0;
+  c.kind = kind;
+  c.k = pick_kernel<T>(P->d, kind, Tl.vw, chain, nts, maxc);
+  const size_t tile_bytes = ((size_t)Tl.lds_elems * sizeof(T) + 15) / 16 * 16;
+  c.shmem = (size_t)Tl.lds_elems * sizeof(T);
+  if (kind == SPINSUM_VARIANT_REG_PIPELINE || kind == SPINSUM_VARIANT_DIRECT_LDS)
+    c.shmem = tile_bytes + (size_t)Tl.max_rep_cnt * 4;
+  else if (kind == SPINSUM_VARIANT_LDS_PIPELINE)
+    c.shmem = ((size_t)Tl.reps.size() * 4 + 15) / 16 * 16 + 2 * tile_bytes;
+  c.threads = (kind == SPINSUM_VARIANT_DIRECT_LDS || kind == SPINSUM_VARIANT_LDS_PIPELINE)
+                  ? P->tile.threads
+                  : kThreads;
+  c.persistent = (kind == SPINSUM_VARIANT_REG_PIPELINE || kind == SPINSUM_VARIANT_LDS_PIPELINE);
+  return c;
+}
+
+template <typename T>
+LaunchCfg batched_cfg(const spinsum_plan_s* P) {
+  LaunchCfg c;
+  c.persistent = P->batch_persistent != 0;
+  c.k = pick_batched<T>(P->d, P->batch_vw, c.persistent);
+  c.shmem = ((size_t)P->batch_lds_elems * sizeof(T) + 15) / 16 * 16 + (size_t)P->batch_rep_bytes;
+  c.threads = kThreads;
+  return c;
+}
+
+// Workgroups of a persistent launch: the occupancy of the kernel (taken
+// when the plan's tables are made, see cache_occupancy) times the CUs,
+// rounded down to a multiple of 8 (one share per XCD).
+int64_t persistent_grid(const spinsum_plan_s* P, int64_t nitems) {
+  int64_t g = (int64_t)std::max(1, P->occ_blocks) * P->num_cus;
   g = std::min<int64_t>(g, ((nitems + 7) / 8) * 8);
-  g = std::max<int64_t>(8, (g / 8) * 8);
-  *grid = g;
-  return SPINSUM_OK;
+  return std::max<int64_t>(8, (g / 8) * 8);
 }
 
 template <typename T>
@@ -99,7 +132,6 @@ spinsum_status launch_exec(spinsum_plan_s* P, const void* in, void* out, hipStre
   const int df = P->G.df;
   const int K = (int)P->stage_a.size();
   const bool chain = (P->flags & SPINSUM_FLAG_CHAIN_STAGES) != 0;
-  const bool nts = Tl.nts != 0;
   const T* coef = reinterpret_cast<const T*>(P->d_mats);
   ExecArgs<T> a;
   std::memset(&a, 0, sizeof(a));
@@ -110,34 +142,24 @@ spinsum_status launch_exec(spinsum_plan_s* P, const void* in, void* out, hipStre
   if (!chain) {
     a.coef = coef + (adjoint ? df : 0);
     a.nstages = 1;
+    a.sparse = P->sparse_expanded;
   } else {
     a.coef = coef + 2 * df + (adjoint ? (size_t)K * df : 0);
     a.nstages = K;
+    a.sparse = adjoint ? P->sparse_adj : P->sparse_fwd;
   }
   a.g = Tl.g;
   a.nitems = Tl.nitems;
   a.reverse = (P->flags & SPINSUM_FLAG_REVERSE_ORDER) ? 1 : 0;
   // kernel variant chosen by the planner (see spinsum_tile_t.variant)
-  int kind = P->tile.variant;
-  if (!nts && kind == SPINSUM_VARIANT_REG_PIPELINE) kind = SPINSUM_VARIANT_REG_ONESHOT;
-  const int maxc = (kind == SPINSUM_VARIANT_REG_PIPELINE) ? (Tl.chunks_per_thread <= 8 ? 8 : 16) : 0;
-  const void* k = pick_kernel<T>(P->d, kind, Tl.vw, chain, nts, maxc);
+  const LaunchCfg c = exec_cfg<T>(P);
   a.lds_tile_bytes = (int32_t)(((size_t)Tl.lds_elems * sizeof(T) + 15) / 16 * 16);
   a.nreps = (int32_t)Tl.reps.size();
-  size_t shmem = (size_t)Tl.lds_elems * sizeof(T);
-  if (kind == SPINSUM_VARIANT_REG_PIPELINE || kind == SPINSUM_VARIANT_DIRECT_LDS)
-    shmem = (size_t)a.lds_tile_bytes + (size_t)Tl.max_rep_cnt * 4;
-  else if (kind == SPINSUM_VARIANT_LDS_PIPELINE)
-    shmem = ((size_t)a.nreps * 4 + 15) / 16 * 16 + 2 * (size_t)a.lds_tile_bytes;
-  spinsum_status st = prepare_kernel(P, k, shmem);
+  spinsum_status st = prepare_kernel(P, c.k, c.shmem);
   if (st != SPINSUM_OK) return st;
-  const int threads = (kind == SPINSUM_VARIANT_DIRECT_LDS || kind == SPINSUM_VARIANT_LDS_PIPELINE)
-                          ? P->tile.threads
-                          : kThreads;
   int64_t grid;
-  if (kind == SPINSUM_VARIANT_REG_PIPELINE || kind == SPINSUM_VARIANT_LDS_PIPELINE) {
-    st = persistent_grid(P, k, threads, shmem, Tl.nitems, &grid);
-    if (st != SPINSUM_OK) return st;
+  if (c.persistent) {
+    grid = persistent_grid(P, Tl.nitems);
     a.xcd_per = (P->flags & SPINSUM_FLAG_NO_XCD_REMAP) ? 0 : (Tl.nitems + 7) / 8;
   } else if (P->flags & SPINSUM_FLAG_NO_XCD_REMAP) {
     a.xcd_per = 0;
@@ -147,7 +169,7 @@ spinsum_status launch_exec(spinsum_plan_s* P, const void* in, void* out, hipStre
     grid = a.xcd_per * 8;
   }
   void* kargs[] = {&a};
-  hipError_t e = hipLaunchKernel(k, dim3((unsigned)grid), dim3(threads), kargs, shmem, stream);
+  hipError_t e = hipLaunchKernel(c.k, dim3((unsigned)grid), dim3(c.threads), kargs, c.shmem, stream);
   if (e != hipSuccess) return hip_error(P, e);
   return SPINSUM_OK;
 }
@@ -172,9 +194,11 @@ spinsum_status launch_pair(spinsum_plan_s* P, const void* in, void* out, hipStre
   if (!chain) {
     a.coef = coef + (adjoint ? df : 0);
     a.nstages = 1;
+    a.sparse = P->sparse_expanded;
   } else {
     a.coef = coef + 2 * df + (adjoint ? (size_t)K * df : 0);
     a.nstages = K;
+    a.sparse = adjoint ? P->sparse_adj : P->sparse_fwd;
   }
   a.g = Tl.g;
   a.pg = P->pg;
@@ -215,15 +239,15 @@ spinsum_status launch_batched(spinsum_plan_s* P, const void* const* in, void* co
   a.items = reinterpret_cast<const BatchItem*>(P->d_items);
   a.nitems = (int64_t)P->items.size();
   a.lds_tile_bytes = (int32_t)(((size_t)P->batch_lds_elems * sizeof(T) + 15) / 16 * 16);
-  const bool persist = P->batch_persistent != 0;
-  const void* k = pick_batched<T>(P->d, P->batch_vw, persist);
-  const size_t shmem = (size_t)a.lds_tile_bytes + (size_t)P->batch_rep_bytes;
+  a.sparse = P->sparse_expanded;
+  const LaunchCfg c = batched_cfg<T>(P);
+  const void* k = c.k;
+  const size_t shmem = c.shmem;
   spinsum_status st = prepare_kernel(P, k, shmem);
   if (st != SPINSUM_OK) return st;
   int64_t grid;
-  if (persist) {
-    st = persistent_grid(P, k, kThreads, shmem, a.nitems, &grid);
-    if (st != SPINSUM_OK) return st;
+  if (c.persistent) {
+    grid = persistent_grid(P, a.nitems);
     a.xcd_per = (P->flags & SPINSUM_FLAG_NO_XCD_REMAP) ? 0 : (a.nitems + 7) / 8;
   } else if (P->flags & SPINSUM_FLAG_NO_XCD_REMAP) {
     a.xcd_per = 0;
@@ -235,6 +259,21 @@ spinsum_status launch_batched(spinsum_plan_s* P, const void* const* in, void* co
   void* kargs[] = {&a};
   hipError_t e = hipLaunchKernel(k, dim3((unsigned)grid), dim3(kThreads), kargs, shmem, stream);
   if (e != hipSuccess) return hip_error(P, e);
+  return SPINSUM_OK;
+}
+
+template <typename T>
+spinsum_status occupancy_of(spinsum_plan_s* P) {
+  P->occ_blocks = 1;
+  if (P->pair) return SPINSUM_OK;
+  const LaunchCfg c = P->batched ? batched_cfg<T>(P) : exec_cfg<T>(P);
+  if (!c.persistent || c.k == nullptr) return SPINSUM_OK;
+  spinsum_status st = prepare_kernel(P, c.k, c.shmem);
+  if (st != SPINSUM_OK) return st;
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, c.k, c.threads, c.shmem);
+  if (e != hipSuccess) return hip_error(P, e);
+  P->occ_blocks = std::max(1, per_cu);
   return SPINSUM_OK;
 }
 
@@ -264,6 +303,15 @@ spinsum_status check_tensor_args(spinsum_plan_s* P, const void* in, const void* 
 }
 
 }  // namespace
+
+// Occupancy of a persistent exec kernel, taken whenever a plan's tables are
+// made (plan creation, spinsum_plan_set_tile, the autotuner), so that exec
+// only reads the plan.
+spinsum_status cache_occupancy(spinsum_plan_s* P) {
+  if (!P->has_dev) return SPINSUM_OK;
+  if (P->dtype == SPINSUM_F32) return occupancy_of<float>(P);
+  return occupancy_of<double>(P);
+}
 
 }  // namespace spinsum
 

@@ -566,7 +566,7 @@ spinsum_status upload_tables(spinsum_plan_s* P) {
     if (st != SPINSUM_OK) return st;
   }
   P->has_dev = true;
-  return SPINSUM_OK;
+  return cache_occupancy(P);
 }
 
 }  // namespace spinsum
@@ -631,6 +631,27 @@ static spinsum_status set_terms(spinsum_plan_s* P, int nstages, const int* nterm
   for (int k = nstages - 1; k >= 0; --k) {
     std::vector<double> r = adjoint_of(P->stage_a[k]);
     P->SMT.insert(P->SMT.end(), r.begin(), r.end());
+  }
+  // Which coefficient vectors leave out a permutation, as the kernels see
+  // them (rounded to the storage type): those combine an element orbit
+  // term by term once one of its inputs is Inf or NaN (Def. 3 sums only
+  // the operator's terms).  Inverting every permutation keeps the zeros'
+  // count, so the adjoint vectors share the forward ones' answer.
+  auto has_zero = [&](const double* a) {
+    for (int g = 0; g < df; ++g) {
+      const double c = (P->dtype == SPINSUM_F32) ? (double)(float)a[g] : a[g];
+      if (c == 0.0) return true;
+    }
+    return false;
+  };
+  P->sparse_expanded = has_zero(P->expanded.data()) ? 1u : 0u;
+  P->sparse_fwd = 0;
+  P->sparse_adj = 0;
+  for (int k = 0; k < nstages; ++k) {  // the kernels treat stages from 32 on as sparse
+    if (has_zero(P->stage_a[k].data())) {
+      if (k < 32) P->sparse_fwd |= 1u << k;
+      if (nstages - 1 - k < 32) P->sparse_adj |= 1u << (nstages - 1 - k);
+    }
   }
   return SPINSUM_OK;
 }
@@ -1094,6 +1115,7 @@ spinsum_status spinsum::build_batched(spinsum_plan_s* P, int64_t item_bytes) {
   const int nblocks = P->nblocks, d = P->d;
   const std::vector<int>& ns = P->bns;
   const std::vector<int64_t>& cs = P->bcs;
+  const std::vector<int>& rs = P->brs;
   spinsum_status st = SPINSUM_OK;
   P->btil.clear();
   P->blocks.clear();
@@ -1109,15 +1131,16 @@ spinsum_status spinsum::build_batched(spinsum_plan_s* P, int64_t item_bytes) {
   // orbits through registers otherwise, with one vector width for all such
   // blocks
   const int esz = elem_size(*P);
+  auto cube_bytes_of = [&](int b) { return ipow(ns[b], d) * rs[b] * esz; };
   int64_t target = 8 * 1024;
   for (int b = 0; b < nblocks; ++b)
-    if (ns[b] > 0 && cs[b] > 0 && ipow(ns[b], d) * esz <= 40 * 1024)
-      target = std::max<int64_t>(target, ipow(ns[b], d) * esz);
+    if (ns[b] > 0 && cs[b] > 0 && cube_bytes_of(b) <= 40 * 1024)
+      target = std::max<int64_t>(target, cube_bytes_of(b));
   if (item_bytes > 0) target = item_bytes;
   int vmax = 16 / esz;
   for (int b = 0; b < nblocks; ++b)
-    if (ns[b] > 0 && cs[b] > 0 && ipow(ns[b], d) * esz > 40 * 1024)
-      vmax = std::min(vmax, max_vector_width(*P, ns[b]));
+    if (ns[b] > 0 && cs[b] > 0 && cube_bytes_of(b) > 40 * 1024)
+      vmax = std::min(vmax, max_vector_width(*P, (int64_t)ns[b] * rs[b]));
   P->batch_vw = vmax;
   P->btil.resize(nblocks);
   P->blocks.resize(nblocks);
@@ -1125,8 +1148,11 @@ spinsum_status spinsum::build_batched(spinsum_plan_s* P, int64_t item_bytes) {
   int group_base = 0;
   for (int b = 0; b < nblocks; ++b) {
     spinsum_tile_t t{};
+    // the tile rules read the inner spectator run from the plan: set it to
+    // this block's for the block's tables (reset to 1 below)
+    P->inner = rs[b];
     if (ns[b] > 0 && cs[b] > 0) {
-      const int64_t cube_bytes = ipow(ns[b], d) * esz;
+      const int64_t cube_bytes = cube_bytes_of(b);
       if (cube_bytes <= 40 * 1024) {
         t.bl = ns[b];
         t.cubes_per_wg = (int)std::max<int64_t>(1, std::min<int64_t>(target / cube_bytes, cs[b]));
@@ -1134,16 +1160,17 @@ spinsum_status spinsum::build_batched(spinsum_plan_s* P, int64_t item_bytes) {
         t.lds_pad = 0;
       } else {
         st = choose_tile(*P, ns[b], cs[b], vmax, &t, false);
-        if (st == SPINSUM_OK && t.bl % vmax != 0) st = SPINSUM_ERR_UNSUPPORTED;
+        if (st == SPINSUM_OK && ((int64_t)t.bl * rs[b]) % vmax != 0) st = SPINSUM_ERR_UNSUPPORTED;
       }
     }
     if (st == SPINSUM_OK) st = build_tiling(*P, ns[b], cs[b], t, vmax, &P->btil[b]);
+    P->inner = 1;
     if (st != SPINSUM_OK) return st;
     Tiling& T = P->btil[b];
     std::memset(&P->blocks[b], 0, sizeof(BatchBlock));
     P->blocks[b].g = T.g;
     P->blocks[b].group_base = group_base;
-    P->block_elems[b] = (ns[b] > 0 ? cs[b] * ipow(ns[b], d) : 0);
+    P->block_elems[b] = (ns[b] > 0 ? cs[b] * ipow(ns[b], d) * rs[b] : 0);
     P->elems += P->block_elems[b];
     P->ncubes += cs[b];
     P->batch_lds_elems = std::max(P->batch_lds_elems, T.lds_elems);
@@ -1178,7 +1205,7 @@ spinsum_status spinsum::build_batched(spinsum_plan_s* P, int64_t item_bytes) {
   auto cost = [&](const BatchItem& it) {
     const Tiling& T = P->btil[it.block];
     const GroupDev& gd = T.groups[it.group - P->blocks[it.block].group_base];
-    int64_t tile = ipow(T.g.bl, d);
+    int64_t tile = ipow(T.g.bl, d) * T.g.inner;
     return (int64_t)it.ncubes * gd.ntiles * tile;
   };
   std::stable_sort(P->items.begin(), P->items.end(),
@@ -1195,24 +1222,26 @@ spinsum_status spinsum::build_batched(spinsum_plan_s* P, int64_t item_bytes) {
 }
 
 extern "C" spinsum_status spinsum_plan_batched(spinsum_plan_t* plan, int nblocks, const int* ndims,
-                                               const int64_t* const* extents, int d, int nstages,
-                                               const int* nterms, const int* perms,
-                                               const double* alpha, spinsum_dtype dtype,
-                                               int inplace, unsigned flags) {
+                                               const int64_t* const* extents, int group_first,
+                                               int d, int nstages, const int* nterms,
+                                               const int* perms, const double* alpha,
+                                               spinsum_dtype dtype, int inplace, unsigned flags) {
   if (plan == nullptr) return SPINSUM_ERR_INVALID_ARG;
   *plan = nullptr;
   spinsum_status st = common_checks(d, dtype, inplace);
   if (st != SPINSUM_OK) return st;
   if (nblocks < 1 || nblocks > (1 << 20) || ndims == nullptr || extents == nullptr)
     return SPINSUM_ERR_INVALID_ARG;
-  std::vector<int> ns(nblocks);
+  if (group_first < -1) return SPINSUM_ERR_INVALID_ARG;
+  if (flags & SPINSUM_FLAG_INDEX_PAIRS) return SPINSUM_ERR_UNSUPPORTED;
+  std::vector<int> ns(nblocks), rs(nblocks);
   std::vector<int64_t> cs(nblocks);
   for (int b = 0; b < nblocks; ++b) {
     if (ndims[b] < d) return SPINSUM_ERR_INVALID_ARG;
-    int inner_b = 1;
-    st = shape_info(ndims[b], extents[b], ndims[b] - d, d, &ns[b], &cs[b], &inner_b);
+    const int gf = group_first < 0 ? ndims[b] - d : group_first;
+    st = shape_info(ndims[b], extents[b], gf, d, &ns[b], &cs[b], &rs[b]);
     if (st != SPINSUM_OK) return st;
-    if (ns[b] > 0 && ipow(ns[b], d) >= (1ll << 31)) return SPINSUM_ERR_UNSUPPORTED;
+    if (ns[b] > 0 && ipow(ns[b], d) * rs[b] >= (1ll << 31)) return SPINSUM_ERR_UNSUPPORTED;
   }
   spinsum_plan_s* P = new (std::nothrow) spinsum_plan_s();
   if (!P) return SPINSUM_ERR_OUT_OF_MEMORY;
@@ -1231,6 +1260,7 @@ extern "C" spinsum_status spinsum_plan_batched(spinsum_plan_t* plan, int nblocks
   query_device(P);
   P->bns = ns;
   P->bcs = cs;
+  P->brs = rs;
   {
     int64_t item_bytes = 0;
     int persistent = 0;

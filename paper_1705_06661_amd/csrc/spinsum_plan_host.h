@@ -67,6 +67,9 @@ struct spinsum_plan_s {
   std::vector<double> expanded;              // coefficient of each permutation rank
   std::vector<double> M, MT;                 // coefficient vectors (forward, adjoint), df each
   std::vector<double> SM, SMT;               // per-stage coefficient vectors, application order
+  // zero coefficients (bit s: stage s in application order; expanded: the
+  // pre-multiplied vector), see set_terms
+  uint32_t sparse_expanded = 0, sparse_fwd = 0, sparse_adj = 0;
 
   // tiling (single tensor)
   spinsum_tile_t tile{};
@@ -98,6 +101,7 @@ struct spinsum_plan_s {
   int batch_grid = 0;
   std::vector<int> bns;          // group extent of each block
   std::vector<int64_t> bcs;      // spectator cubes of each block
+  std::vector<int> brs;          // inner spectator run of each block (1: trailing group)
   int64_t batch_item_bytes = 0;  // whole-cube items are packed up to this size
   int batch_persistent = 0;      // 1: persistent workgroups walk the item list
 
@@ -115,10 +119,7 @@ struct spinsum_plan_s {
   void* d_cg_orbits = nullptr;  // Tc.groups, Tc.reps (cg_pack)
   void* d_cg_reps = nullptr;
   int last_hip_error = 0;
-  const void* occ_kernel = nullptr;  // occupancy cache of the persistent kernel
-  int64_t occ_shmem = -1;
-  int occ_threads = 0;
-  int occ_blocks = 1;
+  int occ_blocks = 1;  // workgroups per CU of the persistent exec kernel (cache_occupancy)
   std::string why;
 };
 
@@ -134,6 +135,8 @@ spinsum_status upload_tables(spinsum_plan_s* P);
 spinsum_status build_batched(spinsum_plan_s* P, int64_t item_bytes);
 void free_device(spinsum_plan_s* P);
 int elem_size(const spinsum_plan_s& P);
+// Implemented in spinsum_exec.hip
+spinsum_status cache_occupancy(spinsum_plan_s* P);
 // Implemented in spinsum_tune.cpp
 bool cache_lookup(const spinsum_plan_s& P, spinsum_tile_t* tile);
 bool batched_cache_lookup(const spinsum_plan_s& P, int64_t* item_bytes, int* persistent);

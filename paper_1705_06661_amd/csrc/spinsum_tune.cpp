@@ -52,7 +52,7 @@ static std::string cache_key(const spinsum_plan_s& P) {
 static std::string batched_key(const spinsum_plan_s& P) {
   int64_t elems = 0;
   for (size_t b = 0; b < P.bns.size(); ++b) {
-    int64_t c = P.bcs[b];
+    int64_t c = P.bcs[b] * (b < P.brs.size() ? P.brs[b] : 1);
     for (int m = 0; m < P.d; ++m) c *= P.bns[b];
     elems += c;
   }

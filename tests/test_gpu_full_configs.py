@@ -218,6 +218,12 @@ def test_batched_power_law_blocks():
         ss.spinsum_exec(ss.spinsum_plan(s, 3, 3, alpha), x, y)
         ref_out.append(y)
     bp = ss.spinsum_plan_batched(shapes, 3, alpha, inplace=True)
+    # the plan the benchmark times: item size and launch style from the
+    # autotuner (which overwrites the buffers it is given)
+    scratch = [torch.empty_like(x) for x in xs]
+    tuned, _ = ss.spinsum_autotune(bp, scratch, scratch)
+    _say("  autotuned", tuned, ss.spinsum_plan_get_info(bp)["batch_item_bytes"])
+    del scratch
     graph = ss.spinsum_graph_create(bp, xs, xs)
     ss.spinsum_graph_launch(graph)
     torch.cuda.synchronize()
@@ -291,7 +297,7 @@ def test_table2_small_and_large_inplace(size, case):
     assert err <= 1e-14
 
 
-@pytest.mark.parametrize("case", [1, 2, 4, 5, 8, 11, 17, 18, 21])
+@pytest.mark.parametrize("case", range(1, 22))
 def test_table2_medium_size_inplace(case):
     d, stages = workloads.table2_case(case)
     n = TABLE2_N[d]

@@ -199,6 +199,55 @@ def test_table2_case1_is_the_3d_coefficient_set():
                                rtol=0, atol=1e-12)
 
 
+def _as_dict(terms):
+    return {tuple(p): a for p, a in terms}
+
+
+def test_expanded_terms_of_printed_products():
+    """oracle.expanded_terms multiplies a chain out: Eq. 8 gives every
+    permutation once (Eq. 7), Table II case 1 the 3D coefficient set, and
+    (2 - P_ij)(2 - P_jk) gives 4 - 2 pi_213 - 2 pi_132 + pi_231 by hand
+    (P_ij pi_132 . x reads x_(p_132 o ..), i.e. pi_231 for the stage order of
+    Def. 4); a product that cancels, (1 + pi_213)(1 - pi_213) = 1 - pi_213^2,
+    gives no term at all."""
+    eq8 = [stage((1, "123"), (1, "321"), (1, "132")), stage((1, "123"), (1, "213"))]
+    assert _as_dict(oracle.expanded_terms(eq8, 3)) == {p: 1.0 for p in itertools.permutations(range(3))}
+    assert _as_dict(oracle.expanded_terms(workloads.table2_case(1)[1], 3)) == _as_dict(
+        workloads.CONFIG_3D_ALPHA)
+    assert _as_dict(oracle.expanded_terms(workloads.FACTORED_PIJ_PJK, 3)) == {
+        P("123"): 4.0, P("213"): -2.0, P("132"): -2.0, P("231"): 1.0}
+    cancel = [stage((1, "123"), (1, "213")), stage((1, "123"), (-1, "213"))]
+    assert oracle.expanded_terms(cancel, 3) == []
+
+
+def test_expanded_terms_agree_with_the_chain():
+    """The multiplied-out sum of every Table II case acts like the chain."""
+    for case in range(1, 22):
+        d, stages = workloads.table2_case(case)
+        x = _rand((2,) + (4,) * d, 60 + case)
+        np.testing.assert_allclose(oracle.spinsum(x, oracle.expanded_terms(stages, d), 1, d),
+                                   oracle.spinsum_chain(x, stages, 1, d), rtol=0, atol=1e-11)
+
+
+def test_flop_reduction_factors_of_sec6():
+    """The FLOP-count reduction the paper states for each group of Table II
+    cases follows from the multiplied-out term counts (golden file)."""
+    ident = {3: (0, 1, 2), 4: (0, 1, 2, 3)}
+    for ln in _lines("flop_reduction.txt"):
+        cases, factor = ln.split()
+        lo, _, hi = cases.partition("-")
+        for case in range(int(lo), int(hi or lo) + 1):
+            d, stages = workloads.table2_case(case)
+            expanded = [p for p, _ in oracle.expanded_terms(stages, d) if p != ident[d]]
+            factor_terms = 0
+            for st in stages:
+                merged = {}
+                for p, a in st:
+                    merged[p] = merged.get(p, 0.0) + a
+                factor_terms += sum(1 for p, a in merged.items() if a != 0.0 and p != ident[d])
+            assert round(len(expanded) / factor_terms) == int(factor), case
+
+
 def test_factored_pij_pjk_closed_form():
     """(2 - P_ij)(2 - P_jk) on A[i,j,k] = 100i + 10j + k.
     By hand from Def. 2: T = 2A - A[i,k,j] = 100i + 19j - 8k, then

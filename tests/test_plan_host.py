@@ -224,7 +224,7 @@ def test_expanded_term_counts_table2(case, count):
     assert ss.spinsum_plan_get_info(p)["nterms_expanded"] == count
 
 
-@pytest.mark.parametrize("case", [1, 5, 6, 9, 13, 17])
+@pytest.mark.parametrize("case", range(1, 22))
 def test_expanded_operator_matches_oracle_chain(case):
     d, stages = workloads.table2_case(case)
     p = plan((2,) + (4,) * d, stages, d=d)
@@ -232,6 +232,8 @@ def test_expanded_operator_matches_oracle_chain(case):
     exp = ss.spinsum_plan_expanded(p)
     np.testing.assert_allclose(oracle.spinsum(x, exp, 1, d), oracle.spinsum_chain(x, stages, 1, d),
                                rtol=0, atol=1e-11)
+    # the planner's product, term by term, against the oracle's own
+    assert _as_dict(exp) == {tuple(q): a for q, a in oracle.expanded_terms(stages, d)}
 
 
 def test_duplicates_merge_and_zeros_drop():
@@ -392,6 +394,32 @@ def test_batched_plan_tables():
     # whole cubes are packed up to the largest cube of at most 40 KiB (o = 16
     # here: 32 KiB), one workgroup per item unless a tuned cache says so
     assert info["batch_item_bytes"] == 16 ** 3 * 8 and info["batch_persistent"] == 0
+
+
+def test_batched_plan_with_inner_runs():
+    """A group at the same position of every block, inner spectator runs of
+    each block's own length behind it: elements and the work decomposition
+    of every block (whole cubes and tile orbits)."""
+    shapes = [(3, 5, 5, 5, 2), (2, 4, 4, 4, 7), (1, 24, 24, 24, 3), (4, 2, 2, 2, 1), (2, 3, 3, 3, 16)]
+    p = ss.spinsum_plan_batched(shapes, 3, [workloads.CONFIG_3D_ALPHA], inplace=True, flags=HOST,
+                                group_first=1)
+    info = ss.spinsum_plan_get_info(p)
+    assert info["elems"] == sum(int(np.prod(s)) for s in shapes)
+    assert info["ncubes"] == sum(s[0] for s in shapes)
+    for b in range(len(shapes)):
+        ok, why = ss.spinsum_plan_check_ownership(p, b)
+        assert ok, (b, why)
+    # -1: the trailing group of each block, whatever its rank
+    q = ss.spinsum_plan_batched([(2, 4, 4, 4), (3, 2, 5, 5, 5)], 3, [workloads.CONFIG_3D_ALPHA],
+                                flags=HOST)
+    assert ss.spinsum_plan_get_info(q)["ncubes"] == 2 + 6
+    with pytest.raises(ss.SpinSumError):
+        ss.spinsum_plan_batched([(2, 4, 4, 4)], 3, [workloads.CONFIG_3D_ALPHA], flags=HOST,
+                                group_first=2)
+    with pytest.raises(ss.SpinSumError) as e:
+        ss.spinsum_plan_batched([(2, 2, 2, 4, 4, 4)], 3, [workloads.CONFIG_3D_ALPHA],
+                                flags=HOST | ss.SPINSUM_FLAG_INDEX_PAIRS, group_first=3)
+    assert e.value.status == ss.SPINSUM_ERR_UNSUPPORTED
 
 
 def test_batched_plan_reads_a_tuned_cache_line(tmp_path, monkeypatch):
