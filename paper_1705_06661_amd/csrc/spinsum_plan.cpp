@@ -1160,7 +1160,16 @@ spinsum_status spinsum::build_batched(spinsum_plan_s* P, int64_t item_bytes) {
         t.lds_pad = 0;
       } else {
         st = choose_tile(*P, ns[b], cs[b], vmax, &t, false);
-        if (st == SPINSUM_OK && ((int64_t)t.bl * rs[b]) % vmax != 0) st = SPINSUM_ERR_UNSUPPORTED;
+        if (st == SPINSUM_OK && t.bl >= ns[b]) {
+          // a whole cube after all (up to 64 KiB): the batched kernel copies
+          // whole cubes as one contiguous run, so their LDS image is unpadded
+          t.bl = ns[b];
+          t.cubes_per_wg = 1;
+          t.lds_pad = 0;
+          t.threads = 256;
+        }
+        if (st == SPINSUM_OK && ((int64_t)t.bl * rs[b]) % vmax != 0 && t.bl != ns[b])
+          st = SPINSUM_ERR_UNSUPPORTED;
       }
     }
     if (st == SPINSUM_OK) st = build_tiling(*P, ns[b], cs[b], t, vmax, &P->btil[b]);

@@ -456,7 +456,7 @@ def test_batched_inner_runs_equal_per_block_and_oracle(dtype):
     """Batched plans with the group before inner spectator runs of each
     block's own length (whole cubes and, for the 24^3 block, tile orbits)."""
     shapes = [(3, 5, 5, 5, 2), (2, 4, 4, 4, 7), (1, 24, 24, 24, 3), (4, 2, 2, 2, 1),
-              (2, 3, 3, 3, 16), (2, 16, 16, 16, 2)]
+              (2, 3, 3, 3, 16), (2, 16, 16, 16, 2), (1, 19, 19, 19, 1)]
     xs = [gpu_uniform(s, 70 + k, dtype) for k, s in enumerate(shapes)]
     st = workloads.FACTORED_PIJ_PJK
     for inplace in (False, True):

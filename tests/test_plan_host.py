@@ -400,7 +400,8 @@ def test_batched_plan_with_inner_runs():
     """A group at the same position of every block, inner spectator runs of
     each block's own length behind it: elements and the work decomposition
     of every block (whole cubes and tile orbits)."""
-    shapes = [(3, 5, 5, 5, 2), (2, 4, 4, 4, 7), (1, 24, 24, 24, 3), (4, 2, 2, 2, 1), (2, 3, 3, 3, 16)]
+    shapes = [(3, 5, 5, 5, 2), (2, 4, 4, 4, 7), (1, 24, 24, 24, 3), (4, 2, 2, 2, 1), (2, 3, 3, 3, 16),
+              (2, 16, 16, 16, 2), (1, 19, 19, 19, 1)]   # the last two: whole cubes of 40-64 KiB
     p = ss.spinsum_plan_batched(shapes, 3, [workloads.CONFIG_3D_ALPHA], inplace=True, flags=HOST,
                                 group_first=1)
     info = ss.spinsum_plan_get_info(p)
@@ -410,9 +411,12 @@ def test_batched_plan_with_inner_runs():
         ok, why = ss.spinsum_plan_check_ownership(p, b)
         assert ok, (b, why)
     # -1: the trailing group of each block, whatever its rank
-    q = ss.spinsum_plan_batched([(2, 4, 4, 4), (3, 2, 5, 5, 5)], 3, [workloads.CONFIG_3D_ALPHA],
-                                flags=HOST)
-    assert ss.spinsum_plan_get_info(q)["ncubes"] == 2 + 6
+    q = ss.spinsum_plan_batched([(2, 4, 4, 4), (3, 2, 5, 5, 5), (2, 18, 18, 18)], 3,
+                                [workloads.CONFIG_3D_ALPHA], flags=HOST)
+    assert ss.spinsum_plan_get_info(q)["ncubes"] == 2 + 6 + 2
+    for b in range(3):
+        ok, why = ss.spinsum_plan_check_ownership(q, b)
+        assert ok, (b, why)
     with pytest.raises(ss.SpinSumError):
         ss.spinsum_plan_batched([(2, 4, 4, 4)], 3, [workloads.CONFIG_3D_ALPHA], flags=HOST,
                                 group_first=2)
