@@ -264,6 +264,20 @@ spinsum_status spinsum_adjoint(spinsum_plan_t plan, const void* grad_out, void* 
 spinsum_status spinsum_coef_grad(spinsum_plan_t plan, const void* x, const void* g,
                                  double* grad, void* stream);
 
+/* spinsum_coef_grad for callers that cannot allocate device memory (code
+ * under hipGraph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, but the partial sums go to a
+ * static array of the library (kGradSlots x d! doubles, at most 384 KiB per
+ * GPU, held until the process ends) instead of the plan's buffer.  Calls no
+ * hipMalloc/hipFree; the first call on a device looks up that device's
+ * copy of the array (hipGetSymbolAddress).  Every call on one GPU shares
+ * the array: calls that overlap on one GPU (any plans, any streams) race
+ * and must be serialised by the caller.  Sizes beyond the array
+ * (SPINSUM_ERR_UNSUPPORTED) cannot occur for d <= 4.  Arguments, layout and
+ * errors as spinsum_coef_grad. */
+spinsum_status spinsum_coef_grad_noalloc(spinsum_plan_t plan, const void* x, const void* g,
+                                         double* grad, void* stream);
+
 /* Capture one spinsum_exec_batched launch into a hipGraph (captured on a
  * private stream) and instantiate it.  The pointer arrays must stay valid
  * for the life of the graph, and so must the plan's device tables: create

@@ -119,6 +119,7 @@ _c_exec = _decl("spinsum_exec", [_vp, _vp, _vp, _vp])
 _c_exec_batched = _decl("spinsum_exec_batched", [_vp, _vp, _vp, _vp])
 _c_adjoint = _decl("spinsum_adjoint", [_vp, _vp, _vp, _vp])
 _c_coef_grad = _decl("spinsum_coef_grad", [_vp, _vp, _vp, _vp, _vp])
+_c_coef_grad_noalloc = _decl("spinsum_coef_grad_noalloc", [_vp, _vp, _vp, _vp, _vp])
 _c_graph_create = _decl("spinsum_graph_create", [_vp, _vp, _vp, ctypes.POINTER(_vp)])
 _c_graph_launch = _decl("spinsum_graph_launch", [_vp, _vp])
 _c_graph_destroy = _decl("spinsum_graph_destroy", [_vp], None)
@@ -133,6 +134,7 @@ _c_version = _decl("spinsum_version", [], ctypes.c_char_p)
 EXPORTED = ["spinsum_plan", "spinsum_plan_batched", "spinsum_plan_set_tile",
             "spinsum_plan_get_info", "spinsum_plan_expanded", "spinsum_plan_check_ownership",
             "spinsum_exec", "spinsum_exec_batched", "spinsum_adjoint", "spinsum_coef_grad",
+            "spinsum_coef_grad_noalloc",
             "spinsum_graph_create",
             "spinsum_graph_launch", "spinsum_graph_destroy", "spinsum_autotune",
             "spinsum_stream_copy", "spinsum_plan_last_hip_error", "spinsum_plan_destroy",
@@ -320,6 +322,21 @@ def spinsum_coef_grad(plan: Plan, x: torch.Tensor, g: torch.Tensor, stream=None)
     out = torch.empty(math.factorial(plan.d), dtype=torch.float64, device=x.device)
     _check(_c_coef_grad(plan._h, a, b, out.data_ptr(), _stream(stream)), "spinsum_coef_grad", plan)
     return out
+
+
+def spinsum_coef_grad_noalloc(plan: Plan, x: torch.Tensor, g: torch.Tensor,
+                              grad: torch.Tensor, stream=None) -> torch.Tensor:
+    """spinsum_coef_grad into a caller-provided ``grad`` (d! float64 values on
+    the device), with the library's static partial-sum array: no device
+    memory is allocated by this call.  Calls on one GPU must not overlap."""
+    a = _tensor_ptr(x, plan, plan.shape, "x")
+    b = _tensor_ptr(g, plan, plan.shape, "g")
+    if (not isinstance(grad, torch.Tensor) or not grad.is_cuda or grad.dtype != torch.float64
+            or grad.numel() != math.factorial(plan.d) or not grad.is_contiguous()):
+        raise SpinSumError(SPINSUM_ERR_INVALID_ARG, "grad must be d! contiguous float64 on the GPU")
+    _check(_c_coef_grad_noalloc(plan._h, a, b, grad.data_ptr(), _stream(stream)),
+           "spinsum_coef_grad_noalloc", plan)
+    return grad
 
 
 class PointerArrays:

@@ -1,6 +1,8 @@
 // spinsum_exec.hip -- exec / adjoint / batched / graph / copy entry points of
 // the C-ABI of libspinsum (argument checks and dispatch to the per-dtype
 // launchers).
+#include <mutex>
+
 #include "spinsum_device.h"
 
 namespace spinsum {
@@ -348,14 +350,14 @@ namespace {
 
 template <typename T>
 spinsum_status launch_cgrad(spinsum_plan_s* P, const void* x, const void* g, double* grad,
-                            hipStream_t stream) {
+                            double* part, hipStream_t stream) {
   // its own packed tiling where the plan has one (see build_cgrad_tiling)
   const Tiling& Tl = P->cg_pack ? P->Tc : P->T;
   CGradArgs<T> a;
   std::memset(&a, 0, sizeof(a));
   a.x = reinterpret_cast<const T*>(x);
   a.gr = reinterpret_cast<const T*>(g);
-  a.grad = reinterpret_cast<double*>(P->d_grad_part);
+  a.grad = part;
   a.orbits = reinterpret_cast<const GroupDev*>(P->cg_pack ? P->d_cg_orbits : P->d_orbits);
   a.reps = reinterpret_cast<const uint32_t*>(P->cg_pack ? P->d_cg_reps : P->d_reps);
   a.g = Tl.g;
@@ -394,8 +396,43 @@ spinsum_status launch_cgrad(spinsum_plan_s* P, const void* x, const void* g, dou
 }  // namespace
 }  // namespace spinsum
 
-extern "C" spinsum_status spinsum_coef_grad(spinsum_plan_t P, const void* x, const void* g,
-                                            double* grad, void* stream) {
+namespace spinsum {
+namespace {
+
+// The coefficient gradient's partial sums for callers that cannot allocate
+// (spinsum_coef_grad_noalloc): one array per GPU for the life of the
+// process, shared by every call on that GPU.  In host code `scratch` only
+// names the symbol; its device address is taken once per device
+// (scratch_on_device) and that address is what the kernels receive.
+constexpr int kScratchDoubles = kGradSlots * kMaxDF;  // 384 KiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+double* scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's `scratch` (the current device, which
+// check_device has matched to the plan's).
+spinsum_status scratch_on_device(spinsum_plan_s* P, double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_error(P, e);
+  if (dev < 0 || dev >= kMaxDevices) return SPINSUM_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) return hip_error(P, e != hipSuccess ? e : hipErrorInvalidSymbol);
+    scratch_ptr[dev] = reinterpret_cast<double*>(ptr);
+  }
+  *out = scratch_ptr[dev];
+  return SPINSUM_OK;
+}
+
+// spinsum_coef_grad with the partial sums in `part` (kGradSlots x d!
+// doubles) or, for part == nullptr, in this device's `scratch`.
+spinsum_status coef_grad_impl(spinsum_plan_s* P, const void* x, const void* g, double* grad,
+                              bool use_scratch, void* stream) {
   if (P == nullptr || P->batched || grad == nullptr) return SPINSUM_ERR_INVALID_ARG;
   if (!P->has_dev) return SPINSUM_ERR_NO_DEVICE;
   if (((uintptr_t)grad) & 7u) return SPINSUM_ERR_MISALIGNED;
@@ -417,8 +454,27 @@ extern "C" spinsum_status spinsum_coef_grad(spinsum_plan_t P, const void* x, con
   const bool whole = Tl.g.bl == Tl.g.n;
   const bool rows = Tl.vw * elem_size(*P) == 16;
   if (P->tile.lds_pad != 0 || !(whole || rows)) return SPINSUM_ERR_UNSUPPORTED;
-  if (P->dtype == SPINSUM_F32) return launch_cgrad<float>(P, x, g, grad, (hipStream_t)stream);
-  return launch_cgrad<double>(P, x, g, grad, (hipStream_t)stream);
+  double* part = reinterpret_cast<double*>(P->d_grad_part);
+  if (use_scratch) {
+    if ((int64_t)kGradSlots * P->G.df > kScratchDoubles) return SPINSUM_ERR_UNSUPPORTED;
+    st = scratch_on_device(P, &part);
+    if (st != SPINSUM_OK) return st;
+  }
+  if (P->dtype == SPINSUM_F32) return launch_cgrad<float>(P, x, g, grad, part, (hipStream_t)stream);
+  return launch_cgrad<double>(P, x, g, grad, part, (hipStream_t)stream);
+}
+
+}  // namespace
+}  // namespace spinsum
+
+extern "C" spinsum_status spinsum_coef_grad(spinsum_plan_t P, const void* x, const void* g,
+                                            double* grad, void* stream) {
+  return coef_grad_impl(P, x, g, grad, false, stream);
+}
+
+extern "C" spinsum_status spinsum_coef_grad_noalloc(spinsum_plan_t P, const void* x,
+                                                    const void* g, double* grad, void* stream) {
+  return coef_grad_impl(P, x, g, grad, true, stream);
 }
 
 extern "C" spinsum_status spinsum_exec_batched(spinsum_plan_t P, const void* const* in,
