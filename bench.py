@@ -82,15 +82,24 @@ def kernel_name(info, dtype="double"):
     return f"k_exec<{dtype}, {d}, {info['vector_width']}, false, true>"
 
 
-def warm(fn, seconds=0.25):
+def warm(fn, seconds=0.25, refill=None):
     """Untimed repeats of a form's call until `seconds` have passed, so that
     a short form is not timed while the GPU clocks are still ramping up
-    after host-side set-up (measured: 4D slab 1.11 ms cold, 0.955 ms warm)."""
+    after host-side set-up (measured: 4D slab 1.11 ms cold, 0.955 ms warm).
+    In-place forms pass `refill`, which restores finite input values after
+    the warm-up: every in-place pass multiplies magnitudes by up to the
+    operator's spectral radius (12 for the 3D set, up to ~85 for 24 random 4D
+    coefficients), so hundreds of passes overflow to Inf/NaN, and non-finite
+    inputs take the slower term-by-term combine of operators with zero
+    coefficients."""
     import torch
     t0 = time.perf_counter()
     while time.perf_counter() - t0 < seconds:
         for _ in range(4):
             fn()
+        torch.cuda.synchronize()
+    if refill is not None:
+        refill()
         torch.cuda.synchronize()
 
 
@@ -437,7 +446,8 @@ def main():
             pf = ss.spinsum_plan(slab_shape, 3, 3, workloads.FACTORED_PIJ_PJK, inplace=True,
                                  flags=flags)
             workloads.fill_uniform(big[0], 1000)  # fresh values: repeated passes grow them
-            warm(lambda: ss.spinsum_exec(pf, big[0], big[0], stream))
+            warm(lambda: ss.spinsum_exec(pf, big[0], big[0], stream),
+                 refill=lambda: workloads.fill_uniform(big[0], 1000))
             fms = timed(lambda: ss.spinsum_exec(pf, big[0], big[0], stream), 5, stream)
             forms[name] = form_entry(2 * big[0].numel() * 8, fms, value)
         # coefficient gradient <g, pi_p(x)> for all 6 permutations: two slabs
@@ -449,14 +459,16 @@ def main():
         # antisymmetrisation (every permutation weighted by its sign), slab 0
         pa = ss.spinsum_plan(slab_shape, 3, 3, [workloads.antisymmetrizer(3)], inplace=True)
         workloads.fill_uniform(big[0], 1000)
-        warm(lambda: ss.spinsum_exec(pa, big[0], big[0], stream))
+        warm(lambda: ss.spinsum_exec(pa, big[0], big[0], stream),
+             refill=lambda: workloads.fill_uniform(big[0], 1000))
         ams = timed(lambda: ss.spinsum_exec(pa, big[0], big[0], stream), 5, stream)
         forms["3d_antisymmetrize"] = form_entry(2 * big[0].numel() * 8, ams, value)
         for name, flags in [("3d_no_nt_stores", ss.SPINSUM_FLAG_NO_NT_STORES),
                             ("3d_no_xcd_grouping", ss.SPINSUM_FLAG_NO_XCD_REMAP)]:
             pf = ss.spinsum_plan(slab_shape, 3, 3, alpha, inplace=True, flags=flags)
             workloads.fill_uniform(big[0], 1000)  # fresh values: repeated passes grow them
-            warm(lambda: ss.spinsum_exec(pf, big[0], big[0], stream))
+            warm(lambda: ss.spinsum_exec(pf, big[0], big[0], stream),
+                 refill=lambda: workloads.fill_uniform(big[0], 1000))
             fms = timed(lambda: ss.spinsum_exec(pf, big[0], big[0], stream), 5, stream)
             forms[name] = form_entry(2 * big[0].numel() * 8, fms, value)
         del big
@@ -468,7 +480,8 @@ def main():
         a4 = workloads.random_4d_alpha(7)
         p4 = ss.spinsum_plan(w4["shape"], 4, 4, [a4], inplace=True)
         ss.spinsum_exec(p4, x4, x4, stream)
-        warm(lambda: ss.spinsum_exec(p4, x4, x4, stream))
+        warm(lambda: ss.spinsum_exec(p4, x4, x4, stream),
+             refill=lambda: workloads.fill_uniform(x4, 2000))
         ms4 = timed(lambda: ss.spinsum_exec(p4, x4, x4, stream), 10, stream)
         forms["4d_v24_o12_inplace"] = form_entry(2 * x4.numel() * 8, ms4, value)
         forms["4d_v24_o12_inplace"]["tile_edge"] = ss.spinsum_plan_get_info(p4)["bl"]
@@ -482,11 +495,16 @@ def main():
         xs = [workloads.uniform(s, 3000 + k, device=dev) for k, s in enumerate(shapes)]
         nbytes = 2 * 8 * sum(x.numel() for x in xs)
         bp = ss.spinsum_plan_batched(shapes, 3, alpha, inplace=True)
+
+        def refill_blocks():
+            for k, x in enumerate(xs):
+                workloads.fill_uniform(x, 3000 + k)
+
         # item size and launch style picked by the library's autotuner
         tuned, _ = ss.spinsum_autotune(bp, xs, xs)
         graph = ss.spinsum_graph_create(bp, xs, xs)
         ss.spinsum_graph_launch(graph, stream)
-        warm(lambda: ss.spinsum_graph_launch(graph, stream))
+        warm(lambda: ss.spinsum_graph_launch(graph, stream), refill=refill_blocks)
         bms = timed(lambda: ss.spinsum_graph_launch(graph, stream), 10, stream)
         singles = [ss.spinsum_plan(s, 3, 3, alpha, inplace=True) for s in shapes]
 
@@ -495,7 +513,7 @@ def main():
                 ss.spinsum_exec(p, x, x, stream)
 
         per_block()
-        warm(per_block)
+        warm(per_block, refill=refill_blocks)
         pms = timed(per_block, 5, stream)
         forms["batched_graph"] = form_entry(nbytes, bms, value)
         forms["batched_graph"].update({"blocks": len(blocks), "block_seed": seed,
@@ -511,7 +529,8 @@ def main():
         xin = workloads.uniform((64, 64, 32, 32, 32, 8), 5000, device=dev)
         pin = ss.spinsum_plan(tuple(xin.shape), 2, 3, alpha, inplace=True)
         ss.spinsum_exec(pin, xin, xin, stream)
-        warm(lambda: ss.spinsum_exec(pin, xin, xin, stream))
+        warm(lambda: ss.spinsum_exec(pin, xin, xin, stream),
+             refill=lambda: workloads.fill_uniform(xin, 5000))
         ims = timed(lambda: ss.spinsum_exec(pin, xin, xin, stream), 5, stream)
         forms["3d_inner_run8_inplace"] = form_entry(2 * xin.numel() * 8, ims, value)
         forms["3d_inner_run8_inplace"]["tile_edge"] = ss.spinsum_plan_get_info(pin)["bl"]
@@ -524,7 +543,8 @@ def main():
         pp = ss.spinsum_plan(w5["shape"], 3, 3, alpha, inplace=True,
                              flags=ss.SPINSUM_FLAG_INDEX_PAIRS)
         ss.spinsum_exec(pp, xp, xp, stream)
-        warm(lambda: ss.spinsum_exec(pp, xp, xp, stream))
+        warm(lambda: ss.spinsum_exec(pp, xp, xp, stream),
+             refill=lambda: workloads.fill_uniform(xp, 5100))
         pms_ = timed(lambda: ss.spinsum_exec(pp, xp, xp, stream), 5, stream)
         forms["3d_pairs_v48_o24_inplace"] = form_entry(2 * xp.numel() * 8, pms_, value)
         forms["3d_pairs_v48_o24_inplace"]["tile_edge"] = ss.spinsum_plan_get_info(pp)["bl"]

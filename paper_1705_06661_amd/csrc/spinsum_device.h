@@ -226,70 +226,25 @@ __device__ __forceinline__ T orbit_row(const T* a, const T* v, std::integer_sequ
   return acc;
 }
 
-// The same row over the operator's own terms only: a permutation whose
-// coefficient is zero is not a term of the sum (Def. 3), so its input is
-// not read at all.  For finite inputs this equals orbit_row (adding 0 * v
-// is exact); it differs where some v_sigma is Inf or NaN, which then
-// reaches only the outputs of the terms that read it.  The coefficients are
-// wave-uniform, so every test is a scalar branch.
-template <typename T, int D, int TAU, int... S>
-__device__ __forceinline__ T orbit_row_terms(const T* a, const T* v, std::integer_sequence<int, S...>) {
-  T acc = T(0);
-  ((acc = (a[GinvMul<D, TAU, S>::value] != T(0)) ? fma_t(a[GinvMul<D, TAU, S>::value], v[S], acc)
-                                                  : acc),
-   ...);
-  return acc;
-}
-
 template <typename T, int D, int... TAU>
-__device__ __forceinline__ void orbit_rows_terms(const T* a, const T* v, T* w,
-                                                 std::integer_sequence<int, TAU...>) {
-  ((w[TAU] = orbit_row_terms<T, D, TAU>(a, v, std::make_integer_sequence<int, Fact<D>::v>{})), ...);
+__device__ __forceinline__ void orbit_rows(const T* a, const T* v, T* w,
+                                           std::integer_sequence<int, TAU...>) {
+  ((w[TAU] = orbit_row<T, D, TAU>(a, v, std::make_integer_sequence<int, Fact<D>::v>{})), ...);
 }
 
-// Whether an element orbit has to be redone over the operator's own terms:
-// w0 = sum_sigma a(sigma) v_sigma is formed over every sigma, zero
-// coefficients included, so one Inf or NaN among the v_sigma makes w0 Inf or
-// NaN (a * Inf is +-Inf, 0 * Inf and anything with NaN are NaN, and a sum
-// holding a non-finite term stays non-finite).  A finite w0 therefore means
-// every v_sigma is finite and the dense product is exact; a non-finite one
-// (or an overflow, which is rare and harmless) sends the whole wave to the
-// term-by-term product.  Operators with every coefficient nonzero
-// (sparse == false) never need it.
-template <typename T>
-__device__ __forceinline__ bool needs_terms(bool sparse, T w0) {
-  return sparse && __builtin_amdgcn_ballot_w64(!__builtin_isfinite(w0)) != 0ull;
-}
-
-template <typename T, int D, int... TAU>
-__device__ __forceinline__ void orbit_rows_tail(const T* a, const T* v, T* w,
-                                                std::integer_sequence<int, TAU...>) {
-  ((w[TAU + 1] = orbit_row<T, D, TAU + 1>(a, v, std::make_integer_sequence<int, Fact<D>::v>{})),
-   ...);
-}
-
-// w = the coefficient product of one element orbit (chained stages); row 0
-// is formed first and decides whether the orbit takes the term-by-term
-// product (needs_terms).
+// w = one stage's coefficient product of an element orbit (chained
+// stages).
 template <typename T, int D>
 __device__ __forceinline__ void orbit_product(const T (&a)[Fact<D>::v], const T (&v)[Fact<D>::v],
-                                              T (&w)[Fact<D>::v], bool sparse) {
-  constexpr int DF = Fact<D>::v;
-  const T w0 = orbit_row<T, D, 0>(a, v, std::make_integer_sequence<int, DF>{});
-  if (needs_terms<T>(sparse, w0)) {
-    orbit_rows_terms<T, D>(a, v, w, std::make_integer_sequence<int, DF>{});
-  } else {
-    w[0] = w0;
-    orbit_rows_tail<T, D>(a, v, w, std::make_integer_sequence<int, DF - 1>{});
-  }
+                                              T (&w)[Fact<D>::v]) {
+  orbit_rows<T, D>(a, v, w, std::make_integer_sequence<int, Fact<D>::v>{});
 }
 
 // The same product, each w_tau written to LDS as soon as it is formed (all
 // v_sigma are already in registers, so the in-place writes are safe); only
 // a few accumulators are live at a time.  (One FMA chain per row is fine:
 // a wave64 FMA occupies its SIMD for four cycles, which covers the
-// dependency latency.)  Row 0 is formed first and decides whether the
-// orbit takes the term-by-term product (needs_terms).
+// dependency latency.)
 template <typename T, int D, int... TAU>
 __device__ __forceinline__ void orbit_rows_store_tail(const T* a, const T* v, T* lds, const int* addr,
                                                       std::integer_sequence<int, TAU...>) {
@@ -298,24 +253,20 @@ __device__ __forceinline__ void orbit_rows_store_tail(const T* a, const T* v, T*
    ...);
 }
 
-template <typename T, int D, int... TAU>
-__device__ __forceinline__ void orbit_rows_store_terms(const T* a, const T* v, T* lds, const int* addr,
-                                                       std::integer_sequence<int, TAU...>) {
-  ((lds[addr[TAU]] = orbit_row_terms<T, D, TAU>(a, v, std::make_integer_sequence<int, Fact<D>::v>{})),
-   ...);
-}
-
+// Combine one element orbit in place in LDS (pre-multiplied operator).
+// Returns w_0, which tells whether an input was Inf or NaN: w_0 is formed
+// over every sigma, zero coefficients included, so one Inf or NaN among the
+// v_sigma makes it Inf or NaN (a * Inf is +-Inf, 0 * Inf and anything with
+// NaN are NaN, and a sum holding a non-finite term stays non-finite); a
+// finite w_0 means every input was finite and the dense product was exact.
 template <typename T, int D>
-__device__ __forceinline__ void orbit_store(const T (&a)[Fact<D>::v], const T (&v)[Fact<D>::v],
-                                            T* lds, const int (&addr)[Fact<D>::v], bool sparse) {
+__device__ __forceinline__ T orbit_store(const T (&a)[Fact<D>::v], const T (&v)[Fact<D>::v],
+                                         T* lds, const int (&addr)[Fact<D>::v]) {
   constexpr int DF = Fact<D>::v;
   const T w0 = orbit_row<T, D, 0>(a, v, std::make_integer_sequence<int, DF>{});
-  if (needs_terms<T>(sparse, w0)) {
-    orbit_rows_store_terms<T, D>(a, v, lds, addr, std::make_integer_sequence<int, DF>{});
-  } else {
-    lds[addr[0]] = w0;
-    orbit_rows_store_tail<T, D>(a, v, lds, addr, std::make_integer_sequence<int, DF - 1>{});
-  }
+  lds[addr[0]] = w0;
+  orbit_rows_store_tail<T, D>(a, v, lds, addr, std::make_integer_sequence<int, DF - 1>{});
+  return w0;
 }
 
 // Unit i of an orbit's combine loop -> cube of the item ci, representative
@@ -338,17 +289,20 @@ __device__ __forceinline__ void split_unit(const Geom& g, uint32_t i, uint32_t r
 // Combine the element orbits of one tile orbit: sb[sigma] = LDS offset of
 // tile sigma . B, rp = its representative list (rep_cnt entries, local
 // coordinates packed one byte per axis), for ncub cubes of the item.
-// sparse: bit s set if stage s (bit 0 alone without CHAIN: the
-// pre-multiplied operator) has a permutation of zero coefficient; stages
-// from 32 on are always treated as having one.
+// Returns (per thread) whether one of its element orbits had an Inf or NaN
+// input (see orbit_store; with chained stages the last stage's w_0 tells,
+// since a non-finite value reaches every row of every later stage).  Where
+// the operator leaves out a permutation, such an item is redone by
+// redo_orbit, kept out of this loop so that the dense product's registers
+// stay as they are.
 template <typename T, int D, bool CHAIN>
-__device__ __forceinline__ void combine_orbit(const Geom& g, const int32_t (&sb)[Fact<D>::v],
+__device__ __forceinline__ bool combine_orbit(const Geom& g, const int32_t (&sb)[Fact<D>::v],
                                               const uint32_t* rp, uint32_t rep_cnt,
                                               const FastDiv& fdr, int ncub, cptr<T> coef,
-                                              int nstages, uint32_t sparse, T (&a)[Fact<D>::v],
-                                              T* lds) {
+                                              int nstages, T (&a)[Fact<D>::v], T* lds) {
   constexpr int DF = Fact<D>::v;
   const uint32_t nrep = (uint32_t)ncub * rep_cnt * (uint32_t)g.inner;
+  bool bad = false;
   for (uint32_t i = threadIdx.x; i < nrep; i += blockDim.x) {
     uint32_t ci, ri, si;
     split_unit(g, i, rep_cnt, fdr, ncub, &ci, &ri, &si);
@@ -363,37 +317,41 @@ __device__ __forceinline__ void combine_orbit(const Geom& g, const int32_t (&sb)
 #pragma unroll
     for (int r = 0; r < DF; ++r) v[r] = lds[addr[r]];
     if constexpr (!CHAIN) {
-      orbit_store<T, D>(a, v, lds, addr, (sparse & 1u) != 0u);
+      const T w0 = orbit_store<T, D>(a, v, lds, addr);
+      bad |= !__builtin_isfinite(w0);
     } else {
       T w[DF];
       for (int s = 0; s < nstages; ++s) {
 #pragma unroll
         for (int r = 0; r < DF; ++r) a[r] = coef[s * DF + r];
-        orbit_product<T, D>(a, v, w, s >= 32 || ((sparse >> s) & 1u) != 0u);
+        orbit_product<T, D>(a, v, w);
 #pragma unroll
         for (int r = 0; r < DF; ++r) v[r] = w[r];
       }
+      bad |= !__builtin_isfinite(v[0]);
 #pragma unroll
       for (int r = 0; r < DF; ++r) lds[addr[r]] = v[r];
     }
   }
+  return bad;
 }
 
 // 2. combine every element orbit of the item in LDS
 // Combine every element orbit of a work item.  The item's tile orbits are
 // visited in turn (uniform loop); their representatives come from global
 // memory (REPS_IN_LDS false: reps + rep_off[k]) or from the item's LDS copy
-// (true: reps + rep_base[k]).
+// (true: reps + rep_base[k]).  Returns the per-thread flag of combine_orbit.
 template <typename T, int D, bool CHAIN, bool REPS_IN_LDS>
-__device__ __forceinline__ void combine_item(const Geom& g, cptr<GroupDev> gd,
+__device__ __forceinline__ bool combine_item(const Geom& g, cptr<GroupDev> gd,
                                              const uint32_t* reps, cptr<T> coef, int nstages,
-                                             uint32_t sparse, int ncub, T* lds) {
+                                             int ncub, T* lds) {
   constexpr int DF = Fact<D>::v;
   T a[DF];
   if constexpr (!CHAIN) {
 #pragma unroll
     for (int r = 0; r < DF; ++r) a[r] = coef[r];
   }
+  bool bad = false;
   const int norb = gd->norb;
   for (int k = 0; k < norb; ++k) {
     int32_t sb[DF];
@@ -401,9 +359,156 @@ __device__ __forceinline__ void combine_item(const Geom& g, cptr<GroupDev> gd,
     for (int r = 0; r < DF; ++r) sb[r] = gd->slot_base[k][r];
     const FastDiv fdr = load_fd(gd->fd_rep[k]);
     const uint32_t* rp = reps + (REPS_IN_LDS ? gd->rep_base[k] : gd->rep_off[k]);
-    combine_orbit<T, D, CHAIN>(g, sb, rp, (uint32_t)gd->rep_cnt[k], fdr, ncub, coef, nstages,
-                               sparse, a, lds);
+    bad |= combine_orbit<T, D, CHAIN>(g, sb, rp, (uint32_t)gd->rep_cnt[k], fdr, ncub, coef, nstages,
+                                      a, lds);
   }
+  return bad;
+}
+
+// Tables of S_d for (wave-uniform) runtime indices, read by redo_orbit: the
+// rank of tau^-1 o sigma, and the inverse of the r-th permutation
+// (inv[r][j] = m where lex_perm(r, m) = j).  The unrolled dense product
+// takes the same values as template constants.
+template <int D>
+struct RuntimeTables {
+  int8_t ginv[Fact<D>::v * Fact<D>::v];
+  int8_t inv[Fact<D>::v][kMaxD];
+  constexpr RuntimeTables() : ginv(), inv() {
+    for (int t = 0; t < Fact<D>::v; ++t)
+      for (int s = 0; s < Fact<D>::v; ++s) ginv[t * Fact<D>::v + s] = (int8_t)ginv_mul(D, t, s);
+    for (int r = 0; r < Fact<D>::v; ++r)
+      for (int m = 0; m < D; ++m) inv[r][lex_perm(D, r, m)] = (int8_t)m;
+  }
+};
+template <int D>
+__constant__ const RuntimeTables<D> kRuntimeTables = RuntimeTables<D>();
+
+// Strides of group axis m (wave-uniform runtime m < D): in LDS and in the
+// tensor.
+__device__ __forceinline__ int32_t lds_stride(const Geom& g, int m) {
+  return m == 0 ? g.lst[0] : m == 1 ? g.lst[1] : m == 2 ? g.lst[2] : g.lst[3];
+}
+__device__ __forceinline__ int32_t glb_stride(const Geom& g, int m) {
+  return m == 0 ? g.gst[0] : m == 1 ? g.gst[1] : m == 2 ? g.gst[2] : g.gst[3];
+}
+
+// The element orbits of one tile orbit again, over the operator's own terms
+// only: a permutation whose coefficient is zero is not a term of the sum
+// (Def. 3), so its input is not read, and an Inf or NaN input reaches only
+// the outputs of the terms that read it (the dense product, exact for
+// finite inputs, would also give 0 * Inf = NaN elsewhere).  This runs only
+// for items in which combine_orbit saw a non-finite input, so it is written
+// for few registers, not for speed: uniform loops walk the d! x d! terms
+// (coefficients and ranks from scalar loads), and every address is formed
+// at run time -- no register array is indexed at run time.  The inputs are
+// read from the tensor `gin` (the item's cube), which still holds them: the
+// item's stores come later, and no other workgroup writes its elements.
+// ltile(s) / gtile(s): LDS and tensor offset of tile sigma_s . B.  Chained
+// stages keep each element orbit's intermediate values in private memory.
+template <typename T, int D, bool CHAIN, typename LT, typename GT>
+__device__ __forceinline__ void redo_orbit(const Geom& g, LT ltile, GT gtile, const uint32_t* rp,
+                                           uint32_t rep_cnt, const FastDiv& fdr, int ncub,
+                                           cptr<T> coef, int nstages, const T* gin, T* lds) {
+  constexpr int DF = Fact<D>::v;
+  const RuntimeTables<D>& tb = kRuntimeTables<D>;
+  const uint32_t nrep = (uint32_t)ncub * rep_cnt * (uint32_t)g.inner;
+  for (uint32_t i = threadIdx.x; i < nrep; i += blockDim.x) {
+    uint32_t ci, ri, si;
+    split_unit(g, i, rep_cnt, fdr, ncub, &ci, &ri, &si);
+    const uint32_t pk = rp[ri];
+    int l[D];
+#pragma unroll
+    for (int m = 0; m < D; ++m) l[m] = (int)((pk >> (8 * m)) & 255u);
+    const int lbase = (int)ci * g.cube_lds + (int)si;
+    const int64_t gbase = (int64_t)ci * g.cube_elems + (int64_t)si;
+    auto laddr = [&](int s) {
+      int x = lbase + ltile(s);
+#pragma unroll
+      for (int j = 0; j < D; ++j) x += l[j] * lds_stride(g, tb.inv[s][j]);
+      return x;
+    };
+    auto gaddr = [&](int s) {
+      int64_t x = gbase + gtile(s);
+#pragma unroll
+      for (int j = 0; j < D; ++j) x += (int64_t)l[j] * glb_stride(g, tb.inv[s][j]);
+      return x;
+    };
+    if constexpr (!CHAIN) {
+#pragma unroll 1
+      for (int t = 0; t < DF; ++t) {
+        T acc = T(0);
+#pragma unroll 1
+        for (int s = 0; s < DF; ++s) {
+          const T c = coef[tb.ginv[t * DF + s]];
+          if (c != T(0)) acc = fma_t(c, gin[gaddr(s)], acc);
+        }
+        lds[laddr(t)] = acc;
+      }
+    } else {
+      volatile T cur[DF];
+      volatile T nxt[DF];
+#pragma unroll 1
+      for (int s = 0; s < DF; ++s) cur[s] = gin[gaddr(s)];
+#pragma unroll 1
+      for (int st = 0; st < nstages; ++st) {
+#pragma unroll 1
+        for (int t = 0; t < DF; ++t) {
+          T acc = T(0);
+#pragma unroll 1
+          for (int s = 0; s < DF; ++s) {
+            const T c = coef[st * DF + tb.ginv[t * DF + s]];
+            if (c != T(0)) acc = fma_t(c, cur[s], acc);
+          }
+          nxt[t] = acc;
+        }
+#pragma unroll 1
+        for (int t = 0; t < DF; ++t) cur[t] = nxt[t];
+      }
+#pragma unroll 1
+      for (int t = 0; t < DF; ++t) lds[laddr(t)] = cur[t];
+    }
+  }
+}
+
+// redo_orbit for every tile orbit of a work item (the GroupDev tables: tile
+// sigma . B of orbit k sits at LDS offset slot_base[k][sigma], which is its
+// slot times g.ts, and at tile_off[slot] in the cube).
+template <typename T, int D, bool CHAIN, bool REPS_IN_LDS>
+__device__ __forceinline__ void redo_item(const Geom& g, cptr<GroupDev> gd, const uint32_t* reps,
+                                          cptr<T> coef, int nstages, int ncub, const T* gin,
+                                          T* lds) {
+  const int norb = gd->norb;
+  const uint32_t ts = (uint32_t)g.ts;
+  for (int k = 0; k < norb; ++k) {
+    auto ltile = [&](int s) -> int32_t { return gd->slot_base[k][s]; };
+    auto gtile = [&](int s) -> int64_t {
+      return gd->tile_off[(uint32_t)gd->slot_base[k][s] / ts];
+    };
+    const FastDiv fdr = load_fd(gd->fd_rep[k]);
+    const uint32_t* rp = reps + (REPS_IN_LDS ? gd->rep_base[k] : gd->rep_off[k]);
+    redo_orbit<T, D, CHAIN>(g, ltile, gtile, rp, (uint32_t)gd->rep_cnt[k], fdr, ncub, coef, nstages,
+                            gin, lds);
+  }
+}
+
+// After the dense combine of an item: does the item have to be redone over
+// the operator's own terms?  Only when the operator (or a chained stage)
+// leaves out a permutation and some thread saw an Inf or NaN input.  The
+// answer travels through one LDS word, cleared by clear_terms_flag before a
+// barrier that precedes the combine, set by the first lane of every wave
+// that saw one, and read after this function's barrier -- the workgroup
+// barrier that the store phase needs anyway.
+__shared__ uint32_t terms_flag;
+
+__device__ __forceinline__ void clear_terms_flag(uint32_t sparse) {
+  if (sparse != 0u && threadIdx.x == 0) terms_flag = 0u;
+}
+
+__device__ __forceinline__ bool item_needs_terms(uint32_t sparse, bool bad) {
+  if (sparse != 0u && __builtin_amdgcn_ballot_w64(bad) != 0ull && (threadIdx.x & 63u) == 0u)
+    __hip_atomic_fetch_or(&terms_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __syncthreads();
+  return sparse != 0u && terms_flag != 0u;
 }
 
 __device__ __forceinline__ void stage_tinfo(int32_t* tinfo, const GroupDev* __restrict__ gd) {
@@ -508,6 +613,7 @@ __global__ void __launch_bounds__(kThreads) k_exec(const ExecArgs<T> a) {
   decode_item(g, item, &cube0, &orbit, &ncub);
   const GroupDev* od = a.orbits + orbit;
   cptr<GroupDev> cod = as_const(od);
+  clear_terms_flag(a.sparse);
   stage_tinfo(tinfo, od);
   __syncthreads();
   const int ntiles = cod->ntiles;
@@ -529,9 +635,12 @@ __global__ void __launch_bounds__(kThreads) k_exec(const ExecArgs<T> a) {
     fill_lds<T, VW, kUnroll>(buf, lo, lds);
   }
   __syncthreads();
-  combine_item<T, D, CHAIN, false>(g, cod, a.reps, as_const(a.coef), a.nstages, a.sparse, ncub,
-                                   lds);
-  __syncthreads();
+  const bool bad =
+      combine_item<T, D, CHAIN, false>(g, cod, a.reps, as_const(a.coef), a.nstages, ncub, lds);
+  if (item_needs_terms(a.sparse, bad)) {
+    redo_item<T, D, CHAIN, false>(g, cod, a.reps, as_const(a.coef), a.nstages, ncub, sbase, lds);
+    __syncthreads();
+  }
   store_item<T, D, VW, NTS>(g, tinfo, ntiles, ragged, nchunks, a.out + cube0 * g.cube_elems, lds);
 }
 
@@ -831,6 +940,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_lds(const ExecArgs<T> a) {
   unsigned char* rep_lds = smem + a.lds_tile_bytes;
   const uint32_t span = (uint32_t)ncub * (uint32_t)g.cube_elems;
   int shift = 0;
+  clear_terms_flag(a.sparse);
   set_memory_priority();
   if (whole)
     shift = flat_issue<T>(a.in + cube0 * g.cube_elems, span, smem);
@@ -841,9 +951,14 @@ __global__ void __launch_bounds__(kMaxThreads) k_lds(const ExecArgs<T> a) {
   __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): everything is in LDS
   __syncthreads();
   // 2. combine
-  combine_item<T, D, CHAIN, true>(g, od, reinterpret_cast<const uint32_t*>(rep_lds),
-                                  as_const(a.coef), a.nstages, a.sparse, ncub, lds + shift);
-  __syncthreads();
+  const bool bad = combine_item<T, D, CHAIN, true>(g, od, reinterpret_cast<const uint32_t*>(rep_lds),
+                                                   as_const(a.coef), a.nstages, ncub, lds + shift);
+  if (item_needs_terms(a.sparse, bad)) {
+    redo_item<T, D, CHAIN, true>(g, od, reinterpret_cast<const uint32_t*>(rep_lds),
+                                 as_const(a.coef), a.nstages, ncub, a.in + cube0 * g.cube_elems,
+                                 lds + shift);
+    __syncthreads();
+  }
   // 3. store (the output may be shifted differently from the input)
   set_memory_priority();
   if (whole)
@@ -966,35 +1081,39 @@ __global__ void __launch_bounds__(kMaxThreads) k_pair(const PairArgs<T> a) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
   };
   // 2. tiles and the representative list straight into LDS
+  clear_terms_flag(a.sparse);
   set_memory_priority();
   const uint32_t tid = threadIdx.x;
   const uint32_t wave_bytes = (tid >> 6) * 1024u;
   const int64_t tile_elems = (int64_t)g.rows * g.bl * g.inner;
-  if (pg.flat) {
-    for (int t = 0; t < ntl; ++t) {
-      const int64_t toff = tile_off(t);
-      flat_issue<T>(src + toff, (uint32_t)tile_elems,
-                    smem + (size_t)t * pg.tile_stride * sizeof(T));
-    }
-  } else {
-    const uint32_t cpt = (uint32_t)g.rows * (uint32_t)g.vpr;
-    for (uint32_t c0 = 0; c0 < cpt; c0 += blockDim.x) {
-      int l[D];
-      chunk_coords<D, VW>(g, c0 + tid, l);
-      const int off = chunk_offset<D>(g, l);
-      const bool in = c0 + tid < cpt;
+  auto issue_tiles = [&]() {
+    if (pg.flat) {
       for (int t = 0; t < ntl; ++t) {
         const int64_t toff = tile_off(t);
-        const bool ok = in && chunk_inside<D>(l, __builtin_amdgcn_readlane(my_text, t), g.inner);
-        const uint32_t lbyte =
-            (uint32_t)(t * pg.tile_stride + (int)c0 * VW) * (uint32_t)sizeof(T) + wave_bytes;
-        if (ok)
-          __builtin_amdgcn_global_load_lds(
-              (const void*)(src + toff + off),
-              (__attribute__((address_space(3))) void*)(smem + lbyte), 16, 0, 0);
+        flat_issue<T>(src + toff, (uint32_t)tile_elems,
+                      smem + (size_t)t * pg.tile_stride * sizeof(T));
+      }
+    } else {
+      const uint32_t cpt = (uint32_t)g.rows * (uint32_t)g.vpr;
+      for (uint32_t c0 = 0; c0 < cpt; c0 += blockDim.x) {
+        int l[D];
+        chunk_coords<D, VW>(g, c0 + tid, l);
+        const int off = chunk_offset<D>(g, l);
+        const bool in = c0 + tid < cpt;
+        for (int t = 0; t < ntl; ++t) {
+          const int64_t toff = tile_off(t);
+          const bool ok = in && chunk_inside<D>(l, __builtin_amdgcn_readlane(my_text, t), g.inner);
+          const uint32_t lbyte =
+              (uint32_t)(t * pg.tile_stride + (int)c0 * VW) * (uint32_t)sizeof(T) + wave_bytes;
+          if (ok)
+            __builtin_amdgcn_global_load_lds(
+                (const void*)(src + toff + off),
+                (__attribute__((address_space(3))) void*)(smem + lbyte), 16, 0, 0);
+        }
       }
     }
-  }
+  };
+  issue_tiles();
   unsigned char* rep_lds = smem + a.lds_tile_bytes;
   {
     const uint32_t wave0 = tid & ~63u;
@@ -1019,10 +1138,21 @@ __global__ void __launch_bounds__(kMaxThreads) k_pair(const PairArgs<T> a) {
 #pragma unroll
     for (int r = 0; r < DF; ++r) sb[r] = __builtin_amdgcn_readlane(sb_lane, r);
     const FastDiv one{1u, 0u, 0u, 0u};
-    combine_orbit<T, D, CHAIN>(g, sb, reinterpret_cast<const uint32_t*>(rep_lds), rep_cnt, one, 1,
-                               coef, a.nstages, a.sparse, co, lds);
+    const uint32_t* rp = reinterpret_cast<const uint32_t*>(rep_lds);
+    const bool bad = combine_orbit<T, D, CHAIN>(g, sb, rp, rep_cnt, one, 1, coef,
+                                                       a.nstages, co, lds);
+    if (item_needs_terms(a.sparse, bad)) {
+      // tile sigma_s . c: LDS slot sb[s] (its slot times the slot stride,
+      // plus the slot's alignment shift, which is below the stride), at
+      // tensor offset tile_off(slot)
+      auto ltile = [&](int r) -> int32_t { return __builtin_amdgcn_readlane(sb_lane, r); };
+      auto gtile = [&](int r) -> int64_t {
+        return tile_off(__builtin_amdgcn_readlane(sb_lane, r) / pg.tile_stride);
+      };
+      redo_orbit<T, D, CHAIN>(g, ltile, gtile, rp, rep_cnt, one, 1, coef, a.nstages, src, lds);
+      __syncthreads();
+    }
   }
-  __syncthreads();
   // 4. store
   set_memory_priority();
   if (pg.flat) {
@@ -1099,6 +1229,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_ldsp(const ExecArgs<T> a) {
   issue_item_lds<T, D>(g, od, whole, ntl, ragged, a.in + cube0 * g.cube_elems, buf0);
   uint32_t par = 0;
   for (int64_t k = 0;; ++k) {
+    clear_terms_flag(a.sparse);
     const int64_t nx = item_at(k + 1);
     int64_t cube0n = 0;
     int orbitn = 0, ncubn = 0, ntln = 0;
@@ -1118,7 +1249,11 @@ __global__ void __launch_bounds__(kMaxThreads) k_ldsp(const ExecArgs<T> a) {
     wait_vmcnt_atmost(pending);
     lds_barrier();
     T* lds = reinterpret_cast<T*>(buf0 + par * bb);
-    combine_item<T, D, CHAIN, false>(g, od, rep_lds, coef, a.nstages, a.sparse, ncub, lds);
+    const bool bad = combine_item<T, D, CHAIN, false>(g, od, rep_lds, coef, a.nstages, ncub, lds);
+    if (a.sparse != 0u && item_needs_terms(a.sparse, bad)) {  // (drains the prefetch: rare path)
+      redo_item<T, D, CHAIN, false>(g, od, rep_lds, coef, a.nstages, ncub,
+                                    a.in + cube0 * g.cube_elems, lds);
+    }
     lds_barrier();
     store_item_lds<T, D, NTS>(g, od, whole, ntl, ragged, a.out + cube0 * g.cube_elems, lds);
     // the buffer is refilled two items on: every wave has read it by then
@@ -1183,6 +1318,7 @@ __global__ void __launch_bounds__(kThreads) k_pipe(const ExecArgs<T> a) {
                               buf, lo);
   int par = 0;
   while (true) {
+    clear_terms_flag(a.sparse);
     const int64_t nx = item_at(k + 1);
     int64_t cube0n = 0;
     int orbitn = 0, ncubn = 0;
@@ -1221,9 +1357,13 @@ __global__ void __launch_bounds__(kThreads) k_pipe(const ExecArgs<T> a) {
                                   a.in + cube0n * g.cube_elems, buf, lo);
     }
     // C.
-    combine_item<T, D, CHAIN, true>(g, as_const(od), rep_lds, coef, a.nstages, a.sparse, ncub,
-                                    lds);
-    __syncthreads();
+    const bool bad =
+        combine_item<T, D, CHAIN, true>(g, as_const(od), rep_lds, coef, a.nstages, ncub, lds);
+    if (item_needs_terms(a.sparse, bad)) {
+      redo_item<T, D, CHAIN, true>(g, as_const(od), rep_lds, coef, a.nstages, ncub,
+                                   a.in + cube0 * g.cube_elems, lds);
+      __syncthreads();
+    }
     // D.
     store_item<T, D, VW, true>(g, tinfo[par], ntiles, ragged, nchunks,
                                a.out + cube0 * g.cube_elems, lds);
@@ -1260,6 +1400,7 @@ __device__ __forceinline__ void batched_item(const BatchArgs<T>& a, int64_t it,
   cptr<GroupDev> cod = as_const(od);
   const cptr<T> coef = as_const(a.coef);
   unsigned char* rep_lds = smem + a.lds_tile_bytes;
+  clear_terms_flag(a.sparse);
   if (g.bl == g.n) {
     const uint32_t span = (uint32_t)incubes * (uint32_t)g.cube_elems;
     set_memory_priority();
@@ -1268,9 +1409,13 @@ __device__ __forceinline__ void batched_item(const BatchArgs<T>& a, int64_t it,
     set_compute_priority();
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): everything is in LDS
     __syncthreads();
-    combine_item<T, D, false, true>(g, cod, reinterpret_cast<const uint32_t*>(rep_lds), coef, 1,
-                                    a.sparse, incubes, lds + shift);
-    __syncthreads();
+    const bool bad = combine_item<T, D, false, true>(
+        g, cod, reinterpret_cast<const uint32_t*>(rep_lds), coef, 1, incubes, lds + shift);
+    if (item_needs_terms(a.sparse, bad)) {
+      redo_item<T, D, false, true>(g, cod, reinterpret_cast<const uint32_t*>(rep_lds), coef, 1,
+                                   incubes, src, lds + shift);
+      __syncthreads();
+    }
     set_memory_priority();
     flat_store<T, true>(dst, span, smem, shift);
     set_compute_priority();
@@ -1298,8 +1443,11 @@ __device__ __forceinline__ void batched_item(const BatchArgs<T>& a, int64_t it,
     fill_lds<T, VW, kUnroll>(buf, lo, lds);
   }
   __syncthreads();
-  combine_item<T, D, false, false>(g, cod, a.reps, coef, 1, a.sparse, incubes, lds);
-  __syncthreads();
+  const bool bad = combine_item<T, D, false, false>(g, cod, a.reps, coef, 1, incubes, lds);
+  if (item_needs_terms(a.sparse, bad)) {
+    redo_item<T, D, false, false>(g, cod, a.reps, coef, 1, incubes, src, lds);
+    __syncthreads();
+  }
   store_item<T, D, VW, true>(g, tinfo, ntiles, ragged, nchunks, dst, lds);
 }
 
