@@ -440,11 +440,18 @@ def main():
         out["roofline"]["frac_of_copy_ceiling"] = round(
             achieved / forms["stream_copy_ceiling"]["GBps"], 4)
         del dst
-        # chained (2 - P_ij)(2 - P_jk) vs its pre-multiplied operator, slab 0
-        for name, flags in [("3d_factored_premultiplied", 0),
-                            ("3d_factored_chained", ss.SPINSUM_FLAG_CHAIN_STAGES)]:
-            pf = ss.spinsum_plan(slab_shape, 3, 3, workloads.FACTORED_PIJ_PJK, inplace=True,
-                                 flags=flags)
+        # factorised sums three ways, slab 0: the pre-multiplied operator (one
+        # pass), the stages chained in registers (one pass), and one pass per
+        # stage through the output (Alg. 3), for (2 - P_ij)(2 - P_jk) and
+        # Table II case 1
+        for name, stages, flags in [
+                ("3d_factored_premultiplied", workloads.FACTORED_PIJ_PJK, 0),
+                ("3d_factored_chained", workloads.FACTORED_PIJ_PJK, ss.SPINSUM_FLAG_CHAIN_STAGES),
+                ("3d_factored_multi_pass", workloads.FACTORED_PIJ_PJK, ss.SPINSUM_FLAG_MULTI_PASS),
+                ("3d_table2_1_premultiplied", workloads.table2_case(1)[1], 0),
+                ("3d_table2_1_chained", workloads.table2_case(1)[1], ss.SPINSUM_FLAG_CHAIN_STAGES),
+                ("3d_table2_1_multi_pass", workloads.table2_case(1)[1], ss.SPINSUM_FLAG_MULTI_PASS)]:
+            pf = ss.spinsum_plan(slab_shape, 3, 3, stages, inplace=True, flags=flags)
             workloads.fill_uniform(big[0], 1000)  # fresh values: repeated passes grow them
             warm(lambda: ss.spinsum_exec(pf, big[0], big[0], stream),
                  refill=lambda: workloads.fill_uniform(big[0], 1000))
@@ -472,6 +479,22 @@ def main():
             fms = timed(lambda: ss.spinsum_exec(pf, big[0], big[0], stream), 5, stream)
             forms[name] = form_entry(2 * big[0].numel() * 8, fms, value)
         del big
+        torch.cuda.empty_cache()
+
+        # Table II case 5 (three stages) on one 80^4 cube, in place: the same
+        # three ways (one pass per stage: three passes over the tensor)
+        x80 = torch.empty((80,) * 4, dtype=torch.float64, device=dev)
+        st5 = workloads.table2_case(5)[1]
+        for name, flags in [("4d_table2_5_80_premultiplied", 0),
+                            ("4d_table2_5_80_chained", ss.SPINSUM_FLAG_CHAIN_STAGES),
+                            ("4d_table2_5_80_multi_pass", ss.SPINSUM_FLAG_MULTI_PASS)]:
+            pt = ss.spinsum_plan(x80.shape, 0, 4, st5, inplace=True, flags=flags)
+            workloads.fill_uniform(x80, 5005)
+            warm(lambda: ss.spinsum_exec(pt, x80, x80, stream),
+                 refill=lambda: workloads.fill_uniform(x80, 5005))
+            tms = timed(lambda: ss.spinsum_exec(pt, x80, x80, stream), 5, stream)
+            forms[name] = form_entry(2 * x80.numel() * 8, tms, value)
+        del x80
         torch.cuda.empty_cache()
 
         # 4D in place, one a-slab 1 x 24^3 x 12^4, 24 random integer coefficients

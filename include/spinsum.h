@@ -82,6 +82,11 @@ typedef enum { SPINSUM_F64 = 0, SPINSUM_F32 = 1 } spinsum_dtype;
 #define SPINSUM_FLAG_NO_DIRECT_LDS 0x40u /* never use the direct-LDS variant (ablation)  */
 #define SPINSUM_FLAG_NT_STORES 0x100u    /* non-temporal stores even where the planner would
                                             use cached ones (see spinsum_plan_info_t.nt_stores) */
+#define SPINSUM_FLAG_MULTI_PASS 0x200u   /* one launch per stage, stage 0 from the input to the
+                                            output and every later stage in place on the output:
+                                            the two-pass form of Alg. 3 (Sec. 4.3) with the
+                                            output as its temporary (ablation of the fused
+                                            chain; not with SPINSUM_FLAG_CHAIN_STAGES) */
 #define SPINSUM_FLAG_INDEX_PAIRS 0x80u   /* index-pair form: the d dims right before the group
                                             (the partner indices, extent V each) are permuted
                                             by the same permutation as the group, e.g.
@@ -263,6 +268,22 @@ spinsum_status spinsum_adjoint(spinsum_plan_t plan, const void* grad_out, void* 
  * SPINSUM_ERR_UNSUPPORTED otherwise.  Asynchronous on `stream`. */
 spinsum_status spinsum_coef_grad(spinsum_plan_t plan, const void* x, const void* g,
                                  double* grad, void* stream);
+
+/* Gradients with respect to the coefficients of every stage of a chain
+ * (Def. 4; not in the paper): S = S_K ... S_1 is linear in the coefficients
+ * of each stage, so for L = <g, S(x)> and stage k
+ *   dL / d alpha_{k,p} = < (S_K ... S_{k+1})^T g , pi_p (S_{k-1} ... S_1 x) >,
+ * the inner stages applied forward and the outer ones as adjoints, one
+ * launch per stage (as SPINSUM_FLAG_MULTI_PASS), then the kernels of
+ * spinsum_coef_grad.  grad[k * d! + r] receives that value for the r-th
+ * permutation of the group in lexicographic order and stage k (stage 0 =
+ * S_1, applied first); grad is a device array of nstages * d! doubles.
+ * work_u, work_h: device buffers of the plan's shape and dtype that are
+ * overwritten (caller-owned; NULL allowed when the plan has one stage).
+ * x, g as for spinsum_coef_grad; same restrictions and errors.  Calls on
+ * one plan must not overlap.  Asynchronous on `stream`. */
+spinsum_status spinsum_coef_grad_stages(spinsum_plan_t plan, const void* x, const void* g,
+                                        double* grad, void* work_u, void* work_h, void* stream);
 
 /* spinsum_coef_grad for callers that cannot allocate device memory (code
  * under hipGraph capture, tight serving loops, harnesses that forbid

@@ -37,6 +37,7 @@ A[.., a_{p[0]}..a_{p[d-1]}, i_{p[0]}..i_{p[d-1]}, ..]``.
 from __future__ import annotations
 
 import ctypes
+import math
 import itertools
 import os
 import subprocess
@@ -201,6 +202,24 @@ def coef_grad(x: np.ndarray, g: np.ndarray, group_first: int, d: int,
         y = spinsum(x, [(p, 1.0)], group_first, d, nthreads, pairs)
         out.append(float(np.sum(np.asarray(g, dtype=np.float64) * y, dtype=np.float64)))
     return np.array(out)
+
+
+def coef_grad_stages(x: np.ndarray, g: np.ndarray, stages: Sequence[Stage], group_first: int,
+                     d: int, nthreads: int = 1, pairs: bool = False) -> np.ndarray:
+    """(stages, d!) array: entry (k, r) is the derivative of <g, S(x)> with
+    respect to the coefficient of the r-th permutation (lexicographic order)
+    in stage k of the chain S = S_K ... S_1 (Def. 4).  The chain is linear in
+    each stage's coefficients, so that derivative is <g, chain(x)> with stage
+    k replaced by the single term (p_r, 1): evaluated here by the oracle's
+    own chain, term by term."""
+    g = np.asarray(g, dtype=np.float64)
+    out = np.zeros((len(stages), math.factorial(d)))
+    for k in range(len(stages)):
+        for r, p in enumerate(itertools.permutations(range(d))):
+            chain = list(stages[:k]) + [[(p, 1.0)]] + list(stages[k + 1:])
+            y = spinsum_chain(x, chain, group_first, d, nthreads, pairs)
+            out[k, r] = float(np.sum(g * y, dtype=np.float64))
+    return out
 
 
 def spinsum_numpy(x: np.ndarray, terms: Stage, group_first: int, d: int,

@@ -58,6 +58,7 @@ SPINSUM_FLAG_NO_LDS_PAD = 0x20
 SPINSUM_FLAG_NO_DIRECT_LDS = 0x40
 SPINSUM_FLAG_INDEX_PAIRS = 0x80
 SPINSUM_FLAG_NT_STORES = 0x100
+SPINSUM_FLAG_MULTI_PASS = 0x200
 
 SPINSUM_VARIANT_AUTO = 0
 SPINSUM_VARIANT_DIRECT_LDS = 1
@@ -120,6 +121,7 @@ _c_exec_batched = _decl("spinsum_exec_batched", [_vp, _vp, _vp, _vp])
 _c_adjoint = _decl("spinsum_adjoint", [_vp, _vp, _vp, _vp])
 _c_coef_grad = _decl("spinsum_coef_grad", [_vp, _vp, _vp, _vp, _vp])
 _c_coef_grad_noalloc = _decl("spinsum_coef_grad_noalloc", [_vp, _vp, _vp, _vp, _vp])
+_c_coef_grad_stages = _decl("spinsum_coef_grad_stages", [_vp, _vp, _vp, _vp, _vp, _vp, _vp])
 _c_graph_create = _decl("spinsum_graph_create", [_vp, _vp, _vp, ctypes.POINTER(_vp)])
 _c_graph_launch = _decl("spinsum_graph_launch", [_vp, _vp])
 _c_graph_destroy = _decl("spinsum_graph_destroy", [_vp], None)
@@ -134,7 +136,7 @@ _c_version = _decl("spinsum_version", [], ctypes.c_char_p)
 EXPORTED = ["spinsum_plan", "spinsum_plan_batched", "spinsum_plan_set_tile",
             "spinsum_plan_get_info", "spinsum_plan_expanded", "spinsum_plan_check_ownership",
             "spinsum_exec", "spinsum_exec_batched", "spinsum_adjoint", "spinsum_coef_grad",
-            "spinsum_coef_grad_noalloc",
+            "spinsum_coef_grad_noalloc", "spinsum_coef_grad_stages",
             "spinsum_graph_create",
             "spinsum_graph_launch", "spinsum_graph_destroy", "spinsum_autotune",
             "spinsum_stream_copy", "spinsum_plan_last_hip_error", "spinsum_plan_destroy",
@@ -321,6 +323,26 @@ def spinsum_coef_grad(plan: Plan, x: torch.Tensor, g: torch.Tensor, stream=None)
     b = _tensor_ptr(g, plan, plan.shape, "g")
     out = torch.empty(math.factorial(plan.d), dtype=torch.float64, device=x.device)
     _check(_c_coef_grad(plan._h, a, b, out.data_ptr(), _stream(stream)), "spinsum_coef_grad", plan)
+    return out
+
+
+def spinsum_coef_grad_stages(plan: Plan, x: torch.Tensor, g: torch.Tensor, work=None,
+                             stream=None) -> torch.Tensor:
+    """<(S_K..S_{k+1})^T g, pi_r(S_{k-1}..S_1 x)> for every stage k and every
+    permutation r of the group (lexicographic order): a (stages, d!) float64
+    tensor, the gradient of <g, S(x)> with respect to every stage's
+    coefficients.  work: two tensors of the plan's shape and dtype that are
+    overwritten (allocated here if None)."""
+    a = _tensor_ptr(x, plan, plan.shape, "x")
+    b = _tensor_ptr(g, plan, plan.shape, "g")
+    K = len(plan.stages)
+    if work is None:
+        work = (torch.empty_like(x), torch.empty_like(x)) if K > 1 else (None, None)
+    wu = _tensor_ptr(work[0], plan, plan.shape, "work") if work[0] is not None else None
+    wh = _tensor_ptr(work[1], plan, plan.shape, "work") if work[1] is not None else None
+    out = torch.empty((K, math.factorial(plan.d)), dtype=torch.float64, device=x.device)
+    _check(_c_coef_grad_stages(plan._h, a, b, out.data_ptr(), wu, wh, _stream(stream)),
+           "spinsum_coef_grad_stages", plan)
     return out
 
 
@@ -512,5 +534,53 @@ class SpinSumCoefFunction(torch.autograd.Function):
         return gx, ga, None, None
 
 
+class SpinSumChainCoefFunction(torch.autograd.Function):
+    """Out = S_K(...S_1(x)), S_k = sum_t alpha_{k,t} pi_{k,t}, with every
+    stage's coefficients in one flat tensor (stage 0 first, then stage 1, ...):
+    the gradient flows to x (adjoint kernel) and to every stage's
+    coefficients (spinsum_coef_grad_stages).  perms: one list of distinct
+    d-tuples per stage; a plan with `flags` (by default the stages chained in
+    registers) is made from the current coefficient values on every call,
+    out-of-place."""
+
+    @staticmethod
+    def forward(ctx, x, alpha, perms, group_first, flags=SPINSUM_FLAG_CHAIN_STAGES):
+        d = len(perms[0][0])
+        vals = alpha.detach().cpu().tolist()
+        stages, pos = [], 0
+        for st in perms:
+            if len(set(tuple(p) for p in st)) != len(st):
+                raise SpinSumError(SPINSUM_ERR_INVALID_ARG, "permutations of a stage must be distinct")
+            stages.append([(tuple(p), float(vals[pos + i])) for i, p in enumerate(st)])
+            pos += len(st)
+        if pos != alpha.numel():
+            raise SpinSumError(SPINSUM_ERR_INVALID_ARG, "one coefficient per term expected")
+        plan = spinsum_plan(tuple(x.shape), group_first, d, stages, dtype=x.dtype, inplace=False,
+                            flags=flags)
+        out = torch.empty_like(x)
+        spinsum_exec(plan, x.contiguous(), out)
+        ctx.plan = plan
+        ctx.perms = [[tuple(p) for p in st] for st in perms]
+        ctx.save_for_backward(x)
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        (x,) = ctx.saved_tensors
+        plan = ctx.plan
+        g = g.contiguous()
+        gx = None
+        if ctx.needs_input_grad[0]:
+            gx = torch.empty_like(g)
+            spinsum_adjoint(plan, g, gx)
+        ga = None
+        if ctx.needs_input_grad[1]:
+            c = spinsum_coef_grad_stages(plan, x.contiguous(), g)
+            d = len(ctx.perms[0][0])
+            rank = {p: r for r, p in enumerate(itertools.permutations(range(d)))}
+            ga = torch.stack([c[k, rank[p]] for k, st in enumerate(ctx.perms) for p in st]).to(x.dtype)
+        return gx, ga, None, None, None
+
+
 __all__ = EXPORTED + ["Plan", "Graph", "PointerArrays", "SpinSumError", "SpinSumFunction",
-                      "SpinSumCoefFunction", "apply"]
+                      "SpinSumCoefFunction", "SpinSumChainCoefFunction", "apply"]

@@ -84,9 +84,8 @@ struct LaunchCfg {
 };
 
 template <typename T>
-LaunchCfg exec_cfg(const spinsum_plan_s* P) {
+LaunchCfg exec_cfg(const spinsum_plan_s* P, bool chain) {
   const Tiling& Tl = P->T;
-  const bool chain = (P->flags & SPINSUM_FLAG_CHAIN_STAGES) != 0;
   const bool nts = Tl.nts != 0;
   LaunchCfg c;
   int kind = P->tile.variant;
@@ -126,14 +125,51 @@ int64_t persistent_grid(const spinsum_plan_s* P, int64_t nitems) {
   return std::max<int64_t>(8, (g / 8) * 8);
 }
 
-template <typename T>
-spinsum_status launch_exec(spinsum_plan_s* P, const void* in, void* out, hipStream_t stream,
-                           bool adjoint) {
-  const Tiling& Tl = P->T;
-  if (Tl.nitems <= 0) return SPINSUM_OK;
+// Which coefficients one launch applies: the pre-multiplied vector (forward
+// or adjoint), every stage in registers (CHAIN), or one stage (the
+// multi-pass form and the per-stage gradients).  offset: in elements of
+// the plan's coefficient buffer (forward | adjoint | stages | adjoint
+// stages, d! each).
+struct CoefSel {
+  size_t offset = 0;
+  int nstages = 1;
+  uint32_t sparse = 0;
+  bool chain = false;
+};
+
+CoefSel coef_sel(const spinsum_plan_s* P, bool adjoint) {
   const int df = P->G.df;
   const int K = (int)P->stage_a.size();
-  const bool chain = (P->flags & SPINSUM_FLAG_CHAIN_STAGES) != 0;
+  CoefSel c;
+  if (P->flags & SPINSUM_FLAG_CHAIN_STAGES) {
+    c.offset = 2 * (size_t)df + (adjoint ? (size_t)K * df : 0);
+    c.nstages = K;
+    c.sparse = adjoint ? P->sparse_adj : P->sparse_fwd;
+    c.chain = true;
+  } else {
+    c.offset = adjoint ? (size_t)df : 0;
+    c.sparse = P->sparse_expanded;
+  }
+  return c;
+}
+
+// Stage j in application order: of the forward chain (stage j) or of the
+// adjoint chain (the inverse of stage K-1-j).
+CoefSel stage_sel(const spinsum_plan_s* P, bool adjoint, int j) {
+  const int df = P->G.df;
+  const int K = (int)P->stage_a.size();
+  CoefSel c;
+  c.offset = 2 * (size_t)df + (adjoint ? (size_t)K * df : 0) + (size_t)j * df;
+  const uint32_t m = adjoint ? P->sparse_adj : P->sparse_fwd;
+  c.sparse = (j >= 32 || ((m >> j) & 1u) != 0u) ? 1u : 0u;
+  return c;
+}
+
+template <typename T>
+spinsum_status launch_exec(spinsum_plan_s* P, const void* in, void* out, hipStream_t stream,
+                           const CoefSel& sel) {
+  const Tiling& Tl = P->T;
+  if (Tl.nitems <= 0) return SPINSUM_OK;
   const T* coef = reinterpret_cast<const T*>(P->d_mats);
   ExecArgs<T> a;
   std::memset(&a, 0, sizeof(a));
@@ -141,20 +177,14 @@ spinsum_status launch_exec(spinsum_plan_s* P, const void* in, void* out, hipStre
   a.out = reinterpret_cast<T*>(out);
   a.orbits = reinterpret_cast<const GroupDev*>(P->d_orbits);
   a.reps = reinterpret_cast<const uint32_t*>(P->d_reps);
-  if (!chain) {
-    a.coef = coef + (adjoint ? df : 0);
-    a.nstages = 1;
-    a.sparse = P->sparse_expanded;
-  } else {
-    a.coef = coef + 2 * df + (adjoint ? (size_t)K * df : 0);
-    a.nstages = K;
-    a.sparse = adjoint ? P->sparse_adj : P->sparse_fwd;
-  }
+  a.coef = coef + sel.offset;
+  a.nstages = sel.nstages;
+  a.sparse = sel.sparse;
   a.g = Tl.g;
   a.nitems = Tl.nitems;
   a.reverse = (P->flags & SPINSUM_FLAG_REVERSE_ORDER) ? 1 : 0;
   // kernel variant chosen by the planner (see spinsum_tile_t.variant)
-  const LaunchCfg c = exec_cfg<T>(P);
+  const LaunchCfg c = exec_cfg<T>(P, sel.chain);
   a.lds_tile_bytes = (int32_t)(((size_t)Tl.lds_elems * sizeof(T) + 15) / 16 * 16);
   a.nreps = (int32_t)Tl.reps.size();
   spinsum_status st = prepare_kernel(P, c.k, c.shmem);
@@ -179,12 +209,10 @@ spinsum_status launch_exec(spinsum_plan_s* P, const void* in, void* out, hipStre
 // Index-pair form: one tile orbit of one pair block per workgroup.
 template <typename T>
 spinsum_status launch_pair(spinsum_plan_s* P, const void* in, void* out, hipStream_t stream,
-                           bool adjoint) {
+                           const CoefSel& sel) {
   const Tiling& Tl = P->T;
   if (Tl.nitems <= 0) return SPINSUM_OK;
-  const int df = P->G.df;
-  const int K = (int)P->stage_a.size();
-  const bool chain = (P->flags & SPINSUM_FLAG_CHAIN_STAGES) != 0;
+  const bool chain = sel.chain;
   const bool nts = Tl.nts != 0;
   const T* coef = reinterpret_cast<const T*>(P->d_mats);
   PairArgs<T> a;
@@ -193,15 +221,9 @@ spinsum_status launch_pair(spinsum_plan_s* P, const void* in, void* out, hipStre
   a.out = reinterpret_cast<T*>(out);
   a.orbits = reinterpret_cast<const uint64_t*>(P->d_orbits);
   a.reps = reinterpret_cast<const uint32_t*>(P->d_reps);
-  if (!chain) {
-    a.coef = coef + (adjoint ? df : 0);
-    a.nstages = 1;
-    a.sparse = P->sparse_expanded;
-  } else {
-    a.coef = coef + 2 * df + (adjoint ? (size_t)K * df : 0);
-    a.nstages = K;
-    a.sparse = adjoint ? P->sparse_adj : P->sparse_fwd;
-  }
+  a.coef = coef + sel.offset;
+  a.nstages = sel.nstages;
+  a.sparse = sel.sparse;
   a.g = Tl.g;
   a.pg = P->pg;
   a.nitems = Tl.nitems;
@@ -268,7 +290,8 @@ template <typename T>
 spinsum_status occupancy_of(spinsum_plan_s* P) {
   P->occ_blocks = 1;
   if (P->pair) return SPINSUM_OK;
-  const LaunchCfg c = P->batched ? batched_cfg<T>(P) : exec_cfg<T>(P);
+  const LaunchCfg c =
+      P->batched ? batched_cfg<T>(P) : exec_cfg<T>(P, (P->flags & SPINSUM_FLAG_CHAIN_STAGES) != 0);
   if (!c.persistent || c.k == nullptr) return SPINSUM_OK;
   spinsum_status st = prepare_kernel(P, c.k, c.shmem);
   if (st != SPINSUM_OK) return st;
@@ -319,30 +342,57 @@ spinsum_status cache_occupancy(spinsum_plan_s* P) {
 
 using namespace spinsum;
 
+namespace spinsum {
+namespace {
+
+// One launch of the plan's kernel with the coefficients `sel`.
+spinsum_status launch_any(spinsum_plan_s* P, const void* in, void* out, hipStream_t stream,
+                          const CoefSel& sel) {
+  if (P->pair) {
+    if (P->dtype == SPINSUM_F32) return launch_pair<float>(P, in, out, stream, sel);
+    return launch_pair<double>(P, in, out, stream, sel);
+  }
+  if (P->dtype == SPINSUM_F32) return launch_exec<float>(P, in, out, stream, sel);
+  return launch_exec<double>(P, in, out, stream, sel);
+}
+
+// Stages j0 .. j1-1 of the forward or adjoint chain, one launch each: the
+// first from `in` to `out`, the others in place on `out` (every launch
+// reads a whole tile orbit before writing it, so a stage can run in place
+// on any buffer).
+spinsum_status launch_stages(spinsum_plan_s* P, const void* in, void* out, hipStream_t stream,
+                             bool adjoint, int j0, int j1) {
+  for (int j = j0; j < j1; ++j) {
+    spinsum_status st = launch_any(P, j == j0 ? in : out, out, stream, stage_sel(P, adjoint, j));
+    if (st != SPINSUM_OK) return st;
+  }
+  return SPINSUM_OK;
+}
+
+// exec / adjoint: one launch (the pre-multiplied operator, or every stage
+// in registers), or with SPINSUM_FLAG_MULTI_PASS one launch per stage
+// through the output buffer (Alg. 3).
+spinsum_status run(spinsum_plan_s* P, const void* in, void* out, hipStream_t stream,
+                   bool adjoint) {
+  if (P->flags & SPINSUM_FLAG_MULTI_PASS)
+    return launch_stages(P, in, out, stream, adjoint, 0, (int)P->stage_a.size());
+  return launch_any(P, in, out, stream, coef_sel(P, adjoint));
+}
+
+}  // namespace
+}  // namespace spinsum
+
 extern "C" spinsum_status spinsum_exec(spinsum_plan_t P, const void* in, void* out, void* stream) {
   spinsum_status st = check_tensor_args(P, in, out);
   if (st != SPINSUM_OK || P->elems == 0) return st;
-  if (P->pair) {
-    if (P->dtype == SPINSUM_F32) return launch_pair<float>(P, in, out, (hipStream_t)stream, false);
-    return launch_pair<double>(P, in, out, (hipStream_t)stream, false);
-  }
-  if (P->dtype == SPINSUM_F32)
-    return launch_exec<float>(P, in, out, (hipStream_t)stream, false);
-  return launch_exec<double>(P, in, out, (hipStream_t)stream, false);
+  return run(P, in, out, (hipStream_t)stream, false);
 }
 
 extern "C" spinsum_status spinsum_adjoint(spinsum_plan_t P, const void* grad_out, void* grad_in,
                                           void* stream) {
   spinsum_status st = check_tensor_args(P, grad_out, grad_in);
   if (st != SPINSUM_OK || P->elems == 0) return st;
-  if (P->pair) {
-    if (P->dtype == SPINSUM_F32)
-      return launch_pair<float>(P, grad_out, grad_in, (hipStream_t)stream, true);
-    return launch_pair<double>(P, grad_out, grad_in, (hipStream_t)stream, true);
-  }
-  if (P->dtype == SPINSUM_F32)
-    return launch_exec<float>(P, grad_out, grad_in, (hipStream_t)stream, true);
-  return launch_exec<double>(P, grad_out, grad_in, (hipStream_t)stream, true);
+  return run(P, grad_out, grad_in, (hipStream_t)stream, true);
 }
 
 namespace spinsum {
@@ -470,6 +520,50 @@ spinsum_status coef_grad_impl(spinsum_plan_s* P, const void* x, const void* g, d
 extern "C" spinsum_status spinsum_coef_grad(spinsum_plan_t P, const void* x, const void* g,
                                             double* grad, void* stream) {
   return coef_grad_impl(P, x, g, grad, false, stream);
+}
+
+extern "C" spinsum_status spinsum_coef_grad_stages(spinsum_plan_t P, const void* x, const void* g,
+                                                   double* grad, void* work_u, void* work_h,
+                                                   void* stream) {
+  if (P == nullptr || P->batched || grad == nullptr) return SPINSUM_ERR_INVALID_ARG;
+  const int K = (int)P->stage_a.size();
+  const int df = P->G.df;
+  hipStream_t s = (hipStream_t)stream;
+  if (K == 1 || P->elems == 0) return coef_grad_impl(P, x, g, grad, false, stream);
+  if (!P->has_dev) return SPINSUM_ERR_NO_DEVICE;
+  if (P->pair) return SPINSUM_ERR_UNSUPPORTED;
+  if (x == nullptr || g == nullptr || work_u == nullptr || work_h == nullptr)
+    return SPINSUM_ERR_INVALID_ARG;
+  if ((((uintptr_t)x) | ((uintptr_t)g) | ((uintptr_t)work_u) | ((uintptr_t)work_h)) & 15u)
+    return SPINSUM_ERR_MISALIGNED;
+  const uintptr_t bytes = (uintptr_t)P->elems * (uintptr_t)elem_size(*P);
+  auto overlap = [&](const void* p, const void* q) {
+    const uintptr_t a = (uintptr_t)p, b = (uintptr_t)q;
+    return a < b + bytes && b < a + bytes;
+  };
+  if (overlap(work_u, work_h) || overlap(work_u, x) || overlap(work_u, g) || overlap(work_h, x) ||
+      overlap(work_h, g))
+    return SPINSUM_ERR_ALIASING;
+  for (int k = 0; k < K; ++k) {
+    // u = S_{k-1} ... S_1 x (stages 0 .. k-1), h = S_{k+1}^T ... S_K^T g
+    // (adjoint chain positions 0 .. K-2-k)
+    const void* u = x;
+    const void* h = g;
+    spinsum_status st;
+    if (k > 0) {
+      st = launch_stages(P, x, work_u, s, false, 0, k);
+      if (st != SPINSUM_OK) return st;
+      u = work_u;
+    }
+    if (k < K - 1) {
+      st = launch_stages(P, g, work_h, s, true, 0, K - 1 - k);
+      if (st != SPINSUM_OK) return st;
+      h = work_h;
+    }
+    st = coef_grad_impl(P, u, h, grad + (size_t)k * df, false, stream);
+    if (st != SPINSUM_OK) return st;
+  }
+  return SPINSUM_OK;
 }
 
 extern "C" spinsum_status spinsum_coef_grad_noalloc(spinsum_plan_t P, const void* x,

@@ -996,8 +996,10 @@ static spinsum_status apply_tile(spinsum_plan_s* P, const spinsum_tile_t* req) {
   return SPINSUM_OK;
 }
 
-static spinsum_status common_checks(int d, spinsum_dtype dtype, int inplace) {
+static spinsum_status common_checks(int d, spinsum_dtype dtype, int inplace, unsigned flags) {
   if (d < 2 || d > 4) return SPINSUM_ERR_UNSUPPORTED;
+  if ((flags & SPINSUM_FLAG_MULTI_PASS) && (flags & SPINSUM_FLAG_CHAIN_STAGES))
+    return SPINSUM_ERR_INVALID_ARG;
   if (dtype != SPINSUM_F64 && dtype != SPINSUM_F32) return SPINSUM_ERR_INVALID_ARG;
   if (inplace != 0 && inplace != 1) return SPINSUM_ERR_INVALID_ARG;
   return SPINSUM_OK;
@@ -1041,7 +1043,7 @@ extern "C" spinsum_status spinsum_plan(spinsum_plan_t* plan, int ndim, const int
                                        spinsum_dtype dtype, int inplace, unsigned flags) {
   if (plan == nullptr) return SPINSUM_ERR_INVALID_ARG;
   *plan = nullptr;
-  spinsum_status st = common_checks(d, dtype, inplace);
+  spinsum_status st = common_checks(d, dtype, inplace, flags);
   if (st != SPINSUM_OK) return st;
   int n = 0, inner = 1;
   int64_t ncubes = 0;
@@ -1237,7 +1239,7 @@ extern "C" spinsum_status spinsum_plan_batched(spinsum_plan_t* plan, int nblocks
                                                spinsum_dtype dtype, int inplace, unsigned flags) {
   if (plan == nullptr) return SPINSUM_ERR_INVALID_ARG;
   *plan = nullptr;
-  spinsum_status st = common_checks(d, dtype, inplace);
+  spinsum_status st = common_checks(d, dtype, inplace, flags);
   if (st != SPINSUM_OK) return st;
   if (nblocks < 1 || nblocks > (1 << 20) || ndims == nullptr || extents == nullptr)
     return SPINSUM_ERR_INVALID_ARG;

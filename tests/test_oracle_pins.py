@@ -248,6 +248,37 @@ def test_flop_reduction_factors_of_sec6():
             assert round(len(expanded) / factor_terms) == int(factor), case
 
 
+@pytest.mark.parametrize("case", [1, 5, 9])
+def test_coef_grad_stages_definition(case):
+    """Per-stage coefficient gradients of a chain: L(alpha) = <g, S(x)> is
+    linear in the coefficients of each stage, so adding 1 to the coefficient
+    of permutation p in stage k changes L by exactly the derivative; and the
+    derivative equals g^T M_K .. M_{k,p} .. M_1 x with the dense matrix of
+    the single term p in place of stage k."""
+    d, stages = workloads.table2_case(case)
+    shape = (1,) + (3,) * d if d == 4 else (2, 3, 3, 3)
+    x = _rand(shape, 70 + case)
+    g = _rand(shape, 80 + case)
+    got = oracle.coef_grad_stages(x, g, stages, 1, d)
+    perms = list(itertools.permutations(range(d)))
+    base = float(np.sum(g * oracle.spinsum_chain(x, stages, 1, d)))
+    rng = np.random.default_rng(case)
+    for k in range(len(stages)):
+        for r in rng.choice(len(perms), size=4, replace=False):
+            p = perms[r]
+            bumped = [list(st) for st in stages]
+            bumped[k] = bumped[k] + [(p, 1.0)]
+            diff = float(np.sum(g * oracle.spinsum_chain(x, bumped, 1, d))) - base
+            assert abs(diff - got[k, r]) <= 1e-12 * max(1.0, abs(diff))
+            mats = [oracle.dense_matrix(shape, st, 1, d) for st in stages]
+            mats[k] = oracle.dense_matrix(shape, [(p, 1.0)], 1, d)
+            M = np.eye(x.size)
+            for m in mats:
+                M = m @ M
+            dense = float(g.ravel() @ (M @ x.ravel()))
+            assert abs(dense - got[k, r]) <= 1e-12 * max(1.0, abs(dense))
+
+
 def test_factored_pij_pjk_closed_form():
     """(2 - P_ij)(2 - P_jk) on A[i,j,k] = 100i + 10j + k.
     By hand from Def. 2: T = 2A - A[i,k,j] = 100i + 19j - 8k, then
