@@ -470,6 +470,19 @@ def main():
              refill=lambda: workloads.fill_uniform(big[0], 1000))
         ams = timed(lambda: ss.spinsum_exec(pa, big[0], big[0], stream), 5, stream)
         forms["3d_antisymmetrize"] = form_entry(2 * big[0].numel() * 8, ams, value)
+        # pi_123 + pi_213 (Fig. 1b) moves two of the three axes: the plan
+        # permutes those two alone (the third moves as whole 256-byte runs),
+        # against the tiling under all of S_3 (SPINSUM_FLAG_FULL_GROUP)
+        fig1b = [[((0, 1, 2), 1.0), (workloads.P("213"), 1.0)]]
+        for name, flags in [("3d_fig1b_subgroup", 0),
+                            ("3d_fig1b_full_group", ss.SPINSUM_FLAG_FULL_GROUP)]:
+            pf = ss.spinsum_plan(slab_shape, 3, 3, fig1b, inplace=True, flags=flags)
+            workloads.fill_uniform(big[0], 1000)
+            warm(lambda: ss.spinsum_exec(pf, big[0], big[0], stream),
+                 refill=lambda: workloads.fill_uniform(big[0], 1000))
+            fms = timed(lambda: ss.spinsum_exec(pf, big[0], big[0], stream), 5, stream)
+            forms[name] = form_entry(2 * big[0].numel() * 8, fms, value)
+            forms[name]["group_axes"] = ss.spinsum_plan_get_info(pf)["exec_d"]
         for name, flags in [("3d_no_nt_stores", ss.SPINSUM_FLAG_NO_NT_STORES),
                             ("3d_no_xcd_grouping", ss.SPINSUM_FLAG_NO_XCD_REMAP)]:
             pf = ss.spinsum_plan(slab_shape, 3, 3, alpha, inplace=True, flags=flags)
@@ -509,6 +522,17 @@ def main():
         forms["4d_v24_o12_inplace"] = form_entry(2 * x4.numel() * 8, ms4, value)
         forms["4d_v24_o12_inplace"]["tile_edge"] = ss.spinsum_plan_get_info(p4)["bl"]
         forms["4d_v24_o12_inplace"]["alpha_seed"] = 7
+        # 2 - pi_2134 moves two of the four axes: the subgroup plan against S_4
+        half = [[((0, 1, 2, 3), 2.0), (workloads.P("2134"), -1.0)]]
+        for name, flags in [("4d_2_minus_p2134_subgroup", 0),
+                            ("4d_2_minus_p2134_full_group", ss.SPINSUM_FLAG_FULL_GROUP)]:
+            ph = ss.spinsum_plan(w4["shape"], 4, 4, half, inplace=True, flags=flags)
+            workloads.fill_uniform(x4, 2000)
+            warm(lambda: ss.spinsum_exec(ph, x4, x4, stream),
+                 refill=lambda: workloads.fill_uniform(x4, 2000))
+            hms = timed(lambda: ss.spinsum_exec(ph, x4, x4, stream), 10, stream)
+            forms[name] = form_entry(2 * x4.numel() * 8, hms, value)
+            forms[name]["group_axes"] = ss.spinsum_plan_get_info(ph)["exec_d"]
         del x4
         torch.cuda.empty_cache()
 

@@ -87,6 +87,9 @@ typedef enum { SPINSUM_F64 = 0, SPINSUM_F32 = 1 } spinsum_dtype;
                                             the two-pass form of Alg. 3 (Sec. 4.3) with the
                                             output as its temporary (ablation of the fused
                                             chain; not with SPINSUM_FLAG_CHAIN_STAGES) */
+#define SPINSUM_FLAG_FULL_GROUP 0x400u   /* tile under the whole of S_d even where the operator's
+                                            permutations move a smaller run of axes (ablation of
+                                            the reduction described at spinsum_plan) */
 #define SPINSUM_FLAG_INDEX_PAIRS 0x80u   /* index-pair form: the d dims right before the group
                                             (the partner indices, extent V each) are permuted
                                             by the same permutation as the group, e.g.
@@ -155,6 +158,10 @@ typedef struct {
                             64 bytes and a cube has at most 128 tile orbits, and for whole
                             cubes); 0: cached stores, which let the L2 merge the partial
                             128-byte lines that short rows or far-apart items write */
+  int exec_d;            /* axes of the group the kernels permute: d, or fewer where the
+                            operator's permutations move a smaller run of axes (see
+                            spinsum_plan); the tiling fields above describe that group */
+  int exec_group_first;  /* its first dim */
 } spinsum_plan_info_t;
 
 /* Create a plan for Out = S_K(...S_1(In)) (Def. 3-4; in-place: Sec. 4.6.5).
@@ -184,6 +191,16 @@ typedef struct {
  * at most 2^26 tile orbits per pair block (their table takes 8 bytes each)
  * and fewer than 2^31 work items, and have no coefficient gradient or
  * autotuner (SPINSUM_ERR_UNSUPPORTED).
+ * Subgroup (Sec. 4.6.4, the connected components of Fig. 1b): the terms
+ * with nonzero coefficient generate a subgroup H of S_d, and every element
+ * (tile) orbit under H lies inside one under S_d.  Where all permutations
+ * of the operator (every stage) move only a contiguous run of the group's
+ * axes [s, e) with e - s >= 2, the plan executes the summation over those
+ * axes alone -- the axes before them become outer spectators, those after
+ * them inner spectators that move as whole contiguous runs -- unless
+ * SPINSUM_FLAG_FULL_GROUP is set (not for index pairs).  The result is the
+ * same; spinsum_plan_info_t.exec_d / exec_group_first report the group the
+ * kernels permute.
  * Host arrays are copied; the caller keeps ownership.  On error *plan is set
  * to NULL. */
 spinsum_status spinsum_plan(spinsum_plan_t* plan, int ndim, const int64_t* extents,

@@ -59,6 +59,7 @@ SPINSUM_FLAG_NO_DIRECT_LDS = 0x40
 SPINSUM_FLAG_INDEX_PAIRS = 0x80
 SPINSUM_FLAG_NT_STORES = 0x100
 SPINSUM_FLAG_MULTI_PASS = 0x200
+SPINSUM_FLAG_FULL_GROUP = 0x400
 
 SPINSUM_VARIANT_AUTO = 0
 SPINSUM_VARIANT_DIRECT_LDS = 1
@@ -87,7 +88,8 @@ class _Info(ctypes.Structure):
                 ("item_tiles", ctypes.c_int), ("chunks_per_thread", ctypes.c_int),
                 ("rep_lds_bytes", ctypes.c_int64), ("inner", ctypes.c_int),
                 ("pair_extent", ctypes.c_int), ("batch_item_bytes", ctypes.c_int64),
-                ("batch_persistent", ctypes.c_int), ("nt_stores", ctypes.c_int)]
+                ("batch_persistent", ctypes.c_int), ("nt_stores", ctypes.c_int),
+                ("exec_d", ctypes.c_int), ("exec_group_first", ctypes.c_int)]
 
 
 _vp = ctypes.c_void_p

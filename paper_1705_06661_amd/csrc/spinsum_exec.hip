@@ -374,6 +374,7 @@ spinsum_status launch_stages(spinsum_plan_s* P, const void* in, void* out, hipSt
 // through the output buffer (Alg. 3).
 spinsum_status run(spinsum_plan_s* P, const void* in, void* out, hipStream_t stream,
                    bool adjoint) {
+  if (P->sub) return run(P->sub, in, out, stream, adjoint);  // the moved axes alone
   if (P->flags & SPINSUM_FLAG_MULTI_PASS)
     return launch_stages(P, in, out, stream, adjoint, 0, (int)P->stage_a.size());
   return launch_any(P, in, out, stream, coef_sel(P, adjoint));

@@ -1037,6 +1037,62 @@ static spinsum_status shape_info(int ndim, const int64_t* extents, int group_fir
   return SPINSUM_OK;
 }
 
+// The group axes that some permutation of the operator moves (a term with
+// nonzero coefficient in any stage), as the range [*s0, *e0) when they are
+// contiguous.  Returns false when no axis moves or the moved axes are not
+// contiguous.
+static bool moved_axes(const spinsum_plan_s& P, int* s0, int* e0) {
+  int lo = P.d, hi = -1;
+  std::vector<bool> moved(P.d, false);
+  for (const std::vector<double>& st : P.stage_a)
+    for (int r = 0; r < P.G.df; ++r) {
+      if (st[r] == 0.0) continue;
+      for (int m = 0; m < P.d; ++m)
+        if (P.G.p[r][m] != m) moved[m] = true;
+    }
+  for (int m = 0; m < P.d; ++m)
+    if (moved[m]) {
+      lo = std::min(lo, m);
+      hi = std::max(hi, m);
+    }
+  if (hi < 0) return false;
+  for (int m = lo; m <= hi; ++m)
+    if (!moved[m]) return false;
+  *s0 = lo;
+  *e0 = hi + 1;
+  return true;
+}
+
+// The subgroup reduction (see spinsum_plan in the header): the plan of the
+// moved axes [s0, e0), its terms the operator's own ones restricted to
+// those axes (they fix every other axis), stage by stage.
+static spinsum_status reduce_to_moved_axes(spinsum_plan_s* P, int s0, int e0) {
+  const int d2 = e0 - s0;
+  const int K = (int)P->stage_a.size();
+  std::vector<int> nt(K, 0), pp;
+  std::vector<double> aa;
+  for (int k = 0; k < K; ++k)
+    for (int r = 0; r < P->G.df; ++r) {
+      const double a = P->stage_a[k][r];
+      if (a == 0.0) continue;
+      for (int m = 0; m < d2; ++m) pp.push_back(P->G.p[r][s0 + m] - s0);
+      aa.push_back(a);
+      ++nt[k];
+    }
+  if (pp.empty()) {
+    pp.push_back(0);
+    aa.push_back(0.0);
+  }
+  spinsum_plan_t sub = nullptr;
+  spinsum_status st = spinsum_plan(&sub, P->ndim, P->extents.data(), P->group_first + s0, d2, K,
+                                   nt.data(), pp.data(), aa.data(), (spinsum_dtype)P->dtype,
+                                   P->inplace, P->flags | SPINSUM_FLAG_FULL_GROUP);
+  if (st != SPINSUM_OK) return st;
+  P->sub = sub;
+  P->sub_first = P->group_first + s0;
+  return SPINSUM_OK;
+}
+
 extern "C" spinsum_status spinsum_plan(spinsum_plan_t* plan, int ndim, const int64_t* extents,
                                        int group_first, int d, int nstages, const int* nterms,
                                        const int* perms, const double* alpha,
@@ -1073,6 +1129,7 @@ extern "C" spinsum_status spinsum_plan(spinsum_plan_t* plan, int ndim, const int
   if (!P) return SPINSUM_ERR_OUT_OF_MEMORY;
   P->d = d;
   P->n = n;
+  P->group_first = group_first;
   P->inner = inner;
   P->pair = pair;
   P->pv = (int)V;
@@ -1102,9 +1159,12 @@ extern "C" spinsum_status spinsum_plan(spinsum_plan_t* plan, int ndim, const int
     st = apply_tile(P, nullptr);
   }
   if (st == SPINSUM_OK) st = upload_tables(P);
+  int s0 = 0, e0 = 0;
+  if (st == SPINSUM_OK && !(flags & (SPINSUM_FLAG_FULL_GROUP | SPINSUM_FLAG_INDEX_PAIRS)) &&
+      !pair && P->elems > 0 && moved_axes(*P, &s0, &e0) && e0 - s0 >= 2 && e0 - s0 < d)
+    st = reduce_to_moved_axes(P, s0, e0);
   if (st != SPINSUM_OK) {
-    free_device(P);
-    delete P;
+    spinsum_plan_destroy(P);
     return st;
   }
   *plan = P;
@@ -1294,6 +1354,7 @@ extern "C" spinsum_status spinsum_plan_batched(spinsum_plan_t* plan, int nblocks
 
 extern "C" spinsum_status spinsum_plan_set_tile(spinsum_plan_t P, const spinsum_tile_t* tile) {
   if (P == nullptr || tile == nullptr || P->batched) return SPINSUM_ERR_INVALID_ARG;
+  if (P->sub) return spinsum_plan_set_tile(P->sub, tile);
   if (tile->bl < 0 || tile->cubes_per_wg < 0) return SPINSUM_ERR_INVALID_ARG;
   spinsum_tile_t keep = P->tile;
   Tiling keepT = P->T;
@@ -1314,7 +1375,21 @@ extern "C" spinsum_status spinsum_plan_set_tile(spinsum_plan_t P, const spinsum_
 
 extern "C" spinsum_status spinsum_plan_get_info(spinsum_plan_t P, spinsum_plan_info_t* info) {
   if (P == nullptr || info == nullptr) return SPINSUM_ERR_INVALID_ARG;
+  if (P->sub) {
+    // the tiling of the group the kernels permute; the operator's own size
+    spinsum_status st = spinsum_plan_get_info(P->sub, info);
+    if (st != SPINSUM_OK) return st;
+    info->d = P->d;
+    info->elems = P->elems;
+    int nz = 0;
+    for (double v : P->expanded) nz += (v != 0.0);
+    info->nterms_expanded = nz;
+    info->exec_group_first = P->sub_first;
+    return SPINSUM_OK;
+  }
   std::memset(info, 0, sizeof(*info));
+  info->exec_d = P->d;
+  info->exec_group_first = P->group_first;
   info->d = P->d;
   info->n = P->n;
   info->ncubes = P->ncubes;
@@ -1625,6 +1700,7 @@ extern "C" spinsum_status spinsum_plan_check_ownership(spinsum_plan_t P, int blo
   };
   if (why) *why = "";
   if (P == nullptr) return SPINSUM_ERR_INVALID_ARG;
+  if (P->sub) return spinsum_plan_check_ownership(P->sub, block, why);
   if (block < 0 || block >= P->nblocks) return SPINSUM_ERR_INVALID_ARG;
   const Tiling& T = P->batched ? P->btil[block] : P->T;
   const Geom& g = T.g;
@@ -1709,11 +1785,16 @@ extern "C" spinsum_status spinsum_plan_check_ownership(spinsum_plan_t P, int blo
 
 extern "C" void spinsum_plan_destroy(spinsum_plan_t P) {
   if (!P) return;
+  if (P->sub) spinsum_plan_destroy(P->sub);
   free_device(P);
   delete P;
 }
 
-extern "C" int spinsum_plan_last_hip_error(spinsum_plan_t P) { return P ? P->last_hip_error : 0; }
+extern "C" int spinsum_plan_last_hip_error(spinsum_plan_t P) {
+  if (!P) return 0;
+  if (P->last_hip_error == 0 && P->sub) return P->sub->last_hip_error;
+  return P->last_hip_error;
+}
 
 extern "C" const char* spinsum_status_string(spinsum_status s) {
   switch (s) {

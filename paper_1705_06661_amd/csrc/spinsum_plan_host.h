@@ -56,6 +56,12 @@ struct Tiling {
 struct spinsum_plan_s {
   // problem
   int d = 0, n = 0;
+  int group_first = 0;
+  // The plan of the subgroup's axes (see reduce_to_moved_axes), which exec,
+  // adjoint, set_tile, autotune and check_ownership use when it is set;
+  // this plan keeps the tables of the whole group (coefficient gradients).
+  spinsum_plan_s* sub = nullptr;
+  int sub_first = 0;  // group position of the sub-plan's first axis
   int inner = 1;  // elements of the inner spectators (dims after the group)
   int ndim = 0;
   std::vector<int64_t> extents;

@@ -209,6 +209,7 @@ extern "C" spinsum_status spinsum_autotune(spinsum_plan_t P, void* in, void* out
                                            const char* cache_path, spinsum_tile_t* best,
                                            float* best_ms) {
   if (P == nullptr) return SPINSUM_ERR_INVALID_ARG;
+  if (P->sub) return spinsum_autotune(P->sub, in, out, stream, cache_path, best, best_ms);
   if (!P->has_dev) return SPINSUM_ERR_NO_DEVICE;
   if (P->batched) {
     if (in == nullptr || out == nullptr) return SPINSUM_ERR_INVALID_ARG;

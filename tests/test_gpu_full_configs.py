@@ -115,6 +115,34 @@ def test_4d_v24_o12_slab_inplace():
     check_cube_sums(x2, in_sums, expanded_sum([a]), 1e-12)
 
 
+# Operators whose permutations move two of the group's axes (Fig. 1b and
+# (2 - pi_2134)), on the full slabs in the configuration the benchmark times:
+# the plan runs the two moved axes alone (the subgroup reduction).
+SUBGROUP_SLABS = {
+    "3d_fig1b": ("3d_v64_o32_slab", 3, [[((0, 1, 2), 1.0), (workloads.P("213"), 1.0)]], 1000),
+    "4d_2_minus_p2134": ("4d_v24_o12_slab", 4,
+                         [[((0, 1, 2, 3), 2.0), (workloads.P("2134"), -1.0)]], 2000),
+}
+
+
+@pytest.mark.parametrize("form", list(SUBGROUP_SLABS))
+def test_subgroup_slabs_inplace(form):
+    wname, d, stages, seed = SUBGROUP_SLABS[form]
+    shape = workloads.WORKLOADS[wname]["shape"]
+    gf = len(shape) - d
+    _say("case subgroup slab", form, shape)
+    x = workloads.uniform(shape, seed, device=DEV)
+    cube = shape[-1] ** d
+    x2 = x.view(-1, cube)
+    in_sums = x2.sum(dim=1, dtype=torch.float64)
+    p = ss.spinsum_plan(shape, gf, d, stages, inplace=True)
+    assert ss.spinsum_plan_get_info(p)["exec_d"] == 2
+    ss.spinsum_exec(p, x, x)
+    torch.cuda.synchronize()
+    check_sampled(x2, seed, stages, d, sample_cubes(x2.shape[0], 32, 3), 1e-14)
+    check_cube_sums(x2, in_sums, expanded_sum(stages), 1e-12)
+
+
 def test_3d_inner_run8_inplace():
     """The slab with its group moved in front of an inner spectator run of
     8: [64, 64, 32, 32, 32, 8], group dims 2..4, in place (the bench line)."""

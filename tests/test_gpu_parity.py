@@ -806,3 +806,58 @@ def test_batched_autotune_and_persistent_launch(tmp_path, monkeypatch):
     torch.cuda.synchronize()
     for k in range(len(xs)):
         assert torch.equal(ys[k], singles[k]), k
+
+
+# ------------------------------------------------ subgroup reduction (a1)
+SUBGROUP_CASES = [
+    # (shape, group_first, d, stages)
+    ((3, 12, 12, 12), 1, 3, [[((0, 1, 2), 1.0), (workloads.P("213"), 1.0)]]),      # Fig. 1b
+    ((4, 16, 16, 16), 1, 3, [[((0, 1, 2), 2.0), (workloads.P("132"), -1.0)]]),
+    ((2, 6, 6, 6, 6), 1, 4, [[((0, 1, 2, 3), 2.0), (workloads.P("2134"), -1.0)]]),
+    ((2, 6, 6, 6, 6), 1, 4, [[((0, 1, 2, 3), 2.0), (workloads.P("1243"), -1.0)],
+                             [((0, 1, 2, 3), 1.0), (workloads.P("1342"), 3.0)]]),   # axes 1..3
+    ((3, 9, 9, 9), 1, 3, [[((0, 1, 2), 2.0), (workloads.P("213"), -1.0)],
+                          [((0, 1, 2), 1.0), (workloads.P("213"), 1.0)]]),          # a chain on (0,1)
+]
+
+
+@pytest.mark.parametrize("case", range(len(SUBGROUP_CASES)))
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_subgroup_reduction_against_oracle(case, dtype):
+    """Operators whose permutations move a contiguous run of the group's
+    axes run on those axes alone: equal to the oracle, to the S_d tiling
+    (SPINSUM_FLAG_FULL_GROUP) bit for bit, forward and adjoint, chained and
+    multi-pass; integer inputs bitwise; the coefficient gradient (kept on the
+    whole group) against the oracle."""
+    shape, gf, d, stages = SUBGROUP_CASES[case]
+    x = gpu_uniform(shape, 2300 + case, dtype)
+    xh = x.cpu().to(torch.float64).numpy()
+    ref = oracle.spinsum_chain(xh, stages, gf, d, nthreads=8)
+    refa = oracle.spinsum_chain_adjoint(xh, stages, gf, d, nthreads=8)
+    xi = gpu_ints(shape, 2400 + case, dtype)
+    refi = oracle.spinsum_chain(xi.cpu().to(torch.float64).numpy(), stages, gf, d)
+    for flags in (0, ss.SPINSUM_FLAG_CHAIN_STAGES, ss.SPINSUM_FLAG_MULTI_PASS):
+        for inplace in (False, True):
+            p = ss.spinsum_plan(shape, gf, d, stages, dtype=dtype, inplace=inplace, flags=flags)
+            info = ss.spinsum_plan_get_info(p)
+            assert info["exec_d"] < d, info
+            q = ss.spinsum_plan(shape, gf, d, stages, dtype=dtype, inplace=inplace,
+                                flags=flags | ss.SPINSUM_FLAG_FULL_GROUP)
+            y = run(p, x)
+            assert nerr(y.cpu().numpy(), ref) <= TOL[dtype], (flags, inplace)
+            assert torch.equal(y, run(q, x)), (flags, inplace)
+            if inplace:
+                ya = x.clone()
+                ss.spinsum_adjoint(p, ya, ya)
+            else:
+                ya = torch.empty_like(x)
+                ss.spinsum_adjoint(p, x, ya)
+            torch.cuda.synchronize()
+            assert nerr(ya.cpu().numpy(), refa) <= TOL[dtype], (flags, inplace)
+            np.testing.assert_array_equal(run(p, xi).cpu().to(torch.float64).numpy(), refi)
+    if len(stages) == 1:
+        p = ss.spinsum_plan(shape, gf, d, stages, dtype=dtype)
+        g = gpu_uniform(shape, 2500 + case, dtype)
+        cg = ss.spinsum_coef_grad(p, x, g).cpu().numpy()
+        refg = oracle.coef_grad(xh, g.cpu().to(torch.float64).numpy(), gf, d, nthreads=8)
+        assert nerr(cg, refg) <= TOL[dtype]

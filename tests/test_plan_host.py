@@ -369,7 +369,8 @@ def test_small_orbits_are_packed_where_few_workgroups_fit():
     """With fewer than four workgroups per CU (4D, 24-tile orbits of 4^4
     tiles), the planner packs consecutive orbits up to the largest one; an
     explicit tile keeps one orbit per item."""
-    p = plan((1, 16, 16, 16, 16), [[((0, 1, 2, 3), 1.0), ((1, 0, 2, 3), 2.0)]], d=4)
+    p = plan((1, 16, 16, 16, 16), [[((0, 1, 2, 3), 1.0), ((1, 0, 2, 3), 2.0)]], d=4,
+             flags=ss.SPINSUM_FLAG_FULL_GROUP)
     info = ss.spinsum_plan_get_info(p)
     assert info["bl"] == 4 and info["item_tiles"] == 24
     assert info["items_per_cube"] < info["norbits"]
@@ -394,6 +395,40 @@ def test_batched_plan_tables():
     # whole cubes are packed up to the largest cube of at most 40 KiB (o = 16
     # here: 32 KiB), one workgroup per item unless a tuned cache says so
     assert info["batch_item_bytes"] == 16 ** 3 * 8 and info["batch_persistent"] == 0
+
+
+def test_subgroup_reduction():
+    """Terms that move only a contiguous run of the group's axes: the plan
+    permutes those axes alone (Sec. 4.6.4's connected components), the fixed
+    trailing axes moving as inner runs and the leading ones as outer
+    spectators; SPINSUM_FLAG_FULL_GROUP keeps S_d.  The expanded operator and
+    the ownership replay are those of the executing plan's group."""
+    ident = (0, 1, 2)
+    cases = [
+        # pi_123 + pi_213 (Fig. 1b): axes 0, 1 of the group; axis 2 inner
+        ((64, 4, 32, 32, 32), 2, [[(ident, 1.0), (P("213"), 1.0)]], 3, 2, 2, 32),  # first dim 2
+        # 2 - pi_132: axes 1, 2; axis 0 an outer spectator
+        ((3, 16, 16, 16), 1, [[(ident, 2.0), (P("132"), -1.0)]], 3, 2, 2, 1),  # first dim 2
+        # (2 - pi_2134) in 4D: axes 0, 1; the other two inner (144 elements)
+        ((1, 24, 12, 12, 12, 12), 2, [[((0, 1, 2, 3), 2.0), ((1, 0, 2, 3), -1.0)]], 4, 2, 2, 144),
+        # a chain whose stages move axes (0,1) and (1,2): all three, no reduction
+        ((3, 8, 8, 8), 1, workloads.FACTORED_PIJ_PJK, 3, 3, 1, 1),  # first dim 1
+        # pi_321 alone moves axes 0 and 2 (not a contiguous run): no reduction
+        ((3, 8, 8, 8), 1, [[(P("321"), 1.0)]], 3, 3, 1, 1),
+    ]
+    for shape, gf, stages, d, want_d, want_first, want_inner in cases:
+        p = ss.spinsum_plan(shape, gf, d, stages, flags=HOST)
+        info = ss.spinsum_plan_get_info(p)
+        assert info["d"] == d and info["exec_d"] == want_d, (shape, info)
+        assert info["exec_group_first"] == want_first
+        assert info["inner"] == want_inner, info
+        assert info["elems"] == int(np.prod(shape))
+        ok, why = ss.spinsum_plan_check_ownership(p)
+        assert ok, why
+        exp = ss.spinsum_plan_expanded(p)
+        assert _as_dict(exp) == {tuple(q): a for q, a in oracle.expanded_terms(stages, d)}
+        full = ss.spinsum_plan(shape, gf, d, stages, flags=HOST | ss.SPINSUM_FLAG_FULL_GROUP)
+        assert ss.spinsum_plan_get_info(full)["exec_d"] == d
 
 
 def test_batched_plan_with_inner_runs():
