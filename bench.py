@@ -483,6 +483,18 @@ def main():
             fms = timed(lambda: ss.spinsum_exec(pf, big[0], big[0], stream), 5, stream)
             forms[name] = form_entry(2 * big[0].numel() * 8, fms, value)
             forms[name]["group_axes"] = ss.spinsum_plan_get_info(pf)["exec_d"]
+        # antisymmetric unpacking of slab 0 from its C(32, 3) = 4960 packed
+        # values per cube, and packing back (bytes: packed + full tensor)
+        pu = ss.spinsum_plan(slab_shape, 3, 3, [workloads.antisymmetrizer(3)])
+        pk = workloads.uniform(ss.packed_shape(pu), 3200, device=dev)
+        ubytes = (pk.numel() + big[0].numel()) * 8
+        warm(lambda: ss.spinsum_unpack(pu, pk, big[0], stream))
+        ums = timed(lambda: ss.spinsum_unpack(pu, pk, big[0], stream), 5, stream)
+        forms["3d_unpack_antisymmetric"] = form_entry(ubytes, ums, value)
+        warm(lambda: ss.spinsum_pack(pu, big[0], pk, stream))
+        pms = timed(lambda: ss.spinsum_pack(pu, big[0], pk, stream), 5, stream)
+        forms["3d_pack_antisymmetric"] = form_entry(ubytes, pms, value)
+        del pk
         for name, flags in [("3d_no_nt_stores", ss.SPINSUM_FLAG_NO_NT_STORES),
                             ("3d_no_xcd_grouping", ss.SPINSUM_FLAG_NO_XCD_REMAP)]:
             pf = ss.spinsum_plan(slab_shape, 3, 3, alpha, inplace=True, flags=flags)

@@ -286,6 +286,28 @@ spinsum_status spinsum_adjoint(spinsum_plan_t plan, const void* grad_out, void* 
 spinsum_status spinsum_coef_grad(spinsum_plan_t plan, const void* x, const void* g,
                                  double* grad, void* stream);
 
+/* Unpacking (the paper names tensor unpacking, Sec. 1 and Sec. 7, as another
+ * sum of permutations; its layout is not fixed there).  A packed tensor
+ * holds one value per strictly increasing tuple i_0 < ... < i_{d-1} of the
+ * group, in lexicographic order, for every outer spectator index and inner
+ * run: shape [outer..., C(N, d), inner...], C-contiguous.
+ *   spinsum_unpack: full = S(E(packed)), E putting the packed values at the
+ *     strictly increasing positions of a zero tensor and S the plan's
+ *     operator (Def. 3; its pre-multiplied form).  With S the
+ *     antisymmetriser (every permutation weighted by its sign) this is the
+ *     unpacking of an antisymmetric tensor: full[sigma . x] = sgn(sigma) *
+ *     packed[x] for increasing x, zero where indices repeat.
+ *   spinsum_pack: the adjoint, packed = E^T S^T full: for every strictly
+ *     increasing x, sum over sigma of a(sigma^-1) full[sigma . x].
+ * The plan is an ordinary plan of the full tensor's shape (not batched, not
+ * index pairs), run on the whole group's tiles in the direct-LDS layout
+ * (SPINSUM_ERR_UNSUPPORTED otherwise, and for N >= 65536).  full: device
+ * pointer, 16-byte aligned; packed: device pointer aligned to the element
+ * size; the two must not overlap (SPINSUM_ERR_ALIASING).  Out-of-place,
+ * asynchronous on `stream`, allocates nothing. */
+spinsum_status spinsum_unpack(spinsum_plan_t plan, const void* packed, void* full, void* stream);
+spinsum_status spinsum_pack(spinsum_plan_t plan, const void* full, void* packed, void* stream);
+
 /* Gradients with respect to the coefficients of every stage of a chain
  * (Def. 4; not in the paper): S = S_K ... S_1 is linear in the coefficients
  * of each stage, so for L = <g, S(x)> and stage k

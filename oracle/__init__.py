@@ -222,6 +222,54 @@ def coef_grad_stages(x: np.ndarray, g: np.ndarray, stages: Sequence[Stage], grou
     return out
 
 
+# ----------------------------------------------------------- unpacking
+def increasing_tuples(n: int, d: int) -> List[Tuple[int, ...]]:
+    """The strictly increasing d-tuples over range(n) in lexicographic order:
+    the positions of a packed tensor (one value per tuple)."""
+    return list(itertools.combinations(range(n), d))
+
+
+def embed_packed(packed: np.ndarray, shape: Sequence[int], group_first: int,
+                 d: int) -> np.ndarray:
+    """A full tensor of `shape` that holds the packed values at the strictly
+    increasing group positions and zeros elsewhere.  packed has the shape
+    [outer..., C(N, d), inner...]."""
+    shape = tuple(int(e) for e in shape)
+    n = shape[group_first]
+    full = np.zeros(shape, dtype=np.float64)
+    packed = np.asarray(packed, dtype=np.float64)
+    for r, t in enumerate(increasing_tuples(n, d)):
+        idx = (slice(None),) * group_first + tuple(t)
+        full[idx] = packed[(slice(None),) * group_first + (r,)]
+    return full
+
+
+def unpack(packed: np.ndarray, shape: Sequence[int], stages: Sequence[Stage],
+           group_first: int, d: int, nthreads: int = 1) -> np.ndarray:
+    """Unpacking as a sum of permutations (tensor unpacking, Sec. 1 and
+    Sec. 7): S(E(packed)) with E the embedding above and S the chain; with S
+    the antisymmetriser this is the unpacking of an antisymmetric tensor
+    from its strictly increasing entries."""
+    return spinsum_chain(embed_packed(packed, shape, group_first, d), stages, group_first, d,
+                         nthreads)
+
+
+def pack(full: np.ndarray, stages: Sequence[Stage], group_first: int, d: int,
+         nthreads: int = 1) -> np.ndarray:
+    """The adjoint of unpack: S^T applied to the full tensor, then its values
+    at the strictly increasing group positions gathered in lexicographic
+    order ([outer..., C(N, d), inner...])."""
+    full = np.asarray(full, dtype=np.float64)
+    n = full.shape[group_first]
+    y = spinsum_chain_adjoint(full, stages, group_first, d, nthreads)
+    tuples = increasing_tuples(n, d)
+    out_shape = full.shape[:group_first] + (len(tuples),) + full.shape[group_first + d:]
+    out = np.zeros(out_shape, dtype=np.float64)
+    for r, t in enumerate(tuples):
+        out[(slice(None),) * group_first + (r,)] = y[(slice(None),) * group_first + tuple(t)]
+    return out
+
+
 def spinsum_numpy(x: np.ndarray, terms: Stage, group_first: int, d: int,
                   pairs: bool = False) -> np.ndarray:
     """sum_t alpha_t * transpose(A) in float64 (second, independent route)."""

@@ -124,6 +124,8 @@ _c_adjoint = _decl("spinsum_adjoint", [_vp, _vp, _vp, _vp])
 _c_coef_grad = _decl("spinsum_coef_grad", [_vp, _vp, _vp, _vp, _vp])
 _c_coef_grad_noalloc = _decl("spinsum_coef_grad_noalloc", [_vp, _vp, _vp, _vp, _vp])
 _c_coef_grad_stages = _decl("spinsum_coef_grad_stages", [_vp, _vp, _vp, _vp, _vp, _vp, _vp])
+_c_unpack = _decl("spinsum_unpack", [_vp, _vp, _vp, _vp])
+_c_pack = _decl("spinsum_pack", [_vp, _vp, _vp, _vp])
 _c_graph_create = _decl("spinsum_graph_create", [_vp, _vp, _vp, ctypes.POINTER(_vp)])
 _c_graph_launch = _decl("spinsum_graph_launch", [_vp, _vp])
 _c_graph_destroy = _decl("spinsum_graph_destroy", [_vp], None)
@@ -138,7 +140,8 @@ _c_version = _decl("spinsum_version", [], ctypes.c_char_p)
 EXPORTED = ["spinsum_plan", "spinsum_plan_batched", "spinsum_plan_set_tile",
             "spinsum_plan_get_info", "spinsum_plan_expanded", "spinsum_plan_check_ownership",
             "spinsum_exec", "spinsum_exec_batched", "spinsum_adjoint", "spinsum_coef_grad",
-            "spinsum_coef_grad_noalloc", "spinsum_coef_grad_stages",
+            "spinsum_coef_grad_noalloc", "spinsum_coef_grad_stages", "spinsum_unpack",
+            "spinsum_pack",
             "spinsum_graph_create",
             "spinsum_graph_launch", "spinsum_graph_destroy", "spinsum_autotune",
             "spinsum_stream_copy", "spinsum_plan_last_hip_error", "spinsum_plan_destroy",
@@ -190,9 +193,10 @@ def _flatten(stages, d):
 class Plan:
     """Owns a spinsum_plan_t (destroyed with the object)."""
 
-    def __init__(self, handle, d, shapes, dtype, inplace, batched, stages):
+    def __init__(self, handle, d, shapes, dtype, inplace, batched, stages, group_first=None):
         self._h = handle
         self.d = d
+        self.group_first = group_first
         self.shapes = shapes
         self.dtype = torch.float64 if dtype == SPINSUM_F64 else torch.float32
         self.inplace = bool(inplace)
@@ -221,7 +225,8 @@ def spinsum_plan(extents: Sequence[int], group_first: int, d: int, stages, dtype
     dt = _DTYPES[dtype]
     _check(_c_plan(ctypes.byref(h), len(extents), ext, int(group_first), int(d), len(stages),
                    nt, pp, aa, dt, int(bool(inplace)), int(flags)), "spinsum_plan")
-    return Plan(h, d, [tuple(int(e) for e in extents)], dt, inplace, False, stages)
+    return Plan(h, d, [tuple(int(e) for e in extents)], dt, inplace, False, stages,
+                int(group_first))
 
 
 def spinsum_plan_batched(shapes: Sequence[Sequence[int]], d: int, stages, dtype="f64",
@@ -326,6 +331,37 @@ def spinsum_coef_grad(plan: Plan, x: torch.Tensor, g: torch.Tensor, stream=None)
     out = torch.empty(math.factorial(plan.d), dtype=torch.float64, device=x.device)
     _check(_c_coef_grad(plan._h, a, b, out.data_ptr(), _stream(stream)), "spinsum_coef_grad", plan)
     return out
+
+
+def packed_shape(plan: Plan):
+    """[outer..., C(N, d), inner...] of a plan's full shape (group_first is
+    taken from the plan's stored arguments)."""
+    shape = plan.shape
+    gf = plan.group_first
+    n = shape[gf]
+    return tuple(shape[:gf]) + (math.comb(n, plan.d),) + tuple(shape[gf + plan.d:])
+
+
+def _packed_ptr(t: torch.Tensor, plan: Plan, what: str) -> int:
+    return _tensor_ptr(t, plan, packed_shape(plan), what)
+
+
+def spinsum_unpack(plan: Plan, packed: torch.Tensor, full: torch.Tensor, stream=None):
+    """full = S(E(packed)): the values at the strictly increasing group
+    positions (lexicographic order) placed and summed over the plan's
+    permutations (the antisymmetriser unpacks an antisymmetric tensor)."""
+    a = _packed_ptr(packed, plan, "packed")
+    b = _tensor_ptr(full, plan, plan.shape, "full")
+    _check(_c_unpack(plan._h, a, b, _stream(stream)), "spinsum_unpack", plan)
+    return full
+
+
+def spinsum_pack(plan: Plan, full: torch.Tensor, packed: torch.Tensor, stream=None):
+    """packed = E^T S^T full (the adjoint of spinsum_unpack)."""
+    a = _tensor_ptr(full, plan, plan.shape, "full")
+    b = _packed_ptr(packed, plan, "packed")
+    _check(_c_pack(plan._h, a, b, _stream(stream)), "spinsum_pack", plan)
+    return packed
 
 
 def spinsum_coef_grad_stages(plan: Plan, x: torch.Tensor, g: torch.Tensor, work=None,

@@ -212,6 +212,26 @@ struct PairArgs {
   uint32_t sparse;         // bit s: stage s has a zero coefficient (see combine_orbit)
 };
 
+// Unpacking and packing: the packed tensor holds one value per strictly
+// increasing tuple of group indices, in lexicographic order, per outer
+// spectator index: [outer.., ncomb = C(N, d), inner..].
+template <typename T>
+struct PackArgs {
+  const T* full_in;    // k_pack: the full tensor
+  T* full_out;         // k_unpack: the full tensor
+  const T* packed_in;  // k_unpack
+  T* packed_out;       // k_pack
+  const GroupDev* orbits;
+  const uint32_t* reps;
+  const T* coef;       // the operator's d! coefficients (forward vector)
+  Geom g;
+  int64_t nitems;
+  int64_t xcd_per;
+  int64_t ncomb;
+  int32_t lds_tile_bytes;
+  int32_t pad;
+};
+
 // Fused multiply-add in the storage type (a float FMA for float: the
 // generic builtin would promote to double).
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -1630,6 +1650,219 @@ __global__ void __launch_bounds__(kThreads) k_grad_reduce(const double* part, do
   if (threadIdx.x == 0) grad[p] = red[0];
 }
 
+// Lexicographic rank of a strictly increasing tuple X of [0, N) among all
+// C(N, d) of them: the tuples after X, read backwards as N-1-X, are counted
+// in the combinatorial number system (sum over m of C(y_m, m+1) for the
+// increasing y), so rank = C(N, d) - 1 - that count.  Exact in 64 bits
+// for N < 2^16.
+__device__ __forceinline__ uint64_t binom_upto4(uint64_t y, int k) {
+  if (k == 1) return y;
+  if (k == 2) return y * (y - 1) / 2;
+  if (k == 3) return y < 3 ? 0 : y * (y - 1) / 2 * (y - 2) / 3;
+  return y < 4 ? 0 : y * (y - 1) / 2 * (y - 2) / 3 * (y - 3) / 4;
+}
+
+template <int D>
+__device__ __forceinline__ int64_t increasing_rank(const int (&X)[D], int n, int64_t ncomb) {
+  uint64_t c = 0;
+#pragma unroll
+  for (int m = 0; m < D; ++m) c += binom_upto4((uint64_t)(n - 1 - X[D - 1 - m]), m + 1);
+  return ncomb - 1 - (int64_t)c;
+}
+
+// Origin (group coordinates) of the identity tile of orbit k of an item.
+template <int D>
+__device__ __forceinline__ void orbit_origin(const Geom& g, cptr<GroupDev> gd, int k,
+                                             int (&org)[D]) {
+  const uint32_t off = (uint32_t)gd->tile_off[(uint32_t)gd->slot_base[k][0] / (uint32_t)g.ts];
+#pragma unroll
+  for (int m = 0; m < D; ++m) org[m] = (int)((off / (uint32_t)g.gst[m]) % (uint32_t)g.n);
+}
+
+template <typename T, int D, int... TAU>
+__device__ __forceinline__ void unpack_rows(const T (&a)[Fact<D>::v], T v, T* lds,
+                                            const int (&addr)[Fact<D>::v],
+                                            std::integer_sequence<int, TAU...>) {
+  // w_tau = a(tau^-1) v: the one input of the element orbit is the packed
+  // value at its increasing tuple (the identity's slot); a zero coefficient
+  // is not a term, so it gives 0 even for a non-finite v
+  ((lds[addr[TAU]] = (a[GinvMul<D, TAU, 0>::value] != T(0)) ? a[GinvMul<D, TAU, 0>::value] * v
+                                                             : T(0)),
+   ...);
+}
+
+template <typename T, int D, int... S>
+__device__ __forceinline__ T pack_row(const T (&a)[Fact<D>::v], const T (&v)[Fact<D>::v],
+                                      std::integer_sequence<int, S...>) {
+  // (S^T f)[x] = sum_sigma a(sigma^-1) f[sigma . x], over the terms only
+  T acc = T(0);
+  ((acc = (a[GinvMul<D, S, 0>::value] != T(0)) ? fma_t(a[GinvMul<D, S, 0>::value], v[S], acc) : acc),
+   ...);
+  return acc;
+}
+
+// Unpacking: full = S(E(packed)), E placing the packed values at the
+// strictly increasing group positions of a zero tensor.  An element orbit
+// {sigma . x} (x sorted) holds one packed value when x is strictly
+// increasing and none otherwise, so its outputs are a(tau^-1) v or zero.
+// Work items, LDS layout and stores as in k_lds; nothing is read from the
+// full tensor.  One work item per workgroup, XCD-grouped.
+template <typename T, int D, bool NTS>
+__global__ void __launch_bounds__(kMaxThreads) k_unpack(const PackArgs<T> a) {
+  constexpr int DF = Fact<D>::v;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  int64_t item;
+  if (a.xcd_per > 0)
+    item = (int64_t)(blockIdx.x & 7u) * a.xcd_per + (int64_t)(blockIdx.x >> 3);
+  else
+    item = blockIdx.x;
+  if (item >= a.nitems) return;
+  const Geom& g = a.g;
+  int64_t cube0;
+  int orbit, ncub;
+  decode_item(g, item, &cube0, &orbit, &ncub);
+  const cptr<GroupDev> od = as_const(a.orbits + orbit);
+  const bool whole = (g.bl == g.n);
+  const int ntl = whole ? ncub : od->ntiles;
+  const bool ragged = od->ragged != 0;
+  T* dst = a.full_out + cube0 * g.cube_elems;
+  // whole cubes are laid out as the contiguous store expects them
+  const int shift = whole ? flat_shift<T>(dst) : 0;
+  T* lds = reinterpret_cast<T*>(smem) + shift;
+  unsigned char* rep_lds = smem + a.lds_tile_bytes;
+  issue_reps_lds(od, a.reps, rep_lds);
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  __syncthreads();
+  T co[DF];
+  const cptr<T> coef = as_const(a.coef);
+#pragma unroll
+  for (int r = 0; r < DF; ++r) co[r] = coef[r];
+  const uint32_t* reps = reinterpret_cast<const uint32_t*>(rep_lds);
+  const int norb = od->norb;
+  for (int k = 0; k < norb; ++k) {
+    int32_t sb[DF];
+#pragma unroll
+    for (int r = 0; r < DF; ++r) sb[r] = od->slot_base[k][r];
+    int org[D];
+    orbit_origin<D>(g, od, k, org);
+    const uint32_t rep_cnt = (uint32_t)od->rep_cnt[k];
+    const FastDiv fdr = load_fd(od->fd_rep[k]);
+    const uint32_t* rp = reps + od->rep_base[k];
+    const uint32_t nrep = (uint32_t)ncub * rep_cnt * (uint32_t)g.inner;
+    for (uint32_t i = threadIdx.x; i < nrep; i += blockDim.x) {
+      uint32_t ci, ri, si;
+      split_unit(g, i, rep_cnt, fdr, ncub, &ci, &ri, &si);
+      const uint32_t pk = rp[ri];
+      int l[D], X[D];
+#pragma unroll
+      for (int m = 0; m < D; ++m) {
+        l[m] = (int)((pk >> (8 * m)) & 255u);
+        X[m] = org[m] + l[m];
+      }
+      bool strict = true;
+#pragma unroll
+      for (int m = 0; m + 1 < D; ++m) strict = strict && (X[m] < X[m + 1]);
+      T v = T(0);
+      if (strict) {
+        const int64_t r = increasing_rank<D>(X, g.n, a.ncomb);
+        v = a.packed_in[((cube0 + (int64_t)ci) * a.ncomb + r) * g.inner + (int64_t)si];
+      }
+      int addr[DF];
+      orbit_addrs<D>(g, (int)ci * g.cube_lds + (int)si, sb, l, addr,
+                     std::make_integer_sequence<int, DF>{});
+      if (strict) {
+        unpack_rows<T, D>(co, v, lds, addr, std::make_integer_sequence<int, DF>{});
+      } else {
+#pragma unroll
+        for (int r = 0; r < DF; ++r) lds[addr[r]] = T(0);
+      }
+    }
+  }
+  __syncthreads();
+  set_memory_priority();
+  if (whole)
+    flat_store<T, NTS>(dst, (uint32_t)ncub * (uint32_t)g.cube_elems, smem, shift);
+  else
+    store_item_lds<T, D, NTS>(g, od, whole, ntl, ragged, dst, lds);
+}
+
+// Packing, the adjoint of unpacking: packed = E^T S^T full -- for every
+// strictly increasing x, sum_sigma a(sigma^-1) full[sigma . x].  The item's
+// tiles are loaded as in k_lds; nothing is stored to the full tensor.
+template <typename T, int D>
+__global__ void __launch_bounds__(kMaxThreads) k_pack(const PackArgs<T> a) {
+  constexpr int DF = Fact<D>::v;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  int64_t item;
+  if (a.xcd_per > 0)
+    item = (int64_t)(blockIdx.x & 7u) * a.xcd_per + (int64_t)(blockIdx.x >> 3);
+  else
+    item = blockIdx.x;
+  if (item >= a.nitems) return;
+  const Geom& g = a.g;
+  int64_t cube0;
+  int orbit, ncub;
+  decode_item(g, item, &cube0, &orbit, &ncub);
+  const cptr<GroupDev> od = as_const(a.orbits + orbit);
+  const bool whole = (g.bl == g.n);
+  const int ntl = whole ? ncub : od->ntiles;
+  const bool ragged = od->ragged != 0;
+  unsigned char* rep_lds = smem + a.lds_tile_bytes;
+  const uint32_t span = (uint32_t)ncub * (uint32_t)g.cube_elems;
+  int shift = 0;
+  set_memory_priority();
+  if (whole)
+    shift = flat_issue<T>(a.full_in + cube0 * g.cube_elems, span, smem);
+  else
+    issue_item_lds<T, D>(g, od, whole, ntl, ragged, a.full_in + cube0 * g.cube_elems, smem);
+  issue_reps_lds(od, a.reps, rep_lds);
+  set_compute_priority();
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+  __syncthreads();
+  const T* lds = reinterpret_cast<const T*>(smem) + shift;
+  T co[DF];
+  const cptr<T> coef = as_const(a.coef);
+#pragma unroll
+  for (int r = 0; r < DF; ++r) co[r] = coef[r];
+  const uint32_t* reps = reinterpret_cast<const uint32_t*>(rep_lds);
+  const int norb = od->norb;
+  for (int k = 0; k < norb; ++k) {
+    int32_t sb[DF];
+#pragma unroll
+    for (int r = 0; r < DF; ++r) sb[r] = od->slot_base[k][r];
+    int org[D];
+    orbit_origin<D>(g, od, k, org);
+    const uint32_t rep_cnt = (uint32_t)od->rep_cnt[k];
+    const FastDiv fdr = load_fd(od->fd_rep[k]);
+    const uint32_t* rp = reps + od->rep_base[k];
+    const uint32_t nrep = (uint32_t)ncub * rep_cnt * (uint32_t)g.inner;
+    for (uint32_t i = threadIdx.x; i < nrep; i += blockDim.x) {
+      uint32_t ci, ri, si;
+      split_unit(g, i, rep_cnt, fdr, ncub, &ci, &ri, &si);
+      const uint32_t pk = rp[ri];
+      int l[D], X[D];
+#pragma unroll
+      for (int m = 0; m < D; ++m) {
+        l[m] = (int)((pk >> (8 * m)) & 255u);
+        X[m] = org[m] + l[m];
+      }
+      bool strict = true;
+#pragma unroll
+      for (int m = 0; m + 1 < D; ++m) strict = strict && (X[m] < X[m + 1]);
+      if (!strict) continue;
+      int addr[DF];
+      T v[DF];
+      orbit_addrs<D>(g, (int)ci * g.cube_lds + (int)si, sb, l, addr,
+                     std::make_integer_sequence<int, DF>{});
+#pragma unroll
+      for (int r = 0; r < DF; ++r) v[r] = lds[addr[r]];
+      const int64_t rk = increasing_rank<D>(X, g.n, a.ncomb);
+      a.packed_out[((cube0 + (int64_t)ci) * a.ncomb + rk) * g.inner + (int64_t)si] =
+          pack_row<T, D>(co, v, std::make_integer_sequence<int, DF>{});
+    }
+  }
+}
+
 // ------------------------------------------------------------ dispatch
 template <typename T, int D, bool CHAIN, bool NTS>
 const void* exec_kernel(int vw) {
@@ -1685,6 +1918,12 @@ const void* cgrad_kernel() {
   return (const void*)k_cgrad<T, D>;
 }
 
+template <typename T, int D>
+const void* pack_kernel(bool pack, bool nts) {
+  if (pack) return (const void*)k_pack<T, D>;
+  return nts ? (const void*)k_unpack<T, D, true> : (const void*)k_unpack<T, D, false>;
+}
+
 template <typename T, int D, bool PERSIST>
 const void* batched_kernel_p(int vw) {
   if constexpr (sizeof(T) == 8) {
@@ -1709,7 +1948,8 @@ const void* batched_kernel(int vw, bool persist) {
 #define SPINSUM_DECLARE_PICK(tag, d)                                                    \
   const void* pick_##tag##_d##d(int kind, int vw, bool chain, bool nts, int maxc);     \
   const void* pick_batched_##tag##_d##d(int vw, bool persist);                         \
-  const void* pick_cgrad_##tag##_d##d();
+  const void* pick_cgrad_##tag##_d##d();                                                \
+  const void* pick_pack_##tag##_d##d(bool pack, bool nts);
 SPINSUM_DECLARE_PICK(f64, 2)
 SPINSUM_DECLARE_PICK(f64, 3)
 SPINSUM_DECLARE_PICK(f64, 4)

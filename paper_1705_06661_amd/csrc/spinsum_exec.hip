@@ -47,6 +47,19 @@ const void* pick_batched(int d, int vw, bool persist) {
 }
 
 template <typename T>
+const void* pick_pack(int d, bool pack, bool nts) {
+  if constexpr (sizeof(T) == 8) {
+    if (d == 2) return pick_pack_f64_d2(pack, nts);
+    if (d == 3) return pick_pack_f64_d3(pack, nts);
+    return pick_pack_f64_d4(pack, nts);
+  } else {
+    if (d == 2) return pick_pack_f32_d2(pack, nts);
+    if (d == 3) return pick_pack_f32_d3(pack, nts);
+    return pick_pack_f32_d4(pack, nts);
+  }
+}
+
+template <typename T>
 const void* pick_cgrad(int d) {
   if constexpr (sizeof(T) == 8) {
     if (d == 2) return pick_cgrad_f64_d2();
@@ -570,6 +583,99 @@ extern "C" spinsum_status spinsum_coef_grad_stages(spinsum_plan_t P, const void*
 extern "C" spinsum_status spinsum_coef_grad_noalloc(spinsum_plan_t P, const void* x,
                                                     const void* g, double* grad, void* stream) {
   return coef_grad_impl(P, x, g, grad, true, stream);
+}
+
+namespace spinsum {
+namespace {
+
+// C(n, d), or -1 beyond 2^62.
+int64_t ncomb_of(int n, int d) {
+  int64_t r = 1;
+  for (int k = 0; k < d; ++k) {
+    if (r > ((int64_t)1 << 62) / std::max(1, n - k)) return -1;
+    r = r * (n - k) / (k + 1);
+  }
+  return r;
+}
+
+template <typename T>
+spinsum_status launch_pack(spinsum_plan_s* P, const void* full, void* packed, bool pack,
+                           hipStream_t stream) {
+  const Tiling& Tl = P->T;
+  if (Tl.nitems <= 0) return SPINSUM_OK;
+  PackArgs<T> a;
+  std::memset(&a, 0, sizeof(a));
+  if (pack) {
+    a.full_in = reinterpret_cast<const T*>(full);
+    a.packed_out = reinterpret_cast<T*>(packed);
+  } else {
+    a.full_out = reinterpret_cast<T*>(const_cast<void*>(full));
+    a.packed_in = reinterpret_cast<const T*>(packed);
+  }
+  a.orbits = reinterpret_cast<const GroupDev*>(P->d_orbits);
+  a.reps = reinterpret_cast<const uint32_t*>(P->d_reps);
+  a.coef = reinterpret_cast<const T*>(P->d_mats);  // the pre-multiplied forward vector
+  a.g = Tl.g;
+  a.nitems = Tl.nitems;
+  a.ncomb = ncomb_of(P->n, P->d);
+  a.lds_tile_bytes = (int32_t)(((size_t)Tl.lds_elems * sizeof(T) + 15) / 16 * 16);
+  const void* k = pick_pack<T>(P->d, pack, Tl.nts != 0);
+  const size_t shmem = (size_t)a.lds_tile_bytes + (size_t)Tl.max_rep_cnt * 4;
+  spinsum_status st = prepare_kernel(P, k, shmem);
+  if (st != SPINSUM_OK) return st;
+  int64_t grid;
+  if (P->flags & SPINSUM_FLAG_NO_XCD_REMAP) {
+    a.xcd_per = 0;
+    grid = Tl.nitems;
+  } else {
+    a.xcd_per = (Tl.nitems + 7) / 8;
+    grid = a.xcd_per * 8;
+  }
+  void* kargs[] = {&a};
+  hipError_t e =
+      hipLaunchKernel(k, dim3((unsigned)grid), dim3(P->tile.threads), kargs, shmem, stream);
+  if (e != hipSuccess) return hip_error(P, e);
+  return SPINSUM_OK;
+}
+
+spinsum_status pack_impl(spinsum_plan_s* P, const void* full, void* packed, bool pack,
+                         void* stream) {
+  if (P == nullptr || P->batched) return SPINSUM_ERR_INVALID_ARG;
+  if (!P->has_dev) return SPINSUM_ERR_NO_DEVICE;
+  if (P->pair) return SPINSUM_ERR_UNSUPPORTED;
+  if (P->elems == 0) return check_device(P);
+  if (full == nullptr || packed == nullptr) return SPINSUM_ERR_INVALID_ARG;
+  const int esz = elem_size(*P);
+  if ((((uintptr_t)full) & 15u) || (((uintptr_t)packed) & (uintptr_t)(esz - 1)))
+    return SPINSUM_ERR_MISALIGNED;
+  const int64_t ncomb = ncomb_of(P->n, P->d);
+  if (ncomb < 0 || P->n >= (1 << 16)) return SPINSUM_ERR_UNSUPPORTED;
+  const uintptr_t fbytes = (uintptr_t)P->elems * (uintptr_t)esz;
+  const uintptr_t pbytes = (uintptr_t)(P->ncubes * ncomb * P->inner) * (uintptr_t)esz;
+  const uintptr_t f = (uintptr_t)full, q = (uintptr_t)packed;
+  if (pbytes > 0 && f < q + pbytes && q < f + fbytes) return SPINSUM_ERR_ALIASING;
+  spinsum_status st = check_device(P);
+  if (st != SPINSUM_OK) return st;
+  // the tiles of the whole group, in the direct-LDS layout
+  const Tiling& Tl = P->T;
+  const bool whole = Tl.g.bl == Tl.g.n;
+  const bool rows = Tl.vw * esz == 16;
+  if (P->tile.lds_pad != 0 || !(whole || rows)) return SPINSUM_ERR_UNSUPPORTED;
+  if (P->dtype == SPINSUM_F32) return launch_pack<float>(P, full, packed, pack, (hipStream_t)stream);
+  return launch_pack<double>(P, full, packed, pack, (hipStream_t)stream);
+}
+
+}  // namespace
+}  // namespace spinsum
+
+extern "C" spinsum_status spinsum_unpack(spinsum_plan_t P, const void* packed, void* full,
+                                         void* stream) {
+  return pack_impl(P, full, const_cast<void*>(packed), false, stream);
+}
+
+extern "C" spinsum_status spinsum_pack(spinsum_plan_t P, const void* full, void* packed,
+                                       void* stream) {
+  return pack_impl(P, full, packed, true, stream);
 }
 
 extern "C" spinsum_status spinsum_exec_batched(spinsum_plan_t P, const void* const* in,

@@ -12,4 +12,6 @@ const void* pick_batched_f32_d3(int vw, bool persist) { return batched_kernel<fl
 
 const void* pick_cgrad_f32_d3() { return cgrad_kernel<float, 3>(); }
 
+const void* pick_pack_f32_d3(bool pack, bool nts) { return pack_kernel<float, 3>(pack, nts); }
+
 }  // namespace spinsum

@@ -12,4 +12,6 @@ const void* pick_batched_f64_d4(int vw, bool persist) { return batched_kernel<do
 
 const void* pick_cgrad_f64_d4() { return cgrad_kernel<double, 4>(); }
 
+const void* pick_pack_f64_d4(bool pack, bool nts) { return pack_kernel<double, 4>(pack, nts); }
+
 }  // namespace spinsum

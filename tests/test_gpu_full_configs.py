@@ -143,6 +143,38 @@ def test_subgroup_slabs_inplace(form):
     check_cube_sums(x2, in_sums, expanded_sum(stages), 1e-12)
 
 
+def test_3d_v64_o32_unpack_and_pack():
+    """Antisymmetric unpacking of the v=64 o=32 slab (C(32, 3) = 4960 packed
+    values per cube into 32^3) and packing back, in the benchmark's
+    configuration: sampled cubes against the oracle (inputs regenerated on
+    the host); unpack then pack with the antisymmetriser gives 3! times the
+    packed values on every cube."""
+    shape = workloads.WORKLOADS["3d_v64_o32_slab"]["shape"]
+    A = [workloads.antisymmetrizer(3)]
+    p = ss.spinsum_plan(shape, 3, 3, A)
+    pshape = ss.packed_shape(p)
+    assert pshape == (64, 64, 8, 4960)
+    pk = workloads.uniform(pshape, 3200, device=DEV)
+    full = torch.empty(shape, dtype=torch.float64, device=DEV)
+    ss.spinsum_unpack(p, pk, full)
+    torch.cuda.synchronize()
+    f2 = full.view(-1, 32 ** 3)
+    worst = 0.0
+    for c in sample_cubes(f2.shape[0], 24, 5):
+        pc = workloads.uniform_numpy(4960, 3200, offset=c * 4960).reshape(1, 4960)
+        ref = oracle.unpack(pc, (1, 32, 32, 32), A, 1, 3)
+        got = f2[c].cpu().numpy().reshape(ref.shape)
+        worst = max(worst, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+    _say(f"  unpack: worst normwise error {worst:.3e}")
+    assert worst <= 1e-14
+    back = torch.empty_like(pk)
+    ss.spinsum_pack(p, full, back)
+    torch.cuda.synchronize()
+    err = float((back - 6.0 * pk).abs().max() / (6.0 * pk).abs().max())
+    _say(f"  pack(unpack(p)) = 6 p: normwise error {err:.3e}")
+    assert err <= 1e-14
+
+
 def test_3d_inner_run8_inplace():
     """The slab with its group moved in front of an inner spectator run of
     8: [64, 64, 32, 32, 32, 8], group dims 2..4, in place (the bench line)."""

@@ -1,0 +1,137 @@
+"""Unpacking and packing on an MI355X against the oracle (oracle.unpack /
+oracle.pack: the embedding of the strictly increasing entries followed by
+the chain, and its adjoint).
+
+Bars: FP64 normwise 1e-14, FP32 2e-6 (against the oracle on the FP32-rounded
+input), integer-valued inputs bit for bit, Inf/NaN patterns exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+ss = pytest.importorskip("paper_1705_06661_amd")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+DEV = torch.device("cuda:0")
+TOL = {torch.float64: 1e-14, torch.float32: 2e-6}
+
+
+def nerr(got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = np.max(np.abs(ref))
+    return float(np.max(np.abs(got - ref)) / scale) if scale > 0 else float(np.max(np.abs(got)))
+
+
+OPS = {
+    "antisym3": (3, [workloads.antisymmetrizer(3)]),
+    "identity3": (3, [[((0, 1, 2), 1.0)]]),
+    "config3": (3, [workloads.CONFIG_3D_ALPHA]),
+    "antisym4": (4, [workloads.antisymmetrizer(4)]),
+    "random4": (4, [workloads.random_4d_alpha(7)]),
+    "antisym2": (2, [workloads.antisymmetrizer(2)]),
+}
+SHAPES = {2: [((3, 33, 33), None), ((4, 16, 16), (8, 1))],
+          3: [((3, 12, 12, 12), None), ((2, 16, 16, 16), (4, 1)), ((2, 14, 14, 14), (4, 1)),
+              ((2, 8, 8, 8, 3), None)],
+          4: [((2, 6, 6, 6, 6), None), ((1, 12, 12, 12, 12), (4, 1)), ((1, 10, 10, 10, 10), (4, 1))]}
+
+
+def packed_shape(shape, d):
+    return (shape[0], math.comb(shape[1], d)) + tuple(shape[1 + d:])
+
+
+@pytest.mark.parametrize("op", list(OPS))
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_unpack_and_pack_against_oracle(op, dtype):
+    d, stages = OPS[op]
+    for shape, tile in SHAPES[d]:
+        print(op, dtype, shape, tile, flush=True)
+        p = ss.spinsum_plan(shape, 1, d, stages, dtype=dtype)
+        if tile is not None:
+            ss.spinsum_plan_set_tile(p, *tile)
+        pk = workloads.uniform(packed_shape(shape, d), 2600 + d, device=DEV, dtype=dtype)
+        full = torch.full(shape, float("nan"), dtype=dtype, device=DEV)
+        info = ss.spinsum_plan_get_info(p)
+        if info["variant"] != ss.SPINSUM_VARIANT_DIRECT_LDS:
+            # tile rows that are not whole 16-byte chunks (FP32 rows of 14):
+            # unpacking needs the direct-LDS layout
+            with pytest.raises(ss.SpinSumError) as e:
+                ss.spinsum_unpack(p, pk, full)
+            assert e.value.status == ss.SPINSUM_ERR_UNSUPPORTED
+            continue
+        ss.spinsum_unpack(p, pk, full)
+        torch.cuda.synchronize()
+        ref = oracle.unpack(pk.cpu().to(torch.float64).numpy(), shape, stages, 1, d)
+        assert nerr(full.cpu().numpy(), ref) <= TOL[dtype], (shape, tile)
+        f = workloads.uniform(shape, 2700 + d, device=DEV, dtype=dtype)
+        out = torch.full(packed_shape(shape, d), float("nan"), dtype=dtype, device=DEV)
+        ss.spinsum_pack(p, f, out)
+        torch.cuda.synchronize()
+        refp = oracle.pack(f.cpu().to(torch.float64).numpy(), stages, 1, d)
+        assert nerr(out.cpu().numpy(), refp) <= TOL[dtype], (shape, tile)
+        # integer-valued inputs: exact
+        pki = workloads.integers(packed_shape(shape, d), 2800 + d, device=DEV, dtype=dtype)
+        ss.spinsum_unpack(p, pki, full)
+        fi = workloads.integers(shape, 2900 + d, device=DEV, dtype=dtype)
+        ss.spinsum_pack(p, fi, out)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(
+            full.cpu().to(torch.float64).numpy(),
+            oracle.unpack(pki.cpu().to(torch.float64).numpy(), shape, stages, 1, d))
+        np.testing.assert_array_equal(
+            out.cpu().to(torch.float64).numpy(),
+            oracle.pack(fi.cpu().to(torch.float64).numpy(), stages, 1, d))
+
+
+def test_antisymmetric_round_trip_and_packed_shape_helper():
+    """X antisymmetric: packing with the identity gathers its increasing
+    entries and unpacking them with the antisymmetriser rebuilds X."""
+    d, n = 3, 11
+    shape = (4, n, n, n)
+    y = workloads.uniform(shape, 3000, device=DEV)
+    A = ss.spinsum_plan(shape, 1, d, [workloads.antisymmetrizer(d)])
+    x = torch.empty_like(y)
+    ss.spinsum_exec(A, y, x)
+    x /= math.factorial(d)
+    I = ss.spinsum_plan(shape, 1, d, [[((0, 1, 2), 1.0)]])
+    assert ss.packed_shape(I) == packed_shape(shape, d)
+    pk = torch.empty(ss.packed_shape(I), dtype=torch.float64, device=DEV)
+    ss.spinsum_pack(I, x, pk)
+    back = torch.empty_like(x)
+    ss.spinsum_unpack(A, pk, back)
+    torch.cuda.synchronize()
+    assert nerr(back.cpu().numpy(), x.cpu().numpy()) <= 1e-14
+
+
+def test_unpack_non_finite_and_errors():
+    d, stages = OPS["antisym3"]
+    shape = (2, 9, 9, 9)
+    pkh = workloads.uniform(packed_shape(shape, d), 3100).numpy()
+    pkh[0, 5] = np.inf
+    pkh[1, 17] = np.nan
+    ref = oracle.unpack(pkh, shape, stages, 1, d)
+    p = ss.spinsum_plan(shape, 1, d, stages)
+    full = torch.empty(shape, dtype=torch.float64, device=DEV)
+    ss.spinsum_unpack(p, torch.from_numpy(pkh).to(DEV), full)
+    torch.cuda.synchronize()
+    got = full.cpu().numpy()
+    np.testing.assert_array_equal(np.isnan(got), np.isnan(ref))
+    np.testing.assert_array_equal(np.isposinf(got), np.isposinf(ref))
+    np.testing.assert_array_equal(np.isneginf(got), np.isneginf(ref))
+    fin = np.isfinite(ref)
+    assert nerr(got[fin], ref[fin]) <= 1e-14
+    big = torch.empty(full.numel() * 2, dtype=torch.float64, device=DEV)
+    st = ss._c_unpack(p._h, big.data_ptr() + 8, big.data_ptr(), None)
+    assert st == ss.SPINSUM_ERR_ALIASING
+    pp = ss.spinsum_plan((2, 3, 3, 3, 4, 4, 4), 4, 3, stages, flags=ss.SPINSUM_FLAG_INDEX_PAIRS)
+    st = ss._c_unpack(pp._h, big.data_ptr(), big.data_ptr() + 8 * 4096, None)
+    assert st == ss.SPINSUM_ERR_UNSUPPORTED

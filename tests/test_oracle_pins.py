@@ -279,6 +279,56 @@ def test_coef_grad_stages_definition(case):
             assert abs(dense - got[k, r]) <= 1e-12 * max(1.0, abs(dense))
 
 
+def test_unpack_worked_example():
+    """N = 3, d = 2, the antisymmetriser: packed (a01, a02, a12) unpacks to
+    [[0, a01, a02], [-a01, 0, a12], [-a02, -a12, 0]] (by hand, Def. 2)."""
+    a01, a02, a12 = 1.5, -2.0, 7.0
+    got = oracle.unpack(np.array([[a01, a02, a12]]), (1, 3, 3), [workloads.antisymmetrizer(2)], 1, 2)
+    want = np.array([[[0.0, a01, a02], [-a01, 0.0, a12], [-a02, -a12, 0.0]]])
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("d,n", [(2, 5), (3, 5), (4, 5)])
+def test_unpack_pack_antisymmetric(d, n):
+    """An antisymmetric tensor X (A(Y)/d! of a random Y) is fixed by A/d! and
+    is rebuilt by unpacking its strictly increasing entries with A; packing
+    with A gives d! times those entries (A is self-adjoint and A X = d! X);
+    unpacking gives an antisymmetric tensor with zero diagonals; and pack is
+    the transpose of unpack (<U p, f> = <p, P f>)."""
+    A = [workloads.antisymmetrizer(d)]
+    shape = (2,) + (n,) * d
+    y = _rand(shape, 90 + d)
+    x = oracle.spinsum(y, A[0], 1, d) / math.factorial(d)
+    np.testing.assert_allclose(oracle.spinsum(x, A[0], 1, d) / math.factorial(d), x, atol=1e-14)
+    tuples = oracle.increasing_tuples(n, d)
+    assert len(tuples) == math.comb(n, d)
+    gathered = np.stack([x[(slice(None),) + t] for t in tuples], axis=1)
+    np.testing.assert_allclose(oracle.unpack(gathered, shape, A, 1, d), x, atol=1e-14)
+    np.testing.assert_allclose(oracle.pack(x, A, 1, d), math.factorial(d) * gathered, atol=1e-13)
+    p = _rand((2, len(tuples)), 95 + d)
+    u = oracle.unpack(p, shape, A, 1, d)
+    for perm in itertools.permutations(range(d)):
+        if _sign(perm) < 0:
+            np.testing.assert_allclose(np.transpose(u, (0,) + tuple(1 + q for q in perm)), -u,
+                                       atol=1e-14)
+    f = _rand(shape, 99 + d)
+    lhs = float(np.sum(u * f))
+    rhs = float(np.sum(p * oracle.pack(f, A, 1, d)))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_unpack_with_identity_is_the_embedding():
+    """With the identity operator unpacking only places the packed values
+    (dense matrix of E checked element by element) and packing gathers."""
+    shape = (2, 4, 4, 4, 3)
+    p = _rand((2, math.comb(4, 3), 3), 101)
+    u = oracle.unpack(p, shape, [[((0, 1, 2), 1.0)]], 1, 3)
+    for r, t in enumerate(itertools.combinations(range(4), 3)):
+        np.testing.assert_array_equal(u[(slice(None),) + t], p[:, r])
+    assert np.count_nonzero(u) == p.size
+    np.testing.assert_array_equal(oracle.pack(u, [[((0, 1, 2), 1.0)]], 1, 3), p)
+
+
 def test_factored_pij_pjk_closed_form():
     """(2 - P_ij)(2 - P_jk) on A[i,j,k] = 100i + 10j + k.
     By hand from Def. 2: T = 2A - A[i,k,j] = 100i + 19j - 8k, then
