@@ -16,6 +16,7 @@ adjoint, and FP32 storage.  ``cpu_baseline`` is the CPU oracle timed on a
 bounded sample of the headline workload.
 
     python bench.py [--steps K] [--warmup W] [--forms all|none] [--no-cpu-baseline]
+    python bench.py --profile FORM [--steps K] [--warmup W]   (one form alone)
 """
 from __future__ import annotations
 
@@ -48,10 +49,11 @@ def kernel_source_hash() -> str:
 
 
 def traffic_from_profile(name: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary
-    (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy's reading), or
-    None when the counters were taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"{name}.traffic.txt")
+    """HBM bytes per launch of the form `name` (one of PROFILE_FORMS) from
+    its committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each
+    scaled by a plain copy's reading), or None when the counters were taken
+    on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"spinsum_{name}.traffic.txt")
     if not os.path.exists(path):
         return None
     rec = {}
@@ -69,17 +71,21 @@ def traffic_from_profile(name: str):
         return None
 
 
-def kernel_name(info, dtype="double"):
+def kernel_name(info, dtype="double", chain=False):
     """Name of the device kernel a plan launches, as rocprofv3 lists it."""
-    d = info["d"]
+    d = info["exec_d"] or info["d"]
     v = info["variant"]
+    c = "true" if chain else "false"
+    nts = "true" if info["nt_stores"] else "false"
+    if info["pair_extent"] > 0:
+        return f"k_pair<{dtype}, {d}, {c}, {nts}>"
     if v == 1:
-        return f"k_lds<{dtype}, {d}, false, true>"
+        return f"k_lds<{dtype}, {d}, {c}, {nts}>"
     if v == 4:
-        return f"k_ldsp<{dtype}, {d}, false, true>"
+        return f"k_ldsp<{dtype}, {d}, {c}, {nts}>"
     if v == 2:
-        return f"k_pipe<{dtype}, {d}, {info['vector_width']}, false, *>"
-    return f"k_exec<{dtype}, {d}, {info['vector_width']}, false, true>"
+        return f"k_pipe<{dtype}, {d}, {info['vector_width']}, {c}, *>"
+    return f"k_exec<{dtype}, {d}, {info['vector_width']}, {c}, {nts}>"
 
 
 def warm(fn, seconds=0.25, refill=None):
@@ -344,6 +350,77 @@ def accuracy_report(ss, workloads, dev, stream):
     return rep
 
 
+PROFILE_FORMS = ("3d_v64_o32_inplace", "4d_v24_o12_inplace", "4d_table2_5_80_premultiplied",
+                 "3d_pairs_v48_o24_inplace", "3d_v48_o24_forward_fp64", "3d_coef_grad",
+                 "stream_copy")
+
+
+def profile_one(name, steps, warmup):
+    """One form alone, for a profiler run: its input is filled, then
+    `warmup` untimed and `steps` timed launches follow, and one JSON line
+    gives the average launch time.  Nothing else touches the GPU, so the
+    counters of every spin-summation dispatch belong to this form."""
+    import torch
+    import workloads
+    import paper_1705_06661_amd as ss
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    alpha = [workloads.CONFIG_3D_ALPHA]
+    slab = workloads.WORKLOADS["3d_v64_o32_slab"]["shape"]
+    if name in ("3d_v64_o32_inplace", "3d_coef_grad", "stream_copy"):
+        x = workloads.uniform(slab, 1000, device=dev)
+        y = workloads.uniform(slab, 1001, device=dev) if name != "3d_v64_o32_inplace" else x
+        p = ss.spinsum_plan(slab, 3, 3, alpha, inplace=True)
+        if name == "3d_coef_grad":
+            fn = lambda: ss.spinsum_coef_grad(p, x, y, stream)
+        elif name == "stream_copy":
+            fn = lambda: ss.spinsum_stream_copy(x, y, stream)
+        else:
+            fn = lambda: ss.spinsum_exec(p, x, x, stream)
+        nbytes = 2 * x.numel() * 8
+    elif name == "4d_v24_o12_inplace":
+        w4 = workloads.WORKLOADS["4d_v24_o12_slab"]
+        x = workloads.uniform(w4["shape"], 2000, device=dev)
+        p = ss.spinsum_plan(w4["shape"], 4, 4, [workloads.random_4d_alpha(7)], inplace=True)
+        fn = lambda: ss.spinsum_exec(p, x, x, stream)
+        nbytes = 2 * x.numel() * 8
+    elif name == "4d_table2_5_80_premultiplied":
+        x = workloads.uniform((80,) * 4, 5005, device=dev)
+        p = ss.spinsum_plan(x.shape, 0, 4, workloads.table2_case(5)[1], inplace=True)
+        fn = lambda: ss.spinsum_exec(p, x, x, stream)
+        nbytes = 2 * x.numel() * 8
+    elif name == "3d_pairs_v48_o24_inplace":
+        w5 = workloads.WORKLOADS["3d_v48_o24"]
+        x = workloads.uniform(w5["shape"], 5100, device=dev)
+        p = ss.spinsum_plan(w5["shape"], 3, 3, alpha, inplace=True,
+                            flags=ss.SPINSUM_FLAG_INDEX_PAIRS)
+        fn = lambda: ss.spinsum_exec(p, x, x, stream)
+        nbytes = 2 * x.numel() * 8
+    elif name == "3d_v48_o24_forward_fp64":
+        w5 = workloads.WORKLOADS["3d_v48_o24"]
+        x = workloads.uniform(w5["shape"], 4000, device=dev)
+        y = torch.empty_like(x)
+        p = ss.spinsum_plan(w5["shape"], 3, 3, workloads.FACTORED_PIJ_PJK, inplace=False)
+        fn = lambda: ss.spinsum_exec(p, x, y, stream)
+        nbytes = 2 * x.numel() * 8
+    else:
+        raise SystemExit(f"unknown form {name!r}; one of {', '.join(PROFILE_FORMS)}")
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        fn()
+    ms = timed(fn, steps, stream)
+    info = ss.spinsum_plan_get_info(p)
+    print(json.dumps({"form": name, "launches": warmup + steps, "avg_launch_ms": round(ms, 4),
+                      "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                      "algorithmic_bytes_per_launch": nbytes,
+                      "kernel": {"stream_copy": "k_copy", "3d_coef_grad": "k_cgrad<double, 3>"}.get(
+                          name, kernel_name(info)),
+                      "tile_edge": info["bl"],
+                      "kernel_source_hash": kernel_source_hash()}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -353,12 +430,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--slabs", type=int, default=8)
+    ap.add_argument("--profile", choices=PROFILE_FORMS, default=None,
+                    help="run one form alone (for rocprofv3) and print its launch time")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the spin summation shards over spectator "
               "slabs with no communication, and no multi-GPU path is implemented.",
               file=sys.stderr)
         sys.exit(2)
+    if args.profile is not None:
+        profile_one(args.profile, args.steps, args.warmup)
+        return
 
     import torch
     import workloads
@@ -417,7 +499,7 @@ def main():
                    "work_items_per_cube": info["items_per_cube"], "tiles_per_item": info["item_tiles"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_GBPS, 4),
-                     "traffic": traffic_from_profile("spinsum_3d_v64_o32_inplace"),
+                     "traffic": traffic_from_profile("3d_v64_o32_inplace"),
                      "single_launch_ms_min": round(singles[0], 4),
                      "single_launch_ms_median": round(singles[len(singles) // 2], 4),
                      "kernel": kernel_name(info),
@@ -463,6 +545,7 @@ def main():
         warm(lambda: ss.spinsum_coef_grad(plan, big[0], big[1], stream))
         cg = timed(lambda: ss.spinsum_coef_grad(plan, big[0], big[1], stream), 5, stream)
         forms["3d_coef_grad"] = form_entry(2 * big[0].numel() * 8, cg, value)
+        forms["3d_coef_grad"]["traffic"] = traffic_from_profile("3d_coef_grad")
         # antisymmetrisation (every permutation weighted by its sign), slab 0
         pa = ss.spinsum_plan(slab_shape, 3, 3, [workloads.antisymmetrizer(3)], inplace=True)
         workloads.fill_uniform(big[0], 1000)
@@ -519,6 +602,8 @@ def main():
                  refill=lambda: workloads.fill_uniform(x80, 5005))
             tms = timed(lambda: ss.spinsum_exec(pt, x80, x80, stream), 5, stream)
             forms[name] = form_entry(2 * x80.numel() * 8, tms, value)
+            if name == "4d_table2_5_80_premultiplied":
+                forms[name]["traffic"] = traffic_from_profile(name)
         del x80
         torch.cuda.empty_cache()
 
@@ -534,6 +619,7 @@ def main():
         forms["4d_v24_o12_inplace"] = form_entry(2 * x4.numel() * 8, ms4, value)
         forms["4d_v24_o12_inplace"]["tile_edge"] = ss.spinsum_plan_get_info(p4)["bl"]
         forms["4d_v24_o12_inplace"]["alpha_seed"] = 7
+        forms["4d_v24_o12_inplace"]["traffic"] = traffic_from_profile("4d_v24_o12_inplace")
         # 2 - pi_2134 moves two of the four axes: the subgroup plan against S_4
         half = [[((0, 1, 2, 3), 2.0), (workloads.P("2134"), -1.0)]]
         for name, flags in [("4d_2_minus_p2134_subgroup", 0),
@@ -607,6 +693,7 @@ def main():
         pms_ = timed(lambda: ss.spinsum_exec(pp, xp, xp, stream), 5, stream)
         forms["3d_pairs_v48_o24_inplace"] = form_entry(2 * xp.numel() * 8, pms_, value)
         forms["3d_pairs_v48_o24_inplace"]["tile_edge"] = ss.spinsum_plan_get_info(pp)["bl"]
+        forms["3d_pairs_v48_o24_inplace"]["traffic"] = traffic_from_profile("3d_pairs_v48_o24_inplace")
         del xp
         torch.cuda.empty_cache()
 
@@ -625,6 +712,9 @@ def main():
             nb = 2 * x5.numel() * x5.element_size()
             forms[f"3d_v48_o24_forward_{tag}"] = form_entry(nb, fwd, value)
             forms[f"3d_v48_o24_adjoint_{tag}"] = form_entry(nb, bwd, value)
+            if tag == "fp64":
+                forms["3d_v48_o24_forward_fp64"]["traffic"] = traffic_from_profile(
+                    "3d_v48_o24_forward_fp64")
             del x5, y5
             torch.cuda.empty_cache()
         accuracy = accuracy_report(ss, workloads, dev, stream)
