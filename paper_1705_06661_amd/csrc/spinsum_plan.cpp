@@ -139,6 +139,70 @@ static int64_t tile_lds_bytes(const spinsum_plan_s& P, int n, int bl, int cpw, i
   return (int64_t)tiles * ts * elem_size(P) + ipow(bl, P.d) * 4;
 }
 
+// LDS bank cost of a representative list: the combine step gives the
+// representatives to the lanes of a wave in list order (64 per wave), and
+// each lane reads and writes element sigma . l of every tile slot sigma,
+// at LDS word offset sum_m l[p_sigma(m)] * lst[m] (the slot base is uniform
+// across the wave).  The cost sums, over waves and permutations, the largest
+// number of distinct 4-byte words that fall in one bank (64 banks, and 32
+// as a second model).  The tile slot base adds the same offset to every lane,
+// so it does not change the count.
+static int64_t rep_bank_cost(const uint32_t* reps, size_t cnt, const SymGroup& G,
+                             const int32_t* lst, int esz) {
+  const int d = G.d;
+  const int words = esz / 4;
+  int64_t cost = 0;
+  std::vector<uint32_t> w;
+  for (size_t g0 = 0; g0 < cnt; g0 += 64) {
+    const size_t g1 = std::min(cnt, g0 + 64);
+    for (int r = 0; r < G.df; ++r) {
+      w.clear();
+      for (size_t i = g0; i < g1; ++i) {
+        int64_t a = 0;
+        for (int m = 0; m < d; ++m) a += (int64_t)((reps[i] >> (8 * G.p[r][m])) & 255u) * lst[m];
+        for (int k = 0; k < words; ++k) w.push_back((uint32_t)(a * words + k));
+      }
+      std::sort(w.begin(), w.end());
+      w.erase(std::unique(w.begin(), w.end()), w.end());
+      for (int banks : {64, 32}) {
+        int hist[64] = {0};
+        int worst = 0;
+        for (uint32_t x : w) worst = std::max(worst, ++hist[x % banks]);
+        cost += worst;
+      }
+    }
+  }
+  return cost;
+}
+
+// Order the representative list reps[off, end) for the LDS banks.  In
+// lexicographic order the 64 lanes of a wave share their leading
+// coordinates, so the tile slots that move the fastest axis to a slow one
+// make them read words a power of two apart (one 3D 8^3 tile: up to 16
+// lanes per bank).  Sorting by the diagonal class (l[d-1] - sum of the
+// other coordinates) mod e gives each wave a Latin set instead: for a
+// generic list with e^(d-1) = 64, every slot spreads the wave over the
+// banks (2 words per bank, the least for 64 lanes of 8 bytes).  The
+// order is kept only where the bank cost above drops; every element
+// orbit is still combined exactly as before, so results do not change.
+static void order_reps_for_banks(std::vector<uint32_t>& reps, size_t off, const SymGroup& G,
+                                 const int32_t* lst, int esz, int e) {
+  const int d = G.d;
+  const size_t cnt = reps.size() - off;
+  if (cnt <= 1 || e <= 1) return;
+  std::vector<uint32_t> alt(reps.begin() + off, reps.end());
+  auto cls = [&](uint32_t pk) {
+    int c = (int)((pk >> (8 * (d - 1))) & 255u);
+    for (int m = 0; m + 1 < d; ++m) c -= (int)((pk >> (8 * m)) & 255u);
+    return ((c % e) + e) % e;
+  };
+  std::stable_sort(alt.begin(), alt.end(),
+                   [&](uint32_t x, uint32_t y) { return cls(x) < cls(y); });
+  if (rep_bank_cost(alt.data(), cnt, G, lst, esz) <
+      rep_bank_cost(reps.data() + off, cnt, G, lst, esz))
+    std::copy(alt.begin(), alt.end(), reps.begin() + off);
+}
+
 // Default tile (measured on MI355X; spinsum_autotune searches more).
 //  1. Cubes up to 64 KiB are processed whole, several per workgroup up to
 //     about 8 KiB, as one contiguous copy (any extent).
@@ -338,6 +402,7 @@ spinsum_status build_tiling(const spinsum_plan_s& P, int n, int64_t ncubes,
         for (int m = 0; m < d; ++m) pk |= (uint32_t)l[m] << (8 * m);
         T.reps.push_back(pk);
       }
+      if (inner == 1) order_reps_for_banks(T.reps, (size_t)off, G, g.lst, elem_size(P), bl);
       ri = rep_index.emplace(key, std::make_pair(off, (int)T.reps.size() - off)).first;
     }
     oh.rep_off = ri->second.first;
@@ -367,10 +432,21 @@ spinsum_status build_tiling(const spinsum_plan_s& P, int n, int64_t ncubes,
                       ? (int)(line / row)
                       : 1;
     if (s > 1) {
+      // Within a line-block tuple, the offsets B[m] mod s follow Morton
+      // order (their bits interleaved across the axes, high bits first).
+      // Two orbits whose tiles share a line differ in one offset; where
+      // they share a 64-byte half line they differ in its lowest bit, and
+      // are then at most 2^(d-1) positions apart (s^(d-1) in loop-nest
+      // order).
+      int sbits = 0;
+      while ((1 << sbits) < s) ++sbits;
       auto key = [&](const OrbitHost& o) {
-        std::vector<int> k(d);
+        std::vector<int> k(d + 1);
         for (int m = 0; m < d; ++m) k[m] = o.B[m] / s;
-        std::sort(k.begin(), k.end());
+        int z = 0;
+        for (int b = sbits - 1; b >= 0; --b)
+          for (int m = 0; m < d; ++m) z = (z << 1) | (((o.B[m] % s) >> b) & 1);
+        k[d] = z;
         return k;
       };
       std::stable_sort(T.orbits.begin(), T.orbits.end(),
@@ -847,6 +923,7 @@ static spinsum_status build_pair_tiling(spinsum_plan_s* P, const spinsum_tile_t&
         for (int m = 0; m < d; ++m) pk |= (uint32_t)l[m] << (8 * m);
         T.reps.push_back(pk);
       }
+      if (inner == 1) order_reps_for_banks(T.reps, (size_t)pg.rep_off[key], P->G, g.lst, esz, bl);
     }
     pg.rep_cnt[key] = (int32_t)T.reps.size() - pg.rep_off[key];
     T.max_rep_cnt = std::max(T.max_rep_cnt, pg.rep_cnt[key]);
