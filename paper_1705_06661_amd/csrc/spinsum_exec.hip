@@ -613,7 +613,10 @@ spinsum_status launch_pack(spinsum_plan_s* P, const void* full, void* packed, bo
     a.packed_in = reinterpret_cast<const T*>(packed);
   }
   a.orbits = reinterpret_cast<const GroupDev*>(P->d_orbits);
-  a.reps = reinterpret_cast<const uint32_t*>(P->d_reps);
+  // packing writes one packed value per representative: in lexicographic
+  // order the lanes of a wave write neighbouring entries (unpacking reads
+  // them, and gains more from the bank-spreading order of its LDS scatter)
+  a.reps = reinterpret_cast<const uint32_t*>(pack && P->d_reps_lex ? P->d_reps_lex : P->d_reps);
   a.coef = reinterpret_cast<const T*>(P->d_mats);  // the pre-multiplied forward vector
   a.g = Tl.g;
   a.nitems = Tl.nitems;

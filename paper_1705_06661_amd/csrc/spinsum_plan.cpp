@@ -185,11 +185,11 @@ static int64_t rep_bank_cost(const uint32_t* reps, size_t cnt, const SymGroup& G
 // banks (2 words per bank, the least for 64 lanes of 8 bytes).  The
 // order is kept only where the bank cost above drops; every element
 // orbit is still combined exactly as before, so results do not change.
-static void order_reps_for_banks(std::vector<uint32_t>& reps, size_t off, const SymGroup& G,
+static bool order_reps_for_banks(std::vector<uint32_t>& reps, size_t off, const SymGroup& G,
                                  const int32_t* lst, int esz, int e) {
   const int d = G.d;
   const size_t cnt = reps.size() - off;
-  if (cnt <= 1 || e <= 1) return;
+  if (cnt <= 1 || e <= 1) return false;
   std::vector<uint32_t> alt(reps.begin() + off, reps.end());
   auto cls = [&](uint32_t pk) {
     int c = (int)((pk >> (8 * (d - 1))) & 255u);
@@ -198,9 +198,11 @@ static void order_reps_for_banks(std::vector<uint32_t>& reps, size_t off, const 
   };
   std::stable_sort(alt.begin(), alt.end(),
                    [&](uint32_t x, uint32_t y) { return cls(x) < cls(y); });
-  if (rep_bank_cost(alt.data(), cnt, G, lst, esz) <
+  if (rep_bank_cost(alt.data(), cnt, G, lst, esz) >=
       rep_bank_cost(reps.data() + off, cnt, G, lst, esz))
-    std::copy(alt.begin(), alt.end(), reps.begin() + off);
+    return false;
+  std::copy(alt.begin(), alt.end(), reps.begin() + off);
+  return true;
 }
 
 // Default tile (measured on MI355X; spinsum_autotune searches more).
@@ -345,6 +347,7 @@ spinsum_status build_tiling(const spinsum_plan_s& P, int n, int64_t ncubes,
 
   // 1. tile orbits: one per sorted block tuple B (the loop nest of Alg. 5a)
   std::map<std::vector<int>, std::pair<int, int>> rep_index;  // shared representative lists
+  bool reordered = false;
   std::vector<int> B(d, 0);
   while (true) {
     OrbitHost oh;
@@ -402,7 +405,9 @@ spinsum_status build_tiling(const spinsum_plan_s& P, int n, int64_t ncubes,
         for (int m = 0; m < d; ++m) pk |= (uint32_t)l[m] << (8 * m);
         T.reps.push_back(pk);
       }
-      if (inner == 1) order_reps_for_banks(T.reps, (size_t)off, G, g.lst, elem_size(P), bl);
+      T.reps_lex.insert(T.reps_lex.end(), T.reps.begin() + off, T.reps.end());
+      if (inner == 1 && order_reps_for_banks(T.reps, (size_t)off, G, g.lst, elem_size(P), bl))
+        reordered = true;
       ri = rep_index.emplace(key, std::make_pair(off, (int)T.reps.size() - off)).first;
     }
     oh.rep_off = ri->second.first;
@@ -453,6 +458,8 @@ spinsum_status build_tiling(const spinsum_plan_s& P, int n, int64_t ncubes,
                        [&](const OrbitHost& a, const OrbitHost& b) { return key(a) < key(b); });
     }
   }
+
+  if (!reordered) T.reps_lex.clear();
 
   // 2. work items: one tile orbit each (item_tiles 0), or runs of
   //    consecutive orbits of the order above (next fit), holding at most
@@ -532,8 +539,9 @@ static spinsum_status hip_fail(spinsum_plan_s* P, hipError_t e) {
 }
 
 void free_device(spinsum_plan_s* P) {
-  void** ptrs[] = {&P->d_orbits,    &P->d_reps,        &P->d_mats,     &P->d_blocks,
-                   &P->d_items,     &P->d_grad_part,   &P->d_cg_orbits, &P->d_cg_reps};
+  void** ptrs[] = {&P->d_orbits,    &P->d_reps,        &P->d_mats,      &P->d_blocks,
+                   &P->d_items,     &P->d_grad_part,   &P->d_cg_orbits, &P->d_cg_reps,
+                   &P->d_reps_lex};
   for (void** p : ptrs) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
@@ -616,6 +624,10 @@ spinsum_status upload_tables(spinsum_plan_s* P) {
     if (st != SPINSUM_OK) return st;
     st = upload(P, &P->d_reps, P->T.reps.data(), P->T.reps.size());
     if (st != SPINSUM_OK) return st;
+    if (!P->T.reps_lex.empty()) {
+      st = upload(P, &P->d_reps_lex, P->T.reps_lex.data(), P->T.reps_lex.size());
+      if (st != SPINSUM_OK) return st;
+    }
     std::vector<double> part((size_t)kGradSlots * P->G.df, 0.0);
     st = upload(P, &P->d_grad_part, part.data(), part.size());
     if (st != SPINSUM_OK) return st;

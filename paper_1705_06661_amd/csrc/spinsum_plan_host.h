@@ -49,6 +49,11 @@ struct Tiling {
   std::vector<OrbitHost> orbits;
   std::vector<GroupDev> groups;
   std::vector<uint32_t> reps;
+  // The same lists in lexicographic order where reps holds them in the
+  // bank-spreading order (empty when no list was reordered).  Packing writes
+  // one packed value per representative, and in this order the lanes of a
+  // wave write neighbouring packed entries.
+  std::vector<uint32_t> reps_lex;
 };
 
 }  // namespace spinsum
@@ -118,6 +123,7 @@ struct spinsum_plan_s {
   int lds_limit = spinsum::kMaxLdsBytes;
   void* d_orbits = nullptr;
   void* d_reps = nullptr;
+  void* d_reps_lex = nullptr;  // Tiling::reps_lex on the device, if any
   void* d_mats = nullptr;   // M | MT | SM | SMT in the storage type
   void* d_blocks = nullptr;
   void* d_items = nullptr;
