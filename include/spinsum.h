@@ -162,6 +162,9 @@ typedef struct {
                             operator's permutations move a smaller run of axes (see
                             spinsum_plan); the tiling fields above describe that group */
   int exec_group_first;  /* its first dim */
+  int persistent_per_cu; /* persistent kernel variants and persistent batched plans:
+                            workgroups launched per CU (the kernel's occupancy, taken
+                            when the tables are built); else 0 */
 } spinsum_plan_info_t;
 
 /* Create a plan for Out = S_K(...S_1(In)) (Def. 3-4; in-place: Sec. 4.6.5).

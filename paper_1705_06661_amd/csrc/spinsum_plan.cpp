@@ -1479,6 +1479,12 @@ extern "C" spinsum_status spinsum_plan_get_info(spinsum_plan_t P, spinsum_plan_i
   std::memset(info, 0, sizeof(*info));
   info->exec_d = P->d;
   info->exec_group_first = P->group_first;
+  const int v = P->tile.variant;
+  // (the register pipeline runs one-shot where the plan picked cached stores)
+  if ((P->batched && P->batch_persistent) ||
+      (!P->batched && !P->pair &&
+       ((v == SPINSUM_VARIANT_REG_PIPELINE && P->T.nts) || v == SPINSUM_VARIANT_LDS_PIPELINE)))
+    info->persistent_per_cu = P->occ_blocks;
   info->d = P->d;
   info->n = P->n;
   info->ncubes = P->ncubes;
