@@ -51,6 +51,7 @@ namespace {
 constexpr int kThreads = 256;     // workgroup size of every kernel but k_lds
 constexpr int kMaxThreads = 1024; // k_lds, k_ldsp: 256, 512 or 1024 (blockDim.x)
 constexpr int kUnroll = 4;
+constexpr int kUnpackBatch = 4;   // k_unpack: packed values requested together per thread
 
 template <int D>
 struct Fact {
@@ -1749,32 +1750,53 @@ __global__ void __launch_bounds__(kMaxThreads) k_unpack(const PackArgs<T> a) {
     const FastDiv fdr = load_fd(od->fd_rep[k]);
     const uint32_t* rp = reps + od->rep_base[k];
     const uint32_t nrep = (uint32_t)ncub * rep_cnt * (uint32_t)g.inner;
-    for (uint32_t i = threadIdx.x; i < nrep; i += blockDim.x) {
-      uint32_t ci, ri, si;
-      split_unit(g, i, rep_cnt, fdr, ncub, &ci, &ri, &si);
-      const uint32_t pk = rp[ri];
-      int l[D], X[D];
+    // kUnpackBatch units per thread at a time: their packed values are all
+    // requested before the first is used, so the gathers overlap
+    for (uint32_t i0 = 0; i0 < nrep; i0 += kUnpackBatch * blockDim.x) {
+      T v[kUnpackBatch];
+      bool strict[kUnpackBatch];
 #pragma unroll
-      for (int m = 0; m < D; ++m) {
-        l[m] = (int)((pk >> (8 * m)) & 255u);
-        X[m] = org[m] + l[m];
+      for (int u = 0; u < kUnpackBatch; ++u) {
+        const uint32_t i = i0 + threadIdx.x + u * blockDim.x;
+        v[u] = T(0);
+        strict[u] = false;
+        if (i < nrep) {
+          uint32_t ci, ri, si;
+          split_unit(g, i, rep_cnt, fdr, ncub, &ci, &ri, &si);
+          const uint32_t pk = rp[ri];
+          int X[D];
+#pragma unroll
+          for (int m = 0; m < D; ++m) X[m] = org[m] + (int)((pk >> (8 * m)) & 255u);
+          bool st = true;
+#pragma unroll
+          for (int m = 0; m + 1 < D; ++m) st = st && (X[m] < X[m + 1]);
+          strict[u] = st;
+          if (st) {
+            const int64_t r = increasing_rank<D>(X, g.n, a.ncomb);
+            v[u] = a.packed_in[((cube0 + (int64_t)ci) * a.ncomb + r) * g.inner + (int64_t)si];
+          }
+        }
       }
-      bool strict = true;
 #pragma unroll
-      for (int m = 0; m + 1 < D; ++m) strict = strict && (X[m] < X[m + 1]);
-      T v = T(0);
-      if (strict) {
-        const int64_t r = increasing_rank<D>(X, g.n, a.ncomb);
-        v = a.packed_in[((cube0 + (int64_t)ci) * a.ncomb + r) * g.inner + (int64_t)si];
-      }
-      int addr[DF];
-      orbit_addrs<D>(g, (int)ci * g.cube_lds + (int)si, sb, l, addr,
-                     std::make_integer_sequence<int, DF>{});
-      if (strict) {
-        unpack_rows<T, D>(co, v, lds, addr, std::make_integer_sequence<int, DF>{});
-      } else {
+      for (int u = 0; u < kUnpackBatch; ++u) {
+        const uint32_t i = i0 + threadIdx.x + u * blockDim.x;
+        if (i < nrep) {
+          uint32_t ci, ri, si;
+          split_unit(g, i, rep_cnt, fdr, ncub, &ci, &ri, &si);
+          const uint32_t pk = rp[ri];
+          int l[D];
 #pragma unroll
-        for (int r = 0; r < DF; ++r) lds[addr[r]] = T(0);
+          for (int m = 0; m < D; ++m) l[m] = (int)((pk >> (8 * m)) & 255u);
+          int addr[DF];
+          orbit_addrs<D>(g, (int)ci * g.cube_lds + (int)si, sb, l, addr,
+                         std::make_integer_sequence<int, DF>{});
+          if (strict[u]) {
+            unpack_rows<T, D>(co, v[u], lds, addr, std::make_integer_sequence<int, DF>{});
+          } else {
+#pragma unroll
+            for (int r = 0; r < DF; ++r) lds[addr[r]] = T(0);
+          }
+        }
       }
     }
   }
