@@ -801,6 +801,7 @@ def test_batched_autotune_and_persistent_launch(tmp_path, monkeypatch):
     monkeypatch.setenv("SPINSUM_AUTOTUNE_CACHE", str(forced))
     pp = ss.spinsum_plan_batched(shapes, 3, [workloads.CONFIG_3D_ALPHA], inplace=True)
     assert ss.spinsum_plan_get_info(pp)["batch_persistent"] == 1
+    assert ss.spinsum_plan_get_info(pp)["persistent_per_cu"] >= 1
     ys = [x.clone() for x in xs]
     ss.spinsum_exec_batched(pp, ys, ys)
     torch.cuda.synchronize()
@@ -861,3 +862,20 @@ def test_subgroup_reduction_against_oracle(case, dtype):
         cg = ss.spinsum_coef_grad(p, x, g).cpu().numpy()
         refg = oracle.coef_grad(xh, g.cpu().to(torch.float64).numpy(), gf, d, nthreads=8)
         assert nerr(cg, refg) <= TOL[dtype]
+
+
+def test_persistent_occupancy_in_plan_info():
+    """persistent_per_cu: the workgroups per CU of a persistent launch (the
+    kernel's occupancy, taken when the tables are built), 0 for one-shot
+    launches; the LDS budget bounds it."""
+    shape = (4, 32, 32, 32)
+    p = ss.spinsum_plan(shape, 1, 3, [workloads.CONFIG_3D_ALPHA])
+    assert ss.spinsum_plan_get_info(p)["persistent_per_cu"] == 0
+    ss.spinsum_plan_set_tile(p, 8, variant=ss.SPINSUM_VARIANT_LDS_PIPELINE, lds_pad=0)
+    info = ss.spinsum_plan_get_info(p)
+    assert info["variant"] == ss.SPINSUM_VARIANT_LDS_PIPELINE
+    per_cu = info["persistent_per_cu"]
+    assert 1 <= per_cu <= max(1, (160 * 1024) // max(1, info["lds_bytes"]))
+    x = gpu_uniform(shape, 90)
+    q = ss.spinsum_plan(shape, 1, 3, [workloads.CONFIG_3D_ALPHA])
+    assert torch.equal(run(p, x), run(q, x))
