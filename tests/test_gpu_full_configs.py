@@ -395,3 +395,28 @@ def test_3d_coef_grad_full_size():
         ref = float((g * y).sum(dtype=torch.float64))
         _say(f"  p={perm} gpu {got[r]:.12e} ref {ref:.12e}")
         assert abs(got[r] - ref) <= 1e-12 * scale
+
+
+def test_3d_v64_o32_slab_spectrum():
+    """The 3D coefficient set acts with eigenvalues 0, 3 and 12 (the trivial,
+    standard and sign representations of S_3), so S^3 - 15 S^2 + 36 S = 0
+    on any input: checked on the whole 8.6 GB slab with the benchmark's own
+    in-place plan, every cube at once (a closed form of the operator, not
+    the oracle)."""
+    w = workloads.WORKLOADS["3d_v64_o32_slab"]
+    shape = w["shape"]
+    s = workloads.uniform(shape, 1000, device=DEV)
+    p = ss.spinsum_plan(shape, 3, 3, [workloads.CONFIG_3D_ALPHA], inplace=True)
+    ss.spinsum_exec(p, s, s)                       # S x
+    r = 36.0 * s
+    ss.spinsum_exec(p, s, s)                       # S^2 x
+    r.add_(s, alpha=-15.0)
+    ss.spinsum_exec(p, s, s)                       # S^3 x
+    r.add_(s)
+    torch.cuda.synchronize()
+    scale = float(s.abs().max())
+    res = float(r.abs().max())
+    _say(f"  max|S^3 - 15 S^2 + 36 S| = {res:.3e} against max|S^3 x| = {scale:.3e}")
+    assert scale > 0 and res <= 1e-13 * scale
+    del s, r
+    torch.cuda.empty_cache()
