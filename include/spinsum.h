@@ -90,6 +90,8 @@ typedef enum { SPINSUM_F64 = 0, SPINSUM_F32 = 1 } spinsum_dtype;
 #define SPINSUM_FLAG_FULL_GROUP 0x400u   /* tile under the whole of S_d even where the operator's
                                             permutations move a smaller run of axes (ablation of
                                             the reduction described at spinsum_plan) */
+#define SPINSUM_FLAG_NO_NT_LOADS 0x800u  /* default-policy tile loads where the planner would use
+                                            non-temporal ones (see spinsum_plan_info_t.nt_loads) */
 #define SPINSUM_FLAG_INDEX_PAIRS 0x80u   /* index-pair form: the d dims right before the group
                                             (the partner indices, extent V each) are permuted
                                             by the same permutation as the group, e.g.
@@ -165,6 +167,12 @@ typedef struct {
   int persistent_per_cu; /* persistent kernel variants and persistent batched plans:
                             workgroups launched per CU (the kernel's occupancy, taken
                             when the tables are built); else 0 */
+  int nt_loads;          /* 1: the direct-LDS kernel loads tiles with the non-temporal
+                            policy, chosen where every work item owns the 128-byte lines
+                            it reads (whole cubes, or tile rows that start and end on line
+                            boundaries), and for the whole-cube items of batched plans;
+                            0: default policy, which keeps lines that several items share
+                            in the L2 */
 } spinsum_plan_info_t;
 
 /* Create a plan for Out = S_K(...S_1(In)) (Def. 3-4; in-place: Sec. 4.6.5).

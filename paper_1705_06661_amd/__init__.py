@@ -60,6 +60,7 @@ SPINSUM_FLAG_INDEX_PAIRS = 0x80
 SPINSUM_FLAG_NT_STORES = 0x100
 SPINSUM_FLAG_MULTI_PASS = 0x200
 SPINSUM_FLAG_FULL_GROUP = 0x400
+SPINSUM_FLAG_NO_NT_LOADS = 0x800
 
 SPINSUM_VARIANT_AUTO = 0
 SPINSUM_VARIANT_DIRECT_LDS = 1
@@ -90,7 +91,7 @@ class _Info(ctypes.Structure):
                 ("pair_extent", ctypes.c_int), ("batch_item_bytes", ctypes.c_int64),
                 ("batch_persistent", ctypes.c_int), ("nt_stores", ctypes.c_int),
                 ("exec_d", ctypes.c_int), ("exec_group_first", ctypes.c_int),
-                ("persistent_per_cu", ctypes.c_int)]
+                ("persistent_per_cu", ctypes.c_int), ("nt_loads", ctypes.c_int)]
 
 
 _vp = ctypes.c_void_p

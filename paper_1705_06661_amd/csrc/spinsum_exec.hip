@@ -196,6 +196,7 @@ spinsum_status launch_exec(spinsum_plan_s* P, const void* in, void* out, hipStre
   a.g = Tl.g;
   a.nitems = Tl.nitems;
   a.reverse = (P->flags & SPINSUM_FLAG_REVERSE_ORDER) ? 1 : 0;
+  a.nt_loads = Tl.ntl;
   // kernel variant chosen by the planner (see spinsum_tile_t.variant)
   const LaunchCfg c = exec_cfg<T>(P, sel.chain);
   a.lds_tile_bytes = (int32_t)(((size_t)Tl.lds_elems * sizeof(T) + 15) / 16 * 16);

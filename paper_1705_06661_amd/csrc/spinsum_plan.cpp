@@ -970,6 +970,23 @@ static int choose_nts(const spinsum_plan_s& P, const Tiling& T, int64_t orbits) 
   return (row >= 64 && orbits <= 128) ? 1 : 0;
 }
 
+// Load policy of the direct-LDS kernel: non-temporal where every work item
+// owns the 128-byte lines it reads, so that no other item needs them in the
+// L2 -- whole cubes (one contiguous run per item), or tile rows that start
+// and end on line boundaries (the row stride, the tile row and the ragged
+// last tile row all multiples of 128 bytes).  Measured on MI355X: inner
+// runs of 8 (256-byte rows) +5 %, Fig. 1b's subgroup plan +6 %, whole
+// 24^3 FP32 cubes +3 to +4 %; with 64-byte rows the same loads are 14 %
+// slower, and with 32-byte rows in one 80^4 cube 23 %.
+static int choose_ntl(const spinsum_plan_s& P, const Tiling& T) {
+  if (P.flags & SPINSUM_FLAG_NO_NT_LOADS) return 0;
+  if (P.pair || T.g.n <= 0) return 0;
+  if (T.g.bl == T.g.n) return 1;
+  const int64_t e = (int64_t)T.g.inner * elem_size(P);
+  const int64_t last = T.g.n - (int64_t)(T.nb - 1) * T.g.bl;
+  return ((e * T.g.n) % 128 == 0 && (e * T.g.bl) % 128 == 0 && (e * last) % 128 == 0) ? 1 : 0;
+}
+
 static spinsum_status apply_pair_tile(spinsum_plan_s* P, const spinsum_tile_t* req) {
   spinsum_tile_t t{};
   if (req && req->bl > 0) {
@@ -1080,6 +1097,7 @@ static spinsum_status apply_tile(spinsum_plan_s* P, const spinsum_tile_t* req) {
     t.threads = per_cu >= 4 ? 256 : per_cu >= 2 ? 512 : 1024;
   }
   T.nts = choose_nts(*P, T, (int64_t)T.orbits.size());
+  T.ntl = choose_ntl(*P, T);
   P->tile = t;
   P->T = std::move(T);
   return SPINSUM_OK;
@@ -1500,6 +1518,7 @@ extern "C" spinsum_status spinsum_plan_get_info(spinsum_plan_t P, spinsum_plan_i
   info->inner = P->inner;
   info->pair_extent = P->pair ? P->pv : 0;
   info->nt_stores = P->batched ? 1 : P->T.nts;
+  info->nt_loads = P->batched ? 1 : P->T.ntl;
   info->batch_item_bytes = P->batched ? P->batch_item_bytes : 0;
   info->batch_persistent = P->batched ? P->batch_persistent : 0;
   if (!P->batched) {

@@ -46,6 +46,7 @@ struct Tiling {
   int chunks_per_thread = 0;  // 16-byte loads per thread for the largest item
   int max_rep_cnt = 0;        // representatives of the largest work item
   int nts = 1;                // non-temporal stores
+  int ntl = 0;                // non-temporal tile loads (items own whole lines)
   std::vector<OrbitHost> orbits;
   std::vector<GroupDev> groups;
   std::vector<uint32_t> reps;

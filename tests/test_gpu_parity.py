@@ -240,7 +240,7 @@ def test_factored_form_chained_and_expanded():
 
 @pytest.mark.parametrize("flags", [ss.SPINSUM_FLAG_REVERSE_ORDER, ss.SPINSUM_FLAG_NO_XCD_REMAP,
                                    ss.SPINSUM_FLAG_NO_LDS_PAD, ss.SPINSUM_FLAG_NO_NT_STORES,
-                                   ss.SPINSUM_FLAG_NO_DIRECT_LDS,
+                                   ss.SPINSUM_FLAG_NO_DIRECT_LDS, ss.SPINSUM_FLAG_NO_NT_LOADS,
                                    ss.SPINSUM_FLAG_NO_DIRECT_LDS | ss.SPINSUM_FLAG_REVERSE_ORDER])
 def test_schedule_variants_are_bitwise_equal(flags):
     shape = (3, 24, 24, 24)
@@ -253,6 +253,38 @@ def test_schedule_variants_are_bitwise_equal(flags):
             v = run(mk(shape, [workloads.CONFIG_3D_ALPHA], 3, inplace=True, flags=flags, tile=tile,
                        variant=variant), x)
             assert torch.equal(base, v), (flags, tile, variant)
+
+
+LOAD_POLICY_CASES = [
+    # shape, group_first, d, stages, dtype: plans whose work items own whole
+    # 128-byte lines, so that the planner loads them non-temporally
+    ((2, 3, 16, 16, 16, 8), 2, 3, [workloads.CONFIG_3D_ALPHA], torch.float64),  # 256-byte rows
+    ((2, 40, 40, 40, 16), 1, 3, [workloads.CONFIG_3D_ALPHA], torch.float64),    # ragged tiles
+    ((2, 3, 16, 16, 16), 2, 3, [[((0, 1, 2), 1.0), (workloads.P("213"), 1.0)]], torch.float64),
+    ((4, 8, 8, 8), 1, 3, [workloads.CONFIG_3D_ALPHA], torch.float64),           # whole cubes
+    ((5, 12, 12, 12), 1, 3, [workloads.CONFIG_3D_ALPHA], torch.float32),
+    ((2, 6, 6, 6, 6, 32), 1, 4, [workloads.random_4d_alpha(7)], torch.float32),
+]
+
+
+@pytest.mark.parametrize("case", range(len(LOAD_POLICY_CASES)))
+def test_load_policy_is_bitwise_neutral(case):
+    """Non-temporal tile loads change where lines live in the L2, not what is
+    read: the planner's policy and SPINSUM_FLAG_NO_NT_LOADS agree bit for bit,
+    in place and out of place, and both match the oracle."""
+    shape, gf, d, stages, dtype = LOAD_POLICY_CASES[case]
+    _say("load policy", shape, gf, d, dtype)
+    x = gpu_uniform(shape, 2600 + case, dtype)
+    ref = oracle.spinsum_chain(x.cpu().to(torch.float64).numpy(), stages, gf, d, nthreads=8)
+    for inplace in (False, True):
+        p = ss.spinsum_plan(shape, gf, d, stages, dtype=dtype, inplace=inplace)
+        q = ss.spinsum_plan(shape, gf, d, stages, dtype=dtype, inplace=inplace,
+                            flags=ss.SPINSUM_FLAG_NO_NT_LOADS)
+        assert ss.spinsum_plan_get_info(p)["nt_loads"] == 1
+        assert ss.spinsum_plan_get_info(q)["nt_loads"] == 0
+        y = run(p, x)
+        assert torch.equal(y, run(q, x)), inplace
+        assert nerr(y.cpu().numpy(), ref) <= TOL[dtype], inplace
 
 
 def test_empty_tensors_are_no_ops():

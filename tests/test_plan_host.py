@@ -165,6 +165,38 @@ def test_store_mode_rule():
     assert nt((2, 32, 32, 32), 1, 3, cfg3, ss.SPINSUM_FLAG_NO_NT_STORES) == 0
 
 
+def test_load_policy_rule():
+    """Non-temporal tile loads exactly where every work item owns the
+    128-byte lines it reads: whole cubes, or tile rows whose stride, length
+    and ragged last length are all multiples of 128 bytes; the index-pair
+    form and SPINSUM_FLAG_NO_NT_LOADS keep the default policy."""
+    cfg3 = [workloads.CONFIG_3D_ALPHA]
+    fig1b = [[((0, 1, 2), 1.0), (P("213"), 1.0)]]
+    a4 = [(p, 1.0) for p in itertools.permutations(range(4))]
+    def info(shape, gf, d, terms, flags=0, dtype="f64"):
+        p = ss.spinsum_plan(shape, gf, d, terms, dtype=dtype, flags=flags | HOST)
+        return ss.spinsum_plan_get_info(p)
+    def ntl(*a, **k):
+        return info(*a, **k)["nt_loads"]
+    assert ntl((2, 32, 32, 32), 1, 3, cfg3) == 0                 # 64-byte rows
+    assert ntl((2, 12, 12, 12, 12), 1, 4, [a4]) == 0             # 48-byte rows
+    assert ntl((80, 80, 80, 80), 0, 4, [a4]) == 0                # 32-byte rows
+    assert ntl((4, 8, 8, 8), 1, 3, cfg3) == 1                    # whole cubes
+    assert ntl((5, 12, 12, 12), 1, 3, cfg3, dtype="f32") == 1    # whole cubes, 48-byte rows
+    i = info((2, 3, 16, 16, 16, 8), 2, 3, cfg3)                  # inner runs of 8: 256-byte rows
+    assert i["bl"] < 16 and i["nt_loads"] == 1
+    i = info((2, 40, 40, 40, 16), 1, 3, cfg3)                    # ragged, rows of 16 k elements
+    assert i["ragged"] == 1 and i["nt_loads"] == 1
+    assert ntl((2, 40, 40, 40, 3), 1, 3, cfg3) == 0              # 24-byte inner runs
+    i = info((2, 3, 16, 16, 16), 2, 3, fig1b)                    # Fig. 1b: last axis as runs
+    assert i["exec_d"] == 2 and i["nt_loads"] == 1
+    assert ntl((2, 3, 16, 16, 16, 8), 2, 3, cfg3, ss.SPINSUM_FLAG_NO_NT_LOADS) == 0
+    assert ntl((4, 8, 8, 8), 1, 3, cfg3, ss.SPINSUM_FLAG_NO_NT_LOADS) == 0
+    assert ntl((4, 4, 4, 8, 8, 8), 3, 3, cfg3, ss.SPINSUM_FLAG_INDEX_PAIRS) == 0
+    bp = ss.spinsum_plan_batched([(8, 8, 8, 4, 4, 4), (6, 6, 6, 10, 10, 10)], 3, cfg3, flags=HOST)
+    assert ss.spinsum_plan_get_info(bp)["nt_loads"] == 1
+
+
 def test_inner_spectator_geometry():
     """A cube of [.., N^d, inner] is N^d * inner contiguous elements; rows
     along the last group axis hold bl * inner elements."""
