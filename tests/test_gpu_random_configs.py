@@ -307,3 +307,51 @@ def test_random_unpack_and_pack(case):
         np.testing.assert_array_equal(
             full.cpu().to(torch.float64).numpy(),
             oracle.unpack(pki.cpu().to(torch.float64).numpy(), shape, stages, gf, d))
+
+
+@pytest.mark.parametrize("case", range(40))
+def test_random_non_finite_inputs(case):
+    """Inf, -Inf and NaN planted at random positions (some on diagonals) under
+    random operators with zero coefficients, in the three forms: the
+    positions of NaN, +Inf and -Inf equal the oracle's exactly -- on the
+    pre-multiplied sum (oracle.expanded_terms) for the default form, on the
+    chain for the chained and multi-pass forms -- and the finite outputs are
+    within the tolerance."""
+    rng = np.random.default_rng(8500 + case)
+    d = int(rng.choice([2, 3, 4], p=[0.2, 0.5, 0.3]))
+    n = int(rng.integers(1, {2: 40, 3: 16, 4: 8}[d] + 1))
+    outer = [int(e) for e in rng.integers(1, 4, size=int(rng.integers(0, 3)))]
+    inner = [int(e) for e in rng.integers(1, 4, size=int(rng.integers(0, 2)))]
+    shape = tuple(outer + [n] * d + inner)
+    gf = len(outer)
+    stages = random_stages(rng, d)
+    form = rng.choice(["expanded", "chained", "multi_pass"], p=[0.5, 0.3, 0.2])
+    flags = {"expanded": 0, "chained": ss.SPINSUM_FLAG_CHAIN_STAGES,
+             "multi_pass": ss.SPINSUM_FLAG_MULTI_PASS}[form]
+    if rng.random() < 0.3:
+        flags |= ss.SPINSUM_FLAG_NO_DIRECT_LDS
+    dtype = torch.float64 if rng.random() < 0.6 else torch.float32
+    inplace = bool(rng.random() < 0.5)
+    _say("non-finite", case, shape, gf, d, form, dtype, inplace, [len(s) for s in stages])
+    xh = workloads.uniform(shape, 8600 + case, dtype=dtype).to(torch.float64).numpy()
+    flat = xh.reshape(-1)
+    for k in range(int(rng.integers(1, 6))):
+        pos = list(np.unravel_index(int(rng.integers(0, flat.size)), shape))
+        if rng.random() < 0.4:  # onto a diagonal: two group indices equal
+            a, b = rng.choice(d, size=2, replace=False) if d > 1 else (0, 0)
+            pos[gf + int(a)] = pos[gf + int(b)]
+        xh[tuple(pos)] = [np.inf, -np.inf, np.nan][k % 3]
+    if form == "expanded":
+        ref = oracle.spinsum(xh, oracle.expanded_terms(stages, d), gf, d, nthreads=8)
+    else:
+        ref = oracle.spinsum_chain(xh, stages, gf, d, nthreads=8)
+    p = ss.spinsum_plan(shape, gf, d, stages, dtype=dtype, inplace=inplace, flags=flags)
+    got = apply(p, torch.from_numpy(xh).to(dtype).to(DEV)).cpu().to(torch.float64).numpy()
+    np.testing.assert_array_equal(np.isnan(got), np.isnan(ref))
+    np.testing.assert_array_equal(np.isposinf(got), np.isposinf(ref))
+    np.testing.assert_array_equal(np.isneginf(got), np.isneginf(ref))
+    fin = np.isfinite(ref)
+    if fin.any():
+        scale = max(gain_of(stages) * float(np.max(np.abs(xh[np.isfinite(xh)]), initial=0.0)),
+                    np.finfo(np.float64).tiny)
+        assert np.max(np.abs(got[fin] - ref[fin])) <= TOL[dtype] * scale
