@@ -415,7 +415,9 @@ def profile_one(name, steps, warmup):
     print(json.dumps({"form": name, "launches": warmup + steps, "avg_launch_ms": round(ms, 4),
                       "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1),
                       "algorithmic_bytes_per_launch": nbytes,
-                      "kernel": {"stream_copy": "k_copy", "3d_coef_grad": "k_cgrad<double, 3>"}.get(
+                      "kernel": {"stream_copy": "k_copy",
+                                 "3d_coef_grad": ("k_cgrad_split<double, 3>" if info["coef_grad_split"]
+                                                  else "k_cgrad<double, 3>")}.get(
                           name, kernel_name(info)),
                       "tile_edge": info["bl"],
                       "kernel_source_hash": kernel_source_hash()}), flush=True)

@@ -173,6 +173,9 @@ typedef struct {
                             boundaries), and for the whole-cube items of batched plans;
                             0: default policy, which keeps lines that several items share
                             in the L2 */
+  int coef_grad_split;   /* 1: spinsum_coef_grad keeps one tensor in LDS at a time (the
+                            upstream gradient waits in registers while x's orbits are
+                            gathered), on this plan's tiling; 0: both tensors in LDS */
 } spinsum_plan_info_t;
 
 /* Create a plan for Out = S_K(...S_1(In)) (Def. 3-4; in-place: Sec. 4.6.5).

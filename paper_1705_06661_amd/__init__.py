@@ -91,7 +91,8 @@ class _Info(ctypes.Structure):
                 ("pair_extent", ctypes.c_int), ("batch_item_bytes", ctypes.c_int64),
                 ("batch_persistent", ctypes.c_int), ("nt_stores", ctypes.c_int),
                 ("exec_d", ctypes.c_int), ("exec_group_first", ctypes.c_int),
-                ("persistent_per_cu", ctypes.c_int), ("nt_loads", ctypes.c_int)]
+                ("persistent_per_cu", ctypes.c_int), ("nt_loads", ctypes.c_int),
+                ("coef_grad_split", ctypes.c_int)]
 
 
 _vp = ctypes.c_void_p

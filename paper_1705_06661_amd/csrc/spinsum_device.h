@@ -1649,6 +1649,138 @@ __global__ void __launch_bounds__(kThreads) k_cgrad(const CGradArgs<T> a) {
   }
 }
 
+// Coefficient gradient with one tile buffer, for tiled items of one tile
+// orbit whose chunks take one pass of the workgroup (every thread holds at
+// most one chunk per tile) and whose element orbits are at most two per
+// thread.  The tiles of x go straight into LDS while those of the upstream
+// gradient go into registers, all loads in flight together; every thread
+// gathers the d! values of x of its element orbits into registers, the
+// gradient's tiles then take x's place in LDS, and each element orbit's
+// terms are formed as in k_cgrad.  Half of k_cgrad's LDS, so twice its
+// workgroups fit a CU (the plan's own tiling: no packed items needed).
+// LDS: [tiles (lds_tile_bytes) | representative list]; the partial sums of
+// the waves reuse it at the end.  At least six waves per SIMD (the second
+// launch bound): unbounded, the compiler takes 184 VGPRs (two waves) for
+// what fits in 78 without spilling, and the LDS would allow six
+// workgroups per CU.
+static_assert(kCgSplitThreads == kThreads, "k_cgrad_split runs kThreads per workgroup");
+
+template <typename T, int D>
+__global__ void __launch_bounds__(kThreads, 6) k_cgrad_split(const CGradArgs<T> a) {
+  constexpr int DF = Fact<D>::v;
+  constexpr int VW = 16 / sizeof(T);
+  typedef typename VecT<T, VW>::type V;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  int64_t item;
+  if (a.xcd_per > 0)
+    item = (int64_t)(blockIdx.x & 7u) * a.xcd_per + (int64_t)(blockIdx.x >> 3);
+  else
+    item = blockIdx.x;
+  if (item >= a.nitems) return;
+  const Geom& g = a.g;
+  int64_t cube0;
+  int orbit, ncub;
+  decode_item(g, item, &cube0, &orbit, &ncub);
+  const cptr<GroupDev> od = as_const(a.orbits + orbit);
+  const int ntl = od->ntiles;
+  const bool ragged = od->ragged != 0;
+  T* lds = reinterpret_cast<T*>(smem);
+  unsigned char* rep_lds = smem + a.lds_tile_bytes;
+  // 1. x's tiles to LDS, the gradient's chunks to registers (chunk tid of
+  //    every tile: the plan allows this kernel only where rows * vpr fits
+  //    the workgroup), the representative list to LDS
+  int l[D];
+  chunk_coords<D, VW>(g, threadIdx.x, l);
+  const int off = chunk_offset<D>(g, l);
+  const bool cin = threadIdx.x < (uint32_t)g.rows * (uint32_t)g.vpr;
+  set_memory_priority();
+  issue_item_lds<T, D, false>(g, od, false, ntl, ragged, a.x + cube0 * g.cube_elems, smem);
+  const T* gsrc = a.gr + cube0 * g.cube_elems;
+  V gb[kCgSplitTiles];
+#pragma unroll
+  for (int t = 0; t < kCgSplitTiles; ++t) {
+    if (t < ntl && cin && (!ragged || chunk_inside<D>(l, od->tile_ext[t], g.inner)))
+      gb[t] = *reinterpret_cast<const V*>(gsrc + od->tile_off[t] + off);
+  }
+  issue_reps_lds(od, a.reps, rep_lds);
+  set_compute_priority();
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): x and the lists in LDS, gb loaded
+  __syncthreads();
+  // 2. the x values of this thread's element orbits
+  int32_t sb[DF];
+#pragma unroll
+  for (int r = 0; r < DF; ++r) sb[r] = od->slot_base[0][r];
+  const uint32_t rep_cnt = (uint32_t)od->rep_cnt[0];
+  const uint32_t* rp = reinterpret_cast<const uint32_t*>(rep_lds);
+  const int eq = od->eqmask[0];
+  double v[kCgSplitUnits][DF];
+  int addr[kCgSplitUnits][DF];
+  double w[kCgSplitUnits];
+#pragma unroll
+  for (int u = 0; u < kCgSplitUnits; ++u) {
+    const uint32_t i = threadIdx.x + u * blockDim.x;
+    w[u] = 0.0;
+    if (i < rep_cnt) {
+      const uint32_t pk = rp[i];
+      int lr[D];
+#pragma unroll
+      for (int m = 0; m < D; ++m) lr[m] = (int)((pk >> (8 * m)) & 255u);
+      orbit_addrs<D>(g, 0, sb, lr, addr[u], std::make_integer_sequence<int, DF>{});
+#pragma unroll
+      for (int r = 0; r < DF; ++r) v[u][r] = (double)lds[addr[u][r]];
+      // |H| as in k_cgrad
+      int h = 1, run = 1;
+#pragma unroll
+      for (int m = 1; m < D; ++m) {
+        if (((eq >> (m - 1)) & 1) && lr[m] == lr[m - 1]) {
+          ++run;
+          h *= run;
+        } else {
+          run = 1;
+        }
+      }
+      w[u] = 1.0 / (double)h;
+    }
+  }
+  __syncthreads();  // every wave is done with x
+  // 3. the gradient's tiles take x's place
+#pragma unroll
+  for (int t = 0; t < kCgSplitTiles; ++t) {
+    if (t < ntl && cin && (!ragged || chunk_inside<D>(l, od->tile_ext[t], g.inner)))
+      *reinterpret_cast<V*>(lds + t * g.ts + (int)threadIdx.x * VW) = gb[t];
+  }
+  __syncthreads();
+  double acc[DF];
+#pragma unroll
+  for (int p = 0; p < DF; ++p) acc[p] = 0.0;
+#pragma unroll
+  for (int u = 0; u < kCgSplitUnits; ++u) {
+    if (w[u] != 0.0) {
+      double gu[DF];
+#pragma unroll
+      for (int r = 0; r < DF; ++r) gu[r] = (double)lds[addr[u][r]];
+      cgrad_rows<D>(acc, gu, v[u], w[u], std::make_integer_sequence<int, DF>{});
+    }
+  }
+  // 4. workgroup sum, as in k_cgrad
+  __syncthreads();
+  double* red = reinterpret_cast<double*>(smem);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int p = 0; p < DF; ++p) {
+    double s = acc[p];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) red[wave * DF + p] = s;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < DF) {
+    double s = 0.0;
+    for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) s += red[wv * DF + threadIdx.x];
+    unsafeAtomicAdd(a.grad + (blockIdx.x & (kGradSlots - 1)) * DF + threadIdx.x, s);
+  }
+}
+
 // Zero n doubles (grid-stride).
 __global__ void __launch_bounds__(kThreads) k_zero_f64(double* p, int n) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0.0;
@@ -1954,7 +2086,10 @@ const void* pick_d(int kind, int vw, bool chain, bool nts, int maxc) {
 }
 
 template <typename T, int D>
-const void* cgrad_kernel() {
+const void* cgrad_kernel(bool split) {
+  if constexpr (D <= 3) {
+    if (split) return (const void*)k_cgrad_split<T, D>;
+  }
   return (const void*)k_cgrad<T, D>;
 }
 
@@ -1988,7 +2123,7 @@ const void* batched_kernel(int vw, bool persist) {
 #define SPINSUM_DECLARE_PICK(tag, d)                                                    \
   const void* pick_##tag##_d##d(int kind, int vw, bool chain, bool nts, int maxc);     \
   const void* pick_batched_##tag##_d##d(int vw, bool persist);                         \
-  const void* pick_cgrad_##tag##_d##d();                                                \
+  const void* pick_cgrad_##tag##_d##d(bool split);                                      \
   const void* pick_pack_##tag##_d##d(bool pack, bool nts);
 SPINSUM_DECLARE_PICK(f64, 2)
 SPINSUM_DECLARE_PICK(f64, 3)

@@ -60,15 +60,15 @@ const void* pick_pack(int d, bool pack, bool nts) {
 }
 
 template <typename T>
-const void* pick_cgrad(int d) {
+const void* pick_cgrad(int d, bool split) {
   if constexpr (sizeof(T) == 8) {
-    if (d == 2) return pick_cgrad_f64_d2();
-    if (d == 3) return pick_cgrad_f64_d3();
-    return pick_cgrad_f64_d4();
+    if (d == 2) return pick_cgrad_f64_d2(split);
+    if (d == 3) return pick_cgrad_f64_d3(split);
+    return pick_cgrad_f64_d4(split);
   } else {
-    if (d == 2) return pick_cgrad_f32_d2();
-    if (d == 3) return pick_cgrad_f32_d3();
-    return pick_cgrad_f32_d4();
+    if (d == 2) return pick_cgrad_f32_d2(split);
+    if (d == 3) return pick_cgrad_f32_d3(split);
+    return pick_cgrad_f32_d4(split);
   }
 }
 
@@ -416,25 +416,30 @@ namespace {
 template <typename T>
 spinsum_status launch_cgrad(spinsum_plan_s* P, const void* x, const void* g, double* grad,
                             double* part, hipStream_t stream) {
-  // its own packed tiling where the plan has one (see build_cgrad_tiling)
-  const Tiling& Tl = P->cg_pack ? P->Tc : P->T;
+  // one tile buffer on the plan's tiling where it allows (k_cgrad_split),
+  // else both tensors in LDS on the packed tiling where the plan has one
+  // (see build_cgrad_tiling)
+  const bool split = cgrad_split_ok(*P);
+  const bool packed = P->cg_pack && !split;
+  const Tiling& Tl = packed ? P->Tc : P->T;
   CGradArgs<T> a;
   std::memset(&a, 0, sizeof(a));
   a.x = reinterpret_cast<const T*>(x);
   a.gr = reinterpret_cast<const T*>(g);
   a.grad = part;
-  a.orbits = reinterpret_cast<const GroupDev*>(P->cg_pack ? P->d_cg_orbits : P->d_orbits);
-  a.reps = reinterpret_cast<const uint32_t*>(P->cg_pack ? P->d_cg_reps : P->d_reps);
+  a.orbits = reinterpret_cast<const GroupDev*>(packed ? P->d_cg_orbits : P->d_orbits);
+  a.reps = reinterpret_cast<const uint32_t*>(packed ? P->d_cg_reps : P->d_reps);
   a.g = Tl.g;
   a.nitems = Tl.nitems;
   a.lds_tile_bytes = (int32_t)(((size_t)Tl.lds_elems * sizeof(T) + 15) / 16 * 16);
   const int df = P->G.df;
-  // LDS: x tiles | gradient tiles | representative lists; the partial sums
-  // of the waves reuse it at the end
-  const size_t shmem = std::max<size_t>(2 * (size_t)a.lds_tile_bytes + (size_t)Tl.max_rep_cnt * 4,
+  // LDS: x tiles | gradient tiles (k_cgrad only) | representative lists;
+  // the partial sums of the waves reuse it at the end
+  const size_t shmem = std::max<size_t>((split ? 1 : 2) * (size_t)a.lds_tile_bytes +
+                                            (size_t)Tl.max_rep_cnt * 4,
                                         (size_t)(kThreads / 64) * df * sizeof(double));
   if ((int64_t)shmem > P->lds_limit) return SPINSUM_ERR_UNSUPPORTED;
-  const void* k = pick_cgrad<T>(P->d);
+  const void* k = pick_cgrad<T>(P->d, split);
   spinsum_status st = prepare_kernel(P, k, shmem);
   if (st != SPINSUM_OK) return st;
   hipLaunchKernelGGL(k_zero_f64, dim3(64), dim3(kThreads), 0, stream, a.grad, kGradSlots * df);

@@ -61,6 +61,11 @@ inline FastDiv make_fastdiv(uint32_t d) {
 }
 
 constexpr int kGradSlots = 2048;     // partial sums of the coefficient gradient (power of 2)
+// k_cgrad_split: tiles of an item (a 3D tile orbit at most), element orbits
+// per thread, and its workgroup size
+constexpr int kCgSplitTiles = 6;
+constexpr int kCgSplitUnits = 2;
+constexpr int kCgSplitThreads = 256;
 constexpr int kMaxGroupTiles = 24;   // tiles of one work item
 constexpr int kMaxGroupOrbits = 8;   // tile orbits of one work item
 

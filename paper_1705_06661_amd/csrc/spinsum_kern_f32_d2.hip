@@ -10,7 +10,7 @@ const void* pick_f32_d2(int kind, int vw, bool chain, bool nts, int maxc) {
 
 const void* pick_batched_f32_d2(int vw, bool persist) { return batched_kernel<float, 2>(vw, persist); }
 
-const void* pick_cgrad_f32_d2() { return cgrad_kernel<float, 2>(); }
+const void* pick_cgrad_f32_d2(bool split) { return cgrad_kernel<float, 2>(split); }
 
 const void* pick_pack_f32_d2(bool pack, bool nts) { return pack_kernel<float, 2>(pack, nts); }
 

@@ -10,7 +10,7 @@ const void* pick_f64_d2(int kind, int vw, bool chain, bool nts, int maxc) {
 
 const void* pick_batched_f64_d2(int vw, bool persist) { return batched_kernel<double, 2>(vw, persist); }
 
-const void* pick_cgrad_f64_d2() { return cgrad_kernel<double, 2>(); }
+const void* pick_cgrad_f64_d2(bool split) { return cgrad_kernel<double, 2>(split); }
 
 const void* pick_pack_f64_d2(bool pack, bool nts) { return pack_kernel<double, 2>(pack, nts); }
 

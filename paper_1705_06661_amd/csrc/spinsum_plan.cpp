@@ -572,9 +572,23 @@ static spinsum_status upload(spinsum_plan_s* P, void** dst, const V* src, size_t
 // workgroups onto a CU and the forward tiling has one orbit per item, it
 // gets a tiling of its own with consecutive orbits packed up to the largest
 // one (3D 32^3 slab: 3.51 -> 4.18 TB/s).
+bool cgrad_split_ok(const spinsum_plan_s& P) {
+  const Tiling& T = P.T;
+  if (P.pair || P.batched || P.d > 3 || T.g.bl >= T.g.n || T.g.inner != 1) return false;
+  if (P.tile.variant != SPINSUM_VARIANT_DIRECT_LDS || P.tile.lds_pad != 0) return false;
+  if ((int64_t)T.vw * elem_size(P) != 16) return false;
+  if ((int64_t)T.g.rows * T.g.vpr > kCgSplitThreads) return false;
+  for (const GroupDev& gd : T.groups)
+    if (gd.norb != 1 || gd.ntiles > kCgSplitTiles || gd.rep_cnt[0] > kCgSplitUnits * kCgSplitThreads)
+      return false;
+  const int64_t lds = (T.lds_elems * elem_size(P) + 15) / 16 * 16 + (int64_t)T.max_rep_cnt * 4;
+  return lds <= P.lds_limit;
+}
+
 static spinsum_status build_cgrad_tiling(spinsum_plan_s* P) {
   const Tiling& T = P->T;
   const int esz = elem_size(*P);
+  if (cgrad_split_ok(*P)) return SPINSUM_OK;  // one tile buffer: no packed tiling needed
   if (P->pair || P->batched || T.g.bl >= T.g.n || T.orbits.size() < 2 ||
       T.groups.size() != T.orbits.size() || P->tile.lds_pad != 0)
     return SPINSUM_OK;
@@ -1492,6 +1506,7 @@ extern "C" spinsum_status spinsum_plan_get_info(spinsum_plan_t P, spinsum_plan_i
     for (double v : P->expanded) nz += (v != 0.0);
     info->nterms_expanded = nz;
     info->exec_group_first = P->sub_first;
+    info->coef_grad_split = cgrad_split_ok(*P) ? 1 : 0;  // the gradient runs on the whole group
     return SPINSUM_OK;
   }
   std::memset(info, 0, sizeof(*info));
@@ -1519,6 +1534,7 @@ extern "C" spinsum_status spinsum_plan_get_info(spinsum_plan_t P, spinsum_plan_i
   info->pair_extent = P->pair ? P->pv : 0;
   info->nt_stores = P->batched ? 1 : P->T.nts;
   info->nt_loads = P->batched ? 1 : P->T.ntl;
+  info->coef_grad_split = cgrad_split_ok(*P) ? 1 : 0;
   info->batch_item_bytes = P->batched ? P->batch_item_bytes : 0;
   info->batch_persistent = P->batched ? P->batch_persistent : 0;
   if (!P->batched) {

@@ -566,6 +566,8 @@ def test_autotune_and_cache(tmp_path):
 
 # ----------------------------------------------------------- coefficient gradient
 COEF_GRAD_CASES = [
+    # the tiled 3D and 2D cases run the one-buffer kernel (k_cgrad_split),
+    # whole cubes and 4D the two-buffer one
     ((3, 8, 8, 8), 3, None),        # whole cubes
     ((2, 16, 16, 16), 3, (8, 1)),   # tile orbits
     ((2, 20, 20, 20), 3, (8, 1)),   # ragged tiles
@@ -595,6 +597,30 @@ def test_coef_grad_against_oracle(shape, d, tile, dtype):
     goti = ss.spinsum_coef_grad(p, xi, gi).cpu().numpy()
     refi = oracle.coef_grad(xi.double().cpu().numpy(), gi.double().cpu().numpy(), 1, d)
     np.testing.assert_array_equal(goti, refi)
+
+
+SPLIT_CASES = [
+    # plans whose coefficient gradient keeps one tensor in LDS at a time
+    ((3, 24, 24, 24), 3, (8, 1, 0), torch.float64),  # the FP64 default tiling
+    ((3, 24, 24, 24), 3, (8, 1, 0), torch.float32),
+    ((2, 20, 20, 20), 3, (8, 1, 0), torch.float64),  # ragged tiles
+    ((2, 20, 20, 20), 3, (8, 1, 0), torch.float32),
+    ((2, 22, 22, 22), 3, (6, 1, 0), torch.float64),  # 48-byte rows, ragged
+    ((2, 16, 16, 16), 3, (4, 1, 0), torch.float32),
+    ((4, 24, 24), 2, (8, 1, 0), torch.float64),
+    ((4, 24, 24), 2, (8, 1, 0), torch.float32),
+]
+
+
+@pytest.mark.parametrize("shape,d,tile,dtype", SPLIT_CASES)
+def test_coef_grad_one_buffer_against_oracle(shape, d, tile, dtype):
+    """The one-buffer gradient kernel (x's orbits gathered first, then the
+    upstream gradient in x's place): the plan reports it, and it matches the
+    oracle as the two-buffer one does; integer inputs bit for bit."""
+    test_coef_grad_against_oracle(shape, d, tile, dtype)
+    p = mk(shape, [workloads.CONFIG_3D_ALPHA if d == 3 else [(tuple(range(d)), 1.0)]], d,
+           dtype=dtype, tile=tile)
+    assert ss.spinsum_plan_get_info(p)["coef_grad_split"] == 1
 
 
 def test_coef_grad_errors_and_empty():

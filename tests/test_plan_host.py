@@ -197,6 +197,30 @@ def test_load_policy_rule():
     assert ss.spinsum_plan_get_info(bp)["nt_loads"] == 1
 
 
+def test_coef_grad_kernel_rule():
+    """The coefficient gradient keeps one tensor in LDS (k_cgrad_split) for
+    tiled direct-LDS items of one tile orbit that one workgroup pass covers,
+    with at most two element orbits per thread, d <= 3 and no inner runs."""
+    cfg3 = [workloads.CONFIG_3D_ALPHA]
+    a4 = [(p, 1.0) for p in itertools.permutations(range(4))]
+    def split(shape, gf, d, terms, dtype="f64", tile=None, flags=0):
+        p = ss.spinsum_plan(shape, gf, d, terms, dtype=dtype, flags=flags | HOST)
+        if tile:
+            ss.spinsum_plan_set_tile(p, *tile)
+        return ss.spinsum_plan_get_info(p)["coef_grad_split"]
+    assert split((64, 64, 8, 32, 32, 32), 3, 3, cfg3) == 1      # 8^3 tiles, 256 chunks
+    assert split((2, 20, 20, 20), 1, 3, cfg3, tile=(8, 1, 0)) == 1
+    assert split((64, 64, 8, 32, 32, 32), 3, 3, cfg3, dtype="f32") == 0  # 1024 chunks a tile
+    assert split((4, 8, 8, 8), 1, 3, cfg3) == 0                  # whole cubes
+    assert split((2, 16, 16, 16, 3), 1, 3, cfg3) == 0            # inner runs
+    assert split((2, 12, 12, 12, 12), 1, 4, [a4]) == 0           # d = 4
+    assert split((2, 20, 20, 20), 1, 3, cfg3,                      # register variant
+                 tile=(8, 1, 1, 0, ss.SPINSUM_VARIANT_REG_ONESHOT)) == 0
+    assert split((4, 4, 4, 24, 24, 24), 3, 3, cfg3, flags=ss.SPINSUM_FLAG_INDEX_PAIRS) == 0
+    bp = ss.spinsum_plan_batched([(8, 8, 8, 4, 4, 4)], 3, cfg3, flags=HOST)
+    assert ss.spinsum_plan_get_info(bp)["coef_grad_split"] == 0
+
+
 def test_inner_spectator_geometry():
     """A cube of [.., N^d, inner] is N^d * inner contiguous elements; rows
     along the last group axis hold bl * inner elements."""
