@@ -386,7 +386,7 @@ __device__ __forceinline__ bool combine_item(const Geom& g, cptr<GroupDev> gd,
   return bad;
 }
 
-// Tables of S_d for (wave-uniform) runtime indices, read by redo_orbit: the
+// Tables of S_d for (wave-uniform) runtime indices, read by the 4D redo: the
 // rank of tau^-1 o sigma, and the inverse of the r-th permutation
 // (inv[r][j] = m where lex_perm(r, m) = j).  The unrolled dense product
 // takes the same values as template constants.
@@ -418,16 +418,111 @@ __device__ __forceinline__ int32_t glb_stride(const Geom& g, int m) {
 // (Def. 3), so its input is not read, and an Inf or NaN input reaches only
 // the outputs of the terms that read it (the dense product, exact for
 // finite inputs, would also give 0 * Inf = NaN elsewhere).  This runs only
-// for items in which combine_orbit saw a non-finite input, so it is written
-// for few registers, not for speed: uniform loops walk the d! x d! terms
-// (coefficients and ranks from scalar loads), and every address is formed
-// at run time -- no register array is indexed at run time.  The inputs are
+// for items in which combine_orbit saw a non-finite input.  The inputs are
 // read from the tensor `gin` (the item's cube), which still holds them: the
 // item's stores come later, and no other workgroup writes its elements.
-// ltile(s) / gtile(s): LDS and tensor offset of tile sigma_s . B.  Chained
-// stages keep each element orbit's intermediate values in private memory.
+// Every output is formed over the nonzero coefficients in the dense
+// product's order, so both forms below give the term-by-term sum bit for
+// bit.  ltile(s) / gtile(s): LDS and tensor offset of tile sigma_s . B.
+
+// Element offset of sigma_R . x inside its tile, for the strides st[] of
+// the group axes (LDS or tensor).
+template <int D, int R, int... M>
+__device__ __forceinline__ int perm_offset(const int32_t* st, const int* l,
+                                           std::integer_sequence<int, M...>) {
+  return ((l[LexPerm<D, R, M>::value] * st[M]) + ... + 0);
+}
+
+// The d! inputs of an element orbit: each load takes its tile's origin as a
+// wave-uniform base and a 32-bit offset inside the item (below 2^31: an
+// item is at most cubes_per_wg cubes, which the planner keeps under 2 GiB).
+template <typename T, int D, typename GT, int... R>
+__device__ __forceinline__ void redo_gather(const Geom& g, GT gtile, const int* l, int gbase,
+                                            const T* gin, T* v, std::integer_sequence<int, R...>) {
+  ((v[R] = (gin + gtile(R))[gbase + perm_offset<D, R>(g.gst, l, std::make_integer_sequence<int, D>{})]),
+   ...);
+}
+
+// w_tau over the operator's terms only: a zero coefficient reads nothing.
+// The coefficients are read where they are used, from the constant address
+// space (scalar loads), so that they take no vector registers.
+template <typename T, int D, int TAU, int... S>
+__device__ __forceinline__ T orbit_row_terms(cptr<T> a, const T* v, std::integer_sequence<int, S...>) {
+  T acc = T(0);
+  ((acc = (a[GinvMul<D, TAU, S>::value] != T(0)) ? fma_t(a[GinvMul<D, TAU, S>::value], v[S], acc)
+                                                 : acc),
+   ...);
+  return acc;
+}
+
+template <typename T, int D, int... TAU>
+__device__ __forceinline__ void orbit_rows_terms(cptr<T> a, const T* v, T* w,
+                                                 std::integer_sequence<int, TAU...>) {
+  ((w[TAU] = orbit_row_terms<T, D, TAU>(a, v, std::make_integer_sequence<int, Fact<D>::v>{})), ...);
+}
+
+template <typename T, int D, typename LT, int... TAU>
+__device__ __forceinline__ void redo_store(const Geom& g, LT ltile, const int* l, int lbase,
+                                           const T* w, T* lds, std::integer_sequence<int, TAU...>) {
+  ((lds[lbase + ltile(TAU) + perm_offset<D, TAU>(g.lst, l, std::make_integer_sequence<int, D>{})] =
+        w[TAU]),
+   ...);
+}
+
+// Each w_tau formed and stored at once (one stage): no vector of results
+template <typename T, int D, typename LT, int... TAU>
+__device__ __forceinline__ void redo_rows_store(const Geom& g, LT ltile, const int* l, int lbase,
+                                                cptr<T> a, const T* v, T* lds,
+                                                std::integer_sequence<int, TAU...>) {
+  ((lds[lbase + ltile(TAU) + perm_offset<D, TAU>(g.lst, l, std::make_integer_sequence<int, D>{})] =
+        orbit_row_terms<T, D, TAU>(a, v, std::make_integer_sequence<int, Fact<D>::v>{})),
+   ...);
+}
+
+// Each element orbit's d! inputs gathered into registers in one trip
+// (addresses from compile-time permutation tables, as in the LDS gather),
+// then the outputs formed from them.
 template <typename T, int D, bool CHAIN, typename LT, typename GT>
-__device__ __forceinline__ void redo_orbit(const Geom& g, LT ltile, GT gtile, const uint32_t* rp,
+__device__ __forceinline__ void redo_orbit_gather(const Geom& g, LT ltile, GT gtile, const uint32_t* rp,
+                                           uint32_t rep_cnt, const FastDiv& fdr, int ncub,
+                                           cptr<T> coef, int nstages, const T* gin, T* lds) {
+  constexpr int DF = Fact<D>::v;
+  const uint32_t nrep = (uint32_t)ncub * rep_cnt * (uint32_t)g.inner;
+  for (uint32_t i = threadIdx.x; i < nrep; i += blockDim.x) {
+    uint32_t ci, ri, si;
+    split_unit(g, i, rep_cnt, fdr, ncub, &ci, &ri, &si);
+    const uint32_t pk = rp[ri];
+    int l[D];
+#pragma unroll
+    for (int m = 0; m < D; ++m) l[m] = (int)((pk >> (8 * m)) & 255u);
+    const int lbase = (int)ci * g.cube_lds + (int)si;
+    const int gbase = (int)ci * (int)g.cube_elems + (int)si;
+    T v[DF];
+    redo_gather<T, D>(g, gtile, l, gbase, gin, v, std::make_integer_sequence<int, DF>{});
+    if constexpr (!CHAIN) {
+      redo_rows_store<T, D>(g, ltile, l, lbase, coef, v, lds, std::make_integer_sequence<int, DF>{});
+    } else {
+      T w[DF];
+      for (int st = 0; st < nstages; ++st) {
+        orbit_rows_terms<T, D>(coef + st * DF, v, w, std::make_integer_sequence<int, DF>{});
+#pragma unroll
+        for (int r = 0; r < DF; ++r) v[r] = w[r];
+      }
+      redo_store<T, D>(g, ltile, l, lbase, v, lds, std::make_integer_sequence<int, DF>{});
+    }
+  }
+}
+
+// The terms walked in loops with few registers: coefficients and ranks from
+// scalar loads, every address formed at run time, no register array
+// indexed at run time.  One stage: the outputs in blocks of kRedoBlock,
+// each input loaded once per block (d! / kRedoBlock times per element
+// orbit instead of d! times).  Chained stages keep each element orbit's
+// intermediate values in private memory.
+constexpr int kRedoBlock = 8;
+
+template <typename T, int D, bool CHAIN, typename LT, typename GT>
+__device__ __forceinline__ void redo_orbit_loops(const Geom& g, LT ltile, GT gtile, const uint32_t* rp,
                                            uint32_t rep_cnt, const FastDiv& fdr, int ncub,
                                            cptr<T> coef, int nstages, const T* gin, T* lds) {
   constexpr int DF = Fact<D>::v;
@@ -455,20 +550,29 @@ __device__ __forceinline__ void redo_orbit(const Geom& g, LT ltile, GT gtile, co
       return x;
     };
     if constexpr (!CHAIN) {
+      // kRedoBlock outputs at a time: each input is loaded once per block
+      // and feeds that many accumulators
 #pragma unroll 1
-      for (int t = 0; t < DF; ++t) {
-        T acc = T(0);
-#pragma unroll 1
+      for (int t0 = 0; t0 < DF; t0 += kRedoBlock) {
+        T acc[kRedoBlock];
+#pragma unroll
+        for (int u = 0; u < kRedoBlock; ++u) acc[u] = T(0);
+#pragma unroll 4
         for (int s = 0; s < DF; ++s) {
-          const T c = coef[tb.ginv[t * DF + s]];
-          if (c != T(0)) acc = fma_t(c, gin[gaddr(s)], acc);
+          const T x = gin[gaddr(s)];
+#pragma unroll
+          for (int u = 0; u < kRedoBlock; ++u) {
+            const T c = coef[tb.ginv[(t0 + u) * DF + s]];
+            acc[u] = (c != T(0)) ? fma_t(c, x, acc[u]) : acc[u];
+          }
         }
-        lds[laddr(t)] = acc;
+#pragma unroll
+        for (int u = 0; u < kRedoBlock; ++u) lds[laddr(t0 + u)] = acc[u];
       }
     } else {
       volatile T cur[DF];
       volatile T nxt[DF];
-#pragma unroll 1
+#pragma unroll 8
       for (int s = 0; s < DF; ++s) cur[s] = gin[gaddr(s)];
 #pragma unroll 1
       for (int st = 0; st < nstages; ++st) {
@@ -489,6 +593,20 @@ __device__ __forceinline__ void redo_orbit(const Geom& g, LT ltile, GT gtile, co
       for (int t = 0; t < DF; ++t) lds[laddr(t)] = cur[t];
     }
   }
+}
+
+// d <= 3: gather each element orbit's inputs once (a few registers, short
+// code).  d = 4: the gathered form (24 inputs, 576 guarded FMAs unrolled)
+// made the dense path of the same kernels 2-5 % slower (registers and code
+// size), so 4D walks the terms in loops that keep eight loads in flight.
+template <typename T, int D, bool CHAIN, typename LT, typename GT>
+__device__ __forceinline__ void redo_orbit(const Geom& g, LT ltile, GT gtile, const uint32_t* rp,
+                                           uint32_t rep_cnt, const FastDiv& fdr, int ncub,
+                                           cptr<T> coef, int nstages, const T* gin, T* lds) {
+  if constexpr (D <= 3)
+    redo_orbit_gather<T, D, CHAIN>(g, ltile, gtile, rp, rep_cnt, fdr, ncub, coef, nstages, gin, lds);
+  else
+    redo_orbit_loops<T, D, CHAIN>(g, ltile, gtile, rp, rep_cnt, fdr, ncub, coef, nstages, gin, lds);
 }
 
 // redo_orbit for every tile orbit of a work item (the GroupDev tables: tile
