@@ -572,7 +572,7 @@ __device__ __forceinline__ void redo_orbit_loops(const Geom& g, LT ltile, GT gti
     } else {
       volatile T cur[DF];
       volatile T nxt[DF];
-#pragma unroll 8
+#pragma unroll 1
       for (int s = 0; s < DF; ++s) cur[s] = gin[gaddr(s)];
 #pragma unroll 1
       for (int st = 0; st < nstages; ++st) {
