@@ -419,7 +419,7 @@ spinsum_status launch_cgrad(spinsum_plan_s* P, const void* x, const void* g, dou
   // one tile buffer on the plan's tiling where it allows (k_cgrad_split),
   // else both tensors in LDS on the packed tiling where the plan has one
   // (see build_cgrad_tiling)
-  const bool split = cgrad_split_ok(*P);
+  const bool split = P->cg_split;
   const bool packed = P->cg_pack && !split;
   const Tiling& Tl = packed ? P->Tc : P->T;
   CGradArgs<T> a;

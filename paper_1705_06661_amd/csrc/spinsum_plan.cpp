@@ -572,7 +572,7 @@ static spinsum_status upload(spinsum_plan_s* P, void** dst, const V* src, size_t
 // workgroups onto a CU and the forward tiling has one orbit per item, it
 // gets a tiling of its own with consecutive orbits packed up to the largest
 // one (3D 32^3 slab: 3.51 -> 4.18 TB/s).
-bool cgrad_split_ok(const spinsum_plan_s& P) {
+static bool cgrad_split_ok(const spinsum_plan_s& P) {
   const Tiling& T = P.T;
   if (P.pair || P.batched || P.d > 3 || T.g.bl >= T.g.n || T.g.inner != 1) return false;
   if (P.tile.variant != SPINSUM_VARIANT_DIRECT_LDS || P.tile.lds_pad != 0) return false;
@@ -588,7 +588,7 @@ bool cgrad_split_ok(const spinsum_plan_s& P) {
 static spinsum_status build_cgrad_tiling(spinsum_plan_s* P) {
   const Tiling& T = P->T;
   const int esz = elem_size(*P);
-  if (cgrad_split_ok(*P)) return SPINSUM_OK;  // one tile buffer: no packed tiling needed
+  if (P->cg_split) return SPINSUM_OK;  // one tile buffer: no packed tiling needed
   if (P->pair || P->batched || T.g.bl >= T.g.n || T.orbits.size() < 2 ||
       T.groups.size() != T.orbits.size() || P->tile.lds_pad != 0)
     return SPINSUM_OK;
@@ -613,6 +613,7 @@ static spinsum_status build_cgrad_tiling(spinsum_plan_s* P) {
 
 spinsum_status upload_tables(spinsum_plan_s* P) {
   free_device(P);
+  P->cg_split = cgrad_split_ok(*P);
   if (P->flags & SPINSUM_FLAG_HOST_ONLY) return SPINSUM_OK;
   spinsum_status st;
   // coefficient vectors in the storage type: forward | adjoint | stages | adjoint stages
@@ -1506,7 +1507,7 @@ extern "C" spinsum_status spinsum_plan_get_info(spinsum_plan_t P, spinsum_plan_i
     for (double v : P->expanded) nz += (v != 0.0);
     info->nterms_expanded = nz;
     info->exec_group_first = P->sub_first;
-    info->coef_grad_split = cgrad_split_ok(*P) ? 1 : 0;  // the gradient runs on the whole group
+    info->coef_grad_split = P->cg_split ? 1 : 0;  // the gradient runs on the whole group
     return SPINSUM_OK;
   }
   std::memset(info, 0, sizeof(*info));
@@ -1534,7 +1535,7 @@ extern "C" spinsum_status spinsum_plan_get_info(spinsum_plan_t P, spinsum_plan_i
   info->pair_extent = P->pair ? P->pv : 0;
   info->nt_stores = P->batched ? 1 : P->T.nts;
   info->nt_loads = P->batched ? 1 : P->T.ntl;
-  info->coef_grad_split = cgrad_split_ok(*P) ? 1 : 0;
+  info->coef_grad_split = P->cg_split ? 1 : 0;
   info->batch_item_bytes = P->batched ? P->batch_item_bytes : 0;
   info->batch_persistent = P->batched ? P->batch_persistent : 0;
   if (!P->batched) {

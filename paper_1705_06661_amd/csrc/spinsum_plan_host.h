@@ -91,6 +91,12 @@ struct spinsum_plan_s {
   // consecutive orbits into items even where T does not (cg_pack)
   spinsum::Tiling Tc;
   bool cg_pack = false;
+  // the coefficient gradient runs k_cgrad_split on the plan's own tiling:
+  // tiled items of one tile orbit in the direct-LDS layout, at most
+  // kCgSplitTiles tiles and kCgSplitUnits element orbits per thread, every
+  // tile's chunks in one pass of the workgroup, no inner runs, d <= 3
+  // (decided with the tables, upload_tables)
+  bool cg_split = false;
 
   // index-pair form (SPINSUM_FLAG_INDEX_PAIRS): T.g describes one pair
   // block, T.reps holds the representative pool, T.nb / T.vw / T.ragged /
@@ -145,11 +151,7 @@ spinsum_status choose_tile(const spinsum_plan_s& P, int n, int64_t ncubes, int v
                            spinsum_tile_t* tile, bool single);
 int max_vector_width(const spinsum_plan_s& P, int64_t row);
 spinsum_status upload_tables(spinsum_plan_s* P);
-// The coefficient gradient runs k_cgrad_split on the plan's own tiling:
-// tiled items of one tile orbit in the direct-LDS layout, at most
-// kCgSplitTiles tiles and kCgSplitUnits element orbits per thread, every
-// tile's chunks in one pass of the workgroup, no inner runs, d <= 3.
-bool cgrad_split_ok(const spinsum_plan_s& P);
+
 spinsum_status build_batched(spinsum_plan_s* P, int64_t item_bytes);
 void free_device(spinsum_plan_s* P);
 int elem_size(const spinsum_plan_s& P);
