@@ -2,7 +2,6 @@
 GPU is refused with a message before anything touches a GPU, and `traffic`
 comes from a counter summary only while the kernel sources it was taken on
 are the current ones."""
-import json
 import os
 import re
 import subprocess
