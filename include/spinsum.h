@@ -170,9 +170,11 @@ typedef struct {
   int nt_loads;          /* 1: the direct-LDS kernel loads tiles with the non-temporal
                             policy, chosen where every work item owns the 128-byte lines
                             it reads (whole cubes, or tile rows that start and end on line
-                            boundaries), and for the whole-cube items of batched plans;
-                            0: default policy, which keeps lines that several items share
-                            in the L2 */
+                            boundaries, for a tensor that starts on a 128-byte boundary as
+                            allocations do; an offset view shares some lines between items,
+                            which costs speed, not results), and for the whole-cube items
+                            of batched plans; 0: default policy, which keeps lines that
+                            several items share in the L2 */
   int coef_grad_split;   /* 1: spinsum_coef_grad keeps one tensor in LDS at a time (the
                             upstream gradient waits in registers while x's orbits are
                             gathered), on this plan's tiling; 0: both tensors in LDS */
