@@ -178,6 +178,10 @@ typedef struct {
   int coef_grad_split;   /* 1: spinsum_coef_grad keeps one tensor in LDS at a time (the
                             upstream gradient waits in registers while x's orbits are
                             gathered), on this plan's tiling; 0: both tensors in LDS */
+  int unpack_bl;         /* tile edge of spinsum_unpack: its own tiling of the largest
+                            items a CU holds (whole cubes where a cube fits the LDS, else
+                            the largest edge whose rows are whole 128-byte lines), or the
+                            plan's bl; 0 for index-pair and batched plans */
 } spinsum_plan_info_t;
 
 /* Create a plan for Out = S_K(...S_1(In)) (Def. 3-4; in-place: Sec. 4.6.5).

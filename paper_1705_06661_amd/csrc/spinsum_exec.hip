@@ -607,7 +607,10 @@ int64_t ncomb_of(int n, int d) {
 template <typename T>
 spinsum_status launch_pack(spinsum_plan_s* P, const void* full, void* packed, bool pack,
                            hipStream_t stream) {
-  const Tiling& Tl = P->T;
+  // unpacking on its own tiling where the plan has one (the largest items
+  // that fit a CU, see build_unpack_tiling); packing on the plan's
+  const bool own = !pack && P->pk_own;
+  const Tiling& Tl = own ? P->Tu : P->T;
   if (Tl.nitems <= 0) return SPINSUM_OK;
   PackArgs<T> a;
   std::memset(&a, 0, sizeof(a));
@@ -618,11 +621,12 @@ spinsum_status launch_pack(spinsum_plan_s* P, const void* full, void* packed, bo
     a.full_out = reinterpret_cast<T*>(const_cast<void*>(full));
     a.packed_in = reinterpret_cast<const T*>(packed);
   }
-  a.orbits = reinterpret_cast<const GroupDev*>(P->d_orbits);
+  a.orbits = reinterpret_cast<const GroupDev*>(own ? P->d_pk_orbits : P->d_orbits);
   // packing writes one packed value per representative: in lexicographic
   // order the lanes of a wave write neighbouring entries (unpacking reads
   // them, and gains more from the bank-spreading order of its LDS scatter)
-  a.reps = reinterpret_cast<const uint32_t*>(pack && P->d_reps_lex ? P->d_reps_lex : P->d_reps);
+  a.reps = reinterpret_cast<const uint32_t*>(
+      own ? P->d_pk_reps : (pack && P->d_reps_lex ? P->d_reps_lex : P->d_reps));
   a.coef = reinterpret_cast<const T*>(P->d_mats);  // the pre-multiplied forward vector
   a.g = Tl.g;
   a.nitems = Tl.nitems;
@@ -641,8 +645,8 @@ spinsum_status launch_pack(spinsum_plan_s* P, const void* full, void* packed, bo
     grid = a.xcd_per * 8;
   }
   void* kargs[] = {&a};
-  hipError_t e =
-      hipLaunchKernel(k, dim3((unsigned)grid), dim3(P->tile.threads), kargs, shmem, stream);
+  hipError_t e = hipLaunchKernel(k, dim3((unsigned)grid), dim3(own ? P->pk_threads : P->tile.threads),
+                                 kargs, shmem, stream);
   if (e != hipSuccess) return hip_error(P, e);
   return SPINSUM_OK;
 }

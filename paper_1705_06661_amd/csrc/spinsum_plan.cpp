@@ -541,13 +541,14 @@ static spinsum_status hip_fail(spinsum_plan_s* P, hipError_t e) {
 void free_device(spinsum_plan_s* P) {
   void** ptrs[] = {&P->d_orbits,    &P->d_reps,        &P->d_mats,      &P->d_blocks,
                    &P->d_items,     &P->d_grad_part,   &P->d_cg_orbits, &P->d_cg_reps,
-                   &P->d_reps_lex};
+                   &P->d_reps_lex,  &P->d_pk_orbits,   &P->d_pk_reps};
   for (void** p : ptrs) {
     if (*p) (void)hipFree(*p);
     *p = nullptr;
   }
   P->has_dev = false;
   P->cg_pack = false;
+  P->pk_own = false;
 }
 
 template <typename V>
@@ -611,9 +612,93 @@ static spinsum_status build_cgrad_tiling(spinsum_plan_s* P) {
   return SPINSUM_OK;
 }
 
+// Store mode (measured on MI355X): non-temporal stores stream whole lines
+// best (3D o=32 slab: +2 %), but where tile rows are shorter than 64 bytes,
+// or a cube is cut into more than 128 tile orbits (the items that write the
+// parts of one 128-byte line then run far apart), cached stores let the L2
+// merge the partial lines first: 4D o=12 slab +3 %, one 352^3 cube +2.5 %,
+// one 80^4 cube +10 %.
+static int choose_nts(const spinsum_plan_s& P, const Tiling& T, int64_t orbits) {
+  if (P.flags & SPINSUM_FLAG_NO_NT_STORES) return 0;
+  if (P.flags & SPINSUM_FLAG_NT_STORES) return 1;
+  const bool whole = (T.g.bl == T.g.n) && !P.pair;
+  if (whole) return 1;
+  const int64_t row = (int64_t)T.g.bl * T.g.inner * elem_size(P);
+  return (row >= 64 && orbits <= 128) ? 1 : 0;
+}
+
+// Load policy of the direct-LDS kernel: non-temporal where every work item
+// owns the 128-byte lines it reads, so that no other item needs them in the
+// L2 -- whole cubes (one contiguous run per item), or tile rows that start
+// and end on line boundaries (the row stride, the tile row and the ragged
+// last tile row all multiples of 128 bytes).  Measured on MI355X: inner
+// runs of 8 (256-byte rows) +5 %, Fig. 1b's subgroup plan +6 %, whole
+// 24^3 FP32 cubes +3 to +4 %; with 64-byte rows the same loads are 14 %
+// slower, and with 32-byte rows in one 80^4 cube 23 %.
+static int choose_ntl(const spinsum_plan_s& P, const Tiling& T) {
+  if (P.flags & SPINSUM_FLAG_NO_NT_LOADS) return 0;
+  if (P.pair || T.g.n <= 0) return 0;
+  if (T.g.bl == T.g.n) return 1;
+  const int64_t e = (int64_t)T.g.inner * elem_size(P);
+  const int64_t last = T.g.n - (int64_t)(T.nb - 1) * T.g.bl;
+  return ((e * T.g.n) % 128 == 0 && (e * T.g.bl) % 128 == 0 && (e * last) % 128 == 0) ? 1 : 0;
+}
+
+// Unpacking's own tiling where it differs from T (pk_own).  Unpacking reads
+// only the packed values and writes every element of its items once, so it
+// gains from the largest items a CU holds: whole cubes where a cube (with
+// its representative list) fits the LDS, else the largest tile edge whose
+// rows are whole 128-byte lines and whose items fit.  The sum and packing
+// keep T.  Measured on MI355X: whole 24^3 FP64 cubes 4.24 against 2.60
+// TB/s, whole 32^3 FP32 cubes 3.37 against 2.46, bl = 16 on 32^3 FP64
+// cubes 2.98 against 2.68 (packing with the same tiles: equal, or 27-37 %
+// slower).
+static void choose_unpack_tiling(spinsum_plan_s* P) {
+  P->pk_own = false;
+  const Tiling& T = P->T;
+  if (P->pair || P->batched || P->ncubes <= 0 || P->elems <= 0 || T.g.bl >= T.g.n ||
+      P->tile.lds_pad != 0 || P->tile.variant != SPINSUM_VARIANT_DIRECT_LDS)
+    return;
+  const int esz = elem_size(*P);
+  const int d = P->d;
+  int64_t df = 1;
+  for (int k = 2; k <= d; ++k) df *= k;
+  const int vmax = max_vector_width(*P, (int64_t)P->n * P->inner);
+  auto lds_of = [&](const Tiling& X) {
+    return (X.lds_elems * esz + 15) / 16 * 16 + (int64_t)X.max_rep_cnt * 4;
+  };
+  std::vector<int> cand;
+  if (ipow(P->n, d) * P->inner * esz <= P->lds_limit) cand.push_back(P->n);  // whole cubes
+  for (int bl = P->n - 1; bl > T.g.bl; --bl) {
+    const int64_t tile_bytes = ipow(bl, d) * P->inner * esz;
+    const int nb = (P->n + bl - 1) / bl;
+    if (((int64_t)bl * P->inner * esz) % 128 != 0) continue;
+    if (tile_bytes * (nb >= d ? df : 1) > P->lds_limit) continue;  // a generic orbit's tiles
+    cand.push_back(bl);
+  }
+  for (int bl : cand) {
+    spinsum_tile_t t = P->tile;
+    t.bl = bl;
+    t.cubes_per_wg = 1;
+    t.item_tiles = 0;
+    t.threads = 0;
+    Tiling Tu;
+    if (build_tiling(*P, P->n, P->ncubes, t, vmax, &Tu) != SPINSUM_OK) continue;
+    if (!Tu.fits || lds_of(Tu) > P->lds_limit) continue;
+    if (bl < P->n && (int64_t)Tu.vw * esz != 16) continue;  // rows of whole 16-byte chunks
+    const int64_t per_cu = std::max<int64_t>(1, P->lds_limit / std::max<int64_t>(1, lds_of(Tu)));
+    Tu.nts = choose_nts(*P, Tu, (int64_t)Tu.orbits.size());
+    P->pk_threads = per_cu >= 4 ? 256 : per_cu >= 2 ? 512 : 1024;
+    P->Tu = std::move(Tu);
+    P->pk_own = true;
+    return;
+  }
+}
+
 spinsum_status upload_tables(spinsum_plan_s* P) {
   free_device(P);
   P->cg_split = cgrad_split_ok(*P);
+  choose_unpack_tiling(P);
   if (P->flags & SPINSUM_FLAG_HOST_ONLY) return SPINSUM_OK;
   spinsum_status st;
   // coefficient vectors in the storage type: forward | adjoint | stages | adjoint stages
@@ -648,6 +733,12 @@ spinsum_status upload_tables(spinsum_plan_s* P) {
     if (st != SPINSUM_OK) return st;
     st = build_cgrad_tiling(P);
     if (st != SPINSUM_OK) return st;
+    if (P->pk_own) {
+      st = upload(P, &P->d_pk_orbits, P->Tu.groups.data(), P->Tu.groups.size());
+      if (st != SPINSUM_OK) return st;
+      st = upload(P, &P->d_pk_reps, P->Tu.reps.data(), P->Tu.reps.size());
+      if (st != SPINSUM_OK) return st;
+    }
   } else {
     std::vector<GroupDev> groups;
     std::vector<uint32_t> reps;
@@ -968,38 +1059,6 @@ static spinsum_status build_pair_tiling(spinsum_plan_s* P, const spinsum_tile_t&
   P->pg = pg;
   P->pair_orbits = std::move(orbits);
   return SPINSUM_OK;
-}
-
-// Store mode (measured on MI355X): non-temporal stores stream whole lines
-// best (3D o=32 slab: +2 %), but where tile rows are shorter than 64 bytes,
-// or a cube is cut into more than 128 tile orbits (the items that write the
-// parts of one 128-byte line then run far apart), cached stores let the L2
-// merge the partial lines first: 4D o=12 slab +3 %, one 352^3 cube +2.5 %,
-// one 80^4 cube +10 %.
-static int choose_nts(const spinsum_plan_s& P, const Tiling& T, int64_t orbits) {
-  if (P.flags & SPINSUM_FLAG_NO_NT_STORES) return 0;
-  if (P.flags & SPINSUM_FLAG_NT_STORES) return 1;
-  const bool whole = (T.g.bl == T.g.n) && !P.pair;
-  if (whole) return 1;
-  const int64_t row = (int64_t)T.g.bl * T.g.inner * elem_size(P);
-  return (row >= 64 && orbits <= 128) ? 1 : 0;
-}
-
-// Load policy of the direct-LDS kernel: non-temporal where every work item
-// owns the 128-byte lines it reads, so that no other item needs them in the
-// L2 -- whole cubes (one contiguous run per item), or tile rows that start
-// and end on line boundaries (the row stride, the tile row and the ragged
-// last tile row all multiples of 128 bytes).  Measured on MI355X: inner
-// runs of 8 (256-byte rows) +5 %, Fig. 1b's subgroup plan +6 %, whole
-// 24^3 FP32 cubes +3 to +4 %; with 64-byte rows the same loads are 14 %
-// slower, and with 32-byte rows in one 80^4 cube 23 %.
-static int choose_ntl(const spinsum_plan_s& P, const Tiling& T) {
-  if (P.flags & SPINSUM_FLAG_NO_NT_LOADS) return 0;
-  if (P.pair || T.g.n <= 0) return 0;
-  if (T.g.bl == T.g.n) return 1;
-  const int64_t e = (int64_t)T.g.inner * elem_size(P);
-  const int64_t last = T.g.n - (int64_t)(T.nb - 1) * T.g.bl;
-  return ((e * T.g.n) % 128 == 0 && (e * T.g.bl) % 128 == 0 && (e * last) % 128 == 0) ? 1 : 0;
 }
 
 static spinsum_status apply_pair_tile(spinsum_plan_s* P, const spinsum_tile_t* req) {
@@ -1508,6 +1567,7 @@ extern "C" spinsum_status spinsum_plan_get_info(spinsum_plan_t P, spinsum_plan_i
     info->nterms_expanded = nz;
     info->exec_group_first = P->sub_first;
     info->coef_grad_split = P->cg_split ? 1 : 0;  // the gradient runs on the whole group
+    info->unpack_bl = P->pk_own ? P->Tu.g.bl : P->T.g.bl;  // and so does unpacking
     return SPINSUM_OK;
   }
   std::memset(info, 0, sizeof(*info));
@@ -1536,6 +1596,7 @@ extern "C" spinsum_status spinsum_plan_get_info(spinsum_plan_t P, spinsum_plan_i
   info->nt_stores = P->batched ? 1 : P->T.nts;
   info->nt_loads = P->batched ? 1 : P->T.ntl;
   info->coef_grad_split = P->cg_split ? 1 : 0;
+  info->unpack_bl = (P->batched || P->pair) ? 0 : P->pk_own ? P->Tu.g.bl : P->T.g.bl;
   info->batch_item_bytes = P->batched ? P->batch_item_bytes : 0;
   info->batch_persistent = P->batched ? P->batch_persistent : 0;
   if (!P->batched) {

@@ -97,6 +97,11 @@ struct spinsum_plan_s {
   // tile's chunks in one pass of the workgroup, no inner runs, d <= 3
   // (decided with the tables, upload_tables)
   bool cg_split = false;
+  // unpacking's own tiling where it differs from T (pk_own): the largest
+  // items that fit a CU (see build_unpack_tiling), with their workgroup size
+  spinsum::Tiling Tu;
+  bool pk_own = false;
+  int pk_threads = 256;
 
   // index-pair form (SPINSUM_FLAG_INDEX_PAIRS): T.g describes one pair
   // block, T.reps holds the representative pool, T.nb / T.vw / T.ragged /
@@ -137,6 +142,8 @@ struct spinsum_plan_s {
   void* d_grad_part = nullptr;  // kGradSlots x d! doubles (spinsum_coef_grad)
   void* d_cg_orbits = nullptr;  // Tc.groups, Tc.reps (cg_pack)
   void* d_cg_reps = nullptr;
+  void* d_pk_orbits = nullptr;  // Tu.groups, Tu.reps (pk_own)
+  void* d_pk_reps = nullptr;
   int last_hip_error = 0;
   int occ_blocks = 1;  // workgroups per CU of the persistent exec kernel (cache_occupancy)
   std::string why;

@@ -5,6 +5,7 @@ the chain, and its adjoint).
 Bars: FP64 normwise 1e-14, FP32 2e-6 (against the oracle on the FP32-rounded
 input), integer-valued inputs bit for bit, Inf/NaN patterns exactly.
 """
+import itertools
 import math
 
 import numpy as np
@@ -135,3 +136,47 @@ def test_unpack_non_finite_and_errors():
     pp = ss.spinsum_plan((2, 3, 3, 3, 4, 4, 4), 4, 3, stages, flags=ss.SPINSUM_FLAG_INDEX_PAIRS)
     st = ss._c_unpack(pp._h, big.data_ptr(), big.data_ptr() + 8 * 4096, None)
     assert st == ss.SPINSUM_ERR_UNSUPPORTED
+
+
+OWN_TILING_CASES = [
+    # (shape, group_first, d, dtype): plans whose unpacking runs on its own
+    # tiling (whole cubes, or tiles with whole-line rows), unpack_bl != bl
+    ((3, 24, 24, 24), 1, 3, torch.float64),      # whole 24^3 cubes
+    ((2, 2, 32, 32, 32), 2, 3, torch.float64),   # bl 16: 128-byte rows
+    ((2, 32, 32, 32), 1, 3, torch.float32),      # whole 32^3 FP32 cubes
+    ((3, 16, 16, 16, 4), 1, 3, torch.float64),   # whole cubes with inner runs
+    ((2, 160, 160), 1, 2, torch.float64),         # bl 80 instead of 40
+]
+
+
+@pytest.mark.parametrize("case", range(len(OWN_TILING_CASES)))
+def test_unpack_on_its_own_tiling(case):
+    """Unpacking on its own tiling (the largest items a CU holds) against the
+    oracle, and bit for bit against the sum of the embedded tensor E(packed)
+    through spinsum_exec on the plan's tiling: each output is the one product
+    a(tau^-1) v either way (the sum adds exact zeros); integers bitwise."""
+    shape, gf, d, dtype = OWN_TILING_CASES[case]
+    coefs = np.random.default_rng(case).integers(-3, 4, math.factorial(d))
+    stages = [workloads.antisymmetrizer(d)] if case % 2 == 0 else [
+        [(p, float(c)) for p, c in zip(itertools.permutations(range(d)), coefs)]]
+    p = ss.spinsum_plan(shape, gf, d, stages, dtype=dtype)
+    info = ss.spinsum_plan_get_info(p)
+    assert info["unpack_bl"] != info["bl"], info
+    pshape = ss.packed_shape(p)
+    pk = workloads.uniform(pshape, 4100 + case, device=DEV, dtype=dtype)
+    full = torch.full(shape, float("nan"), dtype=dtype, device=DEV)
+    ss.spinsum_unpack(p, pk, full)
+    torch.cuda.synchronize()
+    pkh = pk.cpu().to(torch.float64).numpy()
+    ref = oracle.unpack(pkh, shape, stages, gf, d)
+    assert nerr(full.cpu().to(torch.float64).numpy(), ref) <= TOL[dtype]
+    emb = torch.from_numpy(oracle.embed_packed(pkh, shape, gf, d)).to(dtype).to(DEV)
+    y = torch.empty_like(emb)
+    ss.spinsum_exec(p, emb, y)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(full.cpu().numpy(), y.cpu().numpy())
+    pki = workloads.integers(pshape, 4200 + case, device=DEV, dtype=dtype)
+    ss.spinsum_unpack(p, pki, full)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(full.cpu().to(torch.float64).numpy(),
+                                  oracle.unpack(pki.cpu().to(torch.float64).numpy(), shape, stages, gf, d))

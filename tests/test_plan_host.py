@@ -221,6 +221,27 @@ def test_coef_grad_kernel_rule():
     assert ss.spinsum_plan_get_info(bp)["coef_grad_split"] == 0
 
 
+def test_unpack_tiling_rule():
+    """Unpacking runs on the largest items a CU holds: whole cubes where a
+    cube and its representative list fit the LDS, else the largest tile
+    edge whose rows are whole 128-byte lines and whose items fit; the plan's
+    own tiling otherwise (unpack_bl reports it)."""
+    as3, as4 = [workloads.antisymmetrizer(3)], [workloads.antisymmetrizer(4)]
+    def ub(shape, gf, d, terms, dtype="f64"):
+        i = ss.spinsum_plan_get_info(ss.spinsum_plan(shape, gf, d, terms, dtype=dtype, flags=HOST))
+        return i["bl"], i["unpack_bl"]
+    assert ub((64, 64, 8, 32, 32, 32), 3, 3, as3) == (8, 16)       # 256 KiB cubes: 128-byte rows
+    assert ub((48, 48, 48, 24, 24, 24), 3, 3, as3) == (8, 24)      # whole 108 KiB cubes
+    assert ub((64, 64, 8, 32, 32, 32), 3, 3, as3, "f32") == (16, 32)
+    assert ub((3, 16, 16, 16, 4), 1, 3, as3) == (5, 16)            # whole cubes, inner runs
+    assert ub((1, 24, 24, 24, 12, 12, 12, 12), 4, 4, as4) == (6, 6)  # 162 KiB cubes, 48-byte rows
+    assert ub((80, 80, 80, 80), 0, 4, as4) == (4, 4)
+    assert ub((4, 11, 11, 11), 1, 3, as3) == (11, 11)              # whole cubes already
+    assert ub((2, 160, 160), 1, 2, [workloads.antisymmetrizer(2)]) == (40, 80)
+    bp = ss.spinsum_plan_batched([(8, 8, 8, 4, 4, 4)], 3, as3, flags=HOST)
+    assert ss.spinsum_plan_get_info(bp)["unpack_bl"] == 0
+
+
 def test_inner_spectator_geometry():
     """A cube of [.., N^d, inner] is N^d * inner contiguous elements; rows
     along the last group axis hold bl * inner elements."""
