@@ -92,7 +92,8 @@ class _Info(ctypes.Structure):
                 ("batch_persistent", ctypes.c_int), ("nt_stores", ctypes.c_int),
                 ("exec_d", ctypes.c_int), ("exec_group_first", ctypes.c_int),
                 ("persistent_per_cu", ctypes.c_int), ("nt_loads", ctypes.c_int),
-                ("coef_grad_split", ctypes.c_int), ("unpack_bl", ctypes.c_int)]
+                ("coef_grad_split", ctypes.c_int), ("unpack_bl", ctypes.c_int),
+                ("unpack_cubes", ctypes.c_int)]
 
 
 _vp = ctypes.c_void_p

@@ -2076,6 +2076,99 @@ __global__ void __launch_bounds__(kMaxThreads) k_unpack(const PackArgs<T> a) {
     store_item_lds<T, D, NTS>(g, od, whole, ntl, ragged, dst, lds);
 }
 
+// Unpacking of whole cubes, one cube per item, persistent.  A cube's
+// element orbits (representative, inner index) are the same in every cube,
+// so each thread works out once which packed entry each of its units reads
+// (its rank) and whether the unit is strictly increasing, then walks its
+// XCD's range of cubes: the packed values of the next cube are requested
+// before the current cube's stores, so that their trip to memory overlaps
+// the stores instead of following them.  Output as in k_unpack.
+template <typename T, int D, bool NTS>
+__global__ void __launch_bounds__(kMaxThreads) k_unpack_cubes(const PackArgs<T> a) {
+  constexpr int DF = Fact<D>::v;
+  constexpr int U = kUnpackCubeUnits;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const Geom& g = a.g;
+  const int64_t per = a.xcd_per;
+  const int64_t nloc = (int64_t)(gridDim.x >> 3);
+  int64_t c = (int64_t)(blockIdx.x & 7u) * per + (int64_t)(blockIdx.x >> 3);
+  int64_t cend = (int64_t)(blockIdx.x & 7u) * per + per;
+  if (cend > a.nitems) cend = a.nitems;
+  if (c >= cend) return;
+  const cptr<GroupDev> od = as_const(a.orbits);
+  const uint32_t rep_cnt = (uint32_t)od->rep_cnt[0];
+  const uint32_t nunit = rep_cnt * (uint32_t)g.inner;
+  const FastDiv fdr = load_fd(od->fd_rep[0]);
+  const uint32_t* rp = a.reps + od->rep_off[0];
+  int32_t sb[DF];
+#pragma unroll
+  for (int r = 0; r < DF; ++r) sb[r] = od->slot_base[0][r];
+  T co[DF];
+  const cptr<T> coef = as_const(a.coef);
+#pragma unroll
+  for (int r = 0; r < DF; ++r) co[r] = coef[r];
+  // per unit: its representative (one byte per axis), its offset in a
+  // cube's packed values, or -1 where the tuple repeats an index (the
+  // orbit's outputs are zero) or the unit does not exist (-2)
+  uint32_t pk[U];
+  int32_t poff[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint32_t i = threadIdx.x + (uint32_t)u * blockDim.x;
+    pk[u] = 0;
+    poff[u] = -2;
+    if (i < nunit) {
+      uint32_t ci, ri, si;
+      split_unit(g, i, rep_cnt, fdr, 1, &ci, &ri, &si);
+      pk[u] = rp[ri];
+      int X[D];
+#pragma unroll
+      for (int m = 0; m < D; ++m) X[m] = (int)((pk[u] >> (8 * m)) & 255u);
+      bool st = true;
+#pragma unroll
+      for (int m = 0; m + 1 < D; ++m) st = st && (X[m] < X[m + 1]);
+      poff[u] = st ? (int32_t)(increasing_rank<D>(X, g.n, a.ncomb) * g.inner + (int64_t)si) : -1;
+    }
+  }
+  const int64_t pstride = a.ncomb * (int64_t)g.inner;
+  T v[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) v[u] = poff[u] >= 0 ? a.packed_in[c * pstride + poff[u]] : T(0);
+  for (;;) {
+    T* dst = a.full_out + c * g.cube_elems;
+    const int shift = flat_shift<T>(dst);
+    T* lds = reinterpret_cast<T*>(smem) + shift;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (poff[u] == -2) continue;
+      const uint32_t i = threadIdx.x + (uint32_t)u * blockDim.x;
+      const uint32_t si = (g.inner != 1) ? i - fdiv(i, g.fd_inner) * (uint32_t)g.inner : 0u;
+      int l[D];
+#pragma unroll
+      for (int m = 0; m < D; ++m) l[m] = (int)((pk[u] >> (8 * m)) & 255u);
+      int addr[DF];
+      orbit_addrs<D>(g, (int)si, sb, l, addr, std::make_integer_sequence<int, DF>{});
+      if (poff[u] >= 0) {
+        unpack_rows<T, D>(co, v[u], lds, addr, std::make_integer_sequence<int, DF>{});
+      } else {
+#pragma unroll
+        for (int r = 0; r < DF; ++r) lds[addr[r]] = T(0);
+      }
+    }
+    __syncthreads();
+    const int64_t cn = c + nloc;
+    if (cn < cend) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = poff[u] >= 0 ? a.packed_in[cn * pstride + poff[u]] : T(0);
+    }
+    flat_store<T, NTS>(dst, (uint32_t)g.cube_elems, smem, shift);
+    if (cn >= cend) break;
+    // every thread has read its part of this cube from LDS
+    __syncthreads();
+    c = cn;
+  }
+}
+
 // Packing, the adjoint of unpacking: packed = E^T S^T full -- for every
 // strictly increasing x, sum_sigma a(sigma^-1) full[sigma . x].  The item's
 // tiles are loaded as in k_lds; nothing is stored to the full tensor.
@@ -2212,8 +2305,14 @@ const void* cgrad_kernel(bool split) {
 }
 
 template <typename T, int D>
-const void* pack_kernel(bool pack, bool nts) {
+const void* pack_kernel(bool pack, bool nts, bool cubes) {
   if (pack) return (const void*)k_pack<T, D>;
+  if (cubes) {
+    // (d <= 3 only: a 4D orbit's 24 slots per unit would not stay in registers)
+    if constexpr (D <= 3)
+      return nts ? (const void*)k_unpack_cubes<T, D, true> : (const void*)k_unpack_cubes<T, D, false>;
+    return nullptr;
+  }
   return nts ? (const void*)k_unpack<T, D, true> : (const void*)k_unpack<T, D, false>;
 }
 
@@ -2242,7 +2341,7 @@ const void* batched_kernel(int vw, bool persist) {
   const void* pick_##tag##_d##d(int kind, int vw, bool chain, bool nts, int maxc);     \
   const void* pick_batched_##tag##_d##d(int vw, bool persist);                         \
   const void* pick_cgrad_##tag##_d##d(bool split);                                      \
-  const void* pick_pack_##tag##_d##d(bool pack, bool nts);
+  const void* pick_pack_##tag##_d##d(bool pack, bool nts, bool cubes);
 SPINSUM_DECLARE_PICK(f64, 2)
 SPINSUM_DECLARE_PICK(f64, 3)
 SPINSUM_DECLARE_PICK(f64, 4)

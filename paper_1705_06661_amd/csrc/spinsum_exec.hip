@@ -47,15 +47,15 @@ const void* pick_batched(int d, int vw, bool persist) {
 }
 
 template <typename T>
-const void* pick_pack(int d, bool pack, bool nts) {
+const void* pick_pack(int d, bool pack, bool nts, bool cubes) {
   if constexpr (sizeof(T) == 8) {
-    if (d == 2) return pick_pack_f64_d2(pack, nts);
-    if (d == 3) return pick_pack_f64_d3(pack, nts);
-    return pick_pack_f64_d4(pack, nts);
+    if (d == 2) return pick_pack_f64_d2(pack, nts, cubes);
+    if (d == 3) return pick_pack_f64_d3(pack, nts, cubes);
+    return pick_pack_f64_d4(pack, nts, cubes);
   } else {
-    if (d == 2) return pick_pack_f32_d2(pack, nts);
-    if (d == 3) return pick_pack_f32_d3(pack, nts);
-    return pick_pack_f32_d4(pack, nts);
+    if (d == 2) return pick_pack_f32_d2(pack, nts, cubes);
+    if (d == 3) return pick_pack_f32_d3(pack, nts, cubes);
+    return pick_pack_f32_d4(pack, nts, cubes);
   }
 }
 
@@ -316,6 +316,23 @@ spinsum_status occupancy_of(spinsum_plan_s* P) {
   return SPINSUM_OK;
 }
 
+// Workgroups per CU of the persistent whole-cube unpacking kernel.
+template <typename T>
+spinsum_status unpack_occupancy_of(spinsum_plan_s* P) {
+  P->pk_cube_blocks = 1;
+  if (!P->pk_cubes) return SPINSUM_OK;
+  const void* k = pick_pack<T>(P->d, false, P->Tu.nts != 0, true);
+  if (k == nullptr) return SPINSUM_ERR_UNSUPPORTED;
+  const size_t shmem = ((size_t)P->Tu.lds_elems * sizeof(T) + 15) / 16 * 16;
+  spinsum_status st = prepare_kernel(P, k, shmem);
+  if (st != SPINSUM_OK) return st;
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, P->pk_threads, shmem);
+  if (e != hipSuccess) return hip_error(P, e);
+  P->pk_cube_blocks = std::max(1, per_cu);
+  return SPINSUM_OK;
+}
+
 spinsum_status check_device(spinsum_plan_s* P) {
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);
@@ -348,8 +365,9 @@ spinsum_status check_tensor_args(spinsum_plan_s* P, const void* in, const void* 
 // only reads the plan.
 spinsum_status cache_occupancy(spinsum_plan_s* P) {
   if (!P->has_dev) return SPINSUM_OK;
-  if (P->dtype == SPINSUM_F32) return occupancy_of<float>(P);
-  return occupancy_of<double>(P);
+  spinsum_status st = P->dtype == SPINSUM_F32 ? occupancy_of<float>(P) : occupancy_of<double>(P);
+  if (st != SPINSUM_OK) return st;
+  return P->dtype == SPINSUM_F32 ? unpack_occupancy_of<float>(P) : unpack_occupancy_of<double>(P);
 }
 
 }  // namespace spinsum
@@ -632,12 +650,21 @@ spinsum_status launch_pack(spinsum_plan_s* P, const void* full, void* packed, bo
   a.nitems = Tl.nitems;
   a.ncomb = ncomb_of(P->n, P->d);
   a.lds_tile_bytes = (int32_t)(((size_t)Tl.lds_elems * sizeof(T) + 15) / 16 * 16);
-  const void* k = pick_pack<T>(P->d, pack, Tl.nts != 0);
-  const size_t shmem = (size_t)a.lds_tile_bytes + (size_t)Tl.max_rep_cnt * 4;
+  // whole cubes persistently where the plan allows it: an occupancy-sized
+  // grid, each workgroup walking its XCD's range of cubes (no
+  // representative lists in LDS: every thread keeps its own units)
+  const bool cubes = own && P->pk_cubes && !(P->flags & SPINSUM_FLAG_NO_XCD_REMAP);
+  const void* k = pick_pack<T>(P->d, pack, Tl.nts != 0, cubes);
+  const size_t shmem =
+      (size_t)a.lds_tile_bytes + (cubes ? (size_t)0 : (size_t)Tl.max_rep_cnt * 4);
   spinsum_status st = prepare_kernel(P, k, shmem);
   if (st != SPINSUM_OK) return st;
   int64_t grid;
-  if (P->flags & SPINSUM_FLAG_NO_XCD_REMAP) {
+  if (cubes) {
+    a.xcd_per = (Tl.nitems + 7) / 8;
+    grid = std::min<int64_t>((int64_t)std::max(1, P->pk_cube_blocks) * P->num_cus, a.xcd_per * 8);
+    grid = (grid + 7) / 8 * 8;
+  } else if (P->flags & SPINSUM_FLAG_NO_XCD_REMAP) {
     a.xcd_per = 0;
     grid = Tl.nitems;
   } else {

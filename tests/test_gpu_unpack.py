@@ -180,3 +180,59 @@ def test_unpack_on_its_own_tiling(case):
     torch.cuda.synchronize()
     np.testing.assert_array_equal(full.cpu().to(torch.float64).numpy(),
                                   oracle.unpack(pki.cpu().to(torch.float64).numpy(), shape, stages, gf, d))
+
+
+PERSISTENT_CASES = [
+    # (shape, group_first, d, dtype): whole cubes unpacked by the persistent
+    # kernel, several cubes per workgroup
+    ((2000, 24, 24, 24), 1, 3, torch.float64),    # about 8 cubes per workgroup
+    ((400, 16, 16, 16, 3), 1, 3, torch.float64),  # inner runs of 3
+    ((300, 100, 100), 1, 2, torch.float64),
+    ((500, 32, 32, 32), 1, 3, torch.float32),
+    ((64, 2, 2, 24, 24, 24), 3, 3, torch.float64),  # several outer axes
+]
+
+
+def _cube_view(shape, gf, d):
+    """(outer cubes, N, .., N, inner..) and the packed (outer, C(N, d), inner..)."""
+    outer = math.prod(shape[:gf])
+    n = shape[gf]
+    return (outer,) + (n,) * d + tuple(shape[gf + d:]), (outer, math.comb(n, d)) + tuple(shape[gf + d:])
+
+
+@pytest.mark.parametrize("case", range(len(PERSISTENT_CASES)))
+def test_unpack_whole_cubes_persistent(case):
+    """Persistent whole-cube unpacking: bit for bit against the one-item-per-
+    workgroup kernel on the same tiling (SPINSUM_FLAG_NO_XCD_REMAP switches
+    the persistent launch off; each output is the same one product either
+    way), against the oracle on sampled cubes (first, last, and cubes that
+    workgroups take second and later), and bitwise on integers."""
+    shape, gf, d, dtype = PERSISTENT_CASES[case]
+    stages = [workloads.antisymmetrizer(d)] if case % 2 == 0 else [workloads.CONFIG_3D_ALPHA] \
+        if d == 3 else [[((0, 1), 2.0), ((1, 0), -0.5)]]
+    p = ss.spinsum_plan(shape, gf, d, stages, dtype=dtype)
+    q = ss.spinsum_plan(shape, gf, d, stages, dtype=dtype, flags=ss.SPINSUM_FLAG_NO_XCD_REMAP)
+    assert ss.spinsum_plan_get_info(p)["unpack_cubes"] == 1
+    assert ss.spinsum_plan_get_info(q)["unpack_cubes"] == 0
+    cshape, pshape = _cube_view(shape, gf, d)
+    ncube = cshape[0]
+    sample = sorted(c for c in {0, 1, 31, 32, 33, 257, 300, ncube // 2, ncube - 2, ncube - 1}
+                    if c < ncube)
+    for kind in ("uniform", "integers"):
+        gen = workloads.uniform if kind == "uniform" else workloads.integers
+        pk = gen(ss.packed_shape(p), 4300 + case, device=DEV, dtype=dtype)
+        a = torch.full(shape, float("nan"), dtype=dtype, device=DEV)
+        b = torch.full(shape, float("nan"), dtype=dtype, device=DEV)
+        ss.spinsum_unpack(p, pk, a)
+        ss.spinsum_unpack(q, pk, b)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+        pks = pk.reshape(pshape)[sample].cpu().to(torch.float64).numpy()
+        ref = oracle.unpack(pks, (len(sample),) + cshape[1:], stages, 1, d)
+        got = a.reshape(cshape)[sample].cpu().to(torch.float64).numpy()
+        if kind == "uniform":
+            assert nerr(got, ref) <= TOL[dtype]
+        else:
+            np.testing.assert_array_equal(got, ref)
+        del pk, a, b
+        torch.cuda.empty_cache()
