@@ -182,10 +182,11 @@ typedef struct {
                             items a CU holds (whole cubes where a cube fits the LDS, else
                             the largest edge whose rows are whole 128-byte lines), or the
                             plan's bl; 0 for index-pair and batched plans */
-  int unpack_cubes;      /* 1: unpacking runs one whole cube per item in a persistent
-                            launch (each workgroup walks its XCD's range of cubes and
-                            requests the next cube's packed values before the current
-                            cube's stores); 0: one item per workgroup */
+  int unpack_persistent; /* 1: unpacking runs persistently: each workgroup keeps one item
+                            template (a tile orbit or the whole cube), walks its XCD's
+                            range of cubes and requests the next cube's packed values
+                            before the current item's stores; 0: one item per
+                            workgroup */
 } spinsum_plan_info_t;
 
 /* Create a plan for Out = S_K(...S_1(In)) (Def. 3-4; in-place: Sec. 4.6.5).

@@ -230,7 +230,8 @@ struct PackArgs {
   int64_t xcd_per;
   int64_t ncomb;
   int32_t lds_tile_bytes;
-  int32_t pad;
+  int32_t ntmpl;                         // k_unpack_persist: item templates
+  int32_t tmpl_wg[kUnpackTemplates + 1];  // k_unpack_persist: first workgroup of each
 };
 
 // Fused multiply-add in the storage type (a float FMA for float: the
@@ -2076,26 +2077,34 @@ __global__ void __launch_bounds__(kMaxThreads) k_unpack(const PackArgs<T> a) {
     store_item_lds<T, D, NTS>(g, od, whole, ntl, ragged, dst, lds);
 }
 
-// Unpacking of whole cubes, one cube per item, persistent.  A cube's
-// element orbits (representative, inner index) are the same in every cube,
-// so each thread works out once which packed entry each of its units reads
-// (its rank) and whether the unit is strictly increasing, then walks its
-// XCD's range of cubes: the packed values of the next cube are requested
-// before the current cube's stores, so that their trip to memory overlaps
-// the stores instead of following them.  Output as in k_unpack.
+// Unpacking, persistent: each workgroup takes one item template (a tile
+// orbit, or the whole cube) and walks its XCD's range of cubes.  The
+// template's element orbits (representative, inner index) are the same in
+// every cube, so each thread works out once which packed entry each of its
+// units reads (its rank) and whether the unit is strictly increasing; the
+// packed values of the next cube are requested before the current item's
+// stores, so that their trip to memory overlaps the stores instead of
+// following them.  Templates get workgroups in proportion to their tiles
+// (tmpl_wg: prefix sums, multiples of 8).  Output as in k_unpack.
 template <typename T, int D, bool NTS>
-__global__ void __launch_bounds__(kMaxThreads) k_unpack_cubes(const PackArgs<T> a) {
+__global__ void __launch_bounds__(kMaxThreads) k_unpack_persist(const PackArgs<T> a) {
   constexpr int DF = Fact<D>::v;
   constexpr int U = kUnpackCubeUnits;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const Geom& g = a.g;
+  int t = 0;
+  while (t + 1 < a.ntmpl && (int)blockIdx.x >= a.tmpl_wg[t + 1]) ++t;
+  const uint32_t w = blockIdx.x - (uint32_t)a.tmpl_wg[t];
+  const int64_t nloc = (int64_t)((a.tmpl_wg[t + 1] - a.tmpl_wg[t]) >> 3);
   const int64_t per = a.xcd_per;
-  const int64_t nloc = (int64_t)(gridDim.x >> 3);
-  int64_t c = (int64_t)(blockIdx.x & 7u) * per + (int64_t)(blockIdx.x >> 3);
-  int64_t cend = (int64_t)(blockIdx.x & 7u) * per + per;
-  if (cend > a.nitems) cend = a.nitems;
+  int64_t c = (int64_t)(w & 7u) * per + (int64_t)(w >> 3);
+  int64_t cend = (int64_t)(w & 7u) * per + per;
+  if (cend > g.ncubes) cend = g.ncubes;
   if (c >= cend) return;
-  const cptr<GroupDev> od = as_const(a.orbits);
+  const cptr<GroupDev> od = as_const(a.orbits + t);
+  const bool whole = (g.bl == g.n);
+  const bool ragged = od->ragged != 0;
+  const int ntl = whole ? 1 : od->ntiles;
   const uint32_t rep_cnt = (uint32_t)od->rep_cnt[0];
   const uint32_t nunit = rep_cnt * (uint32_t)g.inner;
   const FastDiv fdr = load_fd(od->fd_rep[0]);
@@ -2103,13 +2112,15 @@ __global__ void __launch_bounds__(kMaxThreads) k_unpack_cubes(const PackArgs<T> 
   int32_t sb[DF];
 #pragma unroll
   for (int r = 0; r < DF; ++r) sb[r] = od->slot_base[0][r];
+  int org[D];
+  orbit_origin<D>(g, od, 0, org);
   T co[DF];
   const cptr<T> coef = as_const(a.coef);
 #pragma unroll
   for (int r = 0; r < DF; ++r) co[r] = coef[r];
-  // per unit: its representative (one byte per axis), its offset in a
-  // cube's packed values, or -1 where the tuple repeats an index (the
-  // orbit's outputs are zero) or the unit does not exist (-2)
+  // per unit: its representative (local coordinates, one byte per axis),
+  // its offset in a cube's packed values, or -1 where the tuple repeats an
+  // index (the orbit's outputs are zero) or -2 where the unit does not exist
   uint32_t pk[U];
   int32_t poff[U];
 #pragma unroll
@@ -2123,7 +2134,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_unpack_cubes(const PackArgs<T> 
       pk[u] = rp[ri];
       int X[D];
 #pragma unroll
-      for (int m = 0; m < D; ++m) X[m] = (int)((pk[u] >> (8 * m)) & 255u);
+      for (int m = 0; m < D; ++m) X[m] = org[m] + (int)((pk[u] >> (8 * m)) & 255u);
       bool st = true;
 #pragma unroll
       for (int m = 0; m + 1 < D; ++m) st = st && (X[m] < X[m + 1]);
@@ -2136,7 +2147,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_unpack_cubes(const PackArgs<T> 
   for (int u = 0; u < U; ++u) v[u] = poff[u] >= 0 ? a.packed_in[c * pstride + poff[u]] : T(0);
   for (;;) {
     T* dst = a.full_out + c * g.cube_elems;
-    const int shift = flat_shift<T>(dst);
+    const int shift = whole ? flat_shift<T>(dst) : 0;
     T* lds = reinterpret_cast<T*>(smem) + shift;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -2161,9 +2172,12 @@ __global__ void __launch_bounds__(kMaxThreads) k_unpack_cubes(const PackArgs<T> 
 #pragma unroll
       for (int u = 0; u < U; ++u) v[u] = poff[u] >= 0 ? a.packed_in[cn * pstride + poff[u]] : T(0);
     }
-    flat_store<T, NTS>(dst, (uint32_t)g.cube_elems, smem, shift);
+    if (whole)
+      flat_store<T, NTS>(dst, (uint32_t)g.cube_elems, smem, shift);
+    else
+      store_item_lds<T, D, NTS>(g, od, false, ntl, ragged, dst, lds);
     if (cn >= cend) break;
-    // every thread has read its part of this cube from LDS
+    // every thread has read its part of this item from LDS
     __syncthreads();
     c = cn;
   }
@@ -2305,12 +2319,12 @@ const void* cgrad_kernel(bool split) {
 }
 
 template <typename T, int D>
-const void* pack_kernel(bool pack, bool nts, bool cubes) {
+const void* pack_kernel(bool pack, bool nts, bool persist) {
   if (pack) return (const void*)k_pack<T, D>;
-  if (cubes) {
+  if (persist) {
     // (d <= 3 only: a 4D orbit's 24 slots per unit would not stay in registers)
     if constexpr (D <= 3)
-      return nts ? (const void*)k_unpack_cubes<T, D, true> : (const void*)k_unpack_cubes<T, D, false>;
+      return nts ? (const void*)k_unpack_persist<T, D, true> : (const void*)k_unpack_persist<T, D, false>;
     return nullptr;
   }
   return nts ? (const void*)k_unpack<T, D, true> : (const void*)k_unpack<T, D, false>;
@@ -2341,7 +2355,7 @@ const void* batched_kernel(int vw, bool persist) {
   const void* pick_##tag##_d##d(int kind, int vw, bool chain, bool nts, int maxc);     \
   const void* pick_batched_##tag##_d##d(int vw, bool persist);                         \
   const void* pick_cgrad_##tag##_d##d(bool split);                                      \
-  const void* pick_pack_##tag##_d##d(bool pack, bool nts, bool cubes);
+  const void* pick_pack_##tag##_d##d(bool pack, bool nts, bool persist);
 SPINSUM_DECLARE_PICK(f64, 2)
 SPINSUM_DECLARE_PICK(f64, 3)
 SPINSUM_DECLARE_PICK(f64, 4)

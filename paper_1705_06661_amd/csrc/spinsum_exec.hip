@@ -47,15 +47,15 @@ const void* pick_batched(int d, int vw, bool persist) {
 }
 
 template <typename T>
-const void* pick_pack(int d, bool pack, bool nts, bool cubes) {
+const void* pick_pack(int d, bool pack, bool nts, bool persist) {
   if constexpr (sizeof(T) == 8) {
-    if (d == 2) return pick_pack_f64_d2(pack, nts, cubes);
-    if (d == 3) return pick_pack_f64_d3(pack, nts, cubes);
-    return pick_pack_f64_d4(pack, nts, cubes);
+    if (d == 2) return pick_pack_f64_d2(pack, nts, persist);
+    if (d == 3) return pick_pack_f64_d3(pack, nts, persist);
+    return pick_pack_f64_d4(pack, nts, persist);
   } else {
-    if (d == 2) return pick_pack_f32_d2(pack, nts, cubes);
-    if (d == 3) return pick_pack_f32_d3(pack, nts, cubes);
-    return pick_pack_f32_d4(pack, nts, cubes);
+    if (d == 2) return pick_pack_f32_d2(pack, nts, persist);
+    if (d == 3) return pick_pack_f32_d3(pack, nts, persist);
+    return pick_pack_f32_d4(pack, nts, persist);
   }
 }
 
@@ -316,11 +316,11 @@ spinsum_status occupancy_of(spinsum_plan_s* P) {
   return SPINSUM_OK;
 }
 
-// Workgroups per CU of the persistent whole-cube unpacking kernel.
+// Workgroups per CU of the persistent unpacking kernel.
 template <typename T>
 spinsum_status unpack_occupancy_of(spinsum_plan_s* P) {
-  P->pk_cube_blocks = 1;
-  if (!P->pk_cubes) return SPINSUM_OK;
+  P->pk_persist_blocks = 1;
+  if (!P->pk_persist) return SPINSUM_OK;
   const void* k = pick_pack<T>(P->d, false, P->Tu.nts != 0, true);
   if (k == nullptr) return SPINSUM_ERR_UNSUPPORTED;
   const size_t shmem = ((size_t)P->Tu.lds_elems * sizeof(T) + 15) / 16 * 16;
@@ -329,7 +329,7 @@ spinsum_status unpack_occupancy_of(spinsum_plan_s* P) {
   int per_cu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, P->pk_threads, shmem);
   if (e != hipSuccess) return hip_error(P, e);
-  P->pk_cube_blocks = std::max(1, per_cu);
+  P->pk_persist_blocks = std::max(1, per_cu);
   return SPINSUM_OK;
 }
 
@@ -650,20 +650,32 @@ spinsum_status launch_pack(spinsum_plan_s* P, const void* full, void* packed, bo
   a.nitems = Tl.nitems;
   a.ncomb = ncomb_of(P->n, P->d);
   a.lds_tile_bytes = (int32_t)(((size_t)Tl.lds_elems * sizeof(T) + 15) / 16 * 16);
-  // whole cubes persistently where the plan allows it: an occupancy-sized
-  // grid, each workgroup walking its XCD's range of cubes (no
-  // representative lists in LDS: every thread keeps its own units)
-  const bool cubes = own && P->pk_cubes && !(P->flags & SPINSUM_FLAG_NO_XCD_REMAP);
-  const void* k = pick_pack<T>(P->d, pack, Tl.nts != 0, cubes);
+  // persistently where the plan allows it: an occupancy-sized grid shared
+  // among the item templates in proportion to their tiles, each workgroup
+  // walking its XCD's range of cubes (no representative lists in LDS: every
+  // thread keeps its own units)
+  const bool persist = own && P->pk_persist && !(P->flags & SPINSUM_FLAG_NO_XCD_REMAP);
+  const void* k = pick_pack<T>(P->d, pack, Tl.nts != 0, persist);
   const size_t shmem =
-      (size_t)a.lds_tile_bytes + (cubes ? (size_t)0 : (size_t)Tl.max_rep_cnt * 4);
+      (size_t)a.lds_tile_bytes + (persist ? (size_t)0 : (size_t)Tl.max_rep_cnt * 4);
   spinsum_status st = prepare_kernel(P, k, shmem);
   if (st != SPINSUM_OK) return st;
   int64_t grid;
-  if (cubes) {
-    a.xcd_per = (Tl.nitems + 7) / 8;
-    grid = std::min<int64_t>((int64_t)std::max(1, P->pk_cube_blocks) * P->num_cus, a.xcd_per * 8);
-    grid = (grid + 7) / 8 * 8;
+  if (persist) {
+    a.xcd_per = (P->ncubes + 7) / 8;
+    const int nt = (int)Tl.groups.size();
+    const bool whole = Tl.g.bl == Tl.g.n;
+    int64_t tiles = 0;
+    for (const GroupDev& gd : Tl.groups) tiles += whole ? 1 : gd.ntiles;
+    const int64_t g8 = (int64_t)std::max(1, P->pk_persist_blocks) * P->num_cus / 8;
+    a.ntmpl = nt;
+    a.tmpl_wg[0] = 0;
+    for (int t = 0; t < nt; ++t) {
+      const int64_t share = (g8 * (whole ? 1 : Tl.groups[t].ntiles) + tiles / 2) / std::max<int64_t>(1, tiles);
+      const int64_t w8 = std::min<int64_t>(std::max<int64_t>(1, share), a.xcd_per);
+      a.tmpl_wg[t + 1] = a.tmpl_wg[t] + (int32_t)(8 * w8);
+    }
+    grid = a.tmpl_wg[nt];
   } else if (P->flags & SPINSUM_FLAG_NO_XCD_REMAP) {
     a.xcd_per = 0;
     grid = Tl.nitems;

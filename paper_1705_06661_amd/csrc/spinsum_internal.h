@@ -66,7 +66,8 @@ constexpr int kGradSlots = 2048;     // partial sums of the coefficient gradient
 constexpr int kCgSplitTiles = 6;
 constexpr int kCgSplitUnits = 2;
 constexpr int kCgSplitThreads = 256;
-constexpr int kUnpackCubeUnits = 8;  // k_unpack_cubes: element orbits per thread
+constexpr int kUnpackCubeUnits = 6;  // k_unpack_persist: element orbits per thread
+constexpr int kUnpackTemplates = 8;  // k_unpack_persist: item templates of a launch
 constexpr int kMaxGroupTiles = 24;   // tiles of one work item
 constexpr int kMaxGroupOrbits = 8;   // tile orbits of one work item
 

@@ -12,8 +12,8 @@ const void* pick_batched_f32_d2(int vw, bool persist) { return batched_kernel<fl
 
 const void* pick_cgrad_f32_d2(bool split) { return cgrad_kernel<float, 2>(split); }
 
-const void* pick_pack_f32_d2(bool pack, bool nts, bool cubes) {
-  return pack_kernel<float, 2>(pack, nts, cubes);
+const void* pick_pack_f32_d2(bool pack, bool nts, bool persist) {
+  return pack_kernel<float, 2>(pack, nts, persist);
 }
 
 }  // namespace spinsum

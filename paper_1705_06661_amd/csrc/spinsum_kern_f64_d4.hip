@@ -12,8 +12,8 @@ const void* pick_batched_f64_d4(int vw, bool persist) { return batched_kernel<do
 
 const void* pick_cgrad_f64_d4(bool split) { return cgrad_kernel<double, 4>(split); }
 
-const void* pick_pack_f64_d4(bool pack, bool nts, bool cubes) {
-  return pack_kernel<double, 4>(pack, nts, cubes);
+const void* pick_pack_f64_d4(bool pack, bool nts, bool persist) {
+  return pack_kernel<double, 4>(pack, nts, persist);
 }
 
 }  // namespace spinsum

@@ -655,7 +655,7 @@ static int choose_ntl(const spinsum_plan_s& P, const Tiling& T) {
 // slower).
 static void choose_unpack_tiling(spinsum_plan_s* P) {
   P->pk_own = false;
-  P->pk_cubes = false;
+  P->pk_persist = false;
   const Tiling& T = P->T;
   if (P->pair || P->batched || P->ncubes <= 0 || P->elems <= 0 || T.g.bl >= T.g.n ||
       P->tile.lds_pad != 0 || P->tile.variant != SPINSUM_VARIANT_DIRECT_LDS)
@@ -692,17 +692,20 @@ static void choose_unpack_tiling(spinsum_plan_s* P) {
     P->pk_threads = per_cu >= 4 ? 256 : per_cu >= 2 ? 512 : 1024;
     P->Tu = std::move(Tu);
     P->pk_own = true;
-    // whole cubes (d <= 3), one per item, whose element orbits the
+    // items of one tile orbit (or one whole cube) each, of at most
+    // kUnpackTemplates templates (d <= 3), whose element orbits the
     // workgroup's threads hold all at once (kUnpackCubeUnits each) and whose
-    // packed offsets fit 31 bits: the persistent kernel, k_unpack_cubes
+    // packed offsets fit 31 bits: the persistent kernel, k_unpack_persist
     const Tiling& U = P->Tu;
-    if (d <= 3 && bl == P->n && U.g.cpw == 1 && U.groups.size() == 1 &&
-        U.groups[0].norb == 1) {
+    if (d <= 3 && U.g.cpw == 1 && !U.groups.empty() &&
+        (int)U.groups.size() <= kUnpackTemplates) {
       int64_t nc = 1;
       for (int k = 0; k < d; ++k) nc = nc * (P->n - k) / (k + 1);
-      const int64_t units = (int64_t)U.groups[0].rep_cnt[0] * P->inner;
-      P->pk_cubes = units <= (int64_t)kUnpackCubeUnits * P->pk_threads &&
-                    nc * P->inner < ((int64_t)1 << 31);
+      bool ok = nc * P->inner < ((int64_t)1 << 31);
+      for (const GroupDev& gd : U.groups)
+        ok = ok && gd.norb == 1 &&
+             (int64_t)gd.rep_cnt[0] * P->inner <= (int64_t)kUnpackCubeUnits * P->pk_threads;
+      P->pk_persist = ok;
     }
     return;
   }
@@ -1581,8 +1584,8 @@ extern "C" spinsum_status spinsum_plan_get_info(spinsum_plan_t P, spinsum_plan_i
     info->exec_group_first = P->sub_first;
     info->coef_grad_split = P->cg_split ? 1 : 0;  // the gradient runs on the whole group
     info->unpack_bl = P->pk_own ? P->Tu.g.bl : P->T.g.bl;  // and so does unpacking
-    info->unpack_cubes =
-        (P->pk_own && P->pk_cubes && !(P->flags & SPINSUM_FLAG_NO_XCD_REMAP)) ? 1 : 0;
+    info->unpack_persistent =
+        (P->pk_own && P->pk_persist && !(P->flags & SPINSUM_FLAG_NO_XCD_REMAP)) ? 1 : 0;
     return SPINSUM_OK;
   }
   std::memset(info, 0, sizeof(*info));
@@ -1612,7 +1615,7 @@ extern "C" spinsum_status spinsum_plan_get_info(spinsum_plan_t P, spinsum_plan_i
   info->nt_loads = P->batched ? 1 : P->T.ntl;
   info->coef_grad_split = P->cg_split ? 1 : 0;
   info->unpack_bl = (P->batched || P->pair) ? 0 : P->pk_own ? P->Tu.g.bl : P->T.g.bl;
-  info->unpack_cubes = (!P->batched && !P->pair && P->pk_own && P->pk_cubes &&
+  info->unpack_persistent = (!P->batched && !P->pair && P->pk_own && P->pk_persist &&
                         !(P->flags & SPINSUM_FLAG_NO_XCD_REMAP)) ? 1 : 0;
   info->batch_item_bytes = P->batched ? P->batch_item_bytes : 0;
   info->batch_persistent = P->batched ? P->batch_persistent : 0;

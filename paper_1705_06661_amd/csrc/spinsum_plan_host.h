@@ -102,10 +102,10 @@ struct spinsum_plan_s {
   spinsum::Tiling Tu;
   bool pk_own = false;
   int pk_threads = 256;
-  // whole cubes of Tu run persistently (k_unpack_cubes), pk_cube_blocks
+  // Tu's items run persistently (k_unpack_persist), pk_persist_blocks
   // workgroups per CU (cache_occupancy)
-  bool pk_cubes = false;
-  int pk_cube_blocks = 1;
+  bool pk_persist = false;
+  int pk_persist_blocks = 1;
 
   // index-pair form (SPINSUM_FLAG_INDEX_PAIRS): T.g describes one pair
   // block, T.reps holds the representative pool, T.nb / T.vw / T.ragged /

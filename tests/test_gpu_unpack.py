@@ -183,9 +183,10 @@ def test_unpack_on_its_own_tiling(case):
 
 
 PERSISTENT_CASES = [
-    # (shape, group_first, d, dtype): whole cubes unpacked by the persistent
-    # kernel, several cubes per workgroup
-    ((2000, 24, 24, 24), 1, 3, torch.float64),    # about 8 cubes per workgroup
+    # (shape, group_first, d, dtype): unpacked by the persistent kernel,
+    # several cubes per workgroup
+    ((2000, 24, 24, 24), 1, 3, torch.float64),    # whole cubes, about 8 per workgroup
+    ((400, 32, 32, 32), 1, 3, torch.float64),     # 16^3 tiles: four templates, 1 or 3 tiles
     ((400, 16, 16, 16, 3), 1, 3, torch.float64),  # inner runs of 3
     ((300, 100, 100), 1, 2, torch.float64),
     ((500, 32, 32, 32), 1, 3, torch.float32),
@@ -201,8 +202,8 @@ def _cube_view(shape, gf, d):
 
 
 @pytest.mark.parametrize("case", range(len(PERSISTENT_CASES)))
-def test_unpack_whole_cubes_persistent(case):
-    """Persistent whole-cube unpacking: bit for bit against the one-item-per-
+def test_unpack_persistent(case):
+    """Persistent unpacking: bit for bit against the one-item-per-
     workgroup kernel on the same tiling (SPINSUM_FLAG_NO_XCD_REMAP switches
     the persistent launch off; each output is the same one product either
     way), against the oracle on sampled cubes (first, last, and cubes that
@@ -212,8 +213,8 @@ def test_unpack_whole_cubes_persistent(case):
         if d == 3 else [[((0, 1), 2.0), ((1, 0), -0.5)]]
     p = ss.spinsum_plan(shape, gf, d, stages, dtype=dtype)
     q = ss.spinsum_plan(shape, gf, d, stages, dtype=dtype, flags=ss.SPINSUM_FLAG_NO_XCD_REMAP)
-    assert ss.spinsum_plan_get_info(p)["unpack_cubes"] == 1
-    assert ss.spinsum_plan_get_info(q)["unpack_cubes"] == 0
+    assert ss.spinsum_plan_get_info(p)["unpack_persistent"] == 1
+    assert ss.spinsum_plan_get_info(q)["unpack_persistent"] == 0
     cshape, pshape = _cube_view(shape, gf, d)
     ncube = cshape[0]
     sample = sorted(c for c in {0, 1, 31, 32, 33, 257, 300, ncube // 2, ncube - 2, ncube - 1}

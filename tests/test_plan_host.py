@@ -240,13 +240,16 @@ def test_unpack_tiling_rule():
     assert ub((2, 160, 160), 1, 2, [workloads.antisymmetrizer(2)]) == (40, 80)
     bp = ss.spinsum_plan_batched([(8, 8, 8, 4, 4, 4)], 3, as3, flags=HOST)
     assert ss.spinsum_plan_get_info(bp)["unpack_bl"] == 0
-    # whole cubes of d <= 3 run persistently; tiles, 4D and the ablation flag do not
+    # unpacking's own items of d <= 3 run persistently where each template is
+    # one tile orbit whose units the threads hold; 4D, the plan's own whole
+    # cubes and the ablation flag do not
     cubes = lambda shape, gf, d, terms, dtype="f64", flags=0: ss.spinsum_plan_get_info(
-        ss.spinsum_plan(shape, gf, d, terms, dtype=dtype, flags=HOST | flags))["unpack_cubes"]
+        ss.spinsum_plan(shape, gf, d, terms, dtype=dtype, flags=HOST | flags))["unpack_persistent"]
     assert cubes((48, 48, 48, 24, 24, 24), 3, 3, as3) == 1
     assert cubes((64, 64, 8, 32, 32, 32), 3, 3, as3, "f32") == 1
     assert cubes((300, 100, 100), 1, 2, [workloads.antisymmetrizer(2)]) == 1
-    assert cubes((64, 64, 8, 32, 32, 32), 3, 3, as3) == 0
+    assert cubes((64, 64, 8, 32, 32, 32), 3, 3, as3) == 1
+    assert cubes((60, 160, 160), 1, 2, [workloads.antisymmetrizer(2)]) == 0  # 6400 units
     assert cubes((1, 24, 24, 24, 12, 12, 12, 12), 4, 4, as4) == 0
     assert cubes((4, 11, 11, 11), 1, 3, as3) == 0
     assert cubes((48, 48, 48, 24, 24, 24), 3, 3, as3, flags=ss.SPINSUM_FLAG_NO_XCD_REMAP) == 0
