@@ -352,7 +352,7 @@ def accuracy_report(ss, workloads, dev, stream):
 
 PROFILE_FORMS = ("3d_v64_o32_inplace", "4d_v24_o12_inplace", "4d_table2_5_80_premultiplied",
                  "3d_pairs_v48_o24_inplace", "3d_v48_o24_forward_fp64", "3d_coef_grad",
-                 "stream_copy")
+                 "3d_unpack_antisymmetric", "stream_copy")
 
 
 def profile_one(name, steps, warmup):
@@ -368,6 +368,7 @@ def profile_one(name, steps, warmup):
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
     alpha = [workloads.CONFIG_3D_ALPHA]
+    split = {}  # reads and writes where they are not one each of every element
     slab = workloads.WORKLOADS["3d_v64_o32_slab"]["shape"]
     if name in ("3d_v64_o32_inplace", "3d_coef_grad", "stream_copy"):
         x = workloads.uniform(slab, 1000, device=dev)
@@ -405,6 +406,13 @@ def profile_one(name, steps, warmup):
         p = ss.spinsum_plan(w5["shape"], 3, 3, workloads.FACTORED_PIJ_PJK, inplace=False)
         fn = lambda: ss.spinsum_exec(p, x, y, stream)
         nbytes = 2 * x.numel() * 8
+    elif name == "3d_unpack_antisymmetric":
+        x = torch.empty(slab, dtype=torch.float64, device=dev)
+        p = ss.spinsum_plan(slab, 3, 3, [workloads.antisymmetrizer(3)])
+        pk = workloads.uniform(ss.packed_shape(p), 3200, device=dev)
+        fn = lambda: ss.spinsum_unpack(p, pk, x, stream)
+        split = {"algorithmic_read_bytes": pk.numel() * 8, "algorithmic_write_bytes": x.numel() * 8}
+        nbytes = (pk.numel() + x.numel()) * 8
     else:
         raise SystemExit(f"unknown form {name!r}; one of {', '.join(PROFILE_FORMS)}")
     torch.cuda.synchronize()
@@ -417,9 +425,12 @@ def profile_one(name, steps, warmup):
                       "algorithmic_bytes_per_launch": nbytes,
                       "kernel": {"stream_copy": "k_copy",
                                  "3d_coef_grad": ("k_cgrad_split<double, 3>" if info["coef_grad_split"]
-                                                  else "k_cgrad<double, 3>")}.get(
+                                                  else "k_cgrad<double, 3>"),
+                                 "3d_unpack_antisymmetric": "%s<double, 3, %s>" % (
+                                     "k_unpack_persist" if info["unpack_persistent"] else "k_unpack",
+                                     "true" if info["unpack_nt_stores"] else "false")}.get(
                           name, kernel_name(info)),
-                      "tile_edge": info["bl"],
+                      "tile_edge": info["bl"], **split,
                       "kernel_source_hash": kernel_source_hash()}), flush=True)
 
 
@@ -581,6 +592,7 @@ def main():
         warm(lambda: ss.spinsum_unpack(pu, pk, big[0], stream))
         ums = timed(lambda: ss.spinsum_unpack(pu, pk, big[0], stream), 5, stream)
         forms["3d_unpack_antisymmetric"] = form_entry(ubytes, ums, value)
+        forms["3d_unpack_antisymmetric"]["traffic"] = traffic_from_profile("3d_unpack_antisymmetric")
         warm(lambda: ss.spinsum_pack(pu, big[0], pk, stream))
         pms = timed(lambda: ss.spinsum_pack(pu, big[0], pk, stream), 5, stream)
         forms["3d_pack_antisymmetric"] = form_entry(ubytes, pms, value)

@@ -187,6 +187,7 @@ typedef struct {
                             range of cubes and requests the next cube's packed values
                             before the current item's stores; 0: one item per
                             workgroup */
+  int unpack_nt_stores;  /* 1: unpacking stores with the non-temporal policy */
 } spinsum_plan_info_t;
 
 /* Create a plan for Out = S_K(...S_1(In)) (Def. 3-4; in-place: Sec. 4.6.5).

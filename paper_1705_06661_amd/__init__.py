@@ -93,7 +93,7 @@ class _Info(ctypes.Structure):
                 ("exec_d", ctypes.c_int), ("exec_group_first", ctypes.c_int),
                 ("persistent_per_cu", ctypes.c_int), ("nt_loads", ctypes.c_int),
                 ("coef_grad_split", ctypes.c_int), ("unpack_bl", ctypes.c_int),
-                ("unpack_persistent", ctypes.c_int)]
+                ("unpack_persistent", ctypes.c_int), ("unpack_nt_stores", ctypes.c_int)]
 
 
 _vp = ctypes.c_void_p

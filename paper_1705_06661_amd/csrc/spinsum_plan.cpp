@@ -1586,6 +1586,7 @@ extern "C" spinsum_status spinsum_plan_get_info(spinsum_plan_t P, spinsum_plan_i
     info->unpack_bl = P->pk_own ? P->Tu.g.bl : P->T.g.bl;  // and so does unpacking
     info->unpack_persistent =
         (P->pk_own && P->pk_persist && !(P->flags & SPINSUM_FLAG_NO_XCD_REMAP)) ? 1 : 0;
+    info->unpack_nt_stores = (P->pk_own ? P->Tu.nts : P->T.nts) != 0 ? 1 : 0;
     return SPINSUM_OK;
   }
   std::memset(info, 0, sizeof(*info));
@@ -1615,6 +1616,8 @@ extern "C" spinsum_status spinsum_plan_get_info(spinsum_plan_t P, spinsum_plan_i
   info->nt_loads = P->batched ? 1 : P->T.ntl;
   info->coef_grad_split = P->cg_split ? 1 : 0;
   info->unpack_bl = (P->batched || P->pair) ? 0 : P->pk_own ? P->Tu.g.bl : P->T.g.bl;
+  info->unpack_nt_stores =
+      (!P->batched && !P->pair && (P->pk_own ? P->Tu.nts : P->T.nts) != 0) ? 1 : 0;
   info->unpack_persistent = (!P->batched && !P->pair && P->pk_own && P->pk_persist &&
                         !(P->flags & SPINSUM_FLAG_NO_XCD_REMAP)) ? 1 : 0;
   info->batch_item_bytes = P->batched ? P->batch_item_bytes : 0;
