@@ -88,6 +88,11 @@ def kernel_name(info, dtype="double", chain=False):
     return f"k_exec<{dtype}, {d}, {info['vector_width']}, {c}, {nts}>"
 
 
+def batched_kernel_name(info):
+    """The FP64 3D batched kernel (16-byte chunks), one-shot or persistent."""
+    return "k_batched<double, 3, 2, %s>" % ("true" if info["batch_persistent"] else "false")
+
+
 def warm(fn, seconds=0.25, refill=None):
     """Untimed repeats of a form's call until `seconds` have passed, so that
     a short form is not timed while the GPU clocks are still ramping up
@@ -352,7 +357,8 @@ def accuracy_report(ss, workloads, dev, stream):
 
 PROFILE_FORMS = ("3d_v64_o32_inplace", "4d_v24_o12_inplace", "4d_table2_5_80_premultiplied",
                  "3d_pairs_v48_o24_inplace", "3d_v48_o24_forward_fp64", "3d_coef_grad",
-                 "3d_unpack_antisymmetric", "stream_copy")
+                 "3d_unpack_antisymmetric", "3d_v48_o24_adjoint_fp64", "3d_v48_o24_forward_fp32",
+                 "batched_graph", "stream_copy")
 
 
 def profile_one(name, steps, warmup):
@@ -406,6 +412,31 @@ def profile_one(name, steps, warmup):
         p = ss.spinsum_plan(w5["shape"], 3, 3, workloads.FACTORED_PIJ_PJK, inplace=False)
         fn = lambda: ss.spinsum_exec(p, x, y, stream)
         nbytes = 2 * x.numel() * 8
+    elif name in ("3d_v48_o24_adjoint_fp64", "3d_v48_o24_forward_fp32"):
+        w5 = workloads.WORKLOADS["3d_v48_o24"]
+        dt = torch.float32 if name.endswith("fp32") else torch.float64
+        x = workloads.uniform(w5["shape"], 4000, device=dev, dtype=dt)
+        y = torch.empty_like(x)
+        p = ss.spinsum_plan(w5["shape"], 3, 3, workloads.FACTORED_PIJ_PJK, dtype=dt, inplace=False)
+        if name.startswith("3d_v48_o24_adjoint"):
+            fn = lambda: ss.spinsum_adjoint(p, x, y, stream)
+        else:
+            fn = lambda: ss.spinsum_exec(p, x, y, stream)
+        nbytes = 2 * x.numel() * x.element_size()
+    elif name == "batched_graph":
+        # the 200 power-law blocks, the autotuner's item size and launch
+        # style, one graph launch per step (the tuning launches come first;
+        # the summaries count the last launches only)
+        _, blocks = workloads.batched_blocks()
+        shapes = [(v, v, v, o, o, o) for v, o in blocks]
+        xs = [workloads.uniform(s, 3000 + k, device=dev) for k, s in enumerate(shapes)]
+        p = ss.spinsum_plan_batched(shapes, 3, alpha, inplace=True)
+        ss.spinsum_autotune(p, xs, xs)
+        for k, x in enumerate(xs):  # finite values again after the tuning passes
+            workloads.fill_uniform(x, 3000 + k)
+        graph = ss.spinsum_graph_create(p, xs, xs)
+        fn = lambda: ss.spinsum_graph_launch(graph, stream)
+        nbytes = 2 * 8 * sum(x.numel() for x in xs)
     elif name == "3d_unpack_antisymmetric":
         x = torch.empty(slab, dtype=torch.float64, device=dev)
         p = ss.spinsum_plan(slab, 3, 3, [workloads.antisymmetrizer(3)])
@@ -426,11 +457,12 @@ def profile_one(name, steps, warmup):
                       "kernel": {"stream_copy": "k_copy",
                                  "3d_coef_grad": ("k_cgrad_split<double, 3>" if info["coef_grad_split"]
                                                   else "k_cgrad<double, 3>"),
+                                 "batched_graph": batched_kernel_name(info),
                                  "3d_unpack_antisymmetric": "%s<double, 3, %s>" % (
                                      "k_unpack_persist" if info["unpack_persistent"] else "k_unpack",
                                      "true" if info["unpack_nt_stores"] else "false")}.get(
-                          name, kernel_name(info)),
-                      "tile_edge": info["bl"], **split,
+                          name, kernel_name(info, "float" if name.endswith("fp32") else "double")),
+                      "tile_edge": info["bl"], "launches_timed": steps, **split,
                       "kernel_source_hash": kernel_source_hash()}), flush=True)
 
 
@@ -684,6 +716,7 @@ def main():
                                        "item_kib": tuned["cubes_per_wg"],
                                        "persistent": tuned["variant"],
                                        "vs_per_block_launches": round(pms / bms, 3)})
+        forms["batched_graph"]["traffic"] = traffic_from_profile("batched_graph")
         forms["batched_per_block_launches"] = form_entry(nbytes, pms, value)
         del xs, graph, singles
         torch.cuda.empty_cache()
@@ -734,6 +767,11 @@ def main():
             if tag == "fp64":
                 forms["3d_v48_o24_forward_fp64"]["traffic"] = traffic_from_profile(
                     "3d_v48_o24_forward_fp64")
+                forms["3d_v48_o24_adjoint_fp64"]["traffic"] = traffic_from_profile(
+                    "3d_v48_o24_adjoint_fp64")
+            else:
+                forms["3d_v48_o24_forward_fp32"]["traffic"] = traffic_from_profile(
+                    "3d_v48_o24_forward_fp32")
             del x5, y5
             torch.cuda.empty_cache()
         accuracy = accuracy_report(ss, workloads, dev, stream)
