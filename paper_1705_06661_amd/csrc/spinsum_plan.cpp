@@ -130,6 +130,23 @@ static int max_orbit_tiles(const SymGroup& G, int nb) {
   return best;
 }
 
+// Element orbits of a whole N^d cube under the plan's group (Burnside: the
+// mean over the group of N^(cycles of the permutation)).
+static int64_t cube_orbits(const SymGroup& G, int n) {
+  int64_t sum = 0;
+  for (int r = 0; r < G.df; ++r) {
+    int cycles = 0;
+    bool seen[kMaxD] = {false, false, false, false};
+    for (int m = 0; m < G.d; ++m) {
+      if (seen[m]) continue;
+      ++cycles;
+      for (int j = m; !seen[j]; j = G.p[r][j]) seen[j] = true;
+    }
+    sum += ipow(n, cycles);
+  }
+  return sum / G.df;
+}
+
 static int64_t tile_lds_bytes(const spinsum_plan_s& P, int n, int bl, int cpw, int pad) {
   int32_t lst[kMaxD], ts;
   lds_strides(P.d, bl, pad, P.inner, lst, &ts);
@@ -272,6 +289,22 @@ spinsum_status choose_tile(const spinsum_plan_s& P, int n, int64_t ncubes, int v
   // slower (4.90 against 5.40), so it is not considered there.
   int first = 0;
   for (int pi = 0; pi < 3 && first == 0; ++pi) first = found[pi];
+  // Out of place, nothing has read the output lines into the L2, so tile
+  // rows of less than a 128-byte line, and ragged edge tiles, reach HBM as
+  // partial writes from different workgroups; a whole cube writes whole
+  // lines.  FP64 3D/2D cubes that fit a CU's LDS are therefore processed
+  // whole (one workgroup per CU).  Measured out of place: 24^3 FP64 5.21
+  // against 4.87 TB/s (bl 8), 22^3 4.96 against 2.13 and 26^3 4.78 against
+  // 2.11 (bl 8, ragged).  In place the tiles stay faster (24^3: 5.41 against
+  // 5.24), and so do FP32 32^3 cubes out of place (5.00 against 4.17).
+  if (single && !P.inplace && esz == 8 && d <= 3 && first > 0 &&
+      ((int64_t)first * P.inner * esz < 128 || n % first != 0) &&
+      cube_bytes + 16 + cube_orbits(P.G, n) * 4 <= budget) {
+    t.bl = n;
+    t.cubes_per_wg = 1;
+    *tile = t;
+    return SPINSUM_OK;
+  }
   if (single && first > 0 && (int64_t)first * P.inner * esz < 64) {
     const int cap = std::max((d == 4) ? 6 : (d == 3) ? 3 : 2, 1 + d);  // C(d, d/2) vs 1 + d
     for (int bl = std::min(n - 1, 255); bl > first && (n + bl - 1) / bl <= 2; --bl) {
@@ -590,17 +623,42 @@ static spinsum_status build_cgrad_tiling(spinsum_plan_s* P) {
   const Tiling& T = P->T;
   const int esz = elem_size(*P);
   if (P->cg_split) return SPINSUM_OK;  // one tile buffer: no packed tiling needed
-  if (P->pair || P->batched || T.g.bl >= T.g.n || T.orbits.size() < 2 ||
-      T.groups.size() != T.orbits.size() || P->tile.lds_pad != 0)
-    return SPINSUM_OK;
   auto cg_lds = [&](const Tiling& X) {
     return 2 * ((X.lds_elems * esz + 15) / 16 * 16) + (int64_t)X.max_rep_cnt * 4;
   };
+  const int vmax = max_vector_width(*P, (int64_t)std::max(1, P->n) * P->inner);
+  if (!P->pair && !P->batched && T.g.bl >= T.g.n && P->tile.lds_pad == 0 &&
+      cg_lds(T) > P->lds_limit) {
+    // whole cubes too large for both tensors (out of place, FP64 cubes up
+    // to a CU's LDS are summed whole): the gradient takes tiles of its own,
+    // the largest edge with whole 16-byte chunks per row whose tile orbits,
+    // both tensors, fit half a CU's LDS
+    for (int bl = P->n - 1; bl >= 1; --bl) {
+      spinsum_tile_t t = P->tile;
+      t.bl = bl;
+      t.cubes_per_wg = 1;
+      t.item_tiles = 0;
+      t.threads = 0;
+      Tiling Tc;
+      if (build_tiling(*P, P->n, P->ncubes, t, vmax, &Tc) != SPINSUM_OK) continue;
+      if (!Tc.fits || (int64_t)Tc.vw * esz != 16 || cg_lds(Tc) > P->lds_limit / 2) continue;
+      spinsum_status st = upload(P, &P->d_cg_orbits, Tc.groups.data(), Tc.groups.size());
+      if (st != SPINSUM_OK) return st;
+      st = upload(P, &P->d_cg_reps, Tc.reps.data(), Tc.reps.size());
+      if (st != SPINSUM_OK) return st;
+      P->Tc = std::move(Tc);
+      P->cg_pack = true;
+      return SPINSUM_OK;
+    }
+    return SPINSUM_OK;
+  }
+  if (P->pair || P->batched || T.g.bl >= T.g.n || T.orbits.size() < 2 ||
+      T.groups.size() != T.orbits.size() || P->tile.lds_pad != 0)
+    return SPINSUM_OK;
   if (P->lds_limit / std::max<int64_t>(1, cg_lds(T)) >= 4) return SPINSUM_OK;
   spinsum_tile_t t = P->tile;
   t.item_tiles = T.max_orbit_tiles;
   Tiling Tc;
-  const int vmax = max_vector_width(*P, (int64_t)std::max(1, P->n) * P->inner);
   if (build_tiling(*P, P->n, P->ncubes, t, vmax, &Tc) != SPINSUM_OK) return SPINSUM_OK;
   if (cg_lds(Tc) > P->lds_limit || Tc.vw != T.vw) return SPINSUM_OK;
   spinsum_status st = upload(P, &P->d_cg_orbits, Tc.groups.data(), Tc.groups.size());
@@ -657,8 +715,11 @@ static void choose_unpack_tiling(spinsum_plan_s* P) {
   P->pk_own = false;
   P->pk_persist = false;
   const Tiling& T = P->T;
-  if (P->pair || P->batched || P->ncubes <= 0 || P->elems <= 0 || T.g.bl >= T.g.n ||
-      P->tile.lds_pad != 0 || P->tile.variant != SPINSUM_VARIANT_DIRECT_LDS)
+  // (whole cubes several to a workgroup keep the plan's items; whole cubes
+  // one to a workgroup take the persistent kernel below)
+  if (P->pair || P->batched || P->ncubes <= 0 || P->elems <= 0 ||
+      (T.g.bl >= T.g.n && T.g.cpw > 1) || P->tile.lds_pad != 0 ||
+      P->tile.variant != SPINSUM_VARIANT_DIRECT_LDS)
     return;
   const int esz = elem_size(*P);
   const int d = P->d;

@@ -228,7 +228,8 @@ def test_unpack_tiling_rule():
     own tiling otherwise (unpack_bl reports it)."""
     as3, as4 = [workloads.antisymmetrizer(3)], [workloads.antisymmetrizer(4)]
     def ub(shape, gf, d, terms, dtype="f64"):
-        i = ss.spinsum_plan_get_info(ss.spinsum_plan(shape, gf, d, terms, dtype=dtype, flags=HOST))
+        i = ss.spinsum_plan_get_info(ss.spinsum_plan(shape, gf, d, terms, dtype=dtype, inplace=True,
+                                                     flags=HOST))
         return i["bl"], i["unpack_bl"]
     assert ub((64, 64, 8, 32, 32, 32), 3, 3, as3) == (8, 16)       # 256 KiB cubes: 128-byte rows
     assert ub((48, 48, 48, 24, 24, 24), 3, 3, as3) == (8, 24)      # whole 108 KiB cubes
@@ -241,8 +242,8 @@ def test_unpack_tiling_rule():
     bp = ss.spinsum_plan_batched([(8, 8, 8, 4, 4, 4)], 3, as3, flags=HOST)
     assert ss.spinsum_plan_get_info(bp)["unpack_bl"] == 0
     # unpacking's own items of d <= 3 run persistently where each template is
-    # one tile orbit whose units the threads hold; 4D, the plan's own whole
-    # cubes and the ablation flag do not
+    # one tile orbit or one whole cube whose units the threads hold; 4D,
+    # several cubes per workgroup and the ablation flag do not
     cubes = lambda shape, gf, d, terms, dtype="f64", flags=0: ss.spinsum_plan_get_info(
         ss.spinsum_plan(shape, gf, d, terms, dtype=dtype, flags=HOST | flags))["unpack_persistent"]
     assert cubes((48, 48, 48, 24, 24, 24), 3, 3, as3) == 1
@@ -251,14 +252,16 @@ def test_unpack_tiling_rule():
     assert cubes((64, 64, 8, 32, 32, 32), 3, 3, as3) == 1
     assert cubes((60, 160, 160), 1, 2, [workloads.antisymmetrizer(2)]) == 0  # 6400 units
     assert cubes((1, 24, 24, 24, 12, 12, 12, 12), 4, 4, as4) == 0
-    assert cubes((4, 11, 11, 11), 1, 3, as3) == 0
+    assert cubes((4, 11, 11, 11), 1, 3, as3) == 1                   # whole cubes, one per item
+    assert cubes((8192, 8, 8, 8), 1, 3, as3) == 0                   # two cubes per workgroup
     assert cubes((48, 48, 48, 24, 24, 24), 3, 3, as3, flags=ss.SPINSUM_FLAG_NO_XCD_REMAP) == 0
 
 
 def test_inner_spectator_geometry():
     """A cube of [.., N^d, inner] is N^d * inner contiguous elements; rows
     along the last group axis hold bl * inner elements."""
-    p = ss.spinsum_plan((3, 16, 16, 16, 3), 1, 3, [workloads.CONFIG_3D_ALPHA], flags=HOST)
+    p = ss.spinsum_plan((3, 16, 16, 16, 3), 1, 3, [workloads.CONFIG_3D_ALPHA], inplace=True,
+                        flags=HOST)
     info = ss.spinsum_plan_get_info(p)
     assert info["elems"] == 3 * 16 ** 3 * 3 and info["ncubes"] == 3
     assert info["bl"] < 16 and info["bl"] % 2 == 0      # 16-byte rows: bl * 3 * 8 % 16 == 0
@@ -450,9 +453,25 @@ def test_two_blocks_per_axis_tiles_pack_neighbouring_classes(shape, d, dtype, bl
     assert info["threads"] == 512 and info["lds_bytes"] <= 80 * 1024
     ok, why = ss.spinsum_plan_check_ownership(p)
     assert ok, why
-    # rows of 64 bytes already: no change (3D 24^3 FP64 keeps bl = 8)
-    p = plan((2, 24, 24, 24), [[((0, 1, 2), 1.0)]])
+    # rows of 64 bytes already: no change (3D 24^3 FP64 in place keeps bl = 8)
+    p = ss.spinsum_plan((2, 24, 24, 24), 1, 3, [[((0, 1, 2), 1.0)]], inplace=True, flags=HOST)
     assert ss.spinsum_plan_get_info(p)["bl"] == 8
+
+
+def test_out_of_place_whole_fp64_cubes():
+    """Out of place, FP64 cubes of d <= 3 that fit a CU's LDS are processed
+    whole where the tiles would write partial lines (rows under 128 bytes or
+    ragged edge tiles); in place, FP32 and 4D keep their tiles."""
+    as3 = [workloads.antisymmetrizer(3)]
+    bl = lambda shape, gf, d, terms, dtype="f64", inplace=False: ss.spinsum_plan_get_info(
+        ss.spinsum_plan(shape, gf, d, terms, dtype=dtype, inplace=inplace, flags=HOST))["bl"]
+    assert bl((48, 48, 48, 24, 24, 24), 3, 3, as3) == 24             # 108 KiB cubes
+    assert bl((48, 48, 48, 24, 24, 24), 3, 3, as3, inplace=True) == 8
+    assert bl((52, 52, 52, 22, 22, 22), 3, 3, as3) == 22             # ragged bl = 8 otherwise
+    assert bl((44, 44, 44, 26, 26, 26), 3, 3, as3) == 26             # 137 KiB + 13 KiB of lists
+    assert bl((40, 40, 40, 32, 32, 32), 3, 3, as3, "f32") == 16      # FP32 keeps its tiles
+    assert bl((64, 64, 8, 32, 32, 32), 3, 3, as3) == 8               # 256 KiB: does not fit
+    assert bl((1, 12, 12, 12, 12), 1, 4, [workloads.antisymmetrizer(4)]) == 6
 
 
 def test_small_orbits_are_packed_where_few_workgroups_fit():
