@@ -289,17 +289,22 @@ spinsum_status choose_tile(const spinsum_plan_s& P, int n, int64_t ncubes, int v
   // slower (4.90 against 5.40), so it is not considered there.
   int first = 0;
   for (int pi = 0; pi < 3 && first == 0; ++pi) first = found[pi];
-  // Out of place, nothing has read the output lines into the L2, so tile
-  // rows of less than a 128-byte line, and ragged edge tiles, reach HBM as
-  // partial writes from different workgroups; a whole cube writes whole
-  // lines.  FP64 3D/2D cubes that fit a CU's LDS are therefore processed
-  // whole (one workgroup per CU).  Measured out of place: 24^3 FP64 5.21
-  // against 4.87 TB/s (bl 8), 22^3 4.96 against 2.13 and 26^3 4.78 against
-  // 2.11 (bl 8, ragged).  In place the tiles stay faster (24^3: 5.41 against
-  // 5.24), and so do FP32 32^3 cubes out of place (5.00 against 4.17).
-  if (single && !P.inplace && esz == 8 && d <= 3 && first > 0 &&
-      ((int64_t)first * P.inner * esz < 128 || n % first != 0) &&
-      cube_bytes + 16 + cube_orbits(P.G, n) * 4 <= budget) {
+  // Whole cubes of up to a CU's LDS (one workgroup per CU, d <= 3) where
+  // the tiles would be slow:
+  //  - no tile edge gives rows of whole 16-byte chunks (the register path:
+  //    25^3 FP64 0.51 against 5.17 TB/s whole, 30^3 FP32 0.53 against 4.53);
+  //  - the tiles are ragged (22^3 / 26^3 FP64 in place 4.71 / 4.24 against
+  //    5.03 / 4.77, out of place 2.13 / 2.11 against 4.96 / 4.78; 28^3 FP32
+  //    out of place 3.04 against 4.69);
+  //  - out of place, FP64 rows shorter than a 128-byte line: nothing has
+  //    read the output lines into the L2, so partial rows from different
+  //    workgroups reach HBM as partial writes (24^3 5.21 against 4.87).
+  // In place, full-sized 64-byte tile rows stay faster (24^3 FP64: 5.41
+  // against 5.24), and so do FP32 32^3 cubes out of place (5.00 against
+  // 4.17).
+  if (single && d <= 3 && cube_bytes + 16 + cube_orbits(P.G, n) * 4 <= budget &&
+      (first == 0 || n % first != 0 ||
+       (!P.inplace && esz == 8 && (int64_t)first * P.inner * esz < 128))) {
     t.bl = n;
     t.cubes_per_wg = 1;
     *tile = t;

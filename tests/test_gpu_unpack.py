@@ -144,7 +144,7 @@ OWN_TILING_CASES = [
     ((3, 24, 24, 24), 1, 3, torch.float64),      # whole 24^3 cubes
     ((2, 2, 32, 32, 32), 2, 3, torch.float64),   # bl 16: 128-byte rows
     ((2, 32, 32, 32), 1, 3, torch.float32),      # whole 32^3 FP32 cubes
-    ((3, 16, 16, 16, 4), 1, 3, torch.float64),   # whole cubes with inner runs
+    ((3, 12, 12, 12, 8), 1, 3, torch.float64),   # whole cubes with inner runs (bl 4)
     ((2, 160, 160), 1, 2, torch.float64),         # bl 80 instead of 40
 ]
 

@@ -234,7 +234,7 @@ def test_unpack_tiling_rule():
     assert ub((64, 64, 8, 32, 32, 32), 3, 3, as3) == (8, 16)       # 256 KiB cubes: 128-byte rows
     assert ub((48, 48, 48, 24, 24, 24), 3, 3, as3) == (8, 24)      # whole 108 KiB cubes
     assert ub((64, 64, 8, 32, 32, 32), 3, 3, as3, "f32") == (16, 32)
-    assert ub((3, 16, 16, 16, 4), 1, 3, as3) == (5, 16)            # whole cubes, inner runs
+    assert ub((3, 16, 16, 16, 4), 1, 3, as3) == (16, 16)           # whole cubes (5 would be ragged)
     assert ub((1, 24, 24, 24, 12, 12, 12, 12), 4, 4, as4) == (6, 6)  # 162 KiB cubes, 48-byte rows
     assert ub((80, 80, 80, 80), 0, 4, as4) == (4, 4)
     assert ub((4, 11, 11, 11), 1, 3, as3) == (11, 11)              # whole cubes already
@@ -260,11 +260,11 @@ def test_unpack_tiling_rule():
 def test_inner_spectator_geometry():
     """A cube of [.., N^d, inner] is N^d * inner contiguous elements; rows
     along the last group axis hold bl * inner elements."""
-    p = ss.spinsum_plan((3, 16, 16, 16, 3), 1, 3, [workloads.CONFIG_3D_ALPHA], inplace=True,
+    p = ss.spinsum_plan((2, 32, 32, 32, 3), 1, 3, [workloads.CONFIG_3D_ALPHA], inplace=True,
                         flags=HOST)
     info = ss.spinsum_plan_get_info(p)
-    assert info["elems"] == 3 * 16 ** 3 * 3 and info["ncubes"] == 3
-    assert info["bl"] < 16 and info["bl"] % 2 == 0      # 16-byte rows: bl * 3 * 8 % 16 == 0
+    assert info["elems"] == 2 * 32 ** 3 * 3 and info["ncubes"] == 2
+    assert info["bl"] < 32 and info["bl"] % 2 == 0      # 16-byte rows: bl * 3 * 8 % 16 == 0
     assert info["vector_width"] == 2
     # an empty inner dim empties the tensor
     p0 = ss.spinsum_plan((3, 4, 4, 4, 0), 1, 3, [workloads.CONFIG_3D_ALPHA], flags=HOST)
@@ -458,10 +458,11 @@ def test_two_blocks_per_axis_tiles_pack_neighbouring_classes(shape, d, dtype, bl
     assert ss.spinsum_plan_get_info(p)["bl"] == 8
 
 
-def test_out_of_place_whole_fp64_cubes():
-    """Out of place, FP64 cubes of d <= 3 that fit a CU's LDS are processed
-    whole where the tiles would write partial lines (rows under 128 bytes or
-    ragged edge tiles); in place, FP32 and 4D keep their tiles."""
+def test_whole_cubes_where_tiles_are_slow():
+    """Cubes of d <= 3 that fit a CU's LDS are processed whole where no tile
+    edge gives rows of whole 16-byte chunks, where the tiles would be ragged,
+    and, out of place, where FP64 tile rows would write partial lines; in
+    place with full 64-byte rows, FP32 32^3 cubes and 4D keep their tiles."""
     as3 = [workloads.antisymmetrizer(3)]
     bl = lambda shape, gf, d, terms, dtype="f64", inplace=False: ss.spinsum_plan_get_info(
         ss.spinsum_plan(shape, gf, d, terms, dtype=dtype, inplace=inplace, flags=HOST))["bl"]
@@ -472,6 +473,12 @@ def test_out_of_place_whole_fp64_cubes():
     assert bl((40, 40, 40, 32, 32, 32), 3, 3, as3, "f32") == 16      # FP32 keeps its tiles
     assert bl((64, 64, 8, 32, 32, 32), 3, 3, as3) == 8               # 256 KiB: does not fit
     assert bl((1, 12, 12, 12, 12), 1, 4, [workloads.antisymmetrizer(4)]) == 6
+    # no edge with rows of whole 16-byte chunks, or ragged tiles: whole cubes
+    # in place too (the register path ran at a tenth of the speed)
+    assert bl((40, 40, 40, 25, 25, 25), 3, 3, as3, inplace=True) == 25
+    assert bl((40, 40, 40, 30, 30, 30), 3, 3, as3, "f32", inplace=True) == 30
+    assert bl((52, 52, 52, 22, 22, 22), 3, 3, as3, inplace=True) == 22
+    assert bl((40, 40, 40, 28, 28, 28), 3, 3, as3, "f32") == 28
 
 
 def test_small_orbits_are_packed_where_few_workgroups_fit():
