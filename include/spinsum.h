@@ -308,7 +308,9 @@ spinsum_status spinsum_adjoint(spinsum_plan_t plan, const void* grad_out, void* 
  * bits may differ from run to run; calls on one plan must not overlap.
  * Needs the direct-LDS tile layout (whole cubes, or tile rows of whole
  * 16-byte chunks) and a plan without SPINSUM_FLAG_INDEX_PAIRS:
- * SPINSUM_ERR_UNSUPPORTED otherwise.  Asynchronous on `stream`. */
+ * SPINSUM_ERR_UNSUPPORTED otherwise.  Where the plan's whole cubes are too
+ * large for both tensors in one CU's LDS, the gradient runs on tiles of its
+ * own, made with the plan.  Asynchronous on `stream`. */
 spinsum_status spinsum_coef_grad(spinsum_plan_t plan, const void* x, const void* g,
                                  double* grad, void* stream);
 
