@@ -223,8 +223,8 @@ static bool order_reps_for_banks(std::vector<uint32_t>& reps, size_t off, const 
 }
 
 // Default tile (measured on MI355X; spinsum_autotune searches more).
-//  1. Cubes up to 64 KiB are processed whole, several per workgroup up to
-//     about 8 KiB, as one contiguous copy (any extent).
+//  1. Cubes up to 64 KiB are processed whole, as many per workgroup as
+//     make at least 8 KiB, as one contiguous copy (any extent).
 //  2. Larger cubes use tile orbits whose rows (also the short rows of
 //     ragged edge tiles) are whole 16-byte chunks, for the direct-LDS kernel:
 //     rows of at least 32 bytes with the largest orbit within 32 KiB of LDS,
@@ -245,7 +245,11 @@ spinsum_status choose_tile(const spinsum_plan_s& P, int n, int64_t ncubes, int v
   const int64_t cube_bytes = ipow(n, d) * P.inner * esz;
   if (cube_bytes <= 64 * 1024 && cube_bytes + 16 + ipow(n, d) * 4 <= budget) {
     t.bl = n;
-    int cpw = (int)std::max<int64_t>(1, (8 * 1024) / std::max<int64_t>(1, cube_bytes));
+    // at least 8 KiB per work item: smaller items leave the CU waiting
+    // (9^3 FP64 5.84 TB/s with two cubes against 4.33 with one; 11^3 FP32
+    // 5.22 with two against 3.41; 9^3 FP32 4.66 with three against 3.79)
+    const int64_t cb = std::max<int64_t>(1, cube_bytes);
+    int cpw = (int)std::max<int64_t>(1, (8 * 1024 + cb - 1) / cb);
     // keep at least ~8 workgroups per CU of work when the tensor allows it
     int64_t cap = std::max<int64_t>(1, ncubes / (8 * (int64_t)P.num_cus));
     cpw = (int)std::min<int64_t>(cpw, cap);
